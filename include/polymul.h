@@ -1,0 +1,175 @@
+/*
+ * polymul.h - C ABI of the MI355X (gfx950) modular polynomial multiplication
+ * library: products over Z/pZ by number-theoretic transforms, following
+ * L. Meng, "Automatic Library Generation for Modular Polynomial Multiplication".
+ *
+ * General conventions (apply to every call unless stated otherwise):
+ *  - Coefficient arrays are little-endian in the degree: element i is the
+ *    coefficient of x^i (Def. 1).  Elements are uint32 in canonical form
+ *    [0, p); a value >= p is an error, detected on the device and reported
+ *    as PM_ENOTREDUCED by pm_stream_check (it is never reduced silently).
+ *  - All data pointers are DEVICE pointers on the current HIP device, owned by
+ *    the caller (for instance torch tensors).  The library never frees them.
+ *    Distinct arrays must not overlap.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it and the call returns after host-side validation;
+ *    results are valid once the stream has reached that point.
+ *  - p must be one of 998244353 (119*2^23+1, root 3), 2013265921 (15*2^27+1,
+ *    root 31), 469762049 (7*2^26+1, root 3), 167772161 (5*2^25+1, root 3);
+ *    other values give PM_EUNSUPPORTED.  A transform length L must divide
+ *    p - 1 (L <= 2^23, 2^27, 2^26, 2^25 respectively, and L <= 2^24 overall);
+ *    larger lengths give PM_ETOOLARGE.
+ *  - A zero length or a NULL pointer gives PM_EINVAL.  Errors detected on the
+ *    host leave the outputs untouched and enqueue nothing.
+ *  - The library owns its twiddle tables, plan cache and workspace (allocated
+ *    lazily per device with hipMalloc, freed at process exit).  Calls from
+ *    several host threads are serialised per device.
+ */
+#ifndef POLYMUL_H
+#define POLYMUL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PM_OK = 0,
+  PM_EINVAL = 1,        /* bad argument: NULL pointer, zero length, bad size */
+  PM_EUNSUPPORTED = 2,  /* modulus not among the four supported primes */
+  PM_ETOOLARGE = 3,     /* transform length exceeds what p supports */
+  PM_ENOTREDUCED = 4,   /* an input coefficient was >= p (reported late) */
+  PM_ENOMEM = 5,        /* device allocation failed */
+  PM_EDEVICE = 6        /* a HIP call or kernel launch failed */
+} pm_status;
+
+/* Text for a status code (static storage). */
+const char* pm_status_str(pm_status s);
+
+/* Initialise the library on the current device (optional: every call does it
+ * on first use).  Builds the twiddle tables of all four primes. */
+pm_status pm_init(void);
+
+/*
+ * Polynomial product (Def. 2, eq. 2; the linear convolution of Def. 3):
+ *   c_k = sum_{i+j=k} a_i b_j mod p,   0 <= k <= len_a + len_b - 2.
+ * a: len_a coefficients, b: len_b coefficients, c: len_a + len_b - 1 outputs.
+ * Computed by the convolution theorem (Theorem 1, eq. 10): forward transforms
+ * of both operands, n pointwise products, one inverse transform with scaling.
+ * The transform is the padded power-of-two modular DFT (eq. 12) when
+ * len_a + len_b - 1 is a power of two, otherwise a relaxed truncated Fourier
+ * transform (TFT/ITFT, eq. 14) that computes n' >= len_a + len_b - 1 values,
+ * n' a multiple of the plan's granularity, without padding to the next power
+ * of two.  Products with fewer than 64 outputs use the defining sum directly.
+ * Requires the transform length L (next power of two >= len_a + len_b - 1)
+ * to be supported by p.  c must not overlap a or b.
+ */
+pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p, uint32_t* c,
+                      void* stream);
+
+/* One problem of a batch; all pointers are device pointers. */
+typedef struct {
+  const uint32_t* a;
+  size_t len_a;
+  const uint32_t* b;
+  size_t len_b;
+  uint32_t p;
+  uint32_t* c; /* len_a + len_b - 1 outputs */
+} pm_problem;
+
+/*
+ * Batch of independent products (each as pm_poly_mul), of uneven lengths and
+ * mixed primes.  `probs` is a HOST array of `count` problems.  The batch is
+ * grouped by size class and run as one hipGraph launch of persistent
+ * kernels; graphs are cached by the batch's shape signature.  On a host-side
+ * error no problem is computed.  Output arrays must be pairwise disjoint.
+ */
+pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream);
+
+/*
+ * Integer product by the three-primes algorithm (section 1): A and B are
+ * little-endian integers of na and nb 16-bit limbs (A = sum a_i 2^{16 i}).
+ * The limb sequences are multiplied as polynomials modulo 469762049,
+ * 998244353 and 167772161, the three residues of every coefficient are
+ * combined by the Chinese remainder theorem into the exact (< 2^87) sum, and
+ * carries are propagated.  c receives exactly na + nb limbs of A*B (the top
+ * limb may be 0).  Requires na + nb - 1 <= 2^23.
+ */
+pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint16_t* c, void* stream);
+
+/*
+ * Length-n modular DFT (section 3: evaluation at w^0 .. w^{n-1}, with
+ * w = g^((p-1)/n)), natural order in and out, n a power of two, 2 <= n.
+ * inverse != 0 computes the inverse transform including the factor n^-1.
+ * x: n inputs; y: n outputs (may equal x).
+ */
+pm_status pm_ntt(const uint32_t* x, uint32_t* y, size_t n, uint32_t p, int inverse, void* stream);
+
+/*
+ * Truncated Fourier transform TFT(L, z, n) (section 3, the TFT product):
+ *   out_i = sum_{j<z} x_j w_L^{j rev_l(i)},  0 <= i < n,
+ * with rev_l the bit reversal on l = log2 L bits (the first n values of the
+ * length-L transform in bit-reversed order).  L a power of two, 1 <= z <= L,
+ * 1 <= n <= L.  x: z inputs; out: n outputs.
+ */
+pm_status pm_tft(const uint32_t* x, size_t z, size_t L, size_t n, uint32_t p, uint32_t* out, void* stream);
+
+/*
+ * Inverse truncated Fourier transform ITFT(L, n, n): given the n values
+ * v_i = u(w_L^{rev_l(i)}) of a polynomial u of degree < n, returns
+ * (L u_0, ..., L u_{n-1}), the scaling the paper states for the ITFT.
+ * v: n inputs; out: n outputs.  n must be a multiple of the granularity
+ * pm_itft_granularity(L) (every n when L <= 32); otherwise PM_EINVAL.
+ */
+pm_status pm_itft(const uint32_t* v, size_t L, size_t n, uint32_t p, uint32_t* out, void* stream);
+
+/* Granularity of the relaxed truncation for transform length L: the
+ * multiple n' of the relaxed transforms is taken in steps of this size. */
+size_t pm_itft_granularity(size_t L);
+
+/*
+ * Wait for `stream` and report errors detected on the device since the last
+ * check on this device (PM_ENOTREDUCED), or PM_EDEVICE if the stream failed.
+ * Clears the device error state.
+ */
+pm_status pm_stream_check(void* stream);
+
+/* ---- plans, tuning and the learned cost model --------------------------- */
+
+typedef enum { PM_POLICY_DEFAULT = 0, PM_POLICY_EXHAUSTIVE = 1, PM_POLICY_LEARNED = 2 } pm_policy;
+
+/* Plan description (see pm_plan_for / pm_poly_mul_plan). */
+typedef struct {
+  int32_t kind;  /* 0: defining sum, 1: one work-group in LDS, 2: four-step */
+  int32_t log_l; /* transform length L = 2^log_l */
+  int32_t log_ra; /* first radix (the truncated one) */
+  int32_t log_rb; /* second column radix of the four-step (0: none) */
+  int32_t log_c;  /* row length of the four-step (LDS tile) */
+  int32_t ma;     /* kept blocks of the first radix, 1 .. 2^log_ra */
+  int32_t lq;     /* log radix of the LDS rounds */
+} pm_plan;
+
+/* Select the policy used by pm_poly_mul / pm_poly_mul_batch to pick plans. */
+pm_status pm_set_policy(pm_policy policy);
+
+/* The plan the current policy picks for an output length lc and prime p. */
+pm_status pm_plan_for(size_t lc, uint32_t p, pm_plan* plan);
+
+/* Product with an explicit plan (validated; PM_EINVAL if it does not fit). */
+pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
+                           uint32_t* c, const pm_plan* plan, void* stream);
+
+/* Number of candidate plans for (lc, p) and the i-th one (the tuner's space). */
+size_t pm_plan_candidates(size_t lc, uint32_t p, pm_plan* out, size_t max_out);
+
+/* Record the plan to use for (lc, p) in the plan cache (used by all policies
+ * before they choose). */
+pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan);
+void pm_plan_cache_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -188,8 +188,7 @@ def tft(x, z: int, L: int, n: int, p: int, g: int) -> np.ndarray:
     buf = np.zeros(L, dtype=np.uint32)
     buf[:z] = _as_u32(x)[:z]
     full = ntt(buf, p, g)
-    idx = np.array([bitrev(i, l) for i in range(n)], dtype=np.int64)
-    return full[idx]
+    return full[bitrev_perm(L)[:n]]
 
 
 # --- three-primes integer product (section 1) ---------------------------------
@@ -262,8 +261,14 @@ def int_convolve(a_limbs, b_limbs) -> list:
 
 
 def bitrev_perm(L: int) -> np.ndarray:
+    """[rev_l(i) for i < L], built bit by bit with numpy."""
     l = L.bit_length() - 1
-    return np.array([bitrev(i, l) for i in range(L)], dtype=np.int64)
+    i = np.arange(L, dtype=np.int64)
+    r = np.zeros(L, dtype=np.int64)
+    for _ in range(l):
+        r = (r << 1) | (i & 1)
+        i >>= 1
+    return r
 
 
 def binom_mod(n: int, k: int, p: int) -> int:

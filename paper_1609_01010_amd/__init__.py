@@ -1,1 +1,267 @@
-"""MI355X-native modular polynomial multiplication (NTT / TFT convolution)."""
+"""MI355X-native modular polynomial multiplication (NTT / TFT convolution over Z/pZ).
+
+Thin ctypes binding over the C ABI of ``libpolymul.so`` (declared in
+``include/polymul.h``).  PyTorch supplies device memory and the current HIP
+stream; every step of every product runs in the library's HIP kernels.  If
+the library has not been built the calls raise: there is no fallback.
+
+    import torch, paper_1609_01010_amd as pm
+    a = torch.randint(0, 998244353, (1024,), dtype=torch.int64).to(torch.uint32).cuda()
+    c = pm.poly_mul(a, a, 998244353)          # 2047 coefficients, uint32
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpolymul.so")
+
+PRIMES = (998244353, 2013265921, 469762049, 167772161)
+
+PM_OK, PM_EINVAL, PM_EUNSUPPORTED, PM_ETOOLARGE, PM_ENOTREDUCED, PM_ENOMEM, PM_EDEVICE = range(7)
+POLICY_DEFAULT, POLICY_EXHAUSTIVE, POLICY_LEARNED = range(3)
+
+
+class PolymulError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = _status_str(status)
+        super().__init__(f"{what}: {msg} (status {status})" if what else f"{msg} (status {status})")
+
+
+class Plan(ctypes.Structure):
+    """Mirror of pm_plan."""
+
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("log_l", ctypes.c_int32),
+        ("log_ra", ctypes.c_int32),
+        ("log_rb", ctypes.c_int32),
+        ("log_c", ctypes.c_int32),
+        ("ma", ctypes.c_int32),
+        ("lq", ctypes.c_int32),
+    ]
+
+    def as_tuple(self):
+        return tuple(getattr(self, f) for f, _ in self._fields_)
+
+    def __repr__(self):
+        return "Plan(" + ", ".join(f"{f}={getattr(self, f)}" for f, _ in self._fields_) + ")"
+
+
+class Problem(ctypes.Structure):
+    """Mirror of pm_problem."""
+
+    _fields_ = [
+        ("a", ctypes.c_void_p),
+        ("len_a", ctypes.c_size_t),
+        ("b", ctypes.c_void_p),
+        ("len_b", ctypes.c_size_t),
+        ("p", ctypes.c_uint32),
+        ("c", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+_lock = threading.Lock()
+
+# exported functions: name -> (restype, argtypes)
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_u32 = ctypes.c_uint32
+_int = ctypes.c_int
+SIGNATURES = {
+    "pm_status_str": (ctypes.c_char_p, [_int]),
+    "pm_init": (_int, []),
+    "pm_poly_mul": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, _vp]),
+    "pm_poly_mul_batch": (_int, [ctypes.POINTER(Problem), _sz, _vp]),
+    "pm_int_mul": (_int, [_vp, _sz, _vp, _sz, _vp, _vp]),
+    "pm_ntt": (_int, [_vp, _vp, _sz, _u32, _int, _vp]),
+    "pm_tft": (_int, [_vp, _sz, _sz, _sz, _u32, _vp, _vp]),
+    "pm_itft": (_int, [_vp, _sz, _sz, _u32, _vp, _vp]),
+    "pm_itft_granularity": (_sz, [_sz]),
+    "pm_stream_check": (_int, [_vp]),
+    "pm_set_policy": (_int, [_int]),
+    "pm_plan_for": (_int, [_sz, _u32, ctypes.POINTER(Plan)]),
+    "pm_poly_mul_plan": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, ctypes.POINTER(Plan), _vp]),
+    "pm_plan_candidates": (_sz, [_sz, _u32, ctypes.POINTER(Plan), _sz]),
+    "pm_plan_cache_put": (_int, [_sz, _u32, ctypes.POINTER(Plan)]),
+    "pm_plan_cache_clear": (None, []),
+}
+
+
+def lib():
+    """Load libpolymul.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(
+                    "libpolymul.so is not built; run `python -m paper_1609_01010_amd.build` "
+                    "(there is no non-HIP fallback)"
+                )
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _status_str(st: int) -> str:
+    try:
+        return lib().pm_status_str(st).decode()
+    except ImportError:
+        return "status %d" % st
+
+
+def _check(st: int, what: str = ""):
+    if st != PM_OK:
+        raise PolymulError(st, what)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# products
+
+def poly_mul(a, b, p: int, out=None, plan: Plan | None = None, stream=None):
+    """c_k = sum_{i+j=k} a_i b_j mod p for uint32 device tensors a, b."""
+    torch = _torch()
+    la, lb = a.numel(), b.numel()
+    if out is None:
+        out = torch.empty(max(la + lb - 1, 1), dtype=torch.uint32, device=a.device)
+    args = (_dev_ptr(a, torch.uint32, "a"), la, _dev_ptr(b, torch.uint32, "b"), lb, p, _dev_ptr(out, torch.uint32, "out"))
+    if plan is None:
+        _check(lib().pm_poly_mul(*args, _stream(stream)), "pm_poly_mul")
+    else:
+        _check(lib().pm_poly_mul_plan(*args, ctypes.byref(plan), _stream(stream)), "pm_poly_mul_plan")
+    return out
+
+
+def poly_mul_batch(problems, outs=None, stream=None):
+    """problems: list of (a, b, p); returns the list of products."""
+    torch = _torch()
+    n = len(problems)
+    arr = (Problem * n)()
+    res = []
+    for i, (a, b, p) in enumerate(problems):
+        la, lb = a.numel(), b.numel()
+        c = outs[i] if outs is not None else torch.empty(la + lb - 1, dtype=torch.uint32, device=a.device)
+        arr[i].a = _dev_ptr(a, torch.uint32, "a").value
+        arr[i].len_a = la
+        arr[i].b = _dev_ptr(b, torch.uint32, "b").value
+        arr[i].len_b = lb
+        arr[i].p = p
+        arr[i].c = _dev_ptr(c, torch.uint32, "c").value
+        res.append(c)
+    _check(lib().pm_poly_mul_batch(arr, n, _stream(stream)), "pm_poly_mul_batch")
+    return res
+
+
+def int_mul(a, b, out=None, stream=None):
+    """Product of two little-endian 16-bit-limb integers (uint16 tensors): na + nb limbs."""
+    torch = _torch()
+    na, nb = a.numel(), b.numel()
+    if out is None:
+        out = torch.empty(na + nb, dtype=torch.uint16, device=a.device)
+    _check(
+        lib().pm_int_mul(_dev_ptr(a, torch.uint16, "a"), na, _dev_ptr(b, torch.uint16, "b"), nb,
+                         _dev_ptr(out, torch.uint16, "out"), _stream(stream)),
+        "pm_int_mul",
+    )
+    return out
+
+
+# ---------------------------------------------------------------------------
+# transform hooks
+
+def ntt(x, p: int, inverse: bool = False, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().pm_ntt(_dev_ptr(x, torch.uint32, "x"), _dev_ptr(out, torch.uint32, "out"), x.numel(), p,
+                        1 if inverse else 0, _stream(stream)), "pm_ntt")
+    return out
+
+
+def tft(x, L: int, n: int, p: int, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint32, device=x.device)
+    _check(lib().pm_tft(_dev_ptr(x, torch.uint32, "x"), x.numel(), L, n, p, _dev_ptr(out, torch.uint32, "out"),
+                        _stream(stream)), "pm_tft")
+    return out
+
+
+def itft(v, L: int, p: int, out=None, stream=None):
+    torch = _torch()
+    n = v.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint32, device=v.device)
+    _check(lib().pm_itft(_dev_ptr(v, torch.uint32, "v"), L, n, p, _dev_ptr(out, torch.uint32, "out"),
+                         _stream(stream)), "pm_itft")
+    return out
+
+
+def itft_granularity(L: int) -> int:
+    return int(lib().pm_itft_granularity(L))
+
+
+def stream_check(stream=None) -> int:
+    """Synchronise and return the deferred device status (0 = ok)."""
+    return int(lib().pm_stream_check(_stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# plans
+
+def set_policy(policy: int):
+    _check(lib().pm_set_policy(policy), "pm_set_policy")
+
+
+def plan_for(lc: int, p: int) -> Plan:
+    P = Plan()
+    _check(lib().pm_plan_for(lc, p, ctypes.byref(P)), "pm_plan_for")
+    return P
+
+
+def plan_candidates(lc: int, p: int):
+    n = lib().pm_plan_candidates(lc, p, None, 0)
+    arr = (Plan * max(n, 1))()
+    lib().pm_plan_candidates(lc, p, arr, n)
+    return [arr[i] for i in range(n)]
+
+
+def plan_cache_put(lc: int, p: int, plan: Plan):
+    _check(lib().pm_plan_cache_put(lc, p, ctypes.byref(plan)), "pm_plan_cache_put")
+
+
+def plan_cache_clear():
+    lib().pm_plan_cache_clear()

@@ -1,0 +1,526 @@
+// The C ABI (include/polymul.h): argument validation, plan choice, workspace,
+// and the launch sequences of the product, the hooks and the integer product.
+#include <cstring>
+
+#include "internal.h"
+
+namespace pm {
+hipError_t launch_crt_carry(const u32* r1, const u32* r2, const u32* r3, long lc, long nl, void* ws, uint16_t* out,
+                            hipStream_t s);
+size_t crt_workspace_bytes(long nl);
+hipError_t launch_widen(const uint16_t* in, long n, u32* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// plans
+
+static int ceil_log2(long x) {
+  int l = 0;
+  while ((1l << l) < x) ++l;
+  return l;
+}
+
+static std::mutex g_plan_mu;
+static pm_policy g_policy = PM_POLICY_DEFAULT;
+static std::map<std::pair<long, u32>, Plan> g_plan_cache;
+
+bool plan_valid(const Plan& P, long lc, int pidx) {
+  const PrimeInfo& PI = prime_info(pidx);
+  if (P.lq != 3 && P.lq != 4) return false;
+  if (P.kind == PLAN_DIRECT) return lc >= 1 && lc <= 64;
+  if (P.logL < 1 || P.logL > PI.two_adic || P.logL > 24) return false;
+  if (P.logRA < 1 || P.logRA > 5 || P.ma < 1 || P.ma > (1 << P.logRA)) return false;
+  if (plan_nprime(P) < lc) return false;
+  if (P.kind == PLAN_LDS) {
+    return P.logL >= 6 && P.logL <= 14 && P.logRA <= P.logL && P.logRB == 0;
+  }
+  if (P.kind == PLAN_FOURSTEP) {
+    if (P.logC < 10 || P.logC > 14) return false;
+    if (P.logRB < 0 || P.logRB > 5 || (P.logRB > 0 && P.logRA != 5)) return false;
+    return P.logL == P.logRA + P.logRB + P.logC;
+  }
+  return false;
+}
+
+static int kept_blocks(long lc, int logL, int logRA) {
+  const long g = 1l << (logL - logRA);  // granularity L / RA
+  return (int)((lc + g - 1) / g);
+}
+
+Plan default_plan(long lc, int pidx) {
+  Plan P;
+  if (lc <= 64) {
+    P.kind = PLAN_DIRECT;
+    return P;
+  }
+  P.logL = ceil_log2(lc);
+  if (P.logL <= 14) {
+    P.kind = PLAN_LDS;
+    P.logRA = P.logL < 4 ? P.logL : 4;
+  } else {
+    P.kind = PLAN_FOURSTEP;
+    P.logRA = 5;
+    P.logC = P.logL - 5 < 10 ? 10 : (P.logL - 5 > 14 ? 14 : P.logL - 5);
+    P.logRB = P.logL - P.logC - P.logRA;
+    if (P.logRB < 0) {  // L = 2^15 with C = 2^10 needs RA = 32, RB = 0
+      P.logRA += P.logRB;
+      P.logRB = 0;
+    }
+  }
+  P.ma = kept_blocks(lc, P.logL, P.logRA);
+  return P;
+}
+
+// candidate plans for the tuner: every valid (kind, C, RA, RB, lq) with and
+// without truncation
+std::vector<Plan> plan_candidates(long lc, int pidx) {
+  std::vector<Plan> out;
+  if (lc <= 64) {
+    Plan P;
+    out.push_back(P);
+    return out;
+  }
+  const int logL = ceil_log2(lc);
+  for (int lq = 3; lq <= 4; ++lq) {
+    for (int trunc = 1; trunc >= 0; --trunc) {
+      if (logL <= 14) {
+        for (int lra = 2; lra <= 5 && lra <= logL; ++lra) {
+          Plan P;
+          P.kind = PLAN_LDS;
+          P.logL = logL;
+          P.logRA = lra;
+          P.lq = lq;
+          P.ma = trunc ? kept_blocks(lc, logL, lra) : (1 << lra);
+          if (!trunc && P.ma == kept_blocks(lc, logL, lra)) continue;
+          if (plan_valid(P, lc, pidx)) out.push_back(P);
+        }
+      }
+      if (logL >= 12) {
+        for (int lc_ = 10; lc_ <= 14; ++lc_) {
+          const int lr = logL - lc_;
+          if (lr < 1) continue;
+          for (int lra = 1; lra <= 5; ++lra) {
+            const int lrb = lr - lra;
+            if (lrb < 0 || lrb > 5 || (lrb > 0 && lra != 5)) continue;
+            Plan P;
+            P.kind = PLAN_FOURSTEP;
+            P.logL = logL;
+            P.logC = lc_;
+            P.logRA = lra;
+            P.logRB = lrb;
+            P.lq = lq;
+            P.ma = trunc ? kept_blocks(lc, logL, lra) : (1 << lra);
+            if (!trunc && P.ma == kept_blocks(lc, logL, lra)) continue;
+            if (plan_valid(P, lc, pidx)) out.push_back(P);
+          }
+        }
+      }
+    }
+  }
+  return out;
+}
+
+Plan learned_plan(long lc, int pidx, bool* ok);  // cost model (tune.cpp)
+
+Plan choose_plan(long lc, int pidx) {
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plan_cache.find(std::make_pair(lc, prime_info(pidx).p));
+    if (it != g_plan_cache.end()) return it->second;
+  }
+  if (g_policy == PM_POLICY_LEARNED) {
+    bool ok = false;
+    Plan P = learned_plan(lc, pidx, &ok);
+    if (ok && plan_valid(P, lc, pidx)) return P;
+  }
+  return default_plan(lc, pidx);
+}
+
+static pm_plan to_pub(const Plan& P) {
+  pm_plan q;
+  q.kind = P.kind;
+  q.log_l = P.logL;
+  q.log_ra = P.logRA;
+  q.log_rb = P.logRB;
+  q.log_c = P.logC;
+  q.ma = P.ma;
+  q.lq = P.lq;
+  return q;
+}
+static Plan from_pub(const pm_plan& q) {
+  Plan P;
+  P.kind = q.kind;
+  P.logL = q.log_l;
+  P.logRA = q.log_ra;
+  P.logRB = q.log_rb;
+  P.logC = q.log_c;
+  P.ma = q.ma;
+  P.lq = q.lq;
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// execution
+
+static pm_status dev_status(hipError_t e) { return e == hipSuccess ? PM_OK : PM_EDEVICE; }
+
+// scale constant of the inverse: w = inv * 2^32 mod p (the Montgomery factor
+// of the pointwise product is folded in)
+static uint2 conv_scale(const Plan& P, int pidx) {
+  const PrimeInfo& PI = prime_info(pidx);
+  long denom;
+  const bool full = P.ma == (1 << P.logRA);
+  if (P.kind == PLAN_LDS)
+    denom = (1l << (P.logL - P.logRA)) * (full ? (1l << P.logRA) : 1l);
+  else
+    denom = (1l << P.logC) * (1l << P.logRB) * (full ? (1l << P.logRA) : 1l);
+  const u32 inv = h_inv((u32)(denom % PI.p), PI.p);
+  return h_shoup(h_mulmod(inv, h_powmod(2, 32, PI.p), PI.p), PI.p);
+}
+
+size_t plan_workspace_bytes(const Plan& P) {
+  if (P.kind != PLAN_FOURSTEP) return 0;
+  return 2 * (size_t)plan_nprime(P) * sizeof(u32);
+}
+
+// run one product with plan P; `ws` has plan_workspace_bytes(P) bytes
+pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const void* b, long lb, int in_type, u32* out,
+                      long lc, int pidx, void* ws, hipStream_t s) {
+  pm_status st = ensure_prime_tables(c, pidx);
+  if (st) return st;
+  const PrimeTables& T = c->tabs[pidx];
+  if (P.kind == PLAN_DIRECT) {
+    if (in_type != 0) return PM_EINVAL;
+    return dev_status(launch_direct((const u32*)a, la, (const u32*)b, lb, out, pidx, c->errflag, s));
+  }
+  const uint2 sc = conv_scale(P, pidx);
+  if (P.kind == PLAN_LDS) {
+    if (in_type != 0) return PM_EINVAL;
+    return dev_status(launch_lds_conv(P, (const u32*)a, la, (const u32*)b, lb, out, lc, pidx, T, sc, c->errflag, s));
+  }
+  SplitTables S;
+  st = get_split_tables(c, pidx, P.logL, &S);
+  if (st) return st;
+  u32* Ta = (u32*)ws;
+  u32* Tb = Ta + plan_nprime(P);
+  hipError_t e = launch_col_fwd(P, a, la, b, lb, in_type, Ta, Tb, pidx, T, c->errflag, s);
+  if (e == hipSuccess) e = launch_row_conv(P, Ta, Tb, Ta, pidx, T, S, sc, s);
+  if (e == hipSuccess) e = launch_col_inv(P, Ta, out, lc, pidx, T, s);
+  return dev_status(e);
+}
+
+}  // namespace pm
+
+using namespace pm;
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char* pm_status_str(pm_status s) {
+  switch (s) {
+    case PM_OK:
+      return "ok";
+    case PM_EINVAL:
+      return "invalid argument";
+    case PM_EUNSUPPORTED:
+      return "unsupported modulus";
+    case PM_ETOOLARGE:
+      return "transform length too large for the modulus";
+    case PM_ENOTREDUCED:
+      return "input coefficient not reduced modulo p";
+    case PM_ENOMEM:
+      return "device allocation failed";
+    case PM_EDEVICE:
+      return "device error";
+  }
+  return "unknown status";
+}
+
+pm_status pm_init(void) {
+  pm_status st;
+  DevCtx* c = ctx_current(&st);
+  if (!c) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (int i = 0; i < kNumPrimes; ++i) {
+    st = ensure_prime_tables(c, i);
+    if (st) return st;
+  }
+  return PM_OK;
+}
+
+static pm_status check_product_args(const void* a, size_t la, const void* b, size_t lb, uint32_t p, const void* c,
+                                    int* pidx, long* lc) {
+  if (!a || !b || !c || la == 0 || lb == 0) return PM_EINVAL;
+  if (la > (1ul << 24) || lb > (1ul << 24)) return PM_ETOOLARGE;
+  *pidx = prime_index(p);
+  if (*pidx < 0) return PM_EUNSUPPORTED;
+  *lc = (long)(la + lb - 1);
+  const int logL = ceil_log2(*lc);
+  const PrimeInfo& PI = prime_info(*pidx);
+  if (*lc > 64 && (logL > PI.two_adic || logL > 24)) return PM_ETOOLARGE;
+  return PM_OK;
+}
+
+static pm_status product_with(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
+                              uint32_t* c, const Plan* given, void* stream) {
+  int pidx;
+  long lc;
+  pm_status st = check_product_args(a, len_a, b, len_b, p, c, &pidx, &lc);
+  if (st) return st;
+  DevCtx* ctx = ctx_current(&st);
+  if (!ctx) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  Plan P = given ? *given : choose_plan(lc, pidx);
+  if (!plan_valid(P, lc, pidx)) return given ? PM_EINVAL : PM_ETOOLARGE;
+  const size_t wsb = plan_workspace_bytes(P);
+  if (wsb) {
+    st = ensure_workspace(ctx, wsb);
+    if (st) return st;
+  }
+  return run_product(ctx, P, a, (long)len_a, b, (long)len_b, 0, c, lc, pidx, ctx->ws, (hipStream_t)stream);
+}
+
+pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p, uint32_t* c,
+                      void* stream) {
+  return product_with(a, len_a, b, len_b, p, c, nullptr, stream);
+}
+
+pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
+                           uint32_t* c, const pm_plan* plan, void* stream) {
+  if (!plan) return PM_EINVAL;
+  Plan P = from_pub(*plan);
+  return product_with(a, len_a, b, len_b, p, c, &P, stream);
+}
+
+pm_status pm_set_policy(pm_policy policy) {
+  if (policy != PM_POLICY_DEFAULT && policy != PM_POLICY_EXHAUSTIVE && policy != PM_POLICY_LEARNED) return PM_EINVAL;
+  g_policy = policy;
+  return PM_OK;
+}
+
+pm_status pm_plan_for(size_t lc, uint32_t p, pm_plan* plan) {
+  if (!plan || lc == 0) return PM_EINVAL;
+  const int pidx = prime_index(p);
+  if (pidx < 0) return PM_EUNSUPPORTED;
+  const int logL = ceil_log2((long)lc);
+  if (lc > 64 && (logL > prime_info(pidx).two_adic || logL > 24)) return PM_ETOOLARGE;
+  *plan = to_pub(choose_plan((long)lc, pidx));
+  return PM_OK;
+}
+
+size_t pm_plan_candidates(size_t lc, uint32_t p, pm_plan* out, size_t max_out) {
+  const int pidx = prime_index(p);
+  if (pidx < 0 || lc == 0) return 0;
+  std::vector<Plan> v = plan_candidates((long)lc, pidx);
+  for (size_t i = 0; i < v.size() && i < max_out && out; ++i) out[i] = to_pub(v[i]);
+  return v.size();
+}
+
+pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan) {
+  const int pidx = prime_index(p);
+  if (pidx < 0) return PM_EUNSUPPORTED;
+  if (!plan || lc == 0) return PM_EINVAL;
+  Plan P = from_pub(*plan);
+  if (!plan_valid(P, (long)lc, pidx)) return PM_EINVAL;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plan_cache[std::make_pair((long)lc, p)] = P;
+  return PM_OK;
+}
+
+void pm_plan_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plan_cache.clear();
+}
+
+pm_status pm_stream_check(void* stream) {
+  pm_status st;
+  DevCtx* c = ctx_current(&st);
+  if (!c) return st;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PM_EDEVICE;
+  int flag = 0;
+  if (hipMemcpy(&flag, c->errflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return PM_EDEVICE;
+  if (flag) {
+    if (hipMemset(c->errflag, 0, sizeof(int)) != hipSuccess) return PM_EDEVICE;
+    return PM_ENOTREDUCED;
+  }
+  return PM_OK;
+}
+
+// ---- transform hooks --------------------------------------------------------
+
+size_t pm_itft_granularity(size_t L) { return L <= 32 ? 1 : L / 32; }
+
+// the hooks' plan for length L: one work-group up to 2^14, else four-step
+// with first radix 32
+static Plan hook_plan(int logL, int ma) {
+  Plan P;
+  P.logL = logL;
+  if (logL <= 14) {
+    P.kind = PLAN_LDS;
+    P.logRA = logL < 5 ? logL : 5;
+  } else {
+    P.kind = PLAN_FOURSTEP;
+    P.logRA = 5;
+    P.logC = logL - 5 > 14 ? 14 : logL - 5;
+    P.logRB = logL - 5 - P.logC;
+  }
+  P.ma = ma;
+  return P;
+}
+
+static pm_status hook_setup(size_t L, uint32_t p, int* pidx, int* logL, DevCtx** ctx) {
+  if (L < 1 || (L & (L - 1))) return PM_EINVAL;
+  *pidx = prime_index(p);
+  if (*pidx < 0) return PM_EUNSUPPORTED;
+  *logL = ceil_log2((long)L);
+  if (*logL > prime_info(*pidx).two_adic || *logL > 24) return PM_ETOOLARGE;
+  pm_status st;
+  *ctx = ctx_current(&st);
+  if (!*ctx) return st;
+  return ensure_prime_tables(*ctx, *pidx);
+}
+
+pm_status pm_ntt(const uint32_t* x, uint32_t* y, size_t n, uint32_t p, int inverse, void* stream) {
+  if (!x || !y || n < 2) return PM_EINVAL;
+  int pidx, logL;
+  DevCtx* c;
+  pm_status st = hook_setup(n, p, &pidx, &logL, &c);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  const PrimeInfo& PI = prime_info(pidx);
+  hipStream_t s = (hipStream_t)stream;
+  Plan P = hook_plan(logL, 0);
+  P.ma = 1 << P.logRA;
+  const uint2 ninv = h_shoup(h_inv((u32)(n % PI.p), PI.p), PI.p);
+  if (P.kind == PLAN_LDS)
+    return dev_status(launch_lds_xform(P, x, (long)n, y, (long)n, inverse ? 1 : 0, 1, pidx, c->tabs[pidx], ninv,
+                                       c->errflag, s));
+  st = ensure_workspace(c, n * sizeof(u32));
+  if (st) return st;
+  SplitTables S;
+  st = get_split_tables(c, pidx, logL, &S);
+  if (st) return st;
+  u32* T = (u32*)c->ws;
+  const int logR = P.logRA + P.logRB;
+  hipError_t e;
+  if (!inverse) {
+    e = launch_col_fwd(P, x, (long)n, nullptr, 0, 0, T, nullptr, pidx, c->tabs[pidx], c->errflag, s);
+    if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 0, pidx, c->tabs[pidx], S, ninv, s);
+    if (e == hipSuccess) e = launch_permute(T, y, logR, P.logC, 1, s);
+  } else {
+    e = launch_permute(x, T, logR, P.logC, 0, s);
+    if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 1, pidx, c->tabs[pidx], S, ninv, s);
+    if (e == hipSuccess) e = launch_col_inv(P, T, y, (long)n, pidx, c->tabs[pidx], s);
+  }
+  return dev_status(e);
+}
+
+pm_status pm_tft(const uint32_t* x, size_t z, size_t L, size_t n, uint32_t p, uint32_t* out, void* stream) {
+  if (!x || !out || z < 1 || n < 1 || z > L || n > L) return PM_EINVAL;
+  int pidx, logL;
+  DevCtx* c;
+  pm_status st = hook_setup(L, p, &pidx, &logL, &c);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  Plan P = hook_plan(logL, 0);
+  P.ma = kept_blocks((long)n, logL, P.logRA);
+  const uint2 one = h_shoup(1, prime_info(pidx).p);
+  if (P.kind == PLAN_LDS)
+    return dev_status(
+        launch_lds_xform(P, x, (long)z, out, (long)n, 0, 0, pidx, c->tabs[pidx], one, c->errflag, s));
+  st = ensure_workspace(c, (size_t)plan_nprime(P) * sizeof(u32));
+  if (st) return st;
+  SplitTables S;
+  st = get_split_tables(c, pidx, logL, &S);
+  if (st) return st;
+  u32* T = (u32*)c->ws;
+  hipError_t e = launch_col_fwd(P, x, (long)z, nullptr, 0, 0, T, nullptr, pidx, c->tabs[pidx], c->errflag, s);
+  if (e == hipSuccess) e = launch_row_xform(P, T, out, (long)n, 0, pidx, c->tabs[pidx], S, one, s);
+  return dev_status(e);
+}
+
+pm_status pm_itft(const uint32_t* v, size_t L, size_t n, uint32_t p, uint32_t* out, void* stream) {
+  if (!v || !out || n < 1 || n > L || (L & (L - 1)) || n % pm_itft_granularity(L)) return PM_EINVAL;
+  int pidx, logL;
+  DevCtx* c;
+  pm_status st = hook_setup(L, p, &pidx, &logL, &c);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  const PrimeInfo& PI = prime_info(pidx);
+  hipStream_t s = (hipStream_t)stream;
+  Plan P = hook_plan(logL, 0);
+  P.ma = kept_blocks((long)n, logL, P.logRA);
+  const bool full = P.ma == (1 << P.logRA);
+  // L u = (unscaled inverse) * L / (length of the unscaled part)
+  const uint2 sc = h_shoup(full ? 1u : (u32)(1u << P.logRA), PI.p);
+  if (P.kind == PLAN_LDS)
+    return dev_status(launch_lds_xform(P, v, (long)n, out, (long)n, 1, 0, pidx, c->tabs[pidx], sc, c->errflag, s));
+  st = ensure_workspace(c, (size_t)plan_nprime(P) * sizeof(u32));
+  if (st) return st;
+  SplitTables S;
+  st = get_split_tables(c, pidx, logL, &S);
+  if (st) return st;
+  u32* T = (u32*)c->ws;
+  hipError_t e = launch_row_xform(P, v, T, (long)n, 1, pidx, c->tabs[pidx], S, sc, s);
+  if (e == hipSuccess) e = launch_col_inv(P, T, out, (long)n, pidx, c->tabs[pidx], s);
+  return dev_status(e);
+}
+
+// ---- three-primes integer product -----------------------------------------------
+
+pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint16_t* out, void* stream) {
+  if (!a || !b || !out || na == 0 || nb == 0) return PM_EINVAL;
+  const long lc = (long)(na + nb - 1);
+  if (ceil_log2(lc) > 23) return PM_ETOOLARGE;
+  pm_status st;
+  DevCtx* c = ctx_current(&st);
+  if (!c) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  static const u32 kIntPrimes[3] = {469762049u, 998244353u, 167772161u};
+  const long nl = (long)(na + nb);
+  // workspace: three residue arrays, the widened operands when a plan needs
+  // 32-bit input, the largest plan workspace, the carry state
+  Plan plans[3];
+  size_t pw = 0;
+  bool widen = false;
+  for (int i = 0; i < 3; ++i) {
+    const int pidx = prime_index(kIntPrimes[i]);
+    plans[i] = choose_plan(lc, pidx);
+    if (!plan_valid(plans[i], lc, pidx)) return PM_ETOOLARGE;
+    if (plans[i].kind != PLAN_FOURSTEP) widen = true;
+    size_t w = plan_workspace_bytes(plans[i]);
+    if (w > pw) pw = w;
+  }
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t res_b = al((size_t)lc * 4);
+  const size_t wid_b = widen ? al((na + nb) * 4) : 0;
+  const size_t total = 3 * res_b + wid_b + al(pw) + al(crt_workspace_bytes(nl));
+  st = ensure_workspace(c, total);
+  if (st) return st;
+  char* base = (char*)c->ws;
+  u32* res[3] = {(u32*)base, (u32*)(base + res_b), (u32*)(base + 2 * res_b)};
+  u32* wa = (u32*)(base + 3 * res_b);
+  u32* wb = wa + na;
+  void* pws = base + 3 * res_b + wid_b;
+  void* cws = (char*)pws + al(pw);
+  hipError_t e = hipSuccess;
+  if (widen) {
+    e = launch_widen(a, (long)na, wa, s);
+    if (e == hipSuccess) e = launch_widen(b, (long)nb, wb, s);
+    if (e != hipSuccess) return PM_EDEVICE;
+  }
+  for (int i = 0; i < 3; ++i) {
+    const int pidx = prime_index(kIntPrimes[i]);
+    if (plans[i].kind == PLAN_FOURSTEP)
+      st = run_product(c, plans[i], a, (long)na, b, (long)nb, 1, res[i], lc, pidx, pws, s);
+    else
+      st = run_product(c, plans[i], wa, (long)na, wb, (long)nb, 0, res[i], lc, pidx, pws, s);
+    if (st) return st;
+  }
+  return dev_status(launch_crt_carry(res[0], res[1], res[2], lc, nl, cws, out, s));
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/polymul.h"
+#include "ntt_device.h"
+
+namespace pm {
+
+// the four supported primes p = c * 2^k + 1 with a primitive root g
+struct PrimeInfo {
+  u32 p;
+  u32 g;
+  int two_adic;  // k: transform lengths up to 2^k exist
+  u32 ninv;      // -p^-1 mod 2^32
+  bool lazy;     // p < 2^30: values may live in [0, 2p)
+};
+
+int prime_index(u32 p);                 // -1 if unsupported
+const PrimeInfo& prime_info(int pidx);  // 0..3
+constexpr int kNumPrimes = 4;
+
+// host modular helpers (exact, 64-bit)
+u32 h_mulmod(u32 a, u32 b, u32 p);
+u32 h_powmod(u32 b, u64 e, u32 p);
+u32 h_inv(u32 a, u32 p);
+uint2 h_shoup(u32 w, u32 p);  // (w, floor(w 2^32 / p))
+
+// four-step twiddles w_L^e split as w_L^{e mod 2^h} * w_L^{2^h floor(e / 2^h)}
+struct SplitTables {
+  const uint2* lo_f;
+  const uint2* hi_f;
+  const uint2* lo_i;
+  const uint2* hi_i;
+  int hbits;
+};
+
+struct DevCtx {
+  int dev = -1;
+  uint2* prime_mem[kNumPrimes] = {nullptr, nullptr, nullptr, nullptr};
+  PrimeTables tabs[kNumPrimes];
+  std::map<std::pair<int, int>, std::pair<uint2*, SplitTables>> split;
+  int* errflag = nullptr;  // device word: bit 0 = input not reduced
+  void* ws = nullptr;      // workspace
+  size_t ws_bytes = 0;
+  std::mutex mu;
+};
+
+DevCtx* ctx_current(pm_status* st);
+pm_status ensure_prime_tables(DevCtx* c, int pidx);
+pm_status get_split_tables(DevCtx* c, int pidx, int logL, SplitTables* out);
+pm_status ensure_workspace(DevCtx* c, size_t bytes);
+
+inline ModP modp_of(const PrimeInfo& P) { return ModP{P.p, 2u * P.p, P.ninv}; }
+
+// ---- plans --------------------------------------------------------------
+enum PlanKind { PLAN_DIRECT = 0, PLAN_LDS = 1, PLAN_FOURSTEP = 2 };
+
+struct Plan {
+  int kind = PLAN_DIRECT;
+  int logL = 0;   // transform length L = 2^logL
+  int logRA = 0;  // first (truncated) radix
+  int logRB = 0;  // second column radix of the four-step (0: none)
+  int logC = 0;   // row length of the four-step
+  int ma = 1;     // kept blocks of the first radix, 1..RA
+  int lq = 4;     // log radix of the LDS rounds
+};
+
+// relaxed transform length n' = ma * L / RA
+inline long plan_nprime(const Plan& P) { return (long)P.ma << (P.logL - P.logRA); }
+
+// ---- launchers (return hipSuccess or the launch error) --------------------
+hipError_t launch_direct(const u32* a, long la, const u32* b, long lb, u32* c, int pidx, int* err, hipStream_t s);
+hipError_t launch_lds_conv(const Plan& P, const u32* a, long la, const u32* b, long lb, u32* c, long lc, int pidx,
+                           const PrimeTables& T, uint2 sc, int* err, hipStream_t s);
+// four-step column passes; input element types: 0 = u32, 1 = u16; b == nullptr
+// transforms a alone
+hipError_t launch_col_fwd(const Plan& P, const void* a, long za, const void* b, long zb, int in_type, u32* Ta, u32* Tb,
+                          int pidx, const PrimeTables& T, int* err, hipStream_t s);
+hipError_t launch_row_conv(const Plan& P, const u32* Ta, const u32* Tb, u32* Tc, int pidx, const PrimeTables& T,
+                           const SplitTables& S, uint2 sc, hipStream_t s);
+hipError_t launch_col_inv(const Plan& P, const u32* Tc, u32* c, long lc, int pidx, const PrimeTables& T,
+                          hipStream_t s);
+// standalone row transforms over rows t < ma * RB: dir 0 = twiddle then
+// forward (outputs at flat index < nout), dir 1 = inverse then untwiddle and
+// multiply by sc
+hipError_t launch_row_xform(const Plan& P, const u32* in, u32* out, long nout, int dir, int pidx,
+                            const PrimeTables& T, const SplitTables& S, uint2 sc, hipStream_t s);
+// four-step layout (t1 * C + t2 = bit-reversed order) <-> natural order
+hipError_t launch_permute(const u32* in, u32* out, int logR, int logC, int to_natural, hipStream_t s);
+// one-work-group transform (L <= 2^14) for the hooks: dir 0 forward of zin
+// inputs (natural: out[k] = X_k, else out[i] = bit-reversed value, i < nout);
+// dir 1 inverse of bit-reversed (or natural) inputs times sc, outputs < nout
+hipError_t launch_lds_xform(const Plan& P, const u32* in, long zin, u32* out, long nout, int dir, int natural,
+                            int pidx, const PrimeTables& T, uint2 sc, int* err, hipStream_t s);
+
+}  // namespace pm

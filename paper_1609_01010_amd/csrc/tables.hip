@@ -1,0 +1,211 @@
+// Twiddle-table generation (GPU kernels) and the per-device context.
+//
+// The transforms need the principal roots of unity w_N = g^((p-1)/N) of the
+// ring (section 3: "R contains a principal L-th root of unity") and their
+// powers, each stored with its Shoup companion floor(w * 2^32 / p).
+#include <cstdio>
+#include <cstdlib>
+
+#include "internal.h"
+
+namespace pm {
+
+static const PrimeInfo kPrimes[kNumPrimes] = {
+    {998244353u, 3u, 23, 0u, true},
+    {2013265921u, 31u, 27, 0u, false},
+    {469762049u, 3u, 26, 0u, true},
+    {167772161u, 3u, 25, 0u, true},
+};
+
+static u32 neg_inv32(u32 p) {
+  // Newton iteration for p^-1 mod 2^32 (p odd), then negate
+  u32 x = p;  // correct to 3 bits
+  for (int i = 0; i < 5; ++i) x *= 2u - p * x;
+  return 0u - x;
+}
+
+static PrimeInfo g_primes[kNumPrimes];
+static std::once_flag g_primes_once;
+
+static void init_primes() {
+  for (int i = 0; i < kNumPrimes; ++i) {
+    g_primes[i] = kPrimes[i];
+    g_primes[i].ninv = neg_inv32(kPrimes[i].p);
+  }
+}
+
+int prime_index(u32 p) {
+  for (int i = 0; i < kNumPrimes; ++i)
+    if (kPrimes[i].p == p) return i;
+  return -1;
+}
+
+const PrimeInfo& prime_info(int pidx) {
+  std::call_once(g_primes_once, init_primes);
+  return g_primes[pidx];
+}
+
+u32 h_mulmod(u32 a, u32 b, u32 p) { return (u32)(((u64)a * b) % p); }
+u32 h_powmod(u32 b, u64 e, u32 p) {
+  u64 r = 1 % p, x = b % p;
+  while (e) {
+    if (e & 1) r = r * x % p;
+    x = x * x % p;
+    e >>= 1;
+  }
+  return (u32)r;
+}
+u32 h_inv(u32 a, u32 p) { return h_powmod(a, p - 2, p); }
+uint2 h_shoup(u32 w, u32 p) { return make_uint2(w, (u32)(((u64)w << 32) / p)); }
+
+// ---------------------------------------------------------------------------
+// kernels
+
+__device__ __forceinline__ u32 d_mulmod(u32 a, u32 b, u32 p) { return (u32)(((u64)a * b) % p); }
+__device__ u32 d_powmod(u32 b, u32 e, u32 p) {
+  u32 r = 1, x = b;
+  while (e) {
+    if (e & 1) r = d_mulmod(r, x, p);
+    x = d_mulmod(x, x, p);
+    e >>= 1;
+  }
+  return r;
+}
+__device__ __forceinline__ uint2 d_shoup(u32 w, u32 p) { return make_uint2(w, (u32)(((u64)w << 32) / p)); }
+
+// Pyramids: pf[2^s + x] = w_{2^s}^x, pi[2^s + x] = w_{2^s}^-x (s <= 15),
+// ph[2^s + x] = w_{2^s}^-x / 2 (s <= 5), iv[k] = 2^-k.
+__global__ void k_fill_pyramids(uint2* base, u32 p, u32 g) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  uint2* pf = base;
+  uint2* pi = base + kPyrSize;
+  uint2* ph = pi + kPyrSize;
+  uint2* iv = ph + kHalfSize;
+  if (idx >= 1 && idx < kPyrSize) {
+    const int s = 31 - __clz(idx);
+    const u32 x = (u32)idx - (1u << s);
+    const u32 w = d_powmod(g, (p - 1) >> s, p);  // primitive 2^s-th root
+    const u32 wf = d_powmod(w, x, p);
+    const u32 wi = d_powmod(w, ((1u << s) - x) & ((1u << s) - 1), p);
+    pf[idx] = d_shoup(wf, p);
+    pi[idx] = d_shoup(wi, p);
+    if (idx < kHalfSize) ph[idx] = d_shoup(d_mulmod(wi, (p + 1) / 2, p), p);
+  }
+  if (idx == 0) {
+    pf[0] = pi[0] = make_uint2(0, 0);
+    ph[0] = make_uint2(0, 0);
+  }
+  if (idx < kInvPow) iv[idx] = d_shoup(d_powmod((p + 1) / 2, (u32)idx, p), p);
+}
+
+// out[i] = mult * base^i mod p as Shoup pairs, i < n
+__global__ void k_powtable(uint2* out, int n, u32 p, u32 base, u32 mult) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = d_shoup(d_mulmod(mult, d_powmod(base, (u32)i, p), p), p);
+}
+
+// ---------------------------------------------------------------------------
+// per-device context
+
+static std::mutex g_ctx_mu;
+static std::map<int, DevCtx*> g_ctx;
+
+DevCtx* ctx_current(pm_status* st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *st = PM_EDEVICE;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  auto it = g_ctx.find(dev);
+  if (it != g_ctx.end()) {
+    *st = PM_OK;
+    return it->second;
+  }
+  DevCtx* c = new DevCtx();
+  c->dev = dev;
+  if (hipMalloc(&c->errflag, sizeof(int)) != hipSuccess) {
+    delete c;
+    *st = PM_ENOMEM;
+    return nullptr;
+  }
+  if (hipMemset(c->errflag, 0, sizeof(int)) != hipSuccess) {
+    *st = PM_EDEVICE;
+    return nullptr;
+  }
+  g_ctx[dev] = c;
+  *st = PM_OK;
+  return c;
+}
+
+pm_status ensure_prime_tables(DevCtx* c, int pidx) {
+  if (c->prime_mem[pidx]) return PM_OK;
+  const PrimeInfo& P = prime_info(pidx);
+  const size_t n = 2 * (size_t)kPyrSize + kHalfSize + kInvPow;
+  uint2* mem = nullptr;
+  if (hipMalloc(&mem, n * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
+  k_fill_pyramids<<<kPyrSize / 256, 256>>>(mem, P.p, P.g);
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    hipFree(mem);
+    return PM_EDEVICE;
+  }
+  c->prime_mem[pidx] = mem;
+  c->tabs[pidx].pf = mem;
+  c->tabs[pidx].pi = mem + kPyrSize;
+  c->tabs[pidx].ph = mem + 2 * kPyrSize;
+  c->tabs[pidx].iv = mem + 2 * kPyrSize + kHalfSize;
+  return PM_OK;
+}
+
+pm_status get_split_tables(DevCtx* c, int pidx, int logL, SplitTables* out) {
+  auto key = std::make_pair(pidx, logL);
+  auto it = c->split.find(key);
+  if (it != c->split.end()) {
+    *out = it->second.second;
+    return PM_OK;
+  }
+  const PrimeInfo& P = prime_info(pidx);
+  const int hb = (logL + 1) / 2;
+  const int nlo = 1 << hb, nhi = 1 << (logL - hb);
+  uint2* mem = nullptr;
+  if (hipMalloc(&mem, 2 * (size_t)(nlo + nhi) * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
+  const u32 w = h_powmod(P.g, (P.p - 1) >> logL, P.p);
+  const u32 wi = h_inv(w, P.p);
+  SplitTables S;
+  uint2* lo_f = mem;
+  uint2* hi_f = lo_f + nlo;
+  uint2* lo_i = hi_f + nhi;
+  uint2* hi_i = lo_i + nlo;
+  k_powtable<<<(nlo + 255) / 256, 256>>>(lo_f, nlo, P.p, w, 1);
+  k_powtable<<<(nhi + 255) / 256, 256>>>(hi_f, nhi, P.p, h_powmod(w, (u64)nlo, P.p), 1);
+  k_powtable<<<(nlo + 255) / 256, 256>>>(lo_i, nlo, P.p, wi, 1);
+  k_powtable<<<(nhi + 255) / 256, 256>>>(hi_i, nhi, P.p, h_powmod(wi, (u64)nlo, P.p), 1);
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    hipFree(mem);
+    return PM_EDEVICE;
+  }
+  S.lo_f = lo_f;
+  S.hi_f = hi_f;
+  S.lo_i = lo_i;
+  S.hi_i = hi_i;
+  S.hbits = hb;
+  c->split[key] = std::make_pair(mem, S);
+  *out = S;
+  return PM_OK;
+}
+
+pm_status ensure_workspace(DevCtx* c, size_t bytes) {
+  if (c->ws_bytes >= bytes) return PM_OK;
+  if (c->ws) {
+    if (hipDeviceSynchronize() != hipSuccess) return PM_EDEVICE;
+    hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+  if (hipMalloc(&c->ws, want) != hipSuccess) return PM_ENOMEM;
+  c->ws_bytes = want;
+  return PM_OK;
+}
+
+}  // namespace pm

@@ -1,0 +1,223 @@
+// Standalone transforms behind the test hooks pm_ntt, pm_tft and pm_itft:
+// the modular DFT in natural order (section 3), the truncated transform TFT
+// in bit-reversed order and its inverse ITFT scaled by L (the TFT product,
+// eq. 14).  They reuse the convolution's building blocks.
+#include "internal.h"
+
+namespace pm {
+
+// ---------------------------------------------------------------------------
+// one work-group, L = 2^LN <= 2^14, first radix RA (truncated to ma blocks)
+
+template <int LN, int LRA, bool LAZY>
+__global__ void __launch_bounds__(1024) k_lds_xform(const u32* in, int zin, u32* out, int nout,
+                                                    int ma, int dir, int natural, ModP mp, PrimeTables T, uint2 sc,
+                                                    int* err) {
+  constexpr int N = 1 << LN;
+  constexpr int RA = 1 << LRA;
+  constexpr int LS = LN - LRA;
+  constexpr int S = 1 << LS;
+  extern __shared__ u32 sm[];
+  const Arith<LAZY> A(mp);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nel = ma * S;
+  bool bad = false;
+  if (dir == 0) {
+    for (int j = tid; j < S; j += nthr) {
+      u32 x[RA];
+#pragma unroll
+      for (int s = 0; s < RA; ++s) {
+        const int pos = j + S * s;
+        x[s] = pos < zin ? in[pos] : 0u;
+        bad |= x[s] >= mp.p;
+      }
+      dif_reg<RA>(A, x, T.pf);
+#pragma unroll
+      for (int t = 0; t < RA; ++t) {
+        if (t < ma) {
+          u32 v = x[t];
+          if (S > 1 && t > 0) v = A.mul(v, T.pf[N + j * (int)(__brev((u32)t) >> (32 - LRA))]);
+          sm[j + S * t] = v;
+        }
+      }
+    }
+    __syncthreads();
+    u32* bufs[1] = {sm};
+    dif_lds<LS, 4, LAZY, 1>(A, bufs, nel, T.pf, tid, nthr);
+    if (natural) {
+      for (int k = tid; k < N; k += nthr) out[k] = A.canon(sm[bitrev_n((u32)k, LN)]);
+    } else {
+      for (int i = tid; i < nout; i += nthr) out[i] = A.canon(sm[i]);
+    }
+  } else {
+    if (natural) {
+      for (int t = tid; t < N; t += nthr) {
+        const u32 v = in[bitrev_n((u32)t, LN)];
+        bad |= v >= mp.p;
+        sm[t] = v;
+      }
+    } else {
+      for (int i = tid; i < nel; i += nthr) {
+        const u32 v = in[i];
+        bad |= v >= mp.p;
+        sm[i] = v;
+      }
+    }
+    __syncthreads();
+    dit_lds<LS, 4, LAZY>(A, sm, nel, T.pi, tid, nthr);
+    for (int j = tid; j < S; j += nthr) {
+      u32 x[RA];
+#pragma unroll
+      for (int t = 0; t < RA; ++t) {
+        u32 v = 0;
+        if (t < ma) {
+          v = sm[j + S * t];
+          if (S > 1 && t > 0) v = A.mul(v, T.pi[N + j * (int)(__brev((u32)t) >> (32 - LRA))]);
+        }
+        x[t] = v;
+      }
+      inv_column<RA, LAZY>(A, x, ma, T);
+#pragma unroll
+      for (int s = 0; s < RA; ++s) {
+        const int pos = j + S * s;
+        if (s < ma && pos < nout) out[pos] = A.canon(A.mul(x[s], sc));
+      }
+    }
+  }
+  if (bad) atomicOr(err, 1);
+}
+
+template <int LN, int LRA, bool LAZY>
+static hipError_t lds_xform_inst(const Plan& P, const u32* in, long zin, u32* out, long nout, int dir, int natural,
+                                 const ModP& mp, const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
+  constexpr int N = 1 << LN;
+  int nthr = N / 16;
+  if (nthr < 64) nthr = 64;
+  if (nthr > 1024) nthr = 1024;
+  const size_t lds = (size_t)N * sizeof(u32);
+  auto kern = k_lds_xform<LN, LRA, LAZY>;
+  hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  kern<<<1, nthr, lds, s>>>(in, (int)zin, out, (int)nout, P.ma, dir, natural, mp, T, sc, err);
+  return hipGetLastError();
+}
+
+template <int LN, bool LAZY>
+static hipError_t lds_xform_ln(const Plan& P, const u32* in, long zin, u32* out, long nout, int dir, int natural,
+                               const ModP& mp, const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
+  // the hooks use the first radix min(32, L)
+  constexpr int LRA = LN < 5 ? LN : 5;
+  if (P.logRA != LRA) return hipErrorInvalidValue;
+  return lds_xform_inst<LN, LRA, LAZY>(P, in, zin, out, nout, dir, natural, mp, T, sc, err, s);
+}
+
+hipError_t launch_lds_xform(const Plan& P, const u32* in, long zin, u32* out, long nout, int dir, int natural,
+                            int pidx, const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
+  const PrimeInfo& PI = prime_info(pidx);
+  const ModP mp = modp_of(PI);
+#define PM_LN(n)                                                                                   \
+  case n:                                                                                          \
+    return PI.lazy ? lds_xform_ln<n, true>(P, in, zin, out, nout, dir, natural, mp, T, sc, err, s) \
+                   : lds_xform_ln<n, false>(P, in, zin, out, nout, dir, natural, mp, T, sc, err, s);
+  switch (P.logL) {
+    PM_LN(1) PM_LN(2) PM_LN(3) PM_LN(4) PM_LN(5) PM_LN(6) PM_LN(7) PM_LN(8) PM_LN(9) PM_LN(10) PM_LN(11)
+    PM_LN(12) PM_LN(13) PM_LN(14)
+    default:
+      break;
+  }
+#undef PM_LN
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// four-step row transforms (one operand): forward = twiddle by w_L^{j2 k1}
+// then DIF; inverse = DIT, untwiddle by w_L^{-j2 k1}, times sc.
+
+template <int LC, bool LAZY>
+__global__ void __launch_bounds__(1024) k_row_xform(const u32* in, u32* out, long nout,
+                                                    int dir, int logR, ModP mp, PrimeTables T, SplitTables S,
+                                                    uint2 sc) {
+  constexpr int C = 1 << LC;
+  extern __shared__ u32 sm[];
+  const Arith<LAZY> A(mp);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int row = blockIdx.x;
+  const u32 k1 = bitrev_n((u32)row, logR);
+  const long off = (long)row * C;
+  const u32 lomask = (1u << S.hbits) - 1u;
+  if (dir == 0) {
+    for (int i = tid; i < C; i += nthr) {
+      const u32 e = k1 * (u32)i;
+      sm[i] = A.mul(A.mul(in[off + i], S.lo_f[e & lomask]), S.hi_f[e >> S.hbits]);
+    }
+    __syncthreads();
+    u32* bufs[1] = {sm};
+    dif_lds<LC, 4, LAZY, 1>(A, bufs, C, T.pf, tid, nthr);
+    for (int i = tid; i < C; i += nthr)
+      if (off + i < nout) out[off + i] = A.canon(sm[i]);
+  } else {
+    for (int i = tid; i < C; i += nthr) sm[i] = in[off + i];
+    __syncthreads();
+    dit_lds<LC, 4, LAZY>(A, sm, C, T.pi, tid, nthr);
+    for (int i = tid; i < C; i += nthr) {
+      const u32 e = k1 * (u32)i;
+      out[off + i] = A.mul(A.mul(A.mul(sm[i], S.lo_i[e & lomask]), S.hi_i[e >> S.hbits]), sc);
+    }
+  }
+}
+
+template <int LC, bool LAZY>
+static hipError_t row_xform_inst(const Plan& P, const u32* in, u32* out, long nout, int dir, const ModP& mp,
+                                 const PrimeTables& T, const SplitTables& S, uint2 sc, hipStream_t s) {
+  constexpr int C = 1 << LC;
+  const int rows = P.ma << P.logRB;
+  int nthr = C / 16;
+  if (nthr > 1024) nthr = 1024;
+  if (nthr < 64) nthr = 64;
+  const size_t lds = (size_t)C * sizeof(u32);
+  auto kern = k_row_xform<LC, LAZY>;
+  hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  kern<<<rows, nthr, lds, s>>>(in, out, nout, dir, P.logRA + P.logRB, mp, T, S, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_xform(const Plan& P, const u32* in, u32* out, long nout, int dir, int pidx,
+                            const PrimeTables& T, const SplitTables& S, uint2 sc, hipStream_t s) {
+  const PrimeInfo& PI = prime_info(pidx);
+  const ModP mp = modp_of(PI);
+#define PM_LC(n)                                                                          \
+  case n:                                                                                 \
+    return PI.lazy ? row_xform_inst<n, true>(P, in, out, nout, dir, mp, T, S, sc, s)      \
+                   : row_xform_inst<n, false>(P, in, out, nout, dir, mp, T, S, sc, s);
+  switch (P.logC) {
+    PM_LC(10) PM_LC(11) PM_LC(12) PM_LC(13) PM_LC(14) PM_LC(15)
+    default:
+      break;
+  }
+#undef PM_LC
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// layout changes for the natural-order hooks: the four-step layout holds
+// X_{k1 + R k2} at row t1 = rev_r(k1), column t2 = rev_c(k2).
+
+__global__ void k_permute(const u32* __restrict__ in, u32* __restrict__ out, int logR, int logC, int to_natural) {
+  const long n = 1l << (logR + logC);
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // i: flat index in the four-step layout
+  const u32 t1 = (u32)(i >> logC), t2 = (u32)(i & ((1l << logC) - 1));
+  const long k = (long)bitrev_n(t1, logR) + ((long)bitrev_n(t2, logC) << logR);
+  if (to_natural)
+    out[k] = in[i];
+  else
+    out[i] = in[k];
+}
+
+hipError_t launch_permute(const u32* in, u32* out, int logR, int logC, int to_natural, hipStream_t s) {
+  const long n = 1l << (logR + logC);
+  k_permute<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, out, logR, logC, to_natural);
+  return hipGetLastError();
+}
+
+}  // namespace pm

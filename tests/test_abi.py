@@ -1,0 +1,92 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol,
+and rejects bad arguments on the host before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "polymul.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pm_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1609_01010_amd as pm
+
+    return pm.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("pm_poly_mul", "pm_poly_mul_batch", "pm_int_mul", "pm_ntt", "pm_tft", "pm_itft",
+                 "pm_stream_check", "pm_status_str", "pm_set_policy", "pm_plan_for"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    import paper_1609_01010_amd as pm
+
+    for name in _declared():
+        assert hasattr(L, name), name
+        assert name in pm.SIGNATURES, "binding lacks " + name
+
+
+def test_status_strings(L):
+    for st in range(7):
+        assert L.pm_status_str(st)
+    assert L.pm_status_str(0).decode() == "ok"
+
+
+def test_host_validation_without_device(L):
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    # NULL pointers and zero lengths
+    assert L.pm_poly_mul(null, 4, fake, 4, 998244353, fake, null) == 1
+    assert L.pm_poly_mul(fake, 0, fake, 4, 998244353, fake, null) == 1
+    # unsupported modulus
+    assert L.pm_poly_mul(fake, 4, fake, 4, 1000000007, fake, null) == 2
+    # transform length beyond the prime's 2-adic order (998244353: 2^23)
+    assert L.pm_poly_mul(fake, 1 << 23, fake, 1 << 23, 998244353, fake, null) == 3
+    assert L.pm_int_mul(fake, 1 << 23, fake, 1 << 23, fake, null) == 3
+    assert L.pm_int_mul(null, 3, fake, 3, fake, null) == 1
+    assert L.pm_ntt(fake, fake, 3, 998244353, 0, null) == 1           # not a power of two
+    assert L.pm_tft(fake, 5, 4, 2, 998244353, fake, null) == 1        # z > L
+    assert L.pm_itft(fake, 1 << 10, 33, 998244353, fake, null) == 1   # n not a multiple of L/32
+    assert L.pm_set_policy(7) == 1
+
+
+def test_granularity(L):
+    assert L.pm_itft_granularity(16) == 1
+    assert L.pm_itft_granularity(32) == 1
+    assert L.pm_itft_granularity(1 << 20) == 1 << 15
+
+
+def test_plan_space_on_host():
+    import paper_1609_01010_amd as pm
+
+    for lc in (63, 64, 65, 2047, 5000, 40000, 1000000, (1 << 22) - 1):
+        for p in pm.PRIMES:
+            cands = pm.plan_candidates(lc, p)
+            assert cands, (lc, p)
+            for P in cands:
+                if P.kind == 0:
+                    assert lc <= 64
+                    continue
+                nprime = P.ma << (P.log_l - P.log_ra)
+                assert nprime >= lc
+                assert 1 <= P.ma <= (1 << P.log_ra)
+                if P.kind == 2:
+                    assert P.log_l == P.log_ra + P.log_rb + P.log_c
+    # truncation: a length just past a power of two is not padded to 2L
+    P = pm.plan_for(1000000, 2013265921)
+    assert (P.ma << (P.log_l - P.log_ra)) < (1 << 20)
+    P = pm.plan_for(2047, 998244353)
+    assert P.kind == 1 and P.log_l == 11
