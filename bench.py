@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Throughput of the NTT/TFT modular polynomial product on one MI355X.
+
+One step = the two plain large products over Z/2013265921Z:
+  (a) 2^21 x 2^21 coefficients through transforms of length 2^22, and
+  (b) 600001 x 400000 coefficients through a relaxed truncated transform
+      (10^6 outputs, no padding to 2^20).
+value = output coefficients per second (inputs resident in HBM when the
+timed region starts; buffers rotate over more than the 256 MB MALL).
+
+The JSON line also carries the roofline of the dominant kernel (timed live
+with HIP events on the library's launch stream) and the CPU oracle timed on
+a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+P = 2013265921
+CU, LANES, CLOCK = 256, 64, 2.4e9
+ALU_PEAK = CU * LANES * CLOCK          # 32-bit VALU issue slots per second
+HBM_PEAK = 8.0e12                      # bytes per second
+# algorithmic VALU slots (gfx950: mul_hi is half rate, so it counts 2)
+SLOTS_BUTTERFLY = 10                   # Shoup multiply (5) + add and subtract with range reduction (5)
+SLOTS_MULMOD_CONST = 5                 # Shoup: mul_hi (2) + 2 mul_lo + sub
+SLOTS_MULMOD_VAR = 8                   # Montgomery: 2 mul_hi (4) + 2 mul_lo + add + carry
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def row_conv_units(plan, n_rows_elems):
+    """Algorithmic slots and HBM bytes of one row pass over n_rows_elems elements:
+    three length-C transforms (C/2 log2 C butterflies each), three four-step
+    twiddle multiplies, one pointwise product, one scaling multiply; reads two
+    operands, writes one."""
+    logc = plan.log_c
+    per_el = 3 * (logc / 2) * SLOTS_BUTTERFLY + 4 * SLOTS_MULMOD_CONST + SLOTS_MULMOD_VAR
+    return per_el * n_rows_elems, 12 * n_rows_elems
+
+
+def cpu_baseline(a2, b2, a3, b3, target_s=10.0):
+    """The oracle's defining sum timed on a bounded sample of output coefficients."""
+    import numpy as np
+
+    from oracle import poly as op
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(7)
+
+    def run(n):
+        k2 = np.sort(rng.choice((1 << 22) - 1, size=n, replace=False))
+        k3 = np.sort(rng.choice(1000000, size=max(1, n // 4), replace=False))
+        t0 = time.perf_counter()
+        op.poly_mul_sample(a2, b2, P, k2)
+        op.poly_mul_sample(a3, b3, P, k3)
+        return time.perf_counter() - t0, n + max(1, n // 4)
+
+    dt, cnt = run(64)
+    n = int(min(200000, max(64, 64 * target_s / max(dt, 1e-3))))
+    dt, cnt = run(n)
+    return {
+        "value": cnt / dt,
+        "unit": "coeffs/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{cnt} output coefficients ({n} of the 2^21 x 2^21 product, {cnt - n} of the 600001 x 400000 "
+                  f"product) by the schoolbook sum c_k = sum a_i b_(k-i) mod p, OpenMP over k; {dt:.1f} s",
+    }
+
+
+def traffic_from_profiles(kernel_src_hash):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "row_conv_counters.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("source_sha256") != kernel_src_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rotate", type=int, default=8, help="buffer sets rotated over the steps")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this library's path runs on a single MI355X and has no "
+              "multi-GPU mode (see DESIGN.md for how it would shard). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1609_01010_amd as pm
+    from paper_1609_01010_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    pm.lib()
+    dev = torch.device("cuda:0")
+    a2, b2, _ = inputs.large_pow2_product()
+    a3, b3, _ = inputs.large_tft_product()
+    lc2, lc3 = a2.size + b2.size - 1, a3.size + b3.size - 1
+    sets = []
+    for _ in range(args.rotate):
+        sets.append(tuple(torch.from_numpy(x).to(dev) for x in (a2, b2, a3, b3)) +
+                    (torch.empty(lc2, dtype=torch.uint32, device=dev), torch.empty(lc3, dtype=torch.uint32, device=dev)))
+    plan2 = pm.plan_for(lc2, P)
+    plan3 = pm.plan_for(lc3, P)
+    log("plans:", plan2, plan3)
+
+    def step(i):
+        ta2, tb2, ta3, tb3, c2, c3 = sets[i % len(sets)]
+        pm.poly_mul(ta2, tb2, P, out=c2)
+        pm.poly_mul(ta3, tb3, P, out=c3)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if pm.stream_check() != 0:
+        raise SystemExit("device reported an error during warm-up")
+    # correctness spot check of the timed configuration (the full parity
+    # tests live in tests/)
+    from oracle import poly as op
+
+    ks = np.array([0, 1, 12345, lc2 // 2, lc2 - 1])
+    assert np.array_equal(sets[0][4].cpu().numpy()[ks], op.poly_mul_sample(a2, b2, P, ks))
+
+    pm.trace_reset()
+    pm.trace_enable(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(args.steps):
+        step(i)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pm.trace_enable(False)
+    gpu_ms = e0.elapsed_time(e1)
+    ms_per_step = gpu_ms / args.steps
+    coeffs = (lc2 + lc3) * args.steps
+    value = coeffs / (gpu_ms * 1e-3)
+
+    kernels = {}
+    for name in pm.trace_names():
+        tot, n = pm.trace_query(name)
+        kernels[name] = {"launches": n, "avg_us": 1e3 * tot / max(n, 1), "share": tot / gpu_ms}
+    pm.trace_reset()
+    dom = max(kernels, key=lambda k: kernels[k]["share"])
+    row = kernels.get("row_conv")
+    rows2 = plan2.ma << plan2.log_rb
+    rows3 = plan3.ma << plan3.log_rb
+    slots2, bytes2 = row_conv_units(plan2, rows2 << plan2.log_c)
+    slots3, bytes3 = row_conv_units(plan3, rows3 << plan3.log_c)
+    per_launch_slots = (slots2 + slots3) / 2
+    per_launch_bytes = (bytes2 + bytes3) / 2
+    src = open(os.path.join(ROOT, "paper_1609_01010_amd", "csrc", "fourstep.hip"), "rb").read()
+    src += open(os.path.join(ROOT, "paper_1609_01010_amd", "csrc", "ntt_device.h"), "rb").read()
+    src += open(os.path.join(ROOT, "paper_1609_01010_amd", "csrc", "arith.h"), "rb").read()
+    src_hash = hashlib.sha256(src).hexdigest()
+    achieved = per_launch_slots / (row["avg_us"] * 1e-6)
+    traffic = traffic_from_profiles(src_hash)
+    roofline = {
+        "kernel": "row_conv",
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": ALU_PEAK / 1e12,
+        "unit": "Tslot/s",
+        "frac": achieved / ALU_PEAK,
+        "traffic": traffic,
+        "algorithmic_slots_per_launch": per_launch_slots,
+        "hbm_achieved_GBps": per_launch_bytes / (row["avg_us"] * 1e-6) / 1e9,
+        "hbm_frac": per_launch_bytes / (row["avg_us"] * 1e-6) / HBM_PEAK,
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(a2, b2, a3, b3)
+    out = {
+        "metric": "conv coefficients/s",
+        "value": value,
+        "unit": "coeffs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain large products mod 2013265921: 2^21 x 2^21 (transform 2^22) + "
+                        "600001 x 400000 (relaxed TFT, 10^6 outputs)",
+            "coeffs_per_step": lc2 + lc3,
+            "plans": [list(plan2.as_tuple()), list(plan3.as_tuple())],
+            "dominant_kernel": dom,
+            "wall_s": wall,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

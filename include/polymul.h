@@ -149,6 +149,7 @@ typedef struct {
   int32_t log_c;  /* row length of the four-step (LDS tile) */
   int32_t ma;     /* kept blocks of the first radix, 1 .. 2^log_ra */
   int32_t lq;     /* log radix of the LDS rounds */
+  int32_t lnt;    /* log2 threads per row work-group of the four-step (0: default) */
 } pm_plan;
 
 /* Select the policy used by pm_poly_mul / pm_poly_mul_batch to pick plans. */
@@ -168,6 +169,20 @@ size_t pm_plan_candidates(size_t lc, uint32_t p, pm_plan* out, size_t max_out);
  * before they choose). */
 pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan);
 void pm_plan_cache_clear(void);
+
+/* ---- tracing ------------------------------------------------------------
+ * When enabled, every kernel the library launches is bracketed by two HIP
+ * events recorded on its own stream, so kernel durations can be measured in
+ * a live run.  Kernel names: "direct", "lds_conv", "col_fwd", "row_conv",
+ * "col_inv", "row_xform", "lds_xform", "permute", "crt_sums", "carry_scan",
+ * "carry_apply", "widen". */
+void pm_trace_enable(int on);
+/* Forget all records (waits for the recorded events). */
+void pm_trace_reset(void);
+/* Total duration in ms and number of launches of `kernel` since the reset. */
+pm_status pm_trace_query(const char* kernel, double* total_ms, int64_t* count);
+/* Newline-separated names of the traced kernels; returns the size needed. */
+size_t pm_trace_names(char* buf, size_t cap);
 
 #ifdef __cplusplus
 }

@@ -43,6 +43,7 @@ class Plan(ctypes.Structure):
         ("log_c", ctypes.c_int32),
         ("ma", ctypes.c_int32),
         ("lq", ctypes.c_int32),
+        ("lnt", ctypes.c_int32),
     ]
 
     def as_tuple(self):
@@ -90,6 +91,10 @@ SIGNATURES = {
     "pm_plan_candidates": (_sz, [_sz, _u32, ctypes.POINTER(Plan), _sz]),
     "pm_plan_cache_put": (_int, [_sz, _u32, ctypes.POINTER(Plan)]),
     "pm_plan_cache_clear": (None, []),
+    "pm_trace_enable": (None, [_int]),
+    "pm_trace_reset": (None, []),
+    "pm_trace_query": (_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "pm_trace_names": (_sz, [ctypes.c_char_p, _sz]),
 }
 
 
@@ -265,3 +270,29 @@ def plan_cache_put(lc: int, p: int, plan: Plan):
 
 def plan_cache_clear():
     lib().pm_plan_cache_clear()
+
+
+# ---------------------------------------------------------------------------
+# tracing: per-kernel durations from HIP events recorded on the launch stream
+
+def trace_enable(on: bool = True):
+    lib().pm_trace_enable(1 if on else 0)
+
+
+def trace_reset():
+    lib().pm_trace_reset()
+
+
+def trace_query(kernel: str):
+    """(total milliseconds, number of launches) of a library kernel since the reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().pm_trace_query(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)), "pm_trace_query")
+    return ms.value, n.value
+
+
+def trace_names():
+    need = lib().pm_trace_names(None, 0)
+    buf = ctypes.create_string_buffer(need)
+    lib().pm_trace_names(buf, need)
+    return [x for x in buf.value.decode().split("\n") if x]

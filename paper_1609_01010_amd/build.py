@@ -16,14 +16,23 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpolymul.so")
 ARCH = os.environ.get("PM_OFFLOAD_ARCH", "gfx950")
 
+# (source, extra defines): the kernel families are compiled once per value
+# range of the prime (PM_LAZY=1: p < 2^30, PM_LAZY=0: p < 2^31)
 SOURCES = [
-    "tables.hip",
-    "conv_kernels.hip",
-    "xform_kernels.hip",
-    "crt.hip",
-    "capi.cpp",
-    "batch.cpp",
-    "tune.cpp",
+    ("tables.hip", []),
+    ("direct.hip", []),
+    ("lds_conv.hip", ["-DPM_LAZY=0"]),
+    ("lds_conv.hip", ["-DPM_LAZY=1"]),
+    ("fourstep.hip", ["-DPM_LAZY=0"]),
+    ("fourstep.hip", ["-DPM_LAZY=1"]),
+    ("xform_kernels.hip", ["-DPM_LAZY=0"]),
+    ("xform_kernels.hip", ["-DPM_LAZY=1"]),
+    ("crt.hip", []),
+    ("dispatch.cpp", []),
+    ("capi.cpp", []),
+    ("batch.cpp", []),
+    ("tune.cpp", []),
+    ("trace.cpp", []),
 ]
 
 CFLAGS = [
@@ -37,14 +46,16 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def _compile(item) -> str:
+    src, defs = item
     path = os.path.join(CSRC, src)
-    obj = os.path.join(OBJ, src + ".o")
+    tag = "".join(d.replace("-D", ".").replace("=", "") for d in defs)
+    obj = os.path.join(OBJ, src + tag + ".o")
     deps = [path] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
     deps.append(os.path.join(HERE, "..", "include", "polymul.h"))
     if os.path.exists(obj) and all(os.path.getmtime(obj) >= os.path.getmtime(d) for d in deps):
         return obj
-    cmd = ["hipcc", "-x", "hip", *CFLAGS, "-c", path, "-o", obj + ".tmp"]
+    cmd = ["hipcc", "-x", "hip", *CFLAGS, *defs, "-c", path, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

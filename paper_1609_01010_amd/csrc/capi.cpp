@@ -31,11 +31,13 @@ bool plan_valid(const Plan& P, long lc, int pidx) {
   if (P.logRA < 1 || P.logRA > 5 || P.ma < 1 || P.ma > (1 << P.logRA)) return false;
   if (plan_nprime(P) < lc) return false;
   if (P.kind == PLAN_LDS) {
-    return P.logL >= 6 && P.logL <= 14 && P.logRA <= P.logL && P.logRB == 0;
+    return P.logL >= 6 && P.logL <= 14 && P.logRA >= 3 && P.logRA <= P.logL && P.logRB == 0 && P.lq == 4;
   }
   if (P.kind == PLAN_FOURSTEP) {
     if (P.logC < 10 || P.logC > 14) return false;
-    if (P.logRB < 0 || P.logRB > 5 || (P.logRB > 0 && P.logRA != 5)) return false;
+    if (P.logRB < 0 || P.logRB > 5 || (P.logRB > 0 && P.logRA < 4)) return false;
+    const int lnt = plan_row_lnt(P);
+    if (lnt < 6 || lnt > 10 || P.logC - lnt < 4 || P.logC - lnt > 6) return false;
     return P.logL == P.logRA + P.logRB + P.logC;
   }
   return false;
@@ -47,24 +49,31 @@ static int kept_blocks(long lc, int logL, int logRA) {
 }
 
 Plan default_plan(long lc, int pidx) {
+  // measured on MI355X: row length C = L / 256 (at least 2^10, at most 2^14),
+  // columns split 16 x R/16, 32 elements per row thread; truncation with the
+  // finest first radix (32) when the output length is not a power of two
   Plan P;
   if (lc <= 64) {
     P.kind = PLAN_DIRECT;
     return P;
   }
   P.logL = ceil_log2(lc);
+  const bool pow2 = (lc & (lc - 1)) == 0;
   if (P.logL <= 14) {
     P.kind = PLAN_LDS;
     P.logRA = P.logL < 4 ? P.logL : 4;
   } else {
     P.kind = PLAN_FOURSTEP;
-    P.logRA = 5;
-    P.logC = P.logL - 5 < 10 ? 10 : (P.logL - 5 > 14 ? 14 : P.logL - 5);
-    P.logRB = P.logL - P.logC - P.logRA;
-    if (P.logRB < 0) {  // L = 2^15 with C = 2^10 needs RA = 32, RB = 0
-      P.logRA += P.logRB;
+    P.logC = P.logL - 8 < 10 ? 10 : (P.logL - 8 > 14 ? 14 : P.logL - 8);
+    const int logR = P.logL - P.logC;
+    if (logR <= 4) {
+      P.logRA = logR;
       P.logRB = 0;
+    } else {
+      P.logRA = (!pow2 || logR - 4 > 5) ? 5 : 4;
+      P.logRB = logR - P.logRA;
     }
+    P.lnt = P.logC - 5;
   }
   P.ma = kept_blocks(lc, P.logL, P.logRA);
   return P;
@@ -82,8 +91,8 @@ std::vector<Plan> plan_candidates(long lc, int pidx) {
   const int logL = ceil_log2(lc);
   for (int lq = 3; lq <= 4; ++lq) {
     for (int trunc = 1; trunc >= 0; --trunc) {
-      if (logL <= 14) {
-        for (int lra = 2; lra <= 5 && lra <= logL; ++lra) {
+      if (logL <= 14 && lq == 4) {
+        for (int lra = 3; lra <= 5 && lra <= logL; ++lra) {
           Plan P;
           P.kind = PLAN_LDS;
           P.logL = logL;
@@ -100,17 +109,20 @@ std::vector<Plan> plan_candidates(long lc, int pidx) {
           if (lr < 1) continue;
           for (int lra = 1; lra <= 5; ++lra) {
             const int lrb = lr - lra;
-            if (lrb < 0 || lrb > 5 || (lrb > 0 && lra != 5)) continue;
-            Plan P;
-            P.kind = PLAN_FOURSTEP;
-            P.logL = logL;
-            P.logC = lc_;
-            P.logRA = lra;
-            P.logRB = lrb;
-            P.lq = lq;
-            P.ma = trunc ? kept_blocks(lc, logL, lra) : (1 << lra);
-            if (!trunc && P.ma == kept_blocks(lc, logL, lra)) continue;
-            if (plan_valid(P, lc, pidx)) out.push_back(P);
+            if (lrb < 0 || lrb > 5 || (lrb > 0 && lra < 4)) continue;
+            for (int lnt = lc_ - 6; lnt <= lc_ - 4; ++lnt) {
+              Plan P;
+              P.kind = PLAN_FOURSTEP;
+              P.logL = logL;
+              P.logC = lc_;
+              P.logRA = lra;
+              P.logRB = lrb;
+              P.lq = lq;
+              P.lnt = lnt;
+              P.ma = trunc ? kept_blocks(lc, logL, lra) : (1 << lra);
+              if (!trunc && P.ma == kept_blocks(lc, logL, lra)) continue;
+              if (plan_valid(P, lc, pidx)) out.push_back(P);
+            }
           }
         }
       }
@@ -144,6 +156,7 @@ static pm_plan to_pub(const Plan& P) {
   q.log_c = P.logC;
   q.ma = P.ma;
   q.lq = P.lq;
+  q.lnt = P.lnt;
   return q;
 }
 static Plan from_pub(const pm_plan& q) {
@@ -155,6 +168,7 @@ static Plan from_pub(const pm_plan& q) {
   P.logC = q.log_c;
   P.ma = q.ma;
   P.lq = q.lq;
+  P.lnt = q.lnt;
   return P;
 }
 
@@ -197,13 +211,13 @@ pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const vo
     if (in_type != 0) return PM_EINVAL;
     return dev_status(launch_lds_conv(P, (const u32*)a, la, (const u32*)b, lb, out, lc, pidx, T, sc, c->errflag, s));
   }
-  SplitTables S;
-  st = get_split_tables(c, pidx, P.logL, &S);
+  RowTables W;
+  st = get_row_tables(c, pidx, P.logL, P.logC, plan_row_lnt(P), sc.x, &W);
   if (st) return st;
   u32* Ta = (u32*)ws;
   u32* Tb = Ta + plan_nprime(P);
   hipError_t e = launch_col_fwd(P, a, la, b, lb, in_type, Ta, Tb, pidx, T, c->errflag, s);
-  if (e == hipSuccess) e = launch_row_conv(P, Ta, Tb, Ta, pidx, T, S, sc, s);
+  if (e == hipSuccess) e = launch_row_conv(P, Ta, Tb, Ta, pidx, T, W, s);
   if (e == hipSuccess) e = launch_col_inv(P, Ta, out, lc, pidx, T, s);
   return dev_status(e);
 }
@@ -398,19 +412,19 @@ pm_status pm_ntt(const uint32_t* x, uint32_t* y, size_t n, uint32_t p, int inver
                                        c->errflag, s));
   st = ensure_workspace(c, n * sizeof(u32));
   if (st) return st;
-  SplitTables S;
-  st = get_split_tables(c, pidx, logL, &S);
+  RowTables S;
+  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), inverse ? ninv.x : 1u, &S);
   if (st) return st;
   u32* T = (u32*)c->ws;
   const int logR = P.logRA + P.logRB;
   hipError_t e;
   if (!inverse) {
     e = launch_col_fwd(P, x, (long)n, nullptr, 0, 0, T, nullptr, pidx, c->tabs[pidx], c->errflag, s);
-    if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 0, pidx, c->tabs[pidx], S, ninv, s);
+    if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 0, pidx, c->tabs[pidx], S, s);
     if (e == hipSuccess) e = launch_permute(T, y, logR, P.logC, 1, s);
   } else {
     e = launch_permute(x, T, logR, P.logC, 0, s);
-    if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 1, pidx, c->tabs[pidx], S, ninv, s);
+    if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 1, pidx, c->tabs[pidx], S, s);
     if (e == hipSuccess) e = launch_col_inv(P, T, y, (long)n, pidx, c->tabs[pidx], s);
   }
   return dev_status(e);
@@ -432,12 +446,12 @@ pm_status pm_tft(const uint32_t* x, size_t z, size_t L, size_t n, uint32_t p, ui
         launch_lds_xform(P, x, (long)z, out, (long)n, 0, 0, pidx, c->tabs[pidx], one, c->errflag, s));
   st = ensure_workspace(c, (size_t)plan_nprime(P) * sizeof(u32));
   if (st) return st;
-  SplitTables S;
-  st = get_split_tables(c, pidx, logL, &S);
+  RowTables S;
+  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), 1u, &S);
   if (st) return st;
   u32* T = (u32*)c->ws;
   hipError_t e = launch_col_fwd(P, x, (long)z, nullptr, 0, 0, T, nullptr, pidx, c->tabs[pidx], c->errflag, s);
-  if (e == hipSuccess) e = launch_row_xform(P, T, out, (long)n, 0, pidx, c->tabs[pidx], S, one, s);
+  if (e == hipSuccess) e = launch_row_xform(P, T, out, (long)n, 0, pidx, c->tabs[pidx], S, s);
   return dev_status(e);
 }
 
@@ -459,11 +473,11 @@ pm_status pm_itft(const uint32_t* v, size_t L, size_t n, uint32_t p, uint32_t* o
     return dev_status(launch_lds_xform(P, v, (long)n, out, (long)n, 1, 0, pidx, c->tabs[pidx], sc, c->errflag, s));
   st = ensure_workspace(c, (size_t)plan_nprime(P) * sizeof(u32));
   if (st) return st;
-  SplitTables S;
-  st = get_split_tables(c, pidx, logL, &S);
+  RowTables S;
+  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), sc.x, &S);
   if (st) return st;
   u32* T = (u32*)c->ws;
-  hipError_t e = launch_row_xform(P, v, T, (long)n, 1, pidx, c->tabs[pidx], S, sc, s);
+  hipError_t e = launch_row_xform(P, v, T, (long)n, 1, pidx, c->tabs[pidx], S, s);
   if (e == hipSuccess) e = launch_col_inv(P, T, out, (long)n, pidx, c->tabs[pidx], s);
   return dev_status(e);
 }

@@ -11,6 +11,7 @@
 // parallel scan (function composition is associative), so the carries of
 // all limbs are found in three passes over memory.
 #include "internal.h"
+#include "trace.h"
 
 namespace pm {
 
@@ -204,9 +205,18 @@ hipError_t launch_crt_carry(const u32* r1, const u32* r2, const u32* r3, long lc
   u32* sums = (u32*)ws;
   u32* bmap = sums + nl;
   u32* cin = bmap + nblk;
-  k_crt_sums<<<(unsigned)nblk, kCrtThreads, 0, s>>>(r1, r2, r3, lc, nl, K, sums, bmap);
-  k_carry_scan<<<1, 1024, 0, s>>>(bmap, (int)nblk, cin);
-  k_carry_apply<<<(unsigned)nblk, kCrtThreads, 0, s>>>(sums, nl, cin, out);
+  {
+    TraceScope ts(s, "crt_sums");
+    k_crt_sums<<<(unsigned)nblk, kCrtThreads, 0, s>>>(r1, r2, r3, lc, nl, K, sums, bmap);
+  }
+  {
+    TraceScope ts(s, "carry_scan");
+    k_carry_scan<<<1, 1024, 0, s>>>(bmap, (int)nblk, cin);
+  }
+  {
+    TraceScope ts(s, "carry_apply");
+    k_carry_apply<<<(unsigned)nblk, kCrtThreads, 0, s>>>(sums, nl, cin, out);
+  }
   return hipGetLastError();
 }
 
@@ -217,6 +227,7 @@ __global__ void k_widen(const uint16_t* __restrict__ in, long n, u32* __restrict
 }
 
 hipError_t launch_widen(const uint16_t* in, long n, u32* out, hipStream_t s) {
+  TraceScope ts(s, "widen");
   k_widen<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, n, out);
   return hipGetLastError();
 }

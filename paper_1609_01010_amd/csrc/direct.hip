@@ -1,0 +1,57 @@
+// Convolution kernels: the defining sum for tiny products, the one-work-group
+// LDS-resident convolution, and the three passes of the four-step convolution.
+//
+// The product is computed by the convolution theorem (Theorem 1, eq. 10):
+// forward transforms of both zero-padded operands (eq. 12; the padding is
+// never read from memory), the pointwise product (the operator P of eq. 11),
+// the inverse transform, and the scaling by the inverse length.  With
+// truncation (eq. 14) only the first n' >= len_a + len_b - 1 bit-reversed
+// transform values are formed, multiplied and inverted.
+//
+// Four-step split used throughout, for L = R * C:
+//   input index  j = C j1 + j2   (j1 < R: column position, j2 < C: column)
+//   output index k = k1 + R k2
+//   X_{k1 + R k2} = sum_{j2} w_C^{j2 k2} w_L^{j2 k1} sum_{j1} x_{C j1 + j2} w_R^{j1 k1}
+// Column pass: length-R transforms of the columns (bit-reversed out).  Row
+// pass: row t holds k1 = rev(t); twiddle by w_L^{j2 k1}, length-C transform,
+// and for the convolution the pointwise product and the inverse, untwiddled.
+// Truncating to rows t < m keeps the first m C bit-reversed outputs: the TFT
+// with granularity C (relaxed, as the paper's library relaxes its breakdown).
+#include "internal.h"
+#include "trace.h"
+
+namespace pm {
+
+// ---------------------------------------------------------------------------
+// the defining sum c_k = sum_{i+j=k} a_i b_j (Def. 2) for products with < 64
+// outputs: one thread per output coefficient
+
+template <bool LAZY>
+__global__ void __launch_bounds__(64) k_direct(const u32* __restrict__ a, int la, const u32* __restrict__ b, int lb,
+                                              u32* __restrict__ c, ModP mp, int* err) {
+  const int k = threadIdx.x;
+  const int lc = la + lb - 1;
+  if (k >= lc) return;
+  u64 acc = 0;  // < 64 terms each below 2^31
+  const int i0 = k - (lb - 1) > 0 ? k - (lb - 1) : 0;
+  const int i1 = k < la - 1 ? k : la - 1;
+  for (int i = i0; i <= i1; ++i) {
+    const u32 x = a[i], y = b[k - i];
+    if (x >= mp.p || y >= mp.p) atomicOr(err, 1);
+    acc += (u64)x * y % mp.p;
+  }
+  c[k] = (u32)(acc % mp.p);
+}
+
+hipError_t launch_direct(const u32* a, long la, const u32* b, long lb, u32* c, int pidx, int* err, hipStream_t s) {
+  const PrimeInfo& P = prime_info(pidx);
+  const ModP mp = modp_of(P);
+  TraceScope ts(s, "direct");
+  if (P.lazy)
+    k_direct<true><<<1, 64, 0, s>>>(a, (int)la, b, (int)lb, c, mp, err);
+  else
+    k_direct<false><<<1, 64, 0, s>>>(a, (int)la, b, (int)lb, c, mp, err);
+  return hipGetLastError();
+}
+
+}  // namespace pm

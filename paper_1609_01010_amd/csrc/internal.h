@@ -31,20 +31,32 @@ u32 h_powmod(u32 b, u64 e, u32 p);
 u32 h_inv(u32 a, u32 p);
 uint2 h_shoup(u32 w, u32 p);  // (w, floor(w 2^32 / p))
 
-// four-step twiddles w_L^e split as w_L^{e mod 2^h} * w_L^{2^h floor(e / 2^h)}
-struct SplitTables {
-  const uint2* lo_f;
-  const uint2* hi_f;
-  const uint2* lo_i;
-  const uint2* hi_i;
-  int hbits;
+// Row-pass twiddles of the four-step split for (L, C, nt threads): element
+// j2 = tid + nt e of row k1 is multiplied by gf[k1 tid] * ff[k1 ept + e] =
+// w_L^{k1 j2} (forward) or gi[k1 tid] * fi[k1 ept + e] = w_L^{-k1 j2} * scale.
+struct RowTables {
+  const uint2* gf;
+  const uint2* gi;
+  const uint2* ff;
+  const uint2* fi;
+};
+struct RowKey {
+  int pidx, logL, logC, lnt;
+  u32 scale;
+  bool operator<(const RowKey& o) const {
+    if (pidx != o.pidx) return pidx < o.pidx;
+    if (logL != o.logL) return logL < o.logL;
+    if (logC != o.logC) return logC < o.logC;
+    if (lnt != o.lnt) return lnt < o.lnt;
+    return scale < o.scale;
+  }
 };
 
 struct DevCtx {
   int dev = -1;
   uint2* prime_mem[kNumPrimes] = {nullptr, nullptr, nullptr, nullptr};
   PrimeTables tabs[kNumPrimes];
-  std::map<std::pair<int, int>, std::pair<uint2*, SplitTables>> split;
+  std::map<RowKey, std::pair<uint2*, RowTables>> rowtw;
   int* errflag = nullptr;  // device word: bit 0 = input not reduced
   void* ws = nullptr;      // workspace
   size_t ws_bytes = 0;
@@ -53,8 +65,9 @@ struct DevCtx {
 
 DevCtx* ctx_current(pm_status* st);
 pm_status ensure_prime_tables(DevCtx* c, int pidx);
-pm_status get_split_tables(DevCtx* c, int pidx, int logL, SplitTables* out);
 pm_status ensure_workspace(DevCtx* c, size_t bytes);
+// scale: the value multiplied into the inverse factors (1 for none)
+pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, RowTables* out);
 
 inline ModP modp_of(const PrimeInfo& P) { return ModP{P.p, 2u * P.p, P.ninv}; }
 
@@ -69,7 +82,14 @@ struct Plan {
   int logC = 0;   // row length of the four-step
   int ma = 1;     // kept blocks of the first radix, 1..RA
   int lq = 4;     // log radix of the LDS rounds
+  int lnt = 0;    // log2 threads of the row pass (0: the default for logC)
 };
+
+// threads of the four-step row pass
+inline int plan_row_lnt(const Plan& P) {
+  if (P.lnt) return P.lnt;
+  return P.logC - 5 < 6 ? 6 : (P.logC - 5 > 9 ? 9 : P.logC - 5);  // 32 elements per thread
+}
 
 // relaxed transform length n' = ma * L / RA
 inline long plan_nprime(const Plan& P) { return (long)P.ma << (P.logL - P.logRA); }
@@ -83,14 +103,14 @@ hipError_t launch_lds_conv(const Plan& P, const u32* a, long la, const u32* b, l
 hipError_t launch_col_fwd(const Plan& P, const void* a, long za, const void* b, long zb, int in_type, u32* Ta, u32* Tb,
                           int pidx, const PrimeTables& T, int* err, hipStream_t s);
 hipError_t launch_row_conv(const Plan& P, const u32* Ta, const u32* Tb, u32* Tc, int pidx, const PrimeTables& T,
-                           const SplitTables& S, uint2 sc, hipStream_t s);
+                           const RowTables& W, hipStream_t s);
 hipError_t launch_col_inv(const Plan& P, const u32* Tc, u32* c, long lc, int pidx, const PrimeTables& T,
                           hipStream_t s);
 // standalone row transforms over rows t < ma * RB: dir 0 = twiddle then
 // forward (outputs at flat index < nout), dir 1 = inverse then untwiddle and
 // multiply by sc
 hipError_t launch_row_xform(const Plan& P, const u32* in, u32* out, long nout, int dir, int pidx,
-                            const PrimeTables& T, const SplitTables& S, uint2 sc, hipStream_t s);
+                            const PrimeTables& T, const RowTables& W, hipStream_t s);
 // four-step layout (t1 * C + t2 = bit-reversed order) <-> natural order
 hipError_t launch_permute(const u32* in, u32* out, int logR, int logC, int to_natural, hipStream_t s);
 // one-work-group transform (L <= 2^14) for the hooks: dir 0 forward of zin

@@ -1,0 +1,164 @@
+// Convolution kernels: the defining sum for tiny products, the one-work-group
+// LDS-resident convolution, and the three passes of the four-step convolution.
+//
+// The product is computed by the convolution theorem (Theorem 1, eq. 10):
+// forward transforms of both zero-padded operands (eq. 12; the padding is
+// never read from memory), the pointwise product (the operator P of eq. 11),
+// the inverse transform, and the scaling by the inverse length.  With
+// truncation (eq. 14) only the first n' >= len_a + len_b - 1 bit-reversed
+// transform values are formed, multiplied and inverted.
+//
+// Four-step split used throughout, for L = R * C:
+//   input index  j = C j1 + j2   (j1 < R: column position, j2 < C: column)
+//   output index k = k1 + R k2
+//   X_{k1 + R k2} = sum_{j2} w_C^{j2 k2} w_L^{j2 k1} sum_{j1} x_{C j1 + j2} w_R^{j1 k1}
+// Column pass: length-R transforms of the columns (bit-reversed out).  Row
+// pass: row t holds k1 = rev(t); twiddle by w_L^{j2 k1}, length-C transform,
+// and for the convolution the pointwise product and the inverse, untwiddled.
+// Truncating to rows t < m keeps the first m C bit-reversed outputs: the TFT
+// with granularity C (relaxed, as the paper's library relaxes its breakdown).
+#ifndef PM_LAZY
+#error "compile with -DPM_LAZY=0 or -DPM_LAZY=1"
+#endif
+#define PM_CAT2(a, b) a##b
+#define PM_CAT(a, b) PM_CAT2(a, b)
+#define PM_SUFFIX(name) PM_CAT(name, PM_CAT(_lazy, PM_LAZY))
+#include "internal.h"
+#include "trace.h"
+
+namespace pm {
+constexpr bool kLazy = PM_LAZY != 0;
+
+// ---------------------------------------------------------------------------
+// one work-group per product, everything in LDS (L = 2^LN <= 2^14).
+// The first round (radix RA over the top log2 RA index bits) is done in
+// registers straight from global memory and keeps the first ma of its RA
+// output blocks; the remaining rounds transform those blocks in LDS.
+
+template <int LN, int LRA, int LQ, bool LAZY>
+__global__ void __launch_bounds__(1024) k_lds_conv(const u32* __restrict__ a, int la, const u32* __restrict__ b, int lb,
+                                                   u32* __restrict__ c, int lc, int ma, ModP mp, PrimeTables T,
+                                                   uint2 sc, int* err) {
+  constexpr int N = 1 << LN;
+  constexpr int RA = 1 << LRA;
+  constexpr int LS = LN - LRA;
+  constexpr int S = 1 << LS;
+  extern __shared__ u32 sm[];
+  u32* sa = sm;
+  u32* sb = sm + N;
+  const Arith<LAZY> A(mp);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  bool bad = false;
+
+  for (int j = tid; j < S; j += nthr) {
+    uint2 tw[RA];
+    if constexpr (S > 1) {
+#pragma unroll
+      for (int t = 1; t < RA; ++t) tw[t] = T.rf[LRA - 3][N + j * RA + t];
+    }
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      const u32* in = op ? b : a;
+      const int len = op ? lb : la;
+      u32* out = op ? sb : sa;
+      u32 x[RA];
+#pragma unroll
+      for (int s = 0; s < RA; ++s) {
+        const int pos = j + S * s;
+        x[s] = pos < len ? in[pos] : 0u;
+        bad |= x[s] >= mp.p;
+      }
+      dif_reg<RA>(A, x, T.pf);
+#pragma unroll
+      for (int t = 0; t < RA; ++t) {
+        if (t < ma) {
+          u32 v = x[t];
+          if constexpr (S > 1) {
+            if (t > 0) v = A.mul(v, tw[t]);
+          }
+          out[lds_ix(j + S * t)] = v;
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(err, 1);
+  __syncthreads();
+  const int nel = ma * S;
+  u32* bufs[2] = {sa, sb};
+  dif_lds<LS, LQ, LAZY, 2>(A, bufs, nel, T, tid, nthr);
+  for (int i = tid; i < nel; i += nthr) {
+    const int k = lds_ix(i);
+    sa[k] = A.mul(A.mont(sa[k], sb[k]), sc);
+  }
+  __syncthreads();
+  dit_lds<LS, LQ, LAZY>(A, sa, nel, T, tid, nthr);
+  for (int j = tid; j < S; j += nthr) {
+    u32 x[RA];
+#pragma unroll
+    for (int t = 0; t < RA; ++t) {
+      u32 v = 0;
+      if (t < ma) {
+        v = sa[lds_ix(j + S * t)];
+        if constexpr (S > 1) {
+          if (t > 0) v = A.mul(v, T.ri[LRA - 3][N + j * RA + t]);
+        }
+      }
+      x[t] = v;
+    }
+    inv_column<RA, LAZY>(A, x, ma, T);
+#pragma unroll
+    for (int s = 0; s < RA; ++s) {
+      const int pos = j + S * s;
+      if (s < ma && pos < lc) c[pos] = A.canon(x[s]);
+    }
+  }
+}
+
+template <int LN, int LRA, bool LAZY>
+static hipError_t lds_conv_inst(const Plan& P, const u32* a, long la, const u32* b, long lb, u32* c, long lc,
+                                const ModP& mp, const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
+  constexpr int N = 1 << LN;
+  int nthr = N / 16;
+  if (nthr < 64) nthr = 64;
+  if (nthr > 1024) nthr = 1024;
+  const size_t lds = 2 * (size_t)N * sizeof(u32);
+  auto kern = k_lds_conv<LN, LRA, 4, LAZY>;
+  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  TraceScope ts(s, "lds_conv");
+  kern<<<1, nthr, lds, s>>>(a, (int)la, b, (int)lb, c, (int)lc, P.ma, mp, T, sc, err);
+  return hipGetLastError();
+}
+
+template <int LN, bool LAZY>
+static hipError_t lds_conv_ra(const Plan& P, const u32* a, long la, const u32* b, long lb, u32* c, long lc,
+                              const ModP& mp, const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
+  switch (P.logRA) {
+#define PM_RA(r)                                                                                  \
+  case r:                                                                                         \
+    if constexpr (r <= LN) return lds_conv_inst<LN, r, LAZY>(P, a, la, b, lb, c, lc, mp, T, sc, err, s); \
+    break;
+    PM_RA(3) PM_RA(4) PM_RA(5)
+#undef PM_RA
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t PM_SUFFIX(launch_lds_conv)(const Plan& P, const u32* a, long la, const u32* b, long lb, u32* c, long lc, int pidx,
+                           const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
+  const PrimeInfo& PI = prime_info(pidx);
+  const ModP mp = modp_of(PI);
+#define PM_LN(n)                                                                          \
+  case n:                                                                                 \
+    return lds_conv_ra<n, kLazy>(P, a, la, b, lb, c, lc, mp, T, sc, err, s);
+  switch (P.logL) {
+    PM_LN(6) PM_LN(7) PM_LN(8) PM_LN(9) PM_LN(10) PM_LN(11) PM_LN(12) PM_LN(13) PM_LN(14)
+    default:
+      break;
+  }
+#undef PM_LN
+  return hipErrorInvalidValue;
+}
+
+}  // namespace pm

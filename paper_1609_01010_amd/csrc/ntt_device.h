@@ -14,6 +14,9 @@
 //   pi[2^s + x] = the same for w_{2^s}^{-x}
 //   ph[2^s + x] = w_{2^s}^{-x} / 2                                 s <= 5
 //   iv[k]       = 2^-k                                             k <= 32
+// Round tables, for radix Q = 2^q (q = 3, 4, 5), level B = 2^s >= Q:
+//   rf[q-3][B + j Q + t] = w_B^{j rev_q(t)},  j < B/Q, t < Q   (ri: w_B^{-j rev_q(t)})
+// so the Q twiddles of one group of an LDS round are 8Q contiguous bytes.
 #pragma once
 #include "arith.h"
 
@@ -29,6 +32,8 @@ struct PrimeTables {
   const uint2* pi;
   const uint2* ph;
   const uint2* iv;
+  const uint2* rf[3];
+  const uint2* ri[3];
 };
 
 // ---------------------------------------------------------------------------
@@ -165,10 +170,55 @@ __device__ __forceinline__ void inv_column(const Arith<LAZY>& A, u32* v, int m, 
 //            w_B^{j rev(t)}; the result in place leaves Q sub-blocks of size B/Q
 //            each needing its own length-B/Q transform (section 3, eq. 11).
 //   inverse: the mirror image, unscaled.
+// LDS addresses are swizzled (bits 2-4 ^= bits 6-8): the rounds whose groups
+// are 64 words apart would otherwise hit one bank of the 32; aligned quads
+// stay aligned, so the contiguous groups of the last round load as 16 bytes.
+
+__device__ __forceinline__ int lds_ix(int a) { return a ^ (((a >> 6) & 7) << 2); }
+
+template <int Q>
+__device__ __forceinline__ void load_tw(uint2 (&tw)[Q], const uint2* __restrict__ p) {
+  const uint4* q = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+  for (int t = 0; t < Q / 2; ++t) {
+    const uint4 v = q[t];
+    tw[2 * t] = make_uint2(v.x, v.y);
+    tw[2 * t + 1] = make_uint2(v.z, v.w);
+  }
+}
+
+// Q contiguous words at position `base` (multiple of Q)
+template <int Q>
+__device__ __forceinline__ void lds_load_contig(const u32* buf, int base, u32 (&x)[Q]) {
+  if constexpr (Q >= 4) {
+#pragma unroll
+    for (int k = 0; k < Q; k += 4) {
+      const uint4 v = *reinterpret_cast<const uint4*>(buf + lds_ix(base + k));
+      x[k] = v.x;
+      x[k + 1] = v.y;
+      x[k + 2] = v.z;
+      x[k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) x[k] = buf[lds_ix(base + k)];
+  }
+}
+template <int Q>
+__device__ __forceinline__ void lds_store_contig(u32* buf, int base, const u32 (&x)[Q]) {
+  if constexpr (Q >= 4) {
+#pragma unroll
+    for (int k = 0; k < Q; k += 4)
+      *reinterpret_cast<uint4*>(buf + lds_ix(base + k)) = make_uint4(x[k], x[k + 1], x[k + 2], x[k + 3]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) buf[lds_ix(base + k)] = x[k];
+  }
+}
 
 template <int LB, int LQ, bool LAZY, int NBUF>
 __device__ __forceinline__ void dif_round_lds(const Arith<LAZY>& A, u32* const* bufs, int n_el,
-                                              const uint2* __restrict__ pf, int tid, int nthr) {
+                                              const PrimeTables& T, int tid, int nthr) {
   constexpr int Q = 1 << LQ;
   constexpr int S = 1 << (LB - LQ);
   const int ngroups = n_el >> LQ;
@@ -176,30 +226,33 @@ __device__ __forceinline__ void dif_round_lds(const Arith<LAZY>& A, u32* const* 
     const int j = g & (S - 1);
     const int base = ((g >> (LB - LQ)) << LB) + j;
     uint2 tw[Q];
-    if constexpr (S > 1) {
-#pragma unroll
-      for (int t = 1; t < Q; ++t) tw[t] = pf[(1 << LB) + j * (int)(__brev((u32)t) >> (32 - LQ))];
-    }
+    if constexpr (S > 1) load_tw<Q>(tw, T.rf[LQ - 3] + (1 << LB) + j * Q);
 #pragma unroll
     for (int bi = 0; bi < NBUF; ++bi) {
       u32* buf = bufs[bi];
       u32 x[Q];
+      if constexpr (S == 1) {
+        lds_load_contig<Q>(buf, base, x);
+      } else {
 #pragma unroll
-      for (int s = 0; s < Q; ++s) x[s] = buf[base + S * s];
-      dif_reg<Q>(A, x, pf);
+        for (int s = 0; s < Q; ++s) x[s] = buf[lds_ix(base + S * s)];
+      }
+      dif_reg<Q>(A, x, T.pf);
       if constexpr (S > 1) {
 #pragma unroll
         for (int t = 1; t < Q; ++t) x[t] = A.mul(x[t], tw[t]);
-      }
 #pragma unroll
-      for (int t = 0; t < Q; ++t) buf[base + S * t] = x[t];
+        for (int t = 0; t < Q; ++t) buf[lds_ix(base + S * t)] = x[t];
+      } else {
+        lds_store_contig<Q>(buf, base, x);
+      }
     }
   }
 }
 
 template <int LB, int LQ, bool LAZY>
-__device__ __forceinline__ void dit_round_lds(const Arith<LAZY>& A, u32* buf, int n_el, const uint2* __restrict__ pi,
-                                              int tid, int nthr) {
+__device__ __forceinline__ void dit_round_lds(const Arith<LAZY>& A, u32* buf, int n_el, const PrimeTables& T, int tid,
+                                              int nthr) {
   constexpr int Q = 1 << LQ;
   constexpr int S = 1 << (LB - LQ);
   const int ngroups = n_el >> LQ;
@@ -207,39 +260,132 @@ __device__ __forceinline__ void dit_round_lds(const Arith<LAZY>& A, u32* buf, in
     const int j = g & (S - 1);
     const int base = ((g >> (LB - LQ)) << LB) + j;
     u32 x[Q];
+    if constexpr (S == 1) {
+      lds_load_contig<Q>(buf, base, x);
+    } else {
+      uint2 tw[Q];
+      load_tw<Q>(tw, T.ri[LQ - 3] + (1 << LB) + j * Q);
 #pragma unroll
-    for (int t = 0; t < Q; ++t) x[t] = buf[base + S * t];
-    if constexpr (S > 1) {
+      for (int t = 0; t < Q; ++t) x[t] = buf[lds_ix(base + S * t)];
 #pragma unroll
-      for (int t = 1; t < Q; ++t) x[t] = A.mul(x[t], pi[(1 << LB) + j * (int)(__brev((u32)t) >> (32 - LQ))]);
+      for (int t = 1; t < Q; ++t) x[t] = A.mul(x[t], tw[t]);
     }
-    dit_reg<Q>(A, x, pi);
+    dit_reg<Q>(A, x, T.pi);
+    if constexpr (S == 1) {
+      lds_store_contig<Q>(buf, base, x);
+    } else {
 #pragma unroll
-    for (int s = 0; s < Q; ++s) buf[base + S * s] = x[s];
+      for (int s = 0; s < Q; ++s) buf[lds_ix(base + S * s)] = x[s];
+    }
   }
 }
 
-// forward transform of every block of size 2^LB in the buffers (n_el elements
-// each); ends with a barrier
+// radix of the round that starts at block size 2^LB
+template <int LB, int LQMAX>
+constexpr int round_lq() {
+  return LB < LQMAX ? LB : LQMAX;
+}
+
+// forward transform of every block of size 2^LB in the buffers (n_el
+// elements each); ends with a barrier.  Rounds of radix 2^LQMAX, the last
+// one smaller if LB is not a multiple of LQMAX.
 template <int LB, int LQMAX, bool LAZY, int NBUF>
-__device__ __forceinline__ void dif_lds(const Arith<LAZY>& A, u32* const* bufs, int n_el, const uint2* __restrict__ pf,
+__device__ __forceinline__ void dif_lds(const Arith<LAZY>& A, u32* const* bufs, int n_el, const PrimeTables& T,
                                         int tid, int nthr) {
   if constexpr (LB > 0) {
-    constexpr int LQ = LB < LQMAX ? LB : LQMAX;
-    dif_round_lds<LB, LQ, LAZY, NBUF>(A, bufs, n_el, pf, tid, nthr);
+    constexpr int LQ = round_lq<LB, LQMAX>();
+    dif_round_lds<LB, LQ, LAZY, NBUF>(A, bufs, n_el, T, tid, nthr);
     __syncthreads();
-    dif_lds<LB - LQ, LQMAX, LAZY, NBUF>(A, bufs, n_el, pf, tid, nthr);
+    dif_lds<LB - LQ, LQMAX, LAZY, NBUF>(A, bufs, n_el, T, tid, nthr);
   }
 }
 
 // inverse (unscaled) of dif_lds; ends with a barrier
 template <int LB, int LQMAX, bool LAZY>
-__device__ __forceinline__ void dit_lds(const Arith<LAZY>& A, u32* buf, int n_el, const uint2* __restrict__ pi, int tid,
+__device__ __forceinline__ void dit_lds(const Arith<LAZY>& A, u32* buf, int n_el, const PrimeTables& T, int tid,
                                         int nthr) {
   if constexpr (LB > 0) {
-    constexpr int LQ = LB < LQMAX ? LB : LQMAX;
-    dit_lds<LB - LQ, LQMAX, LAZY>(A, buf, n_el, pi, tid, nthr);
-    dit_round_lds<LB, LQ, LAZY>(A, buf, n_el, pi, tid, nthr);
+    constexpr int LQ = round_lq<LB, LQMAX>();
+    dit_lds<LB - LQ, LQMAX, LAZY>(A, buf, n_el, T, tid, nthr);
+    dit_round_lds<LB, LQ, LAZY>(A, buf, n_el, T, tid, nthr);
     __syncthreads();
   }
+}
+
+// forward rounds on blocks of size 2^LB down to block size 2^LSTOP; ends with a barrier
+template <int LB, int LSTOP, int LQMAX, bool LAZY>
+__device__ __forceinline__ void dif_lds_upto(const Arith<LAZY>& A, u32* const* bufs, int n_el, const PrimeTables& T,
+                                             int tid, int nthr) {
+  if constexpr (LB > LSTOP) {
+    constexpr int LQ = round_lq<LB, LQMAX>();
+    dif_round_lds<LB, LQ, LAZY, 1>(A, bufs, n_el, T, tid, nthr);
+    __syncthreads();
+    dif_lds_upto<LB - LQ, LSTOP, LQMAX, LAZY>(A, bufs, n_el, T, tid, nthr);
+  }
+}
+
+// inverse rounds for block sizes above 2^LSTOP up to 2^LB; ends with a barrier
+template <int LB, int LSTOP, int LQMAX, bool LAZY>
+__device__ __forceinline__ void dit_lds_from(const Arith<LAZY>& A, u32* buf, int n_el, const PrimeTables& T, int tid,
+                                             int nthr) {
+  if constexpr (LB > LSTOP) {
+    constexpr int LQ = round_lq<LB, LQMAX>();
+    dit_lds_from<LB - LQ, LSTOP, LQMAX, LAZY>(A, buf, n_el, T, tid, nthr);
+    dit_round_lds<LB, LQ, LAZY>(A, buf, n_el, T, tid, nthr);
+    __syncthreads();
+  }
+}
+
+// log2 of the block size of the last round of a transform of size 2^LB
+template <int LB, int LQMAX>
+constexpr int last_lb() {
+  if constexpr (LB <= LQMAX)
+    return LB;
+  else
+    return last_lb<LB - LQMAX, LQMAX>();
+}
+
+// All rounds but the last on LDS, then the last round (contiguous groups of
+// Q = 2^last_lb) into registers: x[u Q + t] is slot t of group tid + nthr u.
+// Requires n_el = nthr * EPT.  Ends without a barrier (the caller's next LDS
+// write must be preceded by one).
+template <int LB, int LQMAX, bool LAZY, int EPT>
+__device__ __forceinline__ void dif_lds_to_regs(const Arith<LAZY>& A, u32* buf, int n_el, const PrimeTables& T,
+                                                int tid, int nthr, u32 (&x)[EPT]) {
+  constexpr int LQL = last_lb<LB, LQMAX>();
+  constexpr int QL = 1 << LQL;
+  if constexpr (LB > LQL) {
+    u32* bufs[1] = {buf};
+    // rounds down to block size 2^LQL
+    dif_lds_upto<LB, LQL, LQMAX, LAZY>(A, bufs, n_el, T, tid, nthr);
+  }
+#pragma unroll
+  for (int u = 0; u < EPT / QL; ++u) {
+    const int g = tid + nthr * u;
+    u32 y[QL];
+    lds_load_contig<QL>(buf, g * QL, y);
+    dif_reg<QL>(A, y, T.pf);
+#pragma unroll
+    for (int t = 0; t < QL; ++t) x[u * QL + t] = y[t];
+  }
+}
+
+// Mirror of dif_lds_to_regs: first inverse round from registers to LDS,
+// then the remaining inverse rounds; ends with a barrier.
+template <int LB, int LQMAX, bool LAZY, int EPT>
+__device__ __forceinline__ void dit_regs_to_lds(const Arith<LAZY>& A, u32* buf, int n_el, const PrimeTables& T,
+                                                int tid, int nthr, u32 (&x)[EPT]) {
+  constexpr int LQL = last_lb<LB, LQMAX>();
+  constexpr int QL = 1 << LQL;
+#pragma unroll
+  for (int u = 0; u < EPT / QL; ++u) {
+    const int g = tid + nthr * u;
+    u32 y[QL];
+#pragma unroll
+    for (int t = 0; t < QL; ++t) y[t] = x[u * QL + t];
+    dit_reg<QL>(A, y, T.pi);
+    lds_store_contig<QL>(buf, g * QL, y);
+  }
+  __syncthreads();
+  if constexpr (LB > LQL) dit_lds_from<LB, LQL, LQMAX, LAZY>(A, buf, n_el, T, tid, nthr);
 }

@@ -98,6 +98,34 @@ __global__ void k_fill_pyramids(uint2* base, u32 p, u32 g) {
   if (idx < kInvPow) iv[idx] = d_shoup(d_powmod((p + 1) / 2, (u32)idx, p), p);
 }
 
+// Round tables for radix Q = 2^lq: level B = 2^s (Q <= B <= 2^15),
+// out[B + j Q + t] = w_B^{sign j rev_lq(t)}, j < B/Q, t < Q.
+__global__ void k_fill_round_table(uint2* out, u32 p, u32 g, int lq, int inverse) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Q = 1 << lq;
+  if (idx < Q || idx >= kPyrSize) {
+    if (idx < Q) out[idx] = make_uint2(0, 0);
+    return;
+  }
+  const int s = 31 - __clz(idx);
+  const u32 o = (u32)idx - (1u << s);
+  const u32 j = o >> lq, t = o & (Q - 1);
+  const u32 rt = __brev(t) >> (32 - lq);
+  const u32 w = d_powmod(g, (p - 1) >> s, p);
+  u32 e = (j * rt) & ((1u << s) - 1);
+  if (inverse) e = ((1u << s) - e) & ((1u << s) - 1);
+  out[idx] = d_shoup(d_powmod(w, e, p), p);
+}
+
+// Row-pass twiddle factors: out[k1 * ept + e] = mult * wL^{(k1 * nt * e) mod L}
+__global__ void k_row_factors(uint2* out, int R, int ept, int nt, u32 Lmask, u32 p, u32 wL, u32 mult) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R * ept) return;
+  const u32 k1 = (u32)(i / ept), e = (u32)(i % ept);
+  const u32 ex = (u32)(((u64)k1 * (u32)nt * e) & Lmask);
+  out[i] = d_shoup(d_mulmod(mult, d_powmod(wL, ex, p), p), p);
+}
+
 // out[i] = mult * base^i mod p as Shoup pairs, i < n
 __global__ void k_powtable(uint2* out, int n, u32 p, u32 base, u32 mult) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -141,10 +169,17 @@ DevCtx* ctx_current(pm_status* st) {
 pm_status ensure_prime_tables(DevCtx* c, int pidx) {
   if (c->prime_mem[pidx]) return PM_OK;
   const PrimeInfo& P = prime_info(pidx);
-  const size_t n = 2 * (size_t)kPyrSize + kHalfSize + kInvPow;
+  // pf, pi, ph, iv, then six round tables (Q = 8, 16, 32; both directions)
+  const size_t head = 2 * (size_t)kPyrSize + kHalfSize + kInvPow;
+  const size_t head_al = (head + 63) & ~(size_t)63;
+  const size_t n = head_al + 6 * (size_t)kPyrSize;
   uint2* mem = nullptr;
   if (hipMalloc(&mem, n * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
   k_fill_pyramids<<<kPyrSize / 256, 256>>>(mem, P.p, P.g);
+  for (int q = 0; q < 3; ++q) {
+    k_fill_round_table<<<kPyrSize / 256, 256>>>(mem + head_al + (2 * q) * kPyrSize, P.p, P.g, q + 3, 0);
+    k_fill_round_table<<<kPyrSize / 256, 256>>>(mem + head_al + (2 * q + 1) * kPyrSize, P.p, P.g, q + 3, 1);
+  }
   if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     hipFree(mem);
     return PM_EDEVICE;
@@ -154,43 +189,47 @@ pm_status ensure_prime_tables(DevCtx* c, int pidx) {
   c->tabs[pidx].pi = mem + kPyrSize;
   c->tabs[pidx].ph = mem + 2 * kPyrSize;
   c->tabs[pidx].iv = mem + 2 * kPyrSize + kHalfSize;
+  for (int q = 0; q < 3; ++q) {
+    c->tabs[pidx].rf[q] = mem + head_al + (2 * q) * kPyrSize;
+    c->tabs[pidx].ri[q] = mem + head_al + (2 * q + 1) * kPyrSize;
+  }
   return PM_OK;
 }
 
-pm_status get_split_tables(DevCtx* c, int pidx, int logL, SplitTables* out) {
-  auto key = std::make_pair(pidx, logL);
-  auto it = c->split.find(key);
-  if (it != c->split.end()) {
+pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, RowTables* out) {
+  const RowKey key{pidx, logL, logC, lnt, scale};
+  auto it = c->rowtw.find(key);
+  if (it != c->rowtw.end()) {
     *out = it->second.second;
     return PM_OK;
   }
   const PrimeInfo& P = prime_info(pidx);
-  const int hb = (logL + 1) / 2;
-  const int nlo = 1 << hb, nhi = 1 << (logL - hb);
+  const int R = 1 << (logL - logC), nt = 1 << lnt, ept = 1 << (logC - lnt);
+  const int ng = R * nt, nf = R * ept;
   uint2* mem = nullptr;
-  if (hipMalloc(&mem, 2 * (size_t)(nlo + nhi) * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
+  if (hipMalloc(&mem, 2 * (size_t)(ng + nf) * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
   const u32 w = h_powmod(P.g, (P.p - 1) >> logL, P.p);
   const u32 wi = h_inv(w, P.p);
-  SplitTables S;
-  uint2* lo_f = mem;
-  uint2* hi_f = lo_f + nlo;
-  uint2* lo_i = hi_f + nhi;
-  uint2* hi_i = lo_i + nlo;
-  k_powtable<<<(nlo + 255) / 256, 256>>>(lo_f, nlo, P.p, w, 1);
-  k_powtable<<<(nhi + 255) / 256, 256>>>(hi_f, nhi, P.p, h_powmod(w, (u64)nlo, P.p), 1);
-  k_powtable<<<(nlo + 255) / 256, 256>>>(lo_i, nlo, P.p, wi, 1);
-  k_powtable<<<(nhi + 255) / 256, 256>>>(hi_i, nhi, P.p, h_powmod(wi, (u64)nlo, P.p), 1);
+  RowTables W;
+  uint2* gf = mem;
+  uint2* gi = gf + ng;
+  uint2* ff = gi + ng;
+  uint2* fi = ff + nf;
+  const u32 Lmask = (u32)((1ull << logL) - 1);
+  k_powtable<<<(ng + 255) / 256, 256>>>(gf, ng, P.p, w, 1);
+  k_powtable<<<(ng + 255) / 256, 256>>>(gi, ng, P.p, wi, 1);
+  k_row_factors<<<(nf + 255) / 256, 256>>>(ff, R, ept, nt, Lmask, P.p, w, 1);
+  k_row_factors<<<(nf + 255) / 256, 256>>>(fi, R, ept, nt, Lmask, P.p, wi, scale);
   if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     hipFree(mem);
     return PM_EDEVICE;
   }
-  S.lo_f = lo_f;
-  S.hi_f = hi_f;
-  S.lo_i = lo_i;
-  S.hi_i = hi_i;
-  S.hbits = hb;
-  c->split[key] = std::make_pair(mem, S);
-  *out = S;
+  W.gf = gf;
+  W.gi = gi;
+  W.ff = ff;
+  W.fi = fi;
+  c->rowtw[key] = std::make_pair(mem, W);
+  *out = W;
   return PM_OK;
 }
 

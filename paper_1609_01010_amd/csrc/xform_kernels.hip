@@ -2,9 +2,18 @@
 // the modular DFT in natural order (section 3), the truncated transform TFT
 // in bit-reversed order and its inverse ITFT scaled by L (the TFT product,
 // eq. 14).  They reuse the convolution's building blocks.
+#ifndef PM_LAZY
+#error "compile with -DPM_LAZY=0 or -DPM_LAZY=1"
+#endif
+#define PM_CAT2(a, b) a##b
+#define PM_CAT(a, b) PM_CAT2(a, b)
+#define PM_SUFFIX(name) PM_CAT(name, PM_CAT(_lazy, PM_LAZY))
 #include "internal.h"
+#include "trace.h"
 
 namespace pm {
+constexpr bool kLazy = PM_LAZY != 0;
+
 
 // ---------------------------------------------------------------------------
 // one work-group, L = 2^LN <= 2^14, first radix RA (truncated to ma blocks)
@@ -36,43 +45,47 @@ __global__ void __launch_bounds__(1024) k_lds_xform(const u32* in, int zin, u32*
       for (int t = 0; t < RA; ++t) {
         if (t < ma) {
           u32 v = x[t];
-          if (S > 1 && t > 0) v = A.mul(v, T.pf[N + j * (int)(__brev((u32)t) >> (32 - LRA))]);
-          sm[j + S * t] = v;
+          if constexpr (S > 1) {
+            if (t > 0) v = A.mul(v, T.rf[LRA - 3][N + j * RA + t]);
+          }
+          sm[lds_ix(j + S * t)] = v;
         }
       }
     }
     __syncthreads();
     u32* bufs[1] = {sm};
-    dif_lds<LS, 4, LAZY, 1>(A, bufs, nel, T.pf, tid, nthr);
+    dif_lds<LS, 4, LAZY, 1>(A, bufs, nel, T, tid, nthr);
     if (natural) {
-      for (int k = tid; k < N; k += nthr) out[k] = A.canon(sm[bitrev_n((u32)k, LN)]);
+      for (int k = tid; k < N; k += nthr) out[k] = A.canon(sm[lds_ix(bitrev_n((u32)k, LN))]);
     } else {
-      for (int i = tid; i < nout; i += nthr) out[i] = A.canon(sm[i]);
+      for (int i = tid; i < nout; i += nthr) out[i] = A.canon(sm[lds_ix(i)]);
     }
   } else {
     if (natural) {
       for (int t = tid; t < N; t += nthr) {
         const u32 v = in[bitrev_n((u32)t, LN)];
         bad |= v >= mp.p;
-        sm[t] = v;
+        sm[lds_ix(t)] = v;
       }
     } else {
       for (int i = tid; i < nel; i += nthr) {
         const u32 v = in[i];
         bad |= v >= mp.p;
-        sm[i] = v;
+        sm[lds_ix(i)] = v;
       }
     }
     __syncthreads();
-    dit_lds<LS, 4, LAZY>(A, sm, nel, T.pi, tid, nthr);
+    dit_lds<LS, 4, LAZY>(A, sm, nel, T, tid, nthr);
     for (int j = tid; j < S; j += nthr) {
       u32 x[RA];
 #pragma unroll
       for (int t = 0; t < RA; ++t) {
         u32 v = 0;
         if (t < ma) {
-          v = sm[j + S * t];
-          if (S > 1 && t > 0) v = A.mul(v, T.pi[N + j * (int)(__brev((u32)t) >> (32 - LRA))]);
+          v = sm[lds_ix(j + S * t)];
+          if constexpr (S > 1) {
+            if (t > 0) v = A.mul(v, T.ri[LRA - 3][N + j * RA + t]);
+          }
         }
         x[t] = v;
       }
@@ -96,7 +109,8 @@ static hipError_t lds_xform_inst(const Plan& P, const u32* in, long zin, u32* ou
   if (nthr > 1024) nthr = 1024;
   const size_t lds = (size_t)N * sizeof(u32);
   auto kern = k_lds_xform<LN, LRA, LAZY>;
-  hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  TraceScope ts(s, "lds_xform");
   kern<<<1, nthr, lds, s>>>(in, (int)zin, out, (int)nout, P.ma, dir, natural, mp, T, sc, err);
   return hipGetLastError();
 }
@@ -110,14 +124,13 @@ static hipError_t lds_xform_ln(const Plan& P, const u32* in, long zin, u32* out,
   return lds_xform_inst<LN, LRA, LAZY>(P, in, zin, out, nout, dir, natural, mp, T, sc, err, s);
 }
 
-hipError_t launch_lds_xform(const Plan& P, const u32* in, long zin, u32* out, long nout, int dir, int natural,
+hipError_t PM_SUFFIX(launch_lds_xform)(const Plan& P, const u32* in, long zin, u32* out, long nout, int dir, int natural,
                             int pidx, const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
   const PrimeInfo& PI = prime_info(pidx);
   const ModP mp = modp_of(PI);
 #define PM_LN(n)                                                                                   \
   case n:                                                                                          \
-    return PI.lazy ? lds_xform_ln<n, true>(P, in, zin, out, nout, dir, natural, mp, T, sc, err, s) \
-                   : lds_xform_ln<n, false>(P, in, zin, out, nout, dir, natural, mp, T, sc, err, s);
+    return lds_xform_ln<n, kLazy>(P, in, zin, out, nout, dir, natural, mp, T, sc, err, s);
   switch (P.logL) {
     PM_LN(1) PM_LN(2) PM_LN(3) PM_LN(4) PM_LN(5) PM_LN(6) PM_LN(7) PM_LN(8) PM_LN(9) PM_LN(10) PM_LN(11)
     PM_LN(12) PM_LN(13) PM_LN(14)
@@ -130,73 +143,86 @@ hipError_t launch_lds_xform(const Plan& P, const u32* in, long zin, u32* out, lo
 
 // ---------------------------------------------------------------------------
 // four-step row transforms (one operand): forward = twiddle by w_L^{j2 k1}
-// then DIF; inverse = DIT, untwiddle by w_L^{-j2 k1}, times sc.
+// then DIF; inverse = DIT, then untwiddle by w_L^{-j2 k1} times the scale
+// folded into the row tables.
 
-template <int LC, bool LAZY>
-__global__ void __launch_bounds__(1024) k_row_xform(const u32* in, u32* out, long nout,
-                                                    int dir, int logR, ModP mp, PrimeTables T, SplitTables S,
-                                                    uint2 sc) {
+template <int LC, int LNT, bool LAZY>
+__global__ void __launch_bounds__(1 << LNT) k_row_xform(const u32* in, u32* out, long nout, int dir, int logR, ModP mp,
+                                                        PrimeTables T, RowTables W) {
   constexpr int C = 1 << LC;
+  constexpr int NT = 1 << LNT;
+  constexpr int EPT = C / NT;
   extern __shared__ u32 sm[];
   const Arith<LAZY> A(mp);
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
   const int row = blockIdx.x;
   const u32 k1 = bitrev_n((u32)row, logR);
   const long off = (long)row * C;
-  const u32 lomask = (1u << S.hbits) - 1u;
   if (dir == 0) {
-    for (int i = tid; i < C; i += nthr) {
-      const u32 e = k1 * (u32)i;
-      sm[i] = A.mul(A.mul(in[off + i], S.lo_f[e & lomask]), S.hi_f[e >> S.hbits]);
+    const uint2 gf = W.gf[k1 * (u32)tid];
+    const uint2* ff = W.ff + (size_t)k1 * EPT;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = tid + NT * e;
+      sm[lds_ix(i)] = A.mul(A.mul(in[off + i], gf), ff[e]);
     }
     __syncthreads();
     u32* bufs[1] = {sm};
-    dif_lds<LC, 4, LAZY, 1>(A, bufs, C, T.pf, tid, nthr);
-    for (int i = tid; i < C; i += nthr)
-      if (off + i < nout) out[off + i] = A.canon(sm[i]);
+    dif_lds<LC, 4, LAZY, 1>(A, bufs, C, T, tid, NT);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = tid + NT * e;
+      if (off + i < nout) out[off + i] = A.canon(sm[lds_ix(i)]);
+    }
   } else {
-    for (int i = tid; i < C; i += nthr) sm[i] = in[off + i];
+    const uint2 gi = W.gi[k1 * (u32)tid];
+    const uint2* fi = W.fi + (size_t)k1 * EPT;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = tid + NT * e;
+      sm[lds_ix(i)] = in[off + i];
+    }
     __syncthreads();
-    dit_lds<LC, 4, LAZY>(A, sm, C, T.pi, tid, nthr);
-    for (int i = tid; i < C; i += nthr) {
-      const u32 e = k1 * (u32)i;
-      out[off + i] = A.mul(A.mul(A.mul(sm[i], S.lo_i[e & lomask]), S.hi_i[e >> S.hbits]), sc);
+    dit_lds<LC, 4, LAZY>(A, sm, C, T, tid, NT);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = tid + NT * e;
+      out[off + i] = A.mul(A.mul(sm[lds_ix(i)], gi), fi[e]);
     }
   }
 }
 
 template <int LC, bool LAZY>
 static hipError_t row_xform_inst(const Plan& P, const u32* in, u32* out, long nout, int dir, const ModP& mp,
-                                 const PrimeTables& T, const SplitTables& S, uint2 sc, hipStream_t s) {
+                                 const PrimeTables& T, const RowTables& W, hipStream_t s) {
   constexpr int C = 1 << LC;
+  constexpr int LNT = LC - 5 < 6 ? 6 : (LC - 5 > 9 ? 9 : LC - 5);
+  if (plan_row_lnt(P) != LNT) return hipErrorInvalidValue;
   const int rows = P.ma << P.logRB;
-  int nthr = C / 16;
-  if (nthr > 1024) nthr = 1024;
-  if (nthr < 64) nthr = 64;
   const size_t lds = (size_t)C * sizeof(u32);
-  auto kern = k_row_xform<LC, LAZY>;
-  hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  kern<<<rows, nthr, lds, s>>>(in, out, nout, dir, P.logRA + P.logRB, mp, T, S, sc);
+  auto kern = k_row_xform<LC, LNT, LAZY>;
+  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  TraceScope ts(s, "row_xform");
+  kern<<<rows, 1 << LNT, lds, s>>>(in, out, nout, dir, P.logRA + P.logRB, mp, T, W);
   return hipGetLastError();
 }
 
-hipError_t launch_row_xform(const Plan& P, const u32* in, u32* out, long nout, int dir, int pidx,
-                            const PrimeTables& T, const SplitTables& S, uint2 sc, hipStream_t s) {
-  const PrimeInfo& PI = prime_info(pidx);
-  const ModP mp = modp_of(PI);
-#define PM_LC(n)                                                                          \
-  case n:                                                                                 \
-    return PI.lazy ? row_xform_inst<n, true>(P, in, out, nout, dir, mp, T, S, sc, s)      \
-                   : row_xform_inst<n, false>(P, in, out, nout, dir, mp, T, S, sc, s);
+hipError_t PM_SUFFIX(launch_row_xform)(const Plan& P, const u32* in, u32* out, long nout, int dir, int pidx,
+                                       const PrimeTables& T, const RowTables& W, hipStream_t s) {
+  const ModP mp = modp_of(prime_info(pidx));
   switch (P.logC) {
-    PM_LC(10) PM_LC(11) PM_LC(12) PM_LC(13) PM_LC(14) PM_LC(15)
+#define PM_LC(n) \
+  case n:        \
+    return row_xform_inst<n, kLazy>(P, in, out, nout, dir, mp, T, W, s);
+    PM_LC(10) PM_LC(11) PM_LC(12) PM_LC(13) PM_LC(14)
+#undef PM_LC
     default:
       break;
   }
-#undef PM_LC
   return hipErrorInvalidValue;
 }
 
+#if PM_LAZY == 1
 // ---------------------------------------------------------------------------
 // layout changes for the natural-order hooks: the four-step layout holds
 // X_{k1 + R k2} at row t1 = rev_r(k1), column t2 = rev_c(k2).
@@ -216,8 +242,11 @@ __global__ void k_permute(const u32* __restrict__ in, u32* __restrict__ out, int
 
 hipError_t launch_permute(const u32* in, u32* out, int logR, int logC, int to_natural, hipStream_t s) {
   const long n = 1l << (logR + logC);
+  TraceScope ts(s, "permute");
   k_permute<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, out, logR, logC, to_natural);
   return hipGetLastError();
 }
+
+#endif
 
 }  // namespace pm
