@@ -1,45 +1,255 @@
-// Batched products (pm_poly_mul_batch).
+// Batched products (pm_poly_mul_batch): thousands of independent products of
+// uneven lengths and mixed primes in one hipGraph launch.
+//
+// Products are grouped into classes of equal plan and prime range; each
+// class runs as one launch per pass over all its products (blockIdx.z picks
+// the product's job descriptor).  The class launches are captured once per
+// batch shape into a graph whose classes hang off a fork, so independent
+// classes may run concurrently; later batches of the same shape reuse the
+// graph and only upload their job descriptors.
+#include <algorithm>
+#include <cstring>
+#include <tuple>
+
 #include "internal.h"
+#include "trace.h"
 
 namespace pm {
 bool plan_valid(const Plan& P, long lc, int pidx);
 Plan choose_plan(long lc, int pidx);
 size_t plan_workspace_bytes(const Plan& P);
-pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const void* b, long lb, int in_type, u32* out,
-                      long lc, int pidx, void* ws, hipStream_t s);
+pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
+                   long lc, u32* Ta, u32* Tb, ConvJob* J);
+pm_status launch_class(const Plan& P, bool lazy, int in_type, const JobRef& jr, int njobs, int max_rows,
+                       hipStream_t s);
+void trace_suppress(bool on);
+
+namespace {
+
+typedef std::tuple<int, int, int, int, int, int, int, int> ClassKey;  // kind, L, RA, RB, C, lq, lnt, lazy
+
+ClassKey class_key(const Plan& P, bool lazy) {
+  return ClassKey(P.kind, P.logL, P.logRA, P.logRB, P.logC, P.lq, P.kind == PLAN_FOURSTEP ? plan_row_lnt(P) : 0,
+                  lazy ? 1 : 0);
+}
+
+struct ClassRun {
+  ClassKey key;
+  Plan plan;
+  bool lazy;
+  int first;  // offset in the job array
+  int count;
+  int max_rows;
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  ConvJob* djobs = nullptr;  // device job array baked into the graph
+  size_t njobs = 0;
+};
+
+// the batch shape: classes with their sizes (the graph depends on nothing else)
+typedef std::vector<std::tuple<ClassKey, int, int>> Signature;
+
+struct BatchState {
+  std::map<std::pair<int, Signature>, GraphEntry> graphs;  // (device, shape) -> graph
+  hipStream_t cap = nullptr;                                // capture stream
+  std::vector<hipStream_t> branches;                        // fork streams
+  ConvJob* staging = nullptr;                               // pinned host copy of the jobs
+  size_t staging_cap = 0;
+  hipEvent_t staged = nullptr;  // the last upload from `staging` has completed
+};
+std::map<int, BatchState*> g_batch;
+
+constexpr int kBranches = 4;
+
+pm_status batch_state(DevCtx* c, BatchState** out) {
+  auto it = g_batch.find(c->dev);
+  if (it != g_batch.end()) {
+    *out = it->second;
+    return PM_OK;
+  }
+  BatchState* b = new BatchState();
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return PM_EDEVICE;
+  b->branches.resize(kBranches);
+  for (auto& s : b->branches)
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PM_EDEVICE;
+  if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) return PM_EDEVICE;
+  g_batch[c->dev] = b;
+  *out = b;
+  return PM_OK;
+}
+
+pm_status capture_graph(BatchState* B, const std::vector<ClassRun>& runs, ConvJob* djobs, hipGraphExec_t* exec) {
+  hipStream_t cs = B->cap;
+  trace_suppress(true);
+  pm_status st = PM_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    trace_suppress(false);
+    return PM_EDEVICE;
+  }
+  std::vector<hipEvent_t> evs;
+  hipEvent_t fork;
+  hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  hipEventRecord(fork, cs);
+  std::vector<bool> used(B->branches.size(), false);
+  for (size_t k = 0; k < runs.size() && st == PM_OK; ++k) {
+    const ClassRun& r = runs[k];
+    const size_t bi = k % B->branches.size();
+    hipStream_t bs = B->branches[bi];
+    if (!used[bi]) {
+      hipStreamWaitEvent(bs, fork, 0);
+      used[bi] = true;
+    }
+    JobRef jr;
+    memset(&jr.one, 0, sizeof(jr.one));
+    jr.many = djobs + r.first;
+    st = launch_class(r.plan, r.lazy, 0, jr, r.count, r.max_rows, bs);
+  }
+  for (size_t bi = 0; bi < B->branches.size(); ++bi) {
+    if (!used[bi]) continue;
+    hipEvent_t e;
+    hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    hipEventRecord(e, B->branches[bi]);
+    hipStreamWaitEvent(cs, e, 0);
+    evs.push_back(e);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  trace_suppress(false);
+  for (auto e : evs) hipEventDestroy(e);
+  hipEventDestroy(fork);
+  if (st) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (ec != hipSuccess || !g) return PM_EDEVICE;
+  const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return ei == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
+}  // namespace
 }  // namespace pm
 
 using namespace pm;
 
 extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream) {
   if (!probs && count) return PM_EINVAL;
+  if (count == 0) return PM_OK;
+  if (count > 65535) return PM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
   std::vector<Plan> plans(count);
   std::vector<int> pidx(count);
-  size_t wsb = 0;
   for (size_t i = 0; i < count; ++i) {
     const pm_problem& q = probs[i];
     if (!q.a || !q.b || !q.c || q.len_a == 0 || q.len_b == 0) return PM_EINVAL;
+    if (q.len_a > (1ul << 24) || q.len_b > (1ul << 24)) return PM_ETOOLARGE;
     pidx[i] = prime_index(q.p);
     if (pidx[i] < 0) return PM_EUNSUPPORTED;
     const long lc = (long)(q.len_a + q.len_b - 1);
     plans[i] = choose_plan(lc, pidx[i]);
     if (!plan_valid(plans[i], lc, pidx[i])) return PM_ETOOLARGE;
-    const size_t w = plan_workspace_bytes(plans[i]);
-    if (w > wsb) wsb = w;
   }
   pm_status st;
   DevCtx* c = ctx_current(&st);
   if (!c) return st;
   std::lock_guard<std::mutex> lk(c->mu);
+  BatchState* B;
+  st = batch_state(c, &B);
+  if (st) return st;
+
+  // classes, largest transforms first
+  std::map<ClassKey, std::vector<size_t>> groups;
+  std::vector<size_t> direct;
+  size_t wsb = 0;
+  for (size_t i = 0; i < count; ++i) {
+    if (plans[i].kind == PLAN_DIRECT) {
+      direct.push_back(i);
+      continue;
+    }
+    groups[class_key(plans[i], prime_info(pidx[i]).lazy)].push_back(i);
+    wsb += (plan_workspace_bytes(plans[i]) + 255) & ~(size_t)255;
+  }
   if (wsb) {
     st = ensure_workspace(c, wsb);
     if (st) return st;
   }
-  for (size_t i = 0; i < count; ++i) {
-    const pm_problem& q = probs[i];
-    st = run_product(c, plans[i], q.a, (long)q.len_a, q.b, (long)q.len_b, 0, q.c, (long)(q.len_a + q.len_b - 1),
-                     pidx[i], c->ws, (hipStream_t)stream);
-    if (st) return st;
+  std::vector<ClassRun> runs;
+  std::vector<ConvJob> jobs;
+  jobs.reserve(count);
+  char* ws = (char*)c->ws;
+  for (auto& kv : groups) {
+    ClassRun r;
+    r.key = kv.first;
+    r.plan = plans[kv.second[0]];
+    r.lazy = std::get<7>(kv.first) != 0;
+    r.first = (int)jobs.size();
+    r.count = (int)kv.second.size();
+    r.max_rows = 0;
+    for (size_t i : kv.second) {
+      const pm_problem& q = probs[i];
+      const long lc = (long)(q.len_a + q.len_b - 1);
+      u32 *Ta = nullptr, *Tb = nullptr;
+      const size_t w = plan_workspace_bytes(plans[i]);
+      if (w) {
+        Ta = (u32*)ws;
+        Tb = Ta + plan_nprime(plans[i]);
+        ws += (w + 255) & ~(size_t)255;
+      }
+      ConvJob J;
+      st = make_job(c, plans[i], pidx[i], q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, lc, Ta, Tb, &J);
+      if (st) return st;
+      r.max_rows = std::max(r.max_rows, J.rows);
+      jobs.push_back(J);
+    }
+    runs.push_back(r);
   }
+  std::stable_sort(runs.begin(), runs.end(),
+                   [](const ClassRun& x, const ClassRun& y) { return std::get<1>(x.key) > std::get<1>(y.key); });
+
+  for (size_t i : direct) {
+    const pm_problem& q = probs[i];
+    if (launch_direct(q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, pidx[i], c->errflag, s) != hipSuccess)
+      return PM_EDEVICE;
+  }
+  if (jobs.empty()) return PM_OK;
+
+  Signature sig;
+  for (auto& r : runs) sig.emplace_back(r.key, r.count, r.max_rows);
+  auto gkey = std::make_pair(c->dev, sig);
+  GraphEntry* G = nullptr;
+  auto git = B->graphs.find(gkey);
+  if (git == B->graphs.end()) {
+    GraphEntry ge;
+    ge.njobs = jobs.size();
+    if (hipMalloc(&ge.djobs, jobs.size() * sizeof(ConvJob)) != hipSuccess) return PM_ENOMEM;
+    st = capture_graph(B, runs, ge.djobs, &ge.exec);
+    if (st) {
+      hipFree(ge.djobs);
+      return st;
+    }
+    G = &(B->graphs[gkey] = ge);
+  } else {
+    G = &git->second;
+  }
+  // upload the job descriptors (the graph reads them from G->djobs)
+  if (hipEventSynchronize(B->staged) != hipSuccess) return PM_EDEVICE;
+  if (B->staging_cap < jobs.size()) {
+    if (B->staging) hipHostFree(B->staging);
+    B->staging = nullptr;
+    if (hipHostMalloc((void**)&B->staging, jobs.size() * sizeof(ConvJob), hipHostMallocDefault) != hipSuccess) {
+      B->staging_cap = 0;
+      return PM_ENOMEM;
+    }
+    B->staging_cap = jobs.size();
+  }
+  // the device array keeps the class-by-class layout the graph was captured with
+  memcpy(B->staging, jobs.data(), jobs.size() * sizeof(ConvJob));
+  if (hipMemcpyAsync(G->djobs, B->staging, jobs.size() * sizeof(ConvJob), hipMemcpyHostToDevice, s) != hipSuccess)
+    return PM_EDEVICE;
+  if (hipEventRecord(B->staged, s) != hipSuccess) return PM_EDEVICE;
+  TraceScope ts(s, "batch_graph");
+  if (hipGraphLaunch(G->exec, s) != hipSuccess) return PM_EDEVICE;
   return PM_OK;
 }

@@ -59,6 +59,7 @@ Plan default_plan(long lc, int pidx) {
   }
   P.logL = ceil_log2(lc);
   const bool pow2 = (lc & (lc - 1)) == 0;
+  (void)pidx;
   if (P.logL <= 14) {
     P.kind = PLAN_LDS;
     P.logRA = P.logL < 4 ? P.logL : 4;
@@ -70,10 +71,12 @@ Plan default_plan(long lc, int pidx) {
       P.logRA = logR;
       P.logRB = 0;
     } else {
-      P.logRA = (!pow2 || logR - 4 > 5) ? 5 : 4;
+      // the first radix 32 only where it truncates more finely than 16
+      const bool finer = !pow2 && kept_blocks(lc, P.logL, 5) < 2 * kept_blocks(lc, P.logL, 4);
+      P.logRA = (finer || logR - 4 > 5) ? 5 : 4;
       P.logRB = logR - P.logRA;
     }
-    P.lnt = P.logC - 5;
+    P.lnt = P.logC - 5 < 6 ? 6 : P.logC - 5;
   }
   P.ma = kept_blocks(lc, P.logL, P.logRA);
   return P;
@@ -196,30 +199,63 @@ size_t plan_workspace_bytes(const Plan& P) {
   return 2 * (size_t)plan_nprime(P) * sizeof(u32);
 }
 
+// Fill the job of one product with plan P (tables are built on first use).
+// Ta/Tb: the four-step workspace (n' words each) or null for other plans.
+pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
+                   long lc, u32* Ta, u32* Tb, ConvJob* J) {
+  pm_status st = ensure_prime_tables(c, pidx);
+  if (st) return st;
+  const PrimeInfo& PI = prime_info(pidx);
+  memset(J, 0, sizeof(*J));
+  J->a = a;
+  J->b = b;
+  J->la = la;
+  J->lb = lb;
+  J->c = out;
+  J->lc = lc;
+  J->Ta = Ta;
+  J->Tb = Tb;
+  J->ma = P.ma;
+  J->rows = P.ma << P.logRB;
+  J->mp = modp_of(PI);
+  J->T = c->tabs[pidx];
+  J->err = c->errflag;
+  if (P.kind == PLAN_DIRECT) return PM_OK;
+  J->sc = conv_scale(P, pidx);
+  if (P.kind == PLAN_FOURSTEP) return get_row_tables(c, pidx, P.logL, P.logC, plan_row_lnt(P), J->sc.x, &J->W);
+  return PM_OK;
+}
+
+// Launch the passes of plan P over njobs jobs of one class (same plan, same
+// prime range); max_rows bounds J.rows over the jobs.
+pm_status launch_class(const Plan& P, bool lazy, int in_type, const JobRef& jr, int njobs, int max_rows,
+                       hipStream_t s) {
+  hipError_t e;
+  if (P.kind == PLAN_LDS) {
+    e = launch_lds_conv(P, lazy, jr, njobs, s);
+  } else {
+    e = launch_col_fwd(P, lazy, in_type, 2, jr, njobs, s);
+    if (e == hipSuccess) e = launch_row_conv(P, lazy, max_rows, jr, njobs, s);
+    if (e == hipSuccess) e = launch_col_inv(P, lazy, jr, njobs, s);
+  }
+  return dev_status(e);
+}
+
 // run one product with plan P; `ws` has plan_workspace_bytes(P) bytes
 pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const void* b, long lb, int in_type, u32* out,
                       long lc, int pidx, void* ws, hipStream_t s) {
-  pm_status st = ensure_prime_tables(c, pidx);
-  if (st) return st;
-  const PrimeTables& T = c->tabs[pidx];
   if (P.kind == PLAN_DIRECT) {
     if (in_type != 0) return PM_EINVAL;
     return dev_status(launch_direct((const u32*)a, la, (const u32*)b, lb, out, pidx, c->errflag, s));
   }
-  const uint2 sc = conv_scale(P, pidx);
-  if (P.kind == PLAN_LDS) {
-    if (in_type != 0) return PM_EINVAL;
-    return dev_status(launch_lds_conv(P, (const u32*)a, la, (const u32*)b, lb, out, lc, pidx, T, sc, c->errflag, s));
-  }
-  RowTables W;
-  st = get_row_tables(c, pidx, P.logL, P.logC, plan_row_lnt(P), sc.x, &W);
+  if (P.kind == PLAN_LDS && in_type != 0) return PM_EINVAL;
+  u32* Ta = P.kind == PLAN_FOURSTEP ? (u32*)ws : nullptr;
+  u32* Tb = Ta ? Ta + plan_nprime(P) : nullptr;
+  JobRef jr;
+  jr.many = nullptr;
+  pm_status st = make_job(c, P, pidx, a, la, b, lb, out, lc, Ta, Tb, &jr.one);
   if (st) return st;
-  u32* Ta = (u32*)ws;
-  u32* Tb = Ta + plan_nprime(P);
-  hipError_t e = launch_col_fwd(P, a, la, b, lb, in_type, Ta, Tb, pidx, T, c->errflag, s);
-  if (e == hipSuccess) e = launch_row_conv(P, Ta, Tb, Ta, pidx, T, W, s);
-  if (e == hipSuccess) e = launch_col_inv(P, Ta, out, lc, pidx, T, s);
-  return dev_status(e);
+  return launch_class(P, prime_info(pidx).lazy, in_type, jr, 1, jr.one.rows, s);
 }
 
 }  // namespace pm
@@ -418,14 +454,19 @@ pm_status pm_ntt(const uint32_t* x, uint32_t* y, size_t n, uint32_t p, int inver
   u32* T = (u32*)c->ws;
   const int logR = P.logRA + P.logRB;
   hipError_t e;
+  JobRef jr;
+  jr.many = nullptr;
+  st = make_job(c, P, pidx, x, (long)n, nullptr, 0, y, (long)n, T, nullptr, &jr.one);
+  if (st) return st;
+  const bool lazy = prime_info(pidx).lazy;
   if (!inverse) {
-    e = launch_col_fwd(P, x, (long)n, nullptr, 0, 0, T, nullptr, pidx, c->tabs[pidx], c->errflag, s);
+    e = launch_col_fwd(P, lazy, 0, 1, jr, 1, s);
     if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 0, pidx, c->tabs[pidx], S, s);
     if (e == hipSuccess) e = launch_permute(T, y, logR, P.logC, 1, s);
   } else {
     e = launch_permute(x, T, logR, P.logC, 0, s);
     if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 1, pidx, c->tabs[pidx], S, s);
-    if (e == hipSuccess) e = launch_col_inv(P, T, y, (long)n, pidx, c->tabs[pidx], s);
+    if (e == hipSuccess) e = launch_col_inv(P, lazy, jr, 1, s);
   }
   return dev_status(e);
 }
@@ -450,7 +491,11 @@ pm_status pm_tft(const uint32_t* x, size_t z, size_t L, size_t n, uint32_t p, ui
   st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), 1u, &S);
   if (st) return st;
   u32* T = (u32*)c->ws;
-  hipError_t e = launch_col_fwd(P, x, (long)z, nullptr, 0, 0, T, nullptr, pidx, c->tabs[pidx], c->errflag, s);
+  JobRef jr;
+  jr.many = nullptr;
+  st = make_job(c, P, pidx, x, (long)z, nullptr, 0, out, (long)n, T, nullptr, &jr.one);
+  if (st) return st;
+  hipError_t e = launch_col_fwd(P, prime_info(pidx).lazy, 0, 1, jr, 1, s);
   if (e == hipSuccess) e = launch_row_xform(P, T, out, (long)n, 0, pidx, c->tabs[pidx], S, s);
   return dev_status(e);
 }
@@ -477,8 +522,12 @@ pm_status pm_itft(const uint32_t* v, size_t L, size_t n, uint32_t p, uint32_t* o
   st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), sc.x, &S);
   if (st) return st;
   u32* T = (u32*)c->ws;
+  JobRef jr;
+  jr.many = nullptr;
+  st = make_job(c, P, pidx, v, (long)n, nullptr, 0, out, (long)n, T, nullptr, &jr.one);
+  if (st) return st;
   hipError_t e = launch_row_xform(P, v, T, (long)n, 1, pidx, c->tabs[pidx], S, s);
-  if (e == hipSuccess) e = launch_col_inv(P, T, out, (long)n, pidx, c->tabs[pidx], s);
+  if (e == hipSuccess) e = launch_col_inv(P, prime_info(pidx).lazy, jr, 1, s);
   return dev_status(e);
 }
 

@@ -27,39 +27,39 @@
 #include "trace.h"
 
 namespace pm {
+
 constexpr bool kLazy = PM_LAZY != 0;
 
 // ---------------------------------------------------------------------------
 // four-step column pass (forward), one sub-round (R = RA <= 32): one thread
 // per column j2 loads x_{C j1 + j2}, j1 < RA (zero beyond the operand's
 // length), transforms in registers and keeps output rows t < ma.
-// blockIdx.y selects the operand.
+// blockIdx.y selects the operand, blockIdx.z the job.
 
 template <int LRA, bool LAZY, typename TIn>
-__global__ void __launch_bounds__(64) k_col_fwd1(const TIn* __restrict__ a, long za, const TIn* __restrict__ b, long zb,
-                                                u32* __restrict__ Ta, u32* __restrict__ Tb, int logC, int ma, ModP mp,
-                                                PrimeTables T, int* err) {
+__global__ void __launch_bounds__(64) k_col_fwd1(JobRef jr, int logC) {
   constexpr int RA = 1 << LRA;
+  const ConvJob J = load_job(jr);
   const long C = 1l << logC;
   const long j2 = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (j2 >= C) return;
-  const Arith<LAZY> A(mp);
-  const TIn* in = blockIdx.y ? b : a;
-  const long z = blockIdx.y ? zb : za;
-  u32* out = blockIdx.y ? Tb : Ta;
+  const Arith<LAZY> A(J.mp);
+  const TIn* __restrict__ in = (const TIn*)(blockIdx.y ? J.b : J.a);
+  const long z = blockIdx.y ? J.lb : J.la;
+  u32* __restrict__ out = blockIdx.y ? J.Tb : J.Ta;
   u32 x[RA];
   bool bad = false;
 #pragma unroll
   for (int s = 0; s < RA; ++s) {
     const long pos = C * s + j2;
     x[s] = pos < z ? (u32)in[pos] : 0u;
-    bad |= x[s] >= mp.p;
+    bad |= x[s] >= J.mp.p;
   }
-  if (bad) atomicOr(err, 1);
-  dif_reg<RA>(A, x, T.pf);
+  if (bad) atomicOr(J.err, 1);
+  dif_reg<RA>(A, x, J.T.pf);
 #pragma unroll
   for (int t = 0; t < RA; ++t)
-    if (t < ma) out[C * t + j2] = x[t];
+    if (t < J.ma) out[C * t + j2] = x[t];
 }
 
 // four-step column pass (forward), two sub-rounds (R = RA * RB): a work-group
@@ -69,17 +69,17 @@ __global__ void __launch_bounds__(64) k_col_fwd1(const TIn* __restrict__ a, long
 // t = ta RB + tb.  Only blocks ta < ma are carried into sub-round 2.
 
 template <int LRA, int LRB, int LW, bool LAZY, typename TIn>
-__global__ void __launch_bounds__(1024) k_col_fwd2(const TIn* __restrict__ a, long za, const TIn* __restrict__ b,
-                                                   long zb, u32* __restrict__ Ta, u32* __restrict__ Tb, int logC,
-                                                   int ma, ModP mp, PrimeTables T, int* err) {
+__global__ void __launch_bounds__(1024) k_col_fwd2(JobRef jr, int logC) {
   constexpr int RA = 1 << LRA, RB = 1 << LRB, W = 1 << LW, R = RA * RB;
   extern __shared__ u32 sm[];  // [RA][RB][W]
+  const ConvJob J = load_job(jr);
   const long C = 1l << logC;
   const long c0 = (long)blockIdx.x * W;
-  const Arith<LAZY> A(mp);
-  const TIn* in = blockIdx.y ? b : a;
-  const long z = blockIdx.y ? zb : za;
-  u32* out = blockIdx.y ? Tb : Ta;
+  const Arith<LAZY> A(J.mp);
+  const TIn* __restrict__ in = (const TIn*)(blockIdx.y ? J.b : J.a);
+  const long z = blockIdx.y ? J.lb : J.la;
+  u32* __restrict__ out = blockIdx.y ? J.Tb : J.Ta;
+  const int ma = J.ma;
   const int tid = threadIdx.x, nthr = blockDim.x;
   bool bad = false;
   for (int task = tid; task < W * RB; task += nthr) {
@@ -90,19 +90,21 @@ __global__ void __launch_bounds__(1024) k_col_fwd2(const TIn* __restrict__ a, lo
     for (int e = 0; e < RA; ++e) {
       const long pos = C * (j1b + RB * e) + c0 + c;
       x[e] = pos < z ? (u32)in[pos] : 0u;
-      bad |= x[e] >= mp.p;
+      bad |= x[e] >= J.mp.p;
     }
-    dif_reg<RA>(A, x, T.pf);
+    dif_reg<RA>(A, x, J.T.pf);
+    uint2 tw[RA];
+    load_tw<RA>(tw, J.T.rf[LRA - 3] + R + j1b * RA);
 #pragma unroll
     for (int ta = 0; ta < RA; ++ta) {
       if (ta < ma) {
         u32 v = x[ta];
-        if (ta > 0 && j1b > 0) v = A.mul(v, T.rf[LRA - 3][R + j1b * RA + ta]);
+        if (ta > 0) v = A.mul(v, tw[ta]);
         sm[(ta * RB + j1b) * W + c] = v;
       }
     }
   }
-  if (bad) atomicOr(err, 1);
+  if (bad) atomicOr(J.err, 1);
   __syncthreads();
   for (int task = tid; task < W * ma; task += nthr) {
     const int c = task & (W - 1);
@@ -110,7 +112,7 @@ __global__ void __launch_bounds__(1024) k_col_fwd2(const TIn* __restrict__ a, lo
     u32 x[RB];
 #pragma unroll
     for (int j1b = 0; j1b < RB; ++j1b) x[j1b] = sm[(ta * RB + j1b) * W + c];
-    dif_reg<RB>(A, x, T.pf);
+    dif_reg<RB>(A, x, J.T.pf);
 #pragma unroll
     for (int tb = 0; tb < RB; ++tb) out[C * (ta * RB + tb) + c0 + c] = x[tb];
   }
@@ -122,42 +124,40 @@ template <int LR>
 constexpr int col_lw() {
   return LR <= 8 ? 6 : 5;
 }
+template <int LRA, int LRB>
+constexpr int col_threads() {
+  constexpr int W = 1 << col_lw<LRA + LRB>();
+  constexpr int n = W * ((1 << LRB) > (1 << LRA) ? (1 << LRB) : (1 << LRA));
+  return n > 1024 ? 1024 : n;
+}
 
-template <int LRA, int LRB, bool LAZY, typename TIn>
-static hipError_t col_fwd2_launch(const Plan& P, const TIn* a, long za, const TIn* b, long zb, u32* Ta, u32* Tb,
-                                  int nops, const ModP& mp, const PrimeTables& T, int* err, hipStream_t s) {
+template <int LRA, int LRB, typename TIn>
+static hipError_t col_fwd2_launch(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
   constexpr int LW = col_lw<LRA + LRB>();
-  constexpr int W = 1 << LW;
   const long C = 1l << P.logC;
-  const size_t lds = ((size_t)W << (LRA + LRB)) * sizeof(u32);
-  int nthr = W * ((1 << LRB) > (1 << LRA) ? (1 << LRB) : (1 << LRA));
-  if (nthr > 1024) nthr = 1024;
-  auto kern = k_col_fwd2<LRA, LRB, LW, LAZY, TIn>;
+  const size_t lds = ((size_t)1 << (LW + LRA + LRB)) * sizeof(u32);
+  auto kern = k_col_fwd2<LRA, LRB, LW, kLazy, TIn>;
   (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  dim3 grid((unsigned)(C / W), (unsigned)nops);
   TraceScope ts(s, "col_fwd");
-  kern<<<grid, nthr, lds, s>>>(a, za, b, zb, Ta, Tb, P.logC, P.ma, mp, T, err);
+  kern<<<dim3((unsigned)(C >> LW), nops, njobs), col_threads<LRA, LRB>(), lds, s>>>(jr, P.logC);
   return hipGetLastError();
 }
 
-template <int LRA, bool LAZY, typename TIn>
-static hipError_t col_fwd_ra(const Plan& P, const TIn* a, long za, const TIn* b, long zb, u32* Ta, u32* Tb,
-                             const ModP& mp, const PrimeTables& T, int* err, hipStream_t s) {
-  const int nops = b ? 2 : 1;
+template <int LRA, typename TIn>
+static hipError_t col_fwd_ra(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
   const long C = 1l << P.logC;
   if (P.logRB == 0) {
-    dim3 grid((unsigned)((C + 63) / 64), (unsigned)nops);
     TraceScope ts(s, "col_fwd");
-    k_col_fwd1<LRA, LAZY, TIn><<<grid, 64, 0, s>>>(a, za, b, zb, Ta, Tb, P.logC, P.ma, mp, T, err);
+    k_col_fwd1<LRA, kLazy, TIn><<<dim3((unsigned)((C + 63) / 64), nops, njobs), 64, 0, s>>>(jr, P.logC);
     return hipGetLastError();
   }
   if constexpr (LRA >= 4) {
     switch (P.logRB) {
-      case 1: return col_fwd2_launch<LRA, 1, LAZY, TIn>(P, a, za, b, zb, Ta, Tb, nops, mp, T, err, s);
-      case 2: return col_fwd2_launch<LRA, 2, LAZY, TIn>(P, a, za, b, zb, Ta, Tb, nops, mp, T, err, s);
-      case 3: return col_fwd2_launch<LRA, 3, LAZY, TIn>(P, a, za, b, zb, Ta, Tb, nops, mp, T, err, s);
-      case 4: return col_fwd2_launch<LRA, 4, LAZY, TIn>(P, a, za, b, zb, Ta, Tb, nops, mp, T, err, s);
-      case 5: return col_fwd2_launch<LRA, 5, LAZY, TIn>(P, a, za, b, zb, Ta, Tb, nops, mp, T, err, s);
+      case 1: return col_fwd2_launch<LRA, 1, TIn>(P, nops, jr, njobs, s);
+      case 2: return col_fwd2_launch<LRA, 2, TIn>(P, nops, jr, njobs, s);
+      case 3: return col_fwd2_launch<LRA, 3, TIn>(P, nops, jr, njobs, s);
+      case 4: return col_fwd2_launch<LRA, 4, TIn>(P, nops, jr, njobs, s);
+      case 5: return col_fwd2_launch<LRA, 5, TIn>(P, nops, jr, njobs, s);
       default: break;
     }
   }
@@ -165,27 +165,22 @@ static hipError_t col_fwd_ra(const Plan& P, const TIn* a, long za, const TIn* b,
 }
 
 template <typename TIn>
-static hipError_t col_fwd_t(const Plan& P, const TIn* a, long za, const TIn* b, long zb, u32* Ta, u32* Tb, int pidx,
-                            const PrimeTables& T, int* err, hipStream_t s) {
-  const PrimeInfo& PI = prime_info(pidx);
-  const ModP mp = modp_of(PI);
-#define PM_RA(r)                                                                          \
-  case r:                                                                                 \
-    return col_fwd_ra<r, kLazy, TIn>(P, a, za, b, zb, Ta, Tb, mp, T, err, s);
+static hipError_t col_fwd_t(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
   switch (P.logRA) {
-    PM_RA(1) PM_RA(2) PM_RA(3) PM_RA(4) PM_RA(5)
-    default:
-      break;
+    case 1: return col_fwd_ra<1, TIn>(P, nops, jr, njobs, s);
+    case 2: return col_fwd_ra<2, TIn>(P, nops, jr, njobs, s);
+    case 3: return col_fwd_ra<3, TIn>(P, nops, jr, njobs, s);
+    case 4: return col_fwd_ra<4, TIn>(P, nops, jr, njobs, s);
+    case 5: return col_fwd_ra<5, TIn>(P, nops, jr, njobs, s);
+    default: break;
   }
-#undef PM_RA
   return hipErrorInvalidValue;
 }
 
-hipError_t PM_SUFFIX(launch_col_fwd)(const Plan& P, const void* a, long za, const void* b, long zb, int in_type, u32* Ta, u32* Tb,
-                          int pidx, const PrimeTables& T, int* err, hipStream_t s) {
-  if (in_type == 1)
-    return col_fwd_t<uint16_t>(P, (const uint16_t*)a, za, (const uint16_t*)b, zb, Ta, Tb, pidx, T, err, s);
-  return col_fwd_t<u32>(P, (const u32*)a, za, (const u32*)b, zb, Ta, Tb, pidx, T, err, s);
+hipError_t PM_SUFFIX(launch_col_fwd)(const Plan& P, int in_type, int nops, const JobRef& jr, int njobs,
+                                     hipStream_t s) {
+  if (in_type == 1) return col_fwd_t<uint16_t>(P, nops, jr, njobs, s);
+  return col_fwd_t<u32>(P, nops, jr, njobs, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -195,23 +190,27 @@ hipError_t PM_SUFFIX(launch_col_fwd)(const Plan& P, const void* a, long za, cons
 // undoes the Montgomery factor of the product).  One LDS buffer: the last
 // forward round of each operand and the first inverse round stay in
 // registers, so the product never goes back to LDS between the transforms.
+// The result overwrites Ta.
 
 template <int LC, int LQ, int LNT, bool LAZY>
-__global__ void __launch_bounds__(1 << LNT) k_row_conv(const u32* Ta, const u32* __restrict__ Tb, u32* Tc, int logR,
-                                                       ModP mp, PrimeTables T, RowTables W) {
+__global__ void __launch_bounds__(1 << LNT) k_row_conv(JobRef jr, int logR) {
   constexpr int C = 1 << LC;
   constexpr int NT = 1 << LNT;
   constexpr int EPT = C / NT;
-  extern __shared__ u32 sm[];
-  const Arith<LAZY> A(mp);
-  const int tid = threadIdx.x;
+  const ConvJob J = load_job(jr);
   const int row = blockIdx.x;
+  if (row >= J.rows) return;
+  extern __shared__ u32 sm[];
+  const Arith<LAZY> A(J.mp);
+  const int tid = threadIdx.x;
   const u32 k1 = bitrev_n((u32)row, logR);
   const long off = (long)row * C;
-  const uint2 gf = W.gf[k1 * (u32)tid];
-  const uint2 gi = W.gi[k1 * (u32)tid];
-  const uint2* ff = W.ff + (size_t)k1 * EPT;
-  const uint2* fi = W.fi + (size_t)k1 * EPT;
+  u32* Ta = J.Ta;
+  const u32* __restrict__ Tb = J.Tb;
+  const uint2 gf = J.W.gf[k1 * (u32)tid];
+  const uint2 gi = J.W.gi[k1 * (u32)tid];
+  const uint2* ff = J.W.ff + (size_t)k1 * EPT;
+  const uint2* fi = J.W.fi + (size_t)k1 * EPT;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int i = tid + NT * e;
@@ -219,7 +218,7 @@ __global__ void __launch_bounds__(1 << LNT) k_row_conv(const u32* Ta, const u32*
   }
   __syncthreads();
   u32 xa[EPT];
-  dif_lds_to_regs<LC, LQ, LAZY, EPT>(A, sm, C, T, tid, NT, xa);
+  dif_lds_to_regs<LC, LQ, LAZY, EPT>(A, sm, C, J.T, tid, NT, xa);
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -228,41 +227,37 @@ __global__ void __launch_bounds__(1 << LNT) k_row_conv(const u32* Ta, const u32*
   }
   __syncthreads();
   u32 xb[EPT];
-  dif_lds_to_regs<LC, LQ, LAZY, EPT>(A, sm, C, T, tid, NT, xb);
+  dif_lds_to_regs<LC, LQ, LAZY, EPT>(A, sm, C, J.T, tid, NT, xb);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) xa[e] = A.mont(xa[e], xb[e]);
   __syncthreads();
-  dit_regs_to_lds<LC, LQ, LAZY, EPT>(A, sm, C, T, tid, NT, xa);
+  dit_regs_to_lds<LC, LQ, LAZY, EPT>(A, sm, C, J.T, tid, NT, xa);
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int i = tid + NT * e;
-    Tc[off + i] = A.mul(A.mul(sm[lds_ix(i)], gi), fi[e]);
+    Ta[off + i] = A.mul(A.mul(sm[lds_ix(i)], gi), fi[e]);
   }
 }
 
-template <int LC, int LNT, bool LAZY>
-static hipError_t row_conv_inst(const Plan& P, const u32* Ta, const u32* Tb, u32* Tc, const ModP& mp,
-                                const PrimeTables& T, const RowTables& W, hipStream_t s) {
+template <int LC, int LNT>
+static hipError_t row_conv_inst(const Plan& P, int max_rows, const JobRef& jr, int njobs, hipStream_t s) {
   constexpr int C = 1 << LC;
-  const int rows = P.ma << P.logRB;
   const int logR = P.logRA + P.logRB;
   const size_t lds = (size_t)C * sizeof(u32);
-  auto kern = P.lq == 3 ? k_row_conv<LC, 3, LNT, LAZY> : k_row_conv<LC, 4, LNT, LAZY>;
+  auto kern = P.lq == 3 ? k_row_conv<LC, 3, LNT, kLazy> : k_row_conv<LC, 4, LNT, kLazy>;
   (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   TraceScope ts(s, "row_conv");
-  kern<<<rows, 1 << LNT, lds, s>>>(Ta, Tb, Tc, logR, mp, T, W);
+  kern<<<dim3(max_rows, 1, njobs), 1 << LNT, lds, s>>>(jr, logR);
   return hipGetLastError();
 }
 
 template <int LC>
-static hipError_t row_conv_lc(const Plan& P, const u32* Ta, const u32* Tb, u32* Tc, const ModP& mp,
-                              const PrimeTables& T, const RowTables& W, hipStream_t s) {
-  // 16 to 64 elements per thread, 64 to 1024 threads
+static hipError_t row_conv_lc(const Plan& P, int max_rows, const JobRef& jr, int njobs, hipStream_t s) {
   switch (plan_row_lnt(P)) {
-#define PM_NT(n)                                                                                  \
-  case n:                                                                                         \
-    if constexpr (LC - n >= 4 && LC - n <= 6 && n >= 6 && n <= 10)                                \
-      return row_conv_inst<LC, n, kLazy>(P, Ta, Tb, Tc, mp, T, W, s);                             \
+#define PM_NT(n)                                                               \
+  case n:                                                                      \
+    if constexpr (LC - n >= 4 && LC - n <= 6 && n >= 6 && n <= 10)             \
+      return row_conv_inst<LC, n>(P, max_rows, jr, njobs, s);                  \
     break;
     PM_NT(6) PM_NT(7) PM_NT(8) PM_NT(9) PM_NT(10)
 #undef PM_NT
@@ -272,54 +267,57 @@ static hipError_t row_conv_lc(const Plan& P, const u32* Ta, const u32* Tb, u32* 
   return hipErrorInvalidValue;
 }
 
-hipError_t PM_SUFFIX(launch_row_conv)(const Plan& P, const u32* Ta, const u32* Tb, u32* Tc, int pidx,
-                                      const PrimeTables& T, const RowTables& W, hipStream_t s) {
-  const ModP mp = modp_of(prime_info(pidx));
+hipError_t PM_SUFFIX(launch_row_conv)(const Plan& P, int max_rows, const JobRef& jr, int njobs, hipStream_t s) {
   switch (P.logC) {
-#define PM_LC(n) \
-  case n:        \
-    return row_conv_lc<n>(P, Ta, Tb, Tc, mp, T, W, s);
-    PM_LC(10) PM_LC(11) PM_LC(12) PM_LC(13) PM_LC(14)
-#undef PM_LC
-    default:
-      break;
+    case 10: return row_conv_lc<10>(P, max_rows, jr, njobs, s);
+    case 11: return row_conv_lc<11>(P, max_rows, jr, njobs, s);
+    case 12: return row_conv_lc<12>(P, max_rows, jr, njobs, s);
+    case 13: return row_conv_lc<13>(P, max_rows, jr, njobs, s);
+    case 14: return row_conv_lc<14>(P, max_rows, jr, njobs, s);
+    default: break;
   }
   return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
-// four-step column pass (inverse).  One sub-round: thread per column j2
-// gathers rows t < ma, inverts (full length-RA inverse, or the truncated
-// inverse with ma known values), writes coefficients j1 < ma.
+// four-step column pass (inverse), reading Ta.  One sub-round: thread per
+// column j2 gathers rows t < ma, inverts (full length-RA inverse, or the
+// truncated inverse with ma known values), writes coefficients j1 < ma.
 
-template <int LRA, bool LAZY, typename TOut>
-__global__ void __launch_bounds__(64) k_col_inv1(const u32* __restrict__ Tc, TOut* __restrict__ c, long lc, int logC,
-                                                int ma, ModP mp, PrimeTables T) {
+template <int LRA, bool LAZY>
+__global__ void __launch_bounds__(64) k_col_inv1(JobRef jr, int logC) {
   constexpr int RA = 1 << LRA;
+  const ConvJob J = load_job(jr);
   const long C = 1l << logC;
   const long j2 = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (j2 >= C) return;
-  const Arith<LAZY> A(mp);
+  const Arith<LAZY> A(J.mp);
+  const u32* __restrict__ Tc = J.Ta;
+  u32* __restrict__ c = J.c;
+  const int ma = J.ma;
   u32 x[RA];
 #pragma unroll
   for (int t = 0; t < RA; ++t) x[t] = t < ma ? Tc[C * t + j2] : 0u;
-  inv_column<RA, LAZY>(A, x, ma, T);
+  inv_column<RA, LAZY>(A, x, ma, J.T);
 #pragma unroll
   for (int s = 0; s < RA; ++s) {
     const long pos = C * s + j2;
-    if (s < ma && pos < lc) c[pos] = (TOut)A.canon(x[s]);
+    if (s < ma && pos < J.lc) c[pos] = A.canon(x[s]);
   }
 }
 
 // two sub-rounds: inverse of k_col_fwd2
-template <int LRA, int LRB, int LW, bool LAZY, typename TOut>
-__global__ void __launch_bounds__(1024) k_col_inv2(const u32* __restrict__ Tc, TOut* __restrict__ c, long lc, int logC,
-                                                   int ma, ModP mp, PrimeTables T) {
+template <int LRA, int LRB, int LW, bool LAZY>
+__global__ void __launch_bounds__(1024) k_col_inv2(JobRef jr, int logC) {
   constexpr int RA = 1 << LRA, RB = 1 << LRB, W = 1 << LW, R = RA * RB;
   extern __shared__ u32 sm[];  // [RA][RB][W]
+  const ConvJob J = load_job(jr);
   const long C = 1l << logC;
   const long c0 = (long)blockIdx.x * W;
-  const Arith<LAZY> A(mp);
+  const Arith<LAZY> A(J.mp);
+  const u32* __restrict__ Tc = J.Ta;
+  u32* __restrict__ c = J.c;
+  const int ma = J.ma;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int task = tid; task < W * ma; task += nthr) {
     const int cc = task & (W - 1);
@@ -327,7 +325,7 @@ __global__ void __launch_bounds__(1024) k_col_inv2(const u32* __restrict__ Tc, T
     u32 x[RB];
 #pragma unroll
     for (int tb = 0; tb < RB; ++tb) x[tb] = Tc[C * (ta * RB + tb) + c0 + cc];
-    dit_reg<RB>(A, x, T.pi);
+    dit_reg<RB>(A, x, J.T.pi);
 #pragma unroll
     for (int j1b = 0; j1b < RB; ++j1b) sm[(ta * RB + j1b) * W + cc] = x[j1b];
   }
@@ -335,76 +333,69 @@ __global__ void __launch_bounds__(1024) k_col_inv2(const u32* __restrict__ Tc, T
   for (int task = tid; task < W * RB; task += nthr) {
     const int cc = task & (W - 1);
     const int j1b = task >> LW;
+    uint2 tw[RA];
+    load_tw<RA>(tw, J.T.ri[LRA - 3] + R + j1b * RA);
     u32 x[RA];
 #pragma unroll
     for (int ta = 0; ta < RA; ++ta) {
       u32 v = 0;
       if (ta < ma) {
         v = sm[(ta * RB + j1b) * W + cc];
-        if (ta > 0 && j1b > 0) v = A.mul(v, T.ri[LRA - 3][R + j1b * RA + ta]);
+        if (ta > 0) v = A.mul(v, tw[ta]);
       }
       x[ta] = v;
     }
-    inv_column<RA, LAZY>(A, x, ma, T);
+    inv_column<RA, LAZY>(A, x, ma, J.T);
 #pragma unroll
     for (int e = 0; e < RA; ++e) {
       const long pos = C * (j1b + RB * e) + c0 + cc;
-      if (e < ma && pos < lc) c[pos] = (TOut)A.canon(x[e]);
+      if (e < ma && pos < J.lc) c[pos] = A.canon(x[e]);
     }
   }
 }
 
-template <int LRA, int LRB, bool LAZY>
-static hipError_t col_inv2_launch(const Plan& P, const u32* Tc, u32* c, long lc, const ModP& mp,
-                                  const PrimeTables& T, hipStream_t s) {
+template <int LRA, int LRB>
+static hipError_t col_inv2_launch(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
   constexpr int LW = col_lw<LRA + LRB>();
-  constexpr int W = 1 << LW;
   const long C = 1l << P.logC;
-  const size_t lds = ((size_t)W << (LRA + LRB)) * sizeof(u32);
-  int nthr = W * ((1 << LRB) > (1 << LRA) ? (1 << LRB) : (1 << LRA));
-  if (nthr > 1024) nthr = 1024;
-  auto kern = k_col_inv2<LRA, LRB, LW, LAZY, u32>;
+  const size_t lds = ((size_t)1 << (LW + LRA + LRB)) * sizeof(u32);
+  auto kern = k_col_inv2<LRA, LRB, LW, kLazy>;
   (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   TraceScope ts(s, "col_inv");
-  kern<<<(unsigned)(C / W), nthr, lds, s>>>(Tc, c, lc, P.logC, P.ma, mp, T);
+  kern<<<dim3((unsigned)(C >> LW), 1, njobs), col_threads<LRA, LRB>(), lds, s>>>(jr, P.logC);
   return hipGetLastError();
 }
 
-template <int LRA, bool LAZY>
-static hipError_t col_inv_ra(const Plan& P, const u32* Tc, u32* c, long lc, const ModP& mp, const PrimeTables& T,
-                             hipStream_t s) {
+template <int LRA>
+static hipError_t col_inv_ra(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
   const long C = 1l << P.logC;
   if (P.logRB == 0) {
     TraceScope ts(s, "col_inv");
-    k_col_inv1<LRA, LAZY, u32><<<(unsigned)((C + 63) / 64), 64, 0, s>>>(Tc, c, lc, P.logC, P.ma, mp, T);
+    k_col_inv1<LRA, kLazy><<<dim3((unsigned)((C + 63) / 64), 1, njobs), 64, 0, s>>>(jr, P.logC);
     return hipGetLastError();
   }
   if constexpr (LRA >= 4) {
     switch (P.logRB) {
-      case 1: return col_inv2_launch<LRA, 1, LAZY>(P, Tc, c, lc, mp, T, s);
-      case 2: return col_inv2_launch<LRA, 2, LAZY>(P, Tc, c, lc, mp, T, s);
-      case 3: return col_inv2_launch<LRA, 3, LAZY>(P, Tc, c, lc, mp, T, s);
-      case 4: return col_inv2_launch<LRA, 4, LAZY>(P, Tc, c, lc, mp, T, s);
-      case 5: return col_inv2_launch<LRA, 5, LAZY>(P, Tc, c, lc, mp, T, s);
+      case 1: return col_inv2_launch<LRA, 1>(P, jr, njobs, s);
+      case 2: return col_inv2_launch<LRA, 2>(P, jr, njobs, s);
+      case 3: return col_inv2_launch<LRA, 3>(P, jr, njobs, s);
+      case 4: return col_inv2_launch<LRA, 4>(P, jr, njobs, s);
+      case 5: return col_inv2_launch<LRA, 5>(P, jr, njobs, s);
       default: break;
     }
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t PM_SUFFIX(launch_col_inv)(const Plan& P, const u32* Tc, u32* c, long lc, int pidx, const PrimeTables& T,
-                          hipStream_t s) {
-  const PrimeInfo& PI = prime_info(pidx);
-  const ModP mp = modp_of(PI);
-#define PM_RA(r)                                                           \
-  case r:                                                                  \
-    return col_inv_ra<r, kLazy>(P, Tc, c, lc, mp, T, s);
+hipError_t PM_SUFFIX(launch_col_inv)(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
   switch (P.logRA) {
-    PM_RA(1) PM_RA(2) PM_RA(3) PM_RA(4) PM_RA(5)
-    default:
-      break;
+    case 1: return col_inv_ra<1>(P, jr, njobs, s);
+    case 2: return col_inv_ra<2>(P, jr, njobs, s);
+    case 3: return col_inv_ra<3>(P, jr, njobs, s);
+    case 4: return col_inv_ra<4>(P, jr, njobs, s);
+    case 5: return col_inv_ra<5>(P, jr, njobs, s);
+    default: break;
   }
-#undef PM_RA
   return hipErrorInvalidValue;
 }
 

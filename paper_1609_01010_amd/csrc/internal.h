@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/polymul.h"
+#include "job.h"
 #include "ntt_device.h"
 
 namespace pm {
@@ -31,15 +32,6 @@ u32 h_powmod(u32 b, u64 e, u32 p);
 u32 h_inv(u32 a, u32 p);
 uint2 h_shoup(u32 w, u32 p);  // (w, floor(w 2^32 / p))
 
-// Row-pass twiddles of the four-step split for (L, C, nt threads): element
-// j2 = tid + nt e of row k1 is multiplied by gf[k1 tid] * ff[k1 ept + e] =
-// w_L^{k1 j2} (forward) or gi[k1 tid] * fi[k1 ept + e] = w_L^{-k1 j2} * scale.
-struct RowTables {
-  const uint2* gf;
-  const uint2* gi;
-  const uint2* ff;
-  const uint2* fi;
-};
 struct RowKey {
   int pidx, logL, logC, lnt;
   u32 scale;
@@ -96,16 +88,14 @@ inline long plan_nprime(const Plan& P) { return (long)P.ma << (P.logL - P.logRA)
 
 // ---- launchers (return hipSuccess or the launch error) --------------------
 hipError_t launch_direct(const u32* a, long la, const u32* b, long lb, u32* c, int pidx, int* err, hipStream_t s);
-hipError_t launch_lds_conv(const Plan& P, const u32* a, long la, const u32* b, long lb, u32* c, long lc, int pidx,
-                           const PrimeTables& T, uint2 sc, int* err, hipStream_t s);
-// four-step column passes; input element types: 0 = u32, 1 = u16; b == nullptr
-// transforms a alone
-hipError_t launch_col_fwd(const Plan& P, const void* a, long za, const void* b, long zb, int in_type, u32* Ta, u32* Tb,
-                          int pidx, const PrimeTables& T, int* err, hipStream_t s);
-hipError_t launch_row_conv(const Plan& P, const u32* Ta, const u32* Tb, u32* Tc, int pidx, const PrimeTables& T,
-                           const RowTables& W, hipStream_t s);
-hipError_t launch_col_inv(const Plan& P, const u32* Tc, u32* c, long lc, int pidx, const PrimeTables& T,
+// Convolution launches over njobs jobs of one plan class (jobs in jr: the
+// single inline job, or a device array indexed by blockIdx.z).
+hipError_t launch_lds_conv(const Plan& P, bool lazy, const JobRef& jr, int njobs, hipStream_t s);
+// four-step passes; in_type 0 = u32 inputs, 1 = u16; nops = 1 transforms a only
+hipError_t launch_col_fwd(const Plan& P, bool lazy, int in_type, int nops, const JobRef& jr, int njobs,
                           hipStream_t s);
+hipError_t launch_row_conv(const Plan& P, bool lazy, int max_rows, const JobRef& jr, int njobs, hipStream_t s);
+hipError_t launch_col_inv(const Plan& P, bool lazy, const JobRef& jr, int njobs, hipStream_t s);
 // standalone row transforms over rows t < ma * RB: dir 0 = twiddle then
 // forward (outputs at flat index < nout), dir 1 = inverse then untwiddle and
 // multiply by sc

@@ -1,0 +1,42 @@
+// Per-product job descriptor read by the convolution kernels.  A single
+// product passes its job by value in the kernel arguments; a batch passes a
+// device array indexed by blockIdx.z (one class of equal plans per launch).
+#pragma once
+#include "ntt_device.h"
+
+// Row-pass twiddles of the four-step split for (L, C, nt threads): element
+// j2 = tid + nt e of row k1 is multiplied by gf[k1 tid] * ff[k1 ept + e] =
+// w_L^{k1 j2} (forward) or gi[k1 tid] * fi[k1 ept + e] = w_L^{-k1 j2} * scale.
+struct RowTables {
+  const uint2* gf;
+  const uint2* gi;
+  const uint2* ff;
+  const uint2* fi;
+};
+
+struct ConvJob {
+  const void* a;   // operand a (u32, or u16 limbs for the integer product)
+  const void* b;   // operand b
+  long la, lb;     // operand lengths (positions beyond are zero)
+  u32* c;          // la + lb - 1 outputs, canonical
+  long lc;
+  u32* Ta;         // four-step workspace: n' words each
+  u32* Tb;
+  int ma;          // kept blocks of the first radix
+  int rows;        // four-step rows carried: ma * RB
+  ModP mp;
+  PrimeTables T;
+  RowTables W;     // four-step row twiddles (scale folded into fi)
+  uint2 sc;        // one-work-group plans: inverse scale (times 2^32)
+  int* err;        // device error word
+};
+
+struct JobRef {
+  ConvJob one;
+  const ConvJob* many;
+};
+
+__device__ __forceinline__ ConvJob load_job(const JobRef& r) {
+  if (r.many) return r.many[blockIdx.z];
+  return r.one;
+}

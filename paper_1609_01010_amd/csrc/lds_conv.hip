@@ -36,26 +36,26 @@ constexpr bool kLazy = PM_LAZY != 0;
 // output blocks; the remaining rounds transform those blocks in LDS.
 
 template <int LN, int LRA, int LQ, bool LAZY>
-__global__ void __launch_bounds__(1024) k_lds_conv(const u32* __restrict__ a, int la, const u32* __restrict__ b, int lb,
-                                                   u32* __restrict__ c, int lc, int ma, ModP mp, PrimeTables T,
-                                                   uint2 sc, int* err) {
+__global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
   constexpr int N = 1 << LN;
   constexpr int RA = 1 << LRA;
   constexpr int LS = LN - LRA;
   constexpr int S = 1 << LS;
+  const ConvJob J = load_job(jr);
+  const u32* __restrict__ a = (const u32*)J.a;
+  const u32* __restrict__ b = (const u32*)J.b;
+  const int la = (int)J.la, lb = (int)J.lb, lc = (int)J.lc, ma = J.ma;
+  const PrimeTables& T = J.T;
   extern __shared__ u32 sm[];
   u32* sa = sm;
   u32* sb = sm + N;
-  const Arith<LAZY> A(mp);
+  const Arith<LAZY> A(J.mp);
   const int tid = threadIdx.x, nthr = blockDim.x;
   bool bad = false;
 
   for (int j = tid; j < S; j += nthr) {
     uint2 tw[RA];
-    if constexpr (S > 1) {
-#pragma unroll
-      for (int t = 1; t < RA; ++t) tw[t] = T.rf[LRA - 3][N + j * RA + t];
-    }
+    if constexpr (S > 1) load_tw<RA>(tw, T.rf[LRA - 3] + N + j * RA);
 #pragma unroll
     for (int op = 0; op < 2; ++op) {
       const u32* in = op ? b : a;
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(const u32* __restrict__ a, in
       for (int s = 0; s < RA; ++s) {
         const int pos = j + S * s;
         x[s] = pos < len ? in[pos] : 0u;
-        bad |= x[s] >= mp.p;
+        bad |= x[s] >= J.mp.p;
       }
       dif_reg<RA>(A, x, T.pf);
 #pragma unroll
@@ -81,18 +81,21 @@ __global__ void __launch_bounds__(1024) k_lds_conv(const u32* __restrict__ a, in
       }
     }
   }
-  if (bad) atomicOr(err, 1);
+  if (bad) atomicOr(J.err, 1);
   __syncthreads();
   const int nel = ma * S;
   u32* bufs[2] = {sa, sb};
   dif_lds<LS, LQ, LAZY, 2>(A, bufs, nel, T, tid, nthr);
   for (int i = tid; i < nel; i += nthr) {
     const int k = lds_ix(i);
-    sa[k] = A.mul(A.mont(sa[k], sb[k]), sc);
+    sa[k] = A.mul(A.mont(sa[k], sb[k]), J.sc);
   }
   __syncthreads();
   dit_lds<LS, LQ, LAZY>(A, sa, nel, T, tid, nthr);
+  u32* __restrict__ c = J.c;
   for (int j = tid; j < S; j += nthr) {
+    uint2 tw[RA];
+    if constexpr (S > 1) load_tw<RA>(tw, T.ri[LRA - 3] + N + j * RA);
     u32 x[RA];
 #pragma unroll
     for (int t = 0; t < RA; ++t) {
@@ -100,7 +103,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(const u32* __restrict__ a, in
       if (t < ma) {
         v = sa[lds_ix(j + S * t)];
         if constexpr (S > 1) {
-          if (t > 0) v = A.mul(v, T.ri[LRA - 3][N + j * RA + t]);
+          if (t > 0) v = A.mul(v, tw[t]);
         }
       }
       x[t] = v;
@@ -114,28 +117,29 @@ __global__ void __launch_bounds__(1024) k_lds_conv(const u32* __restrict__ a, in
   }
 }
 
-template <int LN, int LRA, bool LAZY>
-static hipError_t lds_conv_inst(const Plan& P, const u32* a, long la, const u32* b, long lb, u32* c, long lc,
-                                const ModP& mp, const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
+// threads of the one-work-group convolution of length 2^ln
+inline int lds_conv_threads(int ln) {
+  int nthr = (1 << ln) / 16;
+  return nthr < 64 ? 64 : (nthr > 1024 ? 1024 : nthr);
+}
+
+template <int LN, int LRA>
+static hipError_t lds_conv_inst(const JobRef& jr, int njobs, hipStream_t s) {
   constexpr int N = 1 << LN;
-  int nthr = N / 16;
-  if (nthr < 64) nthr = 64;
-  if (nthr > 1024) nthr = 1024;
   const size_t lds = 2 * (size_t)N * sizeof(u32);
-  auto kern = k_lds_conv<LN, LRA, 4, LAZY>;
+  auto kern = k_lds_conv<LN, LRA, 4, kLazy>;
   (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   TraceScope ts(s, "lds_conv");
-  kern<<<1, nthr, lds, s>>>(a, (int)la, b, (int)lb, c, (int)lc, P.ma, mp, T, sc, err);
+  kern<<<dim3(1, 1, njobs), lds_conv_threads(LN), lds, s>>>(jr);
   return hipGetLastError();
 }
 
-template <int LN, bool LAZY>
-static hipError_t lds_conv_ra(const Plan& P, const u32* a, long la, const u32* b, long lb, u32* c, long lc,
-                              const ModP& mp, const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
+template <int LN>
+static hipError_t lds_conv_ra(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
   switch (P.logRA) {
-#define PM_RA(r)                                                                                  \
-  case r:                                                                                         \
-    if constexpr (r <= LN) return lds_conv_inst<LN, r, LAZY>(P, a, la, b, lb, c, lc, mp, T, sc, err, s); \
+#define PM_RA(r)                                                                    \
+  case r:                                                                           \
+    if constexpr (r <= LN) return lds_conv_inst<LN, r>(jr, njobs, s);               \
     break;
     PM_RA(3) PM_RA(4) PM_RA(5)
 #undef PM_RA
@@ -145,13 +149,10 @@ static hipError_t lds_conv_ra(const Plan& P, const u32* a, long la, const u32* b
   return hipErrorInvalidValue;
 }
 
-hipError_t PM_SUFFIX(launch_lds_conv)(const Plan& P, const u32* a, long la, const u32* b, long lb, u32* c, long lc, int pidx,
-                           const PrimeTables& T, uint2 sc, int* err, hipStream_t s) {
-  const PrimeInfo& PI = prime_info(pidx);
-  const ModP mp = modp_of(PI);
-#define PM_LN(n)                                                                          \
-  case n:                                                                                 \
-    return lds_conv_ra<n, kLazy>(P, a, la, b, lb, c, lc, mp, T, sc, err, s);
+hipError_t PM_SUFFIX(launch_lds_conv)(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
+#define PM_LN(n) \
+  case n:        \
+    return lds_conv_ra<n>(P, jr, njobs, s);
   switch (P.logL) {
     PM_LN(6) PM_LN(7) PM_LN(8) PM_LN(9) PM_LN(10) PM_LN(11) PM_LN(12) PM_LN(13) PM_LN(14)
     default:

@@ -14,6 +14,9 @@
 namespace pm {
 
 static std::atomic<bool> g_on{false};
+static thread_local bool g_suppress = false;  // no event records while a graph is being captured
+
+void trace_suppress(bool on) { g_suppress = on; }
 static std::mutex g_mu;
 struct Rec {
   std::string name;
@@ -33,7 +36,7 @@ static hipEvent_t take_event() {
   return e;
 }
 
-bool trace_on() { return g_on.load(std::memory_order_relaxed); }
+bool trace_on() { return g_on.load(std::memory_order_relaxed) && !g_suppress; }
 
 TraceScope::TraceScope(hipStream_t s_, const char* name) : s(s_), slot(-1) {
   if (!trace_on()) return;

@@ -187,14 +187,41 @@ def test_int_mul_full_size(gpu_lib):
     assert np.array_equal(got, op.int_mul(a, b))
 
 
-def test_batch_matches_singles(gpu_lib):
+def test_batch_matches_oracle(gpu_lib):
+    """Uneven lengths, mixed primes, one graph launch; the second call with the
+    same shape replays the cached graph with new data."""
     pm = gpu_lib
-    items = inputs.batch_uneven(count=96, lo=64, hi=20000, tag=(105,))
-    say("case: batch 96")
+    for rep, tag in enumerate(((105,), (106,))):
+        items = inputs.batch_uneven(count=96, lo=1, hi=20000, tag=tag)
+        # same shape both times: reuse the first draw's lengths and primes
+        if rep == 1:
+            rng = np.random.default_rng(3)
+            items = [inputs.BatchItem(rng.integers(0, it.p, it.a.size, dtype=np.uint32),
+                                      rng.integers(0, it.p, it.b.size, dtype=np.uint32), it.p) for it in first]
+        first = items
+        say("case: batch 96 rep", rep)
+        outs = pm.poly_mul_batch([(dev(it.a), dev(it.b), it.p) for it in items])
+        assert pm.stream_check() == 0
+        for it, c in zip(items, outs):
+            assert np.array_equal(host(c), op.poly_mul(it.a, it.b, it.p))
+
+
+def test_batch_uneven_4096(gpu_lib):
+    """The full batch: 4096 products, lengths log-uniform in [64, 65536], four
+    primes; every product against the oracle's transform route, and sampled
+    coefficients against the defining sum."""
+    pm = gpu_lib
+    items = inputs.batch_uneven()
+    say("case: batch 4096")
     outs = pm.poly_mul_batch([(dev(it.a), dev(it.b), it.p) for it in items])
     assert pm.stream_check() == 0
-    for it, c in zip(items, outs):
-        assert np.array_equal(host(c), op.poly_mul(it.a, it.b, it.p))
+    rng = np.random.default_rng(4)
+    for k, (it, c) in enumerate(zip(items, outs)):
+        got = host(c)
+        assert np.array_equal(got, op.poly_mul_ntt(it.a, it.b, it.p, inputs.PRIMES[it.p])), k
+        if k % 64 == 0:
+            ks = rng.integers(0, got.size, 8)
+            assert np.array_equal(got[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
 
 
 def test_not_reduced_input_is_reported(gpu_lib):
