@@ -170,6 +170,56 @@ size_t pm_plan_candidates(size_t lc, uint32_t p, pm_plan* out, size_t max_out);
 pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan);
 void pm_plan_cache_clear(void);
 
+/* ---- the autotuner (empirical search) -------------------------------------
+ * The tuner times every candidate plan of an output length on the device
+ * (hipEvents, median of `reps` runs after a warm-up, deterministic inputs)
+ * and records (length, prime, plan, microseconds) in the in-memory timing
+ * database; the fastest plan of each length goes to the plan cache.  This
+ * follows the paper's search over measured running times (section 2.2, and
+ * the autotuned library of section 5).  Synchronous: returns after timing. */
+pm_status pm_tune(const size_t* lcs, size_t n, uint32_t p, int reps, void* stream);
+/* Median running time of one plan for output length lc (synchronous). */
+pm_status pm_time_plan(size_t lc, uint32_t p, const pm_plan* plan, int reps, double* us);
+size_t pm_tune_db_size(void);
+pm_status pm_tune_db_get(size_t i, size_t* lc, uint32_t* p, pm_plan* plan, double* us);
+pm_status pm_tune_db_add(size_t lc, uint32_t p, const pm_plan* plan, double us);
+void pm_tune_db_clear(void);
+/* Text file, one row per line: lc p kind log_l log_ra log_rb log_c ma lq lnt us.
+ * Load appends (tuning resumes from the rows already measured). */
+pm_status pm_tune_db_save(const char* path);
+pm_status pm_tune_db_load(const char* path);
+
+/* ---- the learned cost model -----------------------------------------------
+ * An FP32 perceptron (16 features, two tanh layers of 64, linear output)
+ * predicts the log running time per relaxed coefficient of a (length, plan)
+ * pair; under PM_POLICY_LEARNED the plan with the least predicted time is
+ * used (and cached).  Trained on the timing database by the library's own
+ * forward, backward and Adam kernels. */
+/* Feature vector (16 floats) of a (length, prime, plan). */
+pm_status pm_model_features(size_t lc, uint32_t p, const pm_plan* plan, float* out);
+/* Train on the database for `steps` full-batch Adam steps at rate lr from
+ * the initial weights `init` (pm_mlp_num_params() floats, host; NULL: a
+ * SplitMix64-seeded Glorot-uniform draw).  losses: NULL or `steps` floats. */
+pm_status pm_model_train(const float* init, int steps, float lr, float* losses);
+/* Weights and target normalisation (log us per coefficient: mean, sd). */
+pm_status pm_model_get(float* params, float* mean, float* sd);
+pm_status pm_model_set(const float* params, float mean, float sd);
+/* Predicted natural log of the running time in microseconds of n plans. */
+pm_status pm_model_predict(size_t lc, uint32_t p, const pm_plan* plans, size_t n, double* log_us);
+pm_status pm_model_save(const char* path);
+pm_status pm_model_load(const char* path);
+
+/* The network's kernels on host arrays (test hooks).  Parameter layout
+ * W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3[1]; X is B x 16 row-major;
+ * loss = mean (y - t)^2. */
+size_t pm_mlp_num_params(void);
+pm_status pm_mlp_forward(const float* params, const float* X, int B, float* y);
+pm_status pm_mlp_loss_grad(const float* params, const float* X, const float* t, int B, float* loss, float* grads);
+/* One bias-corrected Adam step (beta1 0.9, beta2 0.999, eps 1e-8) in place. */
+pm_status pm_mlp_adam(float* params, const float* grads, float* m, float* v, int step, float lr);
+/* `steps` Adam steps of full-batch training in place; losses: NULL or steps floats. */
+pm_status pm_mlp_train(float* params, const float* X, const float* t, int B, int steps, float lr, float* losses);
+
 /* ---- tracing ------------------------------------------------------------
  * When enabled, every kernel the library launches is bracketed by two HIP
  * events recorded on its own stream, so kernel durations can be measured in

@@ -91,6 +91,29 @@ SIGNATURES = {
     "pm_plan_candidates": (_sz, [_sz, _u32, ctypes.POINTER(Plan), _sz]),
     "pm_plan_cache_put": (_int, [_sz, _u32, ctypes.POINTER(Plan)]),
     "pm_plan_cache_clear": (None, []),
+    "pm_tune": (_int, [ctypes.POINTER(_sz), _sz, _u32, _int, _vp]),
+    "pm_time_plan": (_int, [_sz, _u32, ctypes.POINTER(Plan), _int, ctypes.POINTER(ctypes.c_double)]),
+    "pm_tune_db_size": (_sz, []),
+    "pm_tune_db_get": (_int, [_sz, ctypes.POINTER(_sz), ctypes.POINTER(_u32), ctypes.POINTER(Plan),
+                              ctypes.POINTER(ctypes.c_double)]),
+    "pm_tune_db_add": (_int, [_sz, _u32, ctypes.POINTER(Plan), ctypes.c_double]),
+    "pm_tune_db_clear": (None, []),
+    "pm_tune_db_save": (_int, [ctypes.c_char_p]),
+    "pm_tune_db_load": (_int, [ctypes.c_char_p]),
+    "pm_model_features": (_int, [_sz, _u32, ctypes.POINTER(Plan), ctypes.POINTER(ctypes.c_float)]),
+    "pm_model_train": (_int, [ctypes.POINTER(ctypes.c_float), _int, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
+    "pm_model_get": (_int, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                            ctypes.POINTER(ctypes.c_float)]),
+    "pm_model_set": (_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_float, ctypes.c_float]),
+    "pm_model_predict": (_int, [_sz, _u32, ctypes.POINTER(Plan), _sz, ctypes.POINTER(ctypes.c_double)]),
+    "pm_model_save": (_int, [ctypes.c_char_p]),
+    "pm_model_load": (_int, [ctypes.c_char_p]),
+    "pm_mlp_num_params": (_sz, []),
+    "pm_mlp_forward": (_int, [ctypes.POINTER(ctypes.c_float)] * 2 + [_int, ctypes.POINTER(ctypes.c_float)]),
+    "pm_mlp_loss_grad": (_int, [ctypes.POINTER(ctypes.c_float)] * 3 + [_int] + [ctypes.POINTER(ctypes.c_float)] * 2),
+    "pm_mlp_adam": (_int, [ctypes.POINTER(ctypes.c_float)] * 4 + [_int, ctypes.c_float]),
+    "pm_mlp_train": (_int, [ctypes.POINTER(ctypes.c_float)] * 3 + [_int, _int, ctypes.c_float,
+                                                                   ctypes.POINTER(ctypes.c_float)]),
     "pm_trace_enable": (None, [_int]),
     "pm_trace_reset": (None, []),
     "pm_trace_query": (_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
@@ -296,3 +319,152 @@ def trace_names():
     buf = ctypes.create_string_buffer(need)
     lib().pm_trace_names(buf, need)
     return [x for x in buf.value.decode().split("\n") if x]
+
+
+# ---------------------------------------------------------------------------
+# the autotuner and the learned cost model
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _f32(a):
+    import numpy as np
+
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def tune(lcs, p: int, reps: int = 5, stream=None):
+    """Time every candidate plan of each output length; fills the database and the plan cache."""
+    arr = (ctypes.c_size_t * len(lcs))(*[int(x) for x in lcs])
+    _check(lib().pm_tune(arr, len(lcs), p, reps, _stream(stream) if stream is not None else None), "pm_tune")
+
+
+def time_plan(lc: int, p: int, plan: Plan, reps: int = 5) -> float:
+    us = ctypes.c_double()
+    _check(lib().pm_time_plan(lc, p, ctypes.byref(plan), reps, ctypes.byref(us)), "pm_time_plan")
+    return us.value
+
+
+def tune_db_rows():
+    """[(lc, p, Plan, us)] of the timing database."""
+    out = []
+    for i in range(lib().pm_tune_db_size()):
+        lc = ctypes.c_size_t()
+        p = ctypes.c_uint32()
+        P = Plan()
+        us = ctypes.c_double()
+        _check(lib().pm_tune_db_get(i, ctypes.byref(lc), ctypes.byref(p), ctypes.byref(P), ctypes.byref(us)))
+        out.append((lc.value, p.value, P, us.value))
+    return out
+
+
+def tune_db_add(lc: int, p: int, plan: Plan, us: float):
+    _check(lib().pm_tune_db_add(lc, p, ctypes.byref(plan), us), "pm_tune_db_add")
+
+
+def tune_db_clear():
+    lib().pm_tune_db_clear()
+
+
+def tune_db_save(path: str):
+    _check(lib().pm_tune_db_save(path.encode()), "pm_tune_db_save")
+
+
+def tune_db_load(path: str):
+    _check(lib().pm_tune_db_load(path.encode()), "pm_tune_db_load")
+
+
+def mlp_num_params() -> int:
+    return int(lib().pm_mlp_num_params())
+
+
+def model_features(lc: int, p: int, plan: Plan):
+    import numpy as np
+
+    f = np.zeros(16, dtype=np.float32)
+    _check(lib().pm_model_features(lc, p, ctypes.byref(plan), _fptr(f)), "pm_model_features")
+    return f
+
+
+def model_train(init=None, steps: int = 2000, lr: float = 3e-3):
+    """Train on the timing database (device kernels); returns the loss per step."""
+    import numpy as np
+
+    losses = np.zeros(steps, dtype=np.float32)
+    ip = _fptr(_f32(init)) if init is not None else None
+    if init is not None:
+        keep = _f32(init)
+        ip = _fptr(keep)
+    _check(lib().pm_model_train(ip, steps, lr, _fptr(losses)), "pm_model_train")
+    return losses
+
+
+def model_get():
+    import numpy as np
+
+    w = np.zeros(mlp_num_params(), dtype=np.float32)
+    mean = ctypes.c_float()
+    sd = ctypes.c_float()
+    _check(lib().pm_model_get(_fptr(w), ctypes.byref(mean), ctypes.byref(sd)), "pm_model_get")
+    return w, mean.value, sd.value
+
+
+def model_set(w, mean: float, sd: float):
+    w = _f32(w)
+    _check(lib().pm_model_set(_fptr(w), mean, sd), "pm_model_set")
+
+
+def model_predict(lc: int, p: int, plans):
+    import numpy as np
+
+    arr = (Plan * len(plans))(*plans)
+    out = np.zeros(len(plans), dtype=np.float64)
+    _check(lib().pm_model_predict(lc, p, arr, len(plans), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "pm_model_predict")
+    return out
+
+
+def model_save(path: str):
+    _check(lib().pm_model_save(path.encode()), "pm_model_save")
+
+
+def model_load(path: str):
+    _check(lib().pm_model_load(path.encode()), "pm_model_load")
+
+
+def mlp_forward(params, X):
+    import numpy as np
+
+    params, X = _f32(params), _f32(X)
+    y = np.zeros(X.shape[0], dtype=np.float32)
+    _check(lib().pm_mlp_forward(_fptr(params), _fptr(X), X.shape[0], _fptr(y)), "pm_mlp_forward")
+    return y
+
+
+def mlp_loss_grad(params, X, t):
+    import numpy as np
+
+    params, X, t = _f32(params), _f32(X), _f32(t)
+    g = np.zeros(mlp_num_params(), dtype=np.float32)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(lib().pm_mlp_loss_grad(_fptr(params), _fptr(X), _fptr(t), X.shape[0], _fptr(loss), _fptr(g)),
+           "pm_mlp_loss_grad")
+    return float(loss[0]), g
+
+
+def mlp_adam(params, grads, m, v, step: int, lr: float):
+    """One Adam step; returns new (params, m, v)."""
+    params, grads, m, v = (_f32(x).copy() for x in (params, grads, m, v))
+    _check(lib().pm_mlp_adam(_fptr(params), _fptr(grads), _fptr(m), _fptr(v), step, lr), "pm_mlp_adam")
+    return params, m, v
+
+
+def mlp_train(params, X, t, steps: int, lr: float):
+    import numpy as np
+
+    params, X, t = _f32(params).copy(), _f32(X), _f32(t)
+    losses = np.zeros(steps, dtype=np.float32)
+    _check(lib().pm_mlp_train(_fptr(params), _fptr(X), _fptr(t), X.shape[0], steps, lr, _fptr(losses)),
+           "pm_mlp_train")
+    return params, losses

@@ -32,6 +32,7 @@ SOURCES = [
     ("capi.cpp", []),
     ("batch.cpp", []),
     ("tune.cpp", []),
+    ("mlp.hip", []),
     ("trace.cpp", []),
 ]
 

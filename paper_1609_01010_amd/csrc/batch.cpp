@@ -16,7 +16,7 @@
 
 namespace pm {
 bool plan_valid(const Plan& P, long lc, int pidx);
-Plan choose_plan(long lc, int pidx);
+Plan choose_plan(long lc, int pidx, DevCtx* c, hipStream_t s);
 size_t plan_workspace_bytes(const Plan& P);
 pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
                    long lc, u32* Ta, u32* Tb, ConvJob* J);
@@ -148,7 +148,7 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
     pidx[i] = prime_index(q.p);
     if (pidx[i] < 0) return PM_EUNSUPPORTED;
     const long lc = (long)(q.len_a + q.len_b - 1);
-    plans[i] = choose_plan(lc, pidx[i]);
+    plans[i] = choose_plan(lc, pidx[i], nullptr, 0);
     if (!plan_valid(plans[i], lc, pidx[i])) return PM_ETOOLARGE;
   }
   pm_status st;

@@ -135,17 +135,38 @@ std::vector<Plan> plan_candidates(long lc, int pidx) {
 }
 
 Plan learned_plan(long lc, int pidx, bool* ok);  // cost model (tune.cpp)
+pm_status tune_one(DevCtx* c, long lc, int pidx, int reps, hipStream_t s, Plan* best_out);
 
-Plan choose_plan(long lc, int pidx) {
-  {
-    std::lock_guard<std::mutex> lk(g_plan_mu);
-    auto it = g_plan_cache.find(std::make_pair(lc, prime_info(pidx).p));
-    if (it != g_plan_cache.end()) return it->second;
-  }
-  if (g_policy == PM_POLICY_LEARNED) {
+void plan_cache_set(long lc, u32 p, const Plan& P) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plan_cache[std::make_pair(lc, p)] = P;
+}
+
+bool plan_cache_get(long lc, u32 p, Plan* P) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto it = g_plan_cache.find(std::make_pair(lc, p));
+  if (it == g_plan_cache.end()) return false;
+  *P = it->second;
+  return true;
+}
+
+// The plan cache first (tuned or recorded plans); then the policy: the cost
+// model's argmin (cached), the exhaustive search of this length when a
+// device context is at hand (the caller holds its lock), or the default.
+Plan choose_plan(long lc, int pidx, DevCtx* c = nullptr, hipStream_t s = 0) {
+  const u32 p = prime_info(pidx).p;
+  Plan P;
+  if (plan_cache_get(lc, p, &P)) return P;
+  if (lc > 64 && g_policy == PM_POLICY_LEARNED) {
     bool ok = false;
-    Plan P = learned_plan(lc, pidx, &ok);
-    if (ok && plan_valid(P, lc, pidx)) return P;
+    P = learned_plan(lc, pidx, &ok);
+    if (ok && plan_valid(P, lc, pidx)) {
+      plan_cache_set(lc, p, P);
+      return P;
+    }
+  }
+  if (lc > 64 && g_policy == PM_POLICY_EXHAUSTIVE && c) {
+    if (tune_one(c, lc, pidx, 5, s, &P) == PM_OK) return P;
   }
   return default_plan(lc, pidx);
 }
@@ -321,7 +342,7 @@ static pm_status product_with(const uint32_t* a, size_t len_a, const uint32_t* b
   DevCtx* ctx = ctx_current(&st);
   if (!ctx) return st;
   std::lock_guard<std::mutex> lk(ctx->mu);
-  Plan P = given ? *given : choose_plan(lc, pidx);
+  Plan P = given ? *given : choose_plan(lc, pidx, ctx, (hipStream_t)stream);
   if (!plan_valid(P, lc, pidx)) return given ? PM_EINVAL : PM_ETOOLARGE;
   const size_t wsb = plan_workspace_bytes(P);
   if (wsb) {

@@ -159,3 +159,34 @@ def split_output_length(lc: int):
     la = (lc + 2) // 2
     lb = lc + 1 - la
     return la, lb
+
+
+# --- cost-model initial weights -------------------------------------------------
+
+MLP_F, MLP_H = 16, 64
+
+
+def mlp_init(tag=7):
+    """Glorot-uniform initial weights of the cost model, flattened in the
+    library's layout W1[H][F], b1[H], W2[H][H], b2[H], W3[H], b3 (float32)."""
+    rng = rng_for(tag)
+    F, H = MLP_F, MLP_H
+    a1 = math.sqrt(6.0 / (F + H))
+    a2 = math.sqrt(6.0 / (2 * H))
+    a3 = math.sqrt(6.0 / (H + 1))
+    parts = [rng.uniform(-a1, a1, H * F), np.zeros(H), rng.uniform(-a2, a2, H * H), np.zeros(H),
+             rng.uniform(-a3, a3, H), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_unflatten(w):
+    """The flat weight vector as the float64 dict the oracle network uses."""
+    F, H = MLP_F, MLP_H
+    w = np.asarray(w, dtype=np.float64)
+    o = 0
+    out = {}
+    for name, shape in (("W1", (H, F)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (1, H)), ("b3", (1,))):
+        n = int(np.prod(shape))
+        out[name] = w[o:o + n].reshape(shape)
+        o += n
+    return out

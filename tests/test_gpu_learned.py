@@ -1,0 +1,155 @@
+"""The tuner and the learned cost model on the GPU.
+
+The network's forward, backward and Adam kernels run in float32 and are
+checked against the oracle's float64 network (oracle/mlp.py) with a relative
+tolerance of 1e-4 per tensor (largest absolute difference over the largest
+reference magnitude): float32 accumulation over at most 64-term dot products
+and a 32-sample batch stays far inside that.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from oracle import poly as op
+from paper_1609_01010_amd import inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _batch(B=32, tag=8):
+    rng = inputs.rng_for(tag)
+    X = rng.uniform(-1, 1, (B, inputs.MLP_F)).astype(np.float32)
+    t = rng.normal(0, 1, B).astype(np.float32)
+    return X, t
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30)
+
+
+def test_mlp_forward_and_gradients_match_oracle(gpu_lib):
+    pm = gpu_lib
+    w = inputs.mlp_init()
+    X, t = _batch()
+    P = inputs.mlp_unflatten(w)
+    y_ref, _ = omlp.forward(P, X)
+    y = pm.mlp_forward(w, X)
+    assert _rel(y, y_ref) <= TOL
+    loss, g = pm.mlp_loss_grad(w, X, t)
+    assert abs(loss - omlp.loss(P, X, t)) <= TOL * abs(omlp.loss(P, X, t))
+    g_ref = omlp.backward(P, X, t)
+    G = inputs.mlp_unflatten(g)
+    for k in omlp.NAMES:
+        say("grad", k, _rel(G[k], g_ref[k]))
+        assert _rel(G[k], g_ref[k]) <= TOL, k
+
+
+def test_mlp_adam_matches_oracle(gpu_lib):
+    pm = gpu_lib
+    w = inputs.mlp_init()
+    X, t = _batch()
+    _, g = pm.mlp_loss_grad(w, X, t)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    P = inputs.mlp_unflatten(w)
+    G = inputs.mlp_unflatten(g)
+    state = {}
+    ref = {k: np.array(P[k]) for k in omlp.NAMES}
+    for step in (1, 2, 3):
+        w, m, v = pm.mlp_adam(w, g, m, v, step, 1e-3)
+        omlp.adam_step(ref, G, state, lr=1e-3)
+    W = inputs.mlp_unflatten(w)
+    for k in omlp.NAMES:
+        assert _rel(W[k], ref[k]) <= TOL, k
+
+
+def test_mlp_training_follows_oracle_and_learns(gpu_lib):
+    pm = gpu_lib
+    w0 = inputs.mlp_init()
+    rng = inputs.rng_for(9)
+    X = rng.uniform(-1, 1, (64, inputs.MLP_F)).astype(np.float32)
+    t = (np.sin(2 * X[:, 0]) + 0.5 * X[:, 1] * X[:, 2]).astype(np.float32)
+    w, losses = pm.mlp_train(w0, X, t, steps=5, lr=1e-3)
+    ref = omlp.train(inputs.mlp_unflatten(w0), X, t, steps=5, lr=1e-3)
+    W = inputs.mlp_unflatten(w)
+    for k in omlp.NAMES:
+        assert _rel(W[k], ref[k]) <= 1e-3, k
+    w, losses = pm.mlp_train(w0, X, t, steps=400, lr=3e-3)
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_tuner_records_every_candidate_and_caches_the_best(gpu_lib):
+    pm = gpu_lib
+    p = 998244353
+    pm.tune_db_clear()
+    pm.plan_cache_clear()
+    lcs = [3000, 70001]
+    pm.tune(lcs, p, reps=3)
+    rows = pm.tune_db_rows()
+    for lc in lcs:
+        mine = [r for r in rows if r[0] == lc]
+        assert len(mine) == len(pm.plan_candidates(lc, p))
+        assert all(r[3] > 0 for r in mine)
+        best = min(mine, key=lambda r: r[3])[2]
+        assert pm.plan_for(lc, p).as_tuple() == best.as_tuple()
+        la, lb = inputs.split_output_length(lc)
+        a, b = inputs.poly_pair((110, lc), la, lb, p)
+        import torch
+
+        c = pm.poly_mul(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), p)
+        assert np.array_equal(c.cpu().numpy(), op.poly_mul(a, b, p))
+    pm.plan_cache_clear()
+
+
+def test_learned_policy_trains_predicts_and_stays_exact(gpu_lib, tmp_path):
+    """A small version of the learned-plan experiment: tune a few lengths,
+    train the network on the device, pick plans for unseen lengths; the
+    products stay bit-exact and the pick is never far from the tuned best."""
+    import torch
+
+    pm = gpu_lib
+    p = 2013265921
+    pm.tune_db_clear()
+    pm.plan_cache_clear()
+    train = [1 << k for k in range(10, 18)] + [1500, 3001, 9000, 23000, 50001, 100003]
+    pm.tune(train, p, reps=3)
+    losses = pm.model_train(inputs.mlp_init(), steps=1500, lr=3e-3)
+    say("loss", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+    # save and load round trip
+    path = str(tmp_path / "model.txt")
+    pm.model_save(path)
+    w, mean, sd = pm.model_get()
+    pm.model_load(path)
+    w2, mean2, sd2 = pm.model_get()
+    assert np.array_equal(w, w2) and mean == mean2 and sd == sd2
+    pm.plan_cache_clear()
+    pm.set_policy(pm.POLICY_LEARNED)
+    try:
+        for lc in (5000, 40000, 150001):
+            P = pm.plan_for(lc, p)
+            cands = pm.plan_candidates(lc, p)
+            pred = pm.model_predict(lc, p, cands)
+            assert P.as_tuple() == cands[int(np.argmin(pred))].as_tuple()
+            la, lb = inputs.split_output_length(lc)
+            a, b = inputs.poly_pair((111, lc), la, lb, p)
+            c = pm.poly_mul(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), p)
+            assert np.array_equal(c.cpu().numpy(), op.poly_mul(a, b, p))
+            t_pick = pm.time_plan(lc, p, P, reps=5)
+            t_best = min(pm.time_plan(lc, p, Q, reps=5) for Q in cands)
+            say("regret", lc, t_pick / t_best - 1)
+            assert t_pick <= 1.5 * t_best
+    finally:
+        pm.set_policy(pm.POLICY_DEFAULT)
+        pm.plan_cache_clear()
