@@ -81,6 +81,98 @@ def cpu_baseline(a2, b2, a3, b3, target_s=10.0):
     }
 
 
+def learned_pick(pm, lc, p, only_truncated=False):
+    """The cost model's pick among the candidate plans (optionally only the
+    relaxed-TFT plans, n' < L)."""
+    cands = pm.plan_candidates(lc, p)
+    if only_truncated:
+        cands = [c for c in cands if c.kind != 0 and (c.ma << (c.log_l - c.log_ra)) < (1 << c.log_l)]
+    pred = pm.model_predict(lc, p, cands)
+    return cands[int(pred.argmin())]
+
+
+def time_calls(torch, fn, reps):
+    """Median milliseconds of fn() over reps runs, HIP events on the current stream."""
+    import numpy as np
+
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def extra_configs(pm, torch, dev, reps=5):
+    """The other workloads, each timed on its own: the 1024 x 1024 product,
+    the three-primes integer product of two 2^21-limb integers, and the batch
+    of 4096 uneven products, plain (a loop of single products with the
+    default plans) against batched (one graph launch, learned plans)."""
+    import numpy as np
+
+    from oracle import poly as op
+    from paper_1609_01010_amd import inputs
+
+    out = {}
+    a, b, p = inputs.single_product_1024()
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    c = torch.empty(2047, dtype=torch.uint32, device=dev)
+    pm.poly_mul(ta, tb, p, out=c)
+    ms = time_calls(torch, lambda: pm.poly_mul(ta, tb, p, out=c), 50)
+    assert np.array_equal(c.cpu().numpy(), op.poly_mul(a, b, p))
+    out["single_1024x1024_p998244353"] = {"us": ms * 1e3, "coeffs_per_s": 2047 / (ms * 1e-3), "bit_exact": True}
+
+    ia, ib = inputs.int_operands()
+    tia, tib = torch.from_numpy(ia).to(dev), torch.from_numpy(ib).to(dev)
+    ic = torch.empty(ia.size + ib.size, dtype=torch.uint16, device=dev)
+    pm.int_mul(tia, tib, out=ic)
+    ms = time_calls(torch, lambda: pm.int_mul(tia, tib, out=ic), reps)
+    got = ic.cpu().numpy()
+    q = (1 << 61) - 1
+    ok = op.limbs_to_int(got) % q == (op.limbs_to_int(ia) % q) * (op.limbs_to_int(ib) % q) % q
+    out["int_mul_2^21x2^21_limbs"] = {"ms": ms, "limbs_per_s": got.size / (ms * 1e-3),
+                                      "check": "product mod 2^61-1 matches" if ok else "MISMATCH"}
+
+    items = inputs.batch_uneven()
+    probs = [(torch.from_numpy(it.a).to(dev), torch.from_numpy(it.b).to(dev), it.p) for it in items]
+    outs = [torch.empty(it.a.size + it.b.size - 1, dtype=torch.uint32, device=dev) for it in items]
+    ncoef = sum(o.numel() for o in outs)
+
+    def plain():
+        for (x, y, pp), o in zip(probs, outs):
+            pm.poly_mul(x, y, pp, out=o)
+
+    pm.set_policy(pm.POLICY_DEFAULT)
+    pm.plan_cache_clear()
+    plain()
+    ms_plain = time_calls(torch, plain, 3)
+    pm.set_policy(pm.POLICY_LEARNED)
+    pm.plan_cache_clear()
+    pm.poly_mul_batch(probs, outs=outs)
+    torch.cuda.synchronize()
+    ms_batch = time_calls(torch, lambda: pm.poly_mul_batch(probs, outs=outs), reps)
+    pm.set_policy(pm.POLICY_DEFAULT)
+    pm.plan_cache_clear()
+    if pm.stream_check() != 0:
+        raise SystemExit("device error in the batch")
+    rng = np.random.default_rng(5)
+    for k in rng.choice(len(items), 16, replace=False):
+        it = items[int(k)]
+        ks = rng.integers(0, outs[int(k)].numel(), 4)
+        assert np.array_equal(outs[int(k)].cpu().numpy()[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
+    out["batch_4096_uneven"] = {
+        "output_coeffs": ncoef,
+        "plain_ms": ms_plain, "plain_coeffs_per_s": ncoef / (ms_plain * 1e-3),
+        "batched_learned_ms": ms_batch, "batched_learned_coeffs_per_s": ncoef / (ms_batch * 1e-3),
+        "speedup": ms_plain / ms_batch,
+    }
+    return out
+
+
 def traffic_from_profiles(kernel_src_hash):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
@@ -102,7 +194,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rotate", type=int, default=8, help="buffer sets rotated over the steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 256 MiB three times (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.empty(1 << 26, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": src.numel() * 4}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library's path runs on a single MI355X and has no "
               "multi-GPU mode (see DESIGN.md for how it would shard). Run with --gpus 1.", file=sys.stderr)
@@ -126,14 +232,17 @@ def main():
     for _ in range(args.rotate):
         sets.append(tuple(torch.from_numpy(x).to(dev) for x in (a2, b2, a3, b3)) +
                     (torch.empty(lc2, dtype=torch.uint32, device=dev), torch.empty(lc3, dtype=torch.uint32, device=dev)))
-    plan2 = pm.plan_for(lc2, P)
-    plan3 = pm.plan_for(lc3, P)
+    # plans: the trained cost model's picks (for the 10^6 product, among the
+    # relaxed-TFT plans only: the workload excludes padding to 2^20)
+    pm.model_load(os.path.join(ROOT, "paper_1609_01010_amd", "data", "cost_model.txt"))
+    plan2 = learned_pick(pm, lc2, P)
+    plan3 = learned_pick(pm, lc3, P, only_truncated=True)
     log("plans:", plan2, plan3)
 
     def step(i):
         ta2, tb2, ta3, tb3, c2, c3 = sets[i % len(sets)]
-        pm.poly_mul(ta2, tb2, P, out=c2)
-        pm.poly_mul(ta3, tb3, P, out=c3)
+        pm.poly_mul(ta2, tb2, P, out=c2, plan=plan2)
+        pm.poly_mul(ta3, tb3, P, out=c3, plan=plan3)
 
     for i in range(args.warmup):
         step(i)
@@ -199,6 +308,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(a2, b2, a3, b3)
+    extra = None
+    if not args.no_extra:
+        del sets
+        torch.cuda.empty_cache()
+        extra = extra_configs(pm, torch, dev)
     out = {
         "metric": "conv coefficients/s",
         "value": value,
@@ -223,6 +337,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "other_configs": extra,
     }
     print(json.dumps(out), flush=True)
 
