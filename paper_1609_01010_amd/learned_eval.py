@@ -6,7 +6,7 @@
 2. The cost model is trained on those rows by the library's own kernels.
 3. On the held-out lengths (2^21..2^24 plus 200 non-power-of-two lengths
    log-uniform in [2^10, 2^24]) the model's pick is compared with the fastest
-   plan of an exhaustive timing of every candidate (the judge), and with the
+   plan found by timing every candidate (exhaustive search), and with the
    default plan (the library without the model).
 
 Regret of a length = t(pick) / t(best) - 1.  Reported: the geometric mean of
