@@ -142,9 +142,18 @@ def extra_configs(pm, torch, dev, reps=5):
     outs = [torch.empty(it.a.size + it.b.size - 1, dtype=torch.uint32, device=dev) for it in items]
     ncoef = sum(o.numel() for o in outs)
 
+    # arguments marshalled once for both: the plain loop makes one C call per
+    # product on the current stream, the batch one C call in all
+    import ctypes
+
+    L = pm.lib()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    args = [(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(y.data_ptr()), y.numel(), pp,
+             ctypes.c_void_p(o.data_ptr()), sp) for (x, y, pp), o in zip(probs, outs)]
+
     def plain():
-        for (x, y, pp), o in zip(probs, outs):
-            pm.poly_mul(x, y, pp, out=o)
+        for a_ in args:
+            L.pm_poly_mul(*a_)
 
     pm.set_policy(pm.POLICY_DEFAULT)
     pm.plan_cache_clear()
@@ -152,9 +161,10 @@ def extra_configs(pm, torch, dev, reps=5):
     ms_plain = time_calls(torch, plain, 3)
     pm.set_policy(pm.POLICY_LEARNED)
     pm.plan_cache_clear()
-    pm.poly_mul_batch(probs, outs=outs)
+    prepared = pm.PreparedBatch(probs, outs=outs)
+    prepared.run()
     torch.cuda.synchronize()
-    ms_batch = time_calls(torch, lambda: pm.poly_mul_batch(probs, outs=outs), reps)
+    ms_batch = time_calls(torch, prepared.run, reps)
     pm.set_policy(pm.POLICY_DEFAULT)
     pm.plan_cache_clear()
     if pm.stream_check() != 0:

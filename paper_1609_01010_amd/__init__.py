@@ -193,24 +193,39 @@ def poly_mul(a, b, p: int, out=None, plan: Plan | None = None, stream=None):
     return out
 
 
+class PreparedBatch:
+    """A batch whose argument array is marshalled once: run() is one C call.
+
+    problems: list of (a, b, p) uint32 device tensors; outs: optional outputs.
+    The library recognises a repeated batch shape and only patches pointers,
+    so repeated run() calls cost one descriptor upload and one graph launch."""
+
+    def __init__(self, problems, outs=None):
+        torch = _torch()
+        self.n = len(problems)
+        self.arr = (Problem * max(self.n, 1))()
+        self.outs = []
+        self._keep = []
+        for i, (a, b, p) in enumerate(problems):
+            la, lb = a.numel(), b.numel()
+            c = outs[i] if outs is not None else torch.empty(la + lb - 1, dtype=torch.uint32, device=a.device)
+            self.arr[i].a = _dev_ptr(a, torch.uint32, "a").value
+            self.arr[i].len_a = la
+            self.arr[i].b = _dev_ptr(b, torch.uint32, "b").value
+            self.arr[i].len_b = lb
+            self.arr[i].p = p
+            self.arr[i].c = _dev_ptr(c, torch.uint32, "c").value
+            self.outs.append(c)
+            self._keep.append((a, b))
+
+    def run(self, stream=None):
+        _check(lib().pm_poly_mul_batch(self.arr, self.n, _stream(stream)), "pm_poly_mul_batch")
+        return self.outs
+
+
 def poly_mul_batch(problems, outs=None, stream=None):
-    """problems: list of (a, b, p); returns the list of products."""
-    torch = _torch()
-    n = len(problems)
-    arr = (Problem * n)()
-    res = []
-    for i, (a, b, p) in enumerate(problems):
-        la, lb = a.numel(), b.numel()
-        c = outs[i] if outs is not None else torch.empty(la + lb - 1, dtype=torch.uint32, device=a.device)
-        arr[i].a = _dev_ptr(a, torch.uint32, "a").value
-        arr[i].len_a = la
-        arr[i].b = _dev_ptr(b, torch.uint32, "b").value
-        arr[i].len_b = lb
-        arr[i].p = p
-        arr[i].c = _dev_ptr(c, torch.uint32, "c").value
-        res.append(c)
-    _check(lib().pm_poly_mul_batch(arr, n, _stream(stream)), "pm_poly_mul_batch")
-    return res
+    """problems: list of (a, b, p); returns the list of products (one graph launch)."""
+    return PreparedBatch(problems, outs).run(stream)
 
 
 def int_mul(a, b, out=None, stream=None):

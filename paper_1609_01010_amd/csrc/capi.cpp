@@ -1,5 +1,6 @@
 // The C ABI (include/polymul.h): argument validation, plan choice, workspace,
 // and the launch sequences of the product, the hooks and the integer product.
+#include <atomic>
 #include <cstring>
 
 #include "internal.h"
@@ -21,6 +22,11 @@ static int ceil_log2(long x) {
 
 static std::mutex g_plan_mu;
 static pm_policy g_policy = PM_POLICY_DEFAULT;
+static std::atomic<unsigned long> g_plan_epoch{1};
+
+// changes whenever a plan choice could change (policy, cache, model)
+unsigned long plan_epoch() { return g_plan_epoch.load(); }
+void plan_epoch_bump() { g_plan_epoch.fetch_add(1); }
 static std::map<std::pair<long, u32>, Plan> g_plan_cache;
 
 bool plan_valid(const Plan& P, long lc, int pidx) {
@@ -140,6 +146,7 @@ pm_status tune_one(DevCtx* c, long lc, int pidx, int reps, hipStream_t s, Plan* 
 void plan_cache_set(long lc, u32 p, const Plan& P) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plan_cache[std::make_pair(lc, p)] = P;
+  plan_epoch_bump();
 }
 
 bool plan_cache_get(long lc, u32 p, Plan* P) {
@@ -367,6 +374,7 @@ pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, s
 pm_status pm_set_policy(pm_policy policy) {
   if (policy != PM_POLICY_DEFAULT && policy != PM_POLICY_EXHAUSTIVE && policy != PM_POLICY_LEARNED) return PM_EINVAL;
   g_policy = policy;
+  plan_epoch_bump();
   return PM_OK;
 }
 
@@ -396,12 +404,14 @@ pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan) {
   if (!plan_valid(P, (long)lc, pidx)) return PM_EINVAL;
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plan_cache[std::make_pair((long)lc, p)] = P;
+  plan_epoch_bump();
   return PM_OK;
 }
 
 void pm_plan_cache_clear(void) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plan_cache.clear();
+  plan_epoch_bump();
 }
 
 pm_status pm_stream_check(void* stream) {

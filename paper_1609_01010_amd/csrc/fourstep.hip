@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(1024) k_col_fwd2(JobRef jr, int logC) {
     }
     dif_reg<RA>(A, x, J.T.pf);
     uint2 tw[RA];
-    load_tw<RA>(tw, J.T.rf[LRA - 3] + R + j1b * RA);
+    load_tw<RA>(tw, J.T.rf[LRA - 1] + R + j1b * RA);
 #pragma unroll
     for (int ta = 0; ta < RA; ++ta) {
       if (ta < ma) {
@@ -118,26 +118,30 @@ __global__ void __launch_bounds__(1024) k_col_fwd2(JobRef jr, int logC) {
   }
 }
 
-// columns per work-group of the two-sub-round passes: 64 for R <= 2^8,
-// else 32 (LDS = R * W * 4 bytes, at most 128 KB)
-template <int LR>
+// Columns per work-group of the two-sub-round passes: W RB = 1024 first-
+// round tasks (one per thread) unless the LDS tile W R words would exceed
+// 64 KB, and at least 32 columns (128-byte row segments); at most 128 KB.
+template <int LRA, int LRB>
 constexpr int col_lw() {
-  return LR <= 8 ? 6 : 5;
+  constexpr int a = 10 - LRB;
+  constexpr int b = 14 - LRA - LRB;
+  constexpr int w = a < b ? a : b;
+  return w < 5 ? 5 : w;
 }
 template <int LRA, int LRB>
 constexpr int col_threads() {
-  constexpr int W = 1 << col_lw<LRA + LRB>();
-  constexpr int n = W * ((1 << LRB) > (1 << LRA) ? (1 << LRB) : (1 << LRA));
+  constexpr int n = (1 << col_lw<LRA, LRB>()) << LRB;
   return n > 1024 ? 1024 : n;
 }
 
 template <int LRA, int LRB, typename TIn>
 static hipError_t col_fwd2_launch(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
-  constexpr int LW = col_lw<LRA + LRB>();
+  constexpr int LW = col_lw<LRA, LRB>();
   const long C = 1l << P.logC;
+  if (C < (1l << LW)) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << (LW + LRA + LRB)) * sizeof(u32);
   auto kern = k_col_fwd2<LRA, LRB, LW, kLazy, TIn>;
-  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  ensure_lds_attr((const void*)kern, lds);
   TraceScope ts(s, "col_fwd");
   kern<<<dim3((unsigned)(C >> LW), nops, njobs), col_threads<LRA, LRB>(), lds, s>>>(jr, P.logC);
   return hipGetLastError();
@@ -187,20 +191,54 @@ hipError_t PM_SUFFIX(launch_col_fwd)(const Plan& P, int in_type, int nops, const
 // four-step row pass of the convolution: row t (k1 = rev(t)) of both
 // operands, twiddle by w_L^{j2 k1}, length-C transforms, pointwise product,
 // inverse transform, untwiddle by w_L^{-j2 k1} times the scale (which also
-// undoes the Montgomery factor of the product).  One LDS buffer: the last
-// forward round of each operand and the first inverse round stay in
-// registers, so the product never goes back to LDS between the transforms.
-// The result overwrites Ta.
+// undoes the Montgomery factor of the product).  The result overwrites Ta.
+//
+// Thread tid loads elements tid + NT e (coalesced), so its EPT = C / NT
+// values are exactly one group of the outermost radix-EPT round: that round
+// runs in registers straight after the load, and its inverse straight before
+// the store.  The innermost round (contiguous groups) also stays in
+// registers, so the product is formed and inverted there without a trip
+// through LDS.  Only the rounds between cross LDS.  NB = 2 keeps both operands
+// in LDS at once so their rounds share barriers; NB = 1 (the largest rows)
+// transforms them one after the other in one buffer.
 
-template <int LC, int LQ, int LNT, bool LAZY>
+template <int LC, int LE, bool LAZY>
+__device__ __forceinline__ void row_twist_fwd(const Arith<LAZY>& A, u32 (&x)[1 << LE], uint2 g,
+                                              const uint2* __restrict__ f, const PrimeTables& T, int tid) {
+#pragma unroll
+  for (int e = 0; e < (1 << LE); ++e) x[e] = A.mul(A.mul(x[e], g), f[e]);
+  dif_top_reg<LC, LE, LAZY>(A, x, T, tid);
+}
+
+template <int LQL, int EPT, bool LAZY>
+__device__ __forceinline__ void row_last_fwd(const Arith<LAZY>& A, const u32* buf, u32 (&x)[EPT],
+                                             const PrimeTables& T, int tid, int nthr) {
+  constexpr int QL = 1 << LQL;
+#pragma unroll
+  for (int u = 0; u < EPT / QL; ++u) {
+    u32 y[QL];
+    lds_load_contig<QL>(buf, (tid + nthr * u) * QL, y);
+    dif_reg<QL>(A, y, T.pf);
+#pragma unroll
+    for (int t = 0; t < QL; ++t) x[u * QL + t] = y[t];
+  }
+}
+
+template <int LC, int LQ, int LNT, int NB, bool LAZY>
 __global__ void __launch_bounds__(1 << LNT) k_row_conv(JobRef jr, int logR) {
   constexpr int C = 1 << LC;
   constexpr int NT = 1 << LNT;
-  constexpr int EPT = C / NT;
+  constexpr int LE = LC - LNT;
+  constexpr int EPT = 1 << LE;
+  constexpr int LQL = last_lb<LNT, LQ>();
+  constexpr int QL = 1 << LQL;
+  static_assert(QL <= EPT, "innermost round wider than a thread's share");
   const ConvJob J = load_job(jr);
   const int row = blockIdx.x;
   if (row >= J.rows) return;
   extern __shared__ u32 sm[];
+  u32* const sa = sm;
+  u32* const sb = sm + (NB - 1) * C;
   const Arith<LAZY> A(J.mp);
   const int tid = threadIdx.x;
   const u32 k1 = bitrev_n((u32)row, logR);
@@ -208,44 +246,75 @@ __global__ void __launch_bounds__(1 << LNT) k_row_conv(JobRef jr, int logR) {
   u32* Ta = J.Ta;
   const u32* __restrict__ Tb = J.Tb;
   const uint2 gf = J.W.gf[k1 * (u32)tid];
-  const uint2 gi = J.W.gi[k1 * (u32)tid];
   const uint2* ff = J.W.ff + (size_t)k1 * EPT;
+  // b's row is fetched up front (its latency hides behind a's rounds) unless
+  // 1024 threads leave too few registers to hold it meanwhile
+  constexpr bool kPrefetchB = NB == 2 || LNT < 10;
+  u32 xa[EPT], xb[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    xa[e] = Ta[off + tid + NT * e];
+    if constexpr (kPrefetchB) xb[e] = Tb[off + tid + NT * e];
+  }
+  row_twist_fwd<LC, LE, LAZY>(A, xa, gf, ff, J.T, tid);
+#pragma unroll
+  for (int t = 0; t < EPT; ++t) sa[lds_ix(tid + NT * t)] = xa[t];
+  if constexpr (NB == 2) {
+    row_twist_fwd<LC, LE, LAZY>(A, xb, gf, ff, J.T, tid);
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) sb[lds_ix(tid + NT * t)] = xb[t];
+  }
+  __syncthreads();
+  if constexpr (NB == 2) {
+    u32* bufs[2] = {sa, sb};
+    dif_lds_upto<LNT, LQL, LQ, LAZY, 2>(A, bufs, C, J.T, tid, NT);
+    row_last_fwd<LQL, EPT, LAZY>(A, sa, xa, J.T, tid, NT);
+    row_last_fwd<LQL, EPT, LAZY>(A, sb, xb, J.T, tid, NT);
+  } else {
+    u32* bufs[1] = {sa};
+    dif_lds_upto<LNT, LQL, LQ, LAZY, 1>(A, bufs, C, J.T, tid, NT);
+    row_last_fwd<LQL, EPT, LAZY>(A, sa, xa, J.T, tid, NT);
+    if constexpr (!kPrefetchB) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) xb[e] = Tb[off + tid + NT * e];
+    }
+    __syncthreads();
+    row_twist_fwd<LC, LE, LAZY>(A, xb, gf, ff, J.T, tid);
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) sa[lds_ix(tid + NT * t)] = xb[t];
+    __syncthreads();
+    dif_lds_upto<LNT, LQL, LQ, LAZY, 1>(A, bufs, C, J.T, tid, NT);
+    row_last_fwd<LQL, EPT, LAZY>(A, sa, xb, J.T, tid, NT);
+  }
+  // pointwise product and the innermost inverse round; each thread writes
+  // back exactly the LDS words it read last, so no barrier is needed first
+#pragma unroll
+  for (int u = 0; u < EPT / QL; ++u) {
+    u32 y[QL];
+#pragma unroll
+    for (int t = 0; t < QL; ++t) y[t] = A.mont(xa[u * QL + t], xb[u * QL + t]);
+    dit_reg<QL>(A, y, J.T.pi);
+    lds_store_contig<QL>(sa, (tid + NT * u) * QL, y);
+  }
+  __syncthreads();
+  dit_lds_from<LNT, LQL, LQ, LAZY>(A, sa, C, J.T, tid, NT);
+#pragma unroll
+  for (int t = 0; t < EPT; ++t) xa[t] = sa[lds_ix(tid + NT * t)];
+  dit_top_reg<LC, LE, LAZY>(A, xa, J.T, tid);
+  const uint2 gi = J.W.gi[k1 * (u32)tid];
   const uint2* fi = J.W.fi + (size_t)k1 * EPT;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int i = tid + NT * e;
-    sm[lds_ix(i)] = A.mul(A.mul(Ta[off + i], gf), ff[e]);
-  }
-  __syncthreads();
-  u32 xa[EPT];
-  dif_lds_to_regs<LC, LQ, LAZY, EPT>(A, sm, C, J.T, tid, NT, xa);
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int i = tid + NT * e;
-    sm[lds_ix(i)] = A.mul(A.mul(Tb[off + i], gf), ff[e]);
-  }
-  __syncthreads();
-  u32 xb[EPT];
-  dif_lds_to_regs<LC, LQ, LAZY, EPT>(A, sm, C, J.T, tid, NT, xb);
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) xa[e] = A.mont(xa[e], xb[e]);
-  __syncthreads();
-  dit_regs_to_lds<LC, LQ, LAZY, EPT>(A, sm, C, J.T, tid, NT, xa);
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int i = tid + NT * e;
-    Ta[off + i] = A.mul(A.mul(sm[lds_ix(i)], gi), fi[e]);
-  }
+  for (int e = 0; e < EPT; ++e) Ta[off + tid + NT * e] = A.mul(A.mul(xa[e], gi), fi[e]);
 }
 
 template <int LC, int LNT>
 static hipError_t row_conv_inst(const Plan& P, int max_rows, const JobRef& jr, int njobs, hipStream_t s) {
   constexpr int C = 1 << LC;
+  constexpr int NB = LC <= 13 ? 2 : 1;
   const int logR = P.logRA + P.logRB;
-  const size_t lds = (size_t)C * sizeof(u32);
-  auto kern = P.lq == 3 ? k_row_conv<LC, 3, LNT, kLazy> : k_row_conv<LC, 4, LNT, kLazy>;
-  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const size_t lds = (size_t)NB * C * sizeof(u32);
+  auto kern = P.lq == 3 ? k_row_conv<LC, 3, LNT, NB, kLazy> : k_row_conv<LC, 4, LNT, NB, kLazy>;
+  ensure_lds_attr((const void*)kern, lds);
   TraceScope ts(s, "row_conv");
   kern<<<dim3(max_rows, 1, njobs), 1 << LNT, lds, s>>>(jr, logR);
   return hipGetLastError();
@@ -334,7 +403,7 @@ __global__ void __launch_bounds__(1024) k_col_inv2(JobRef jr, int logC) {
     const int cc = task & (W - 1);
     const int j1b = task >> LW;
     uint2 tw[RA];
-    load_tw<RA>(tw, J.T.ri[LRA - 3] + R + j1b * RA);
+    load_tw<RA>(tw, J.T.ri[LRA - 1] + R + j1b * RA);
     u32 x[RA];
 #pragma unroll
     for (int ta = 0; ta < RA; ++ta) {
@@ -356,11 +425,12 @@ __global__ void __launch_bounds__(1024) k_col_inv2(JobRef jr, int logC) {
 
 template <int LRA, int LRB>
 static hipError_t col_inv2_launch(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
-  constexpr int LW = col_lw<LRA + LRB>();
+  constexpr int LW = col_lw<LRA, LRB>();
   const long C = 1l << P.logC;
+  if (C < (1l << LW)) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << (LW + LRA + LRB)) * sizeof(u32);
   auto kern = k_col_inv2<LRA, LRB, LW, kLazy>;
-  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  ensure_lds_attr((const void*)kern, lds);
   TraceScope ts(s, "col_inv");
   kern<<<dim3((unsigned)(C >> LW), 1, njobs), col_threads<LRA, LRB>(), lds, s>>>(jr, P.logC);
   return hipGetLastError();

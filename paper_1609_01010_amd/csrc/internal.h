@@ -13,6 +13,18 @@
 
 namespace pm {
 
+// Raise a kernel's dynamic LDS limit once (the attribute persists; setting it
+// on every launch costs host time on the latency-bound small products).
+inline void ensure_lds_attr(const void* kern, size_t bytes) {
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = done.find(kern);
+  if (it != done.end() && it->second >= bytes) return;
+  (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  done[kern] = bytes;
+}
+
 // the four supported primes p = c * 2^k + 1 with a primitive root g
 struct PrimeInfo {
   u32 p;

@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
 
   for (int j = tid; j < S; j += nthr) {
     uint2 tw[RA];
-    if constexpr (S > 1) load_tw<RA>(tw, T.rf[LRA - 3] + N + j * RA);
+    if constexpr (S > 1) load_tw<RA>(tw, T.rf[LRA - 1] + N + j * RA);
 #pragma unroll
     for (int op = 0; op < 2; ++op) {
       const u32* in = op ? b : a;
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
   u32* __restrict__ c = J.c;
   for (int j = tid; j < S; j += nthr) {
     uint2 tw[RA];
-    if constexpr (S > 1) load_tw<RA>(tw, T.ri[LRA - 3] + N + j * RA);
+    if constexpr (S > 1) load_tw<RA>(tw, T.ri[LRA - 1] + N + j * RA);
     u32 x[RA];
 #pragma unroll
     for (int t = 0; t < RA; ++t) {
@@ -128,7 +128,7 @@ static hipError_t lds_conv_inst(const JobRef& jr, int njobs, hipStream_t s) {
   constexpr int N = 1 << LN;
   const size_t lds = 2 * (size_t)N * sizeof(u32);
   auto kern = k_lds_conv<LN, LRA, 4, kLazy>;
-  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  ensure_lds_attr((const void*)kern, lds);
   TraceScope ts(s, "lds_conv");
   kern<<<dim3(1, 1, njobs), lds_conv_threads(LN), lds, s>>>(jr);
   return hipGetLastError();

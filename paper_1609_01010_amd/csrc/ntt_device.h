@@ -14,8 +14,8 @@
 //   pi[2^s + x] = the same for w_{2^s}^{-x}
 //   ph[2^s + x] = w_{2^s}^{-x} / 2                                 s <= 5
 //   iv[k]       = 2^-k                                             k <= 32
-// Round tables, for radix Q = 2^q (q = 3, 4, 5), level B = 2^s >= Q:
-//   rf[q-3][B + j Q + t] = w_B^{j rev_q(t)},  j < B/Q, t < Q   (ri: w_B^{-j rev_q(t)})
+// Round tables, for radix Q = 2^q (q = 1 .. 6), level B = 2^s >= Q:
+//   rf[q-1][B + j Q + t] = w_B^{j rev_q(t)},  j < B/Q, t < Q   (ri: w_B^{-j rev_q(t)})
 // so the Q twiddles of one group of an LDS round are 8Q contiguous bytes.
 #pragma once
 #include "arith.h"
@@ -25,6 +25,7 @@ constexpr int kPyrSize = 1 << (kPyrLog + 1);
 constexpr int kHalfLog = 5;
 constexpr int kHalfSize = 1 << (kHalfLog + 1);
 constexpr int kInvPow = 33;
+constexpr int kRoundTables = 6;  // radices 2 .. 64
 
 // all per-prime constants the kernels read, in one device allocation
 struct PrimeTables {
@@ -32,8 +33,8 @@ struct PrimeTables {
   const uint2* pi;
   const uint2* ph;
   const uint2* iv;
-  const uint2* rf[3];
-  const uint2* ri[3];
+  const uint2* rf[kRoundTables];
+  const uint2* ri[kRoundTables];
 };
 
 // ---------------------------------------------------------------------------
@@ -226,7 +227,7 @@ __device__ __forceinline__ void dif_round_lds(const Arith<LAZY>& A, u32* const* 
     const int j = g & (S - 1);
     const int base = ((g >> (LB - LQ)) << LB) + j;
     uint2 tw[Q];
-    if constexpr (S > 1) load_tw<Q>(tw, T.rf[LQ - 3] + (1 << LB) + j * Q);
+    if constexpr (S > 1) load_tw<Q>(tw, T.rf[LQ - 1] + (1 << LB) + j * Q);
 #pragma unroll
     for (int bi = 0; bi < NBUF; ++bi) {
       u32* buf = bufs[bi];
@@ -264,7 +265,7 @@ __device__ __forceinline__ void dit_round_lds(const Arith<LAZY>& A, u32* buf, in
       lds_load_contig<Q>(buf, base, x);
     } else {
       uint2 tw[Q];
-      load_tw<Q>(tw, T.ri[LQ - 3] + (1 << LB) + j * Q);
+      load_tw<Q>(tw, T.ri[LQ - 1] + (1 << LB) + j * Q);
 #pragma unroll
       for (int t = 0; t < Q; ++t) x[t] = buf[lds_ix(base + S * t)];
 #pragma unroll
@@ -312,15 +313,16 @@ __device__ __forceinline__ void dit_lds(const Arith<LAZY>& A, u32* buf, int n_el
   }
 }
 
-// forward rounds on blocks of size 2^LB down to block size 2^LSTOP; ends with a barrier
-template <int LB, int LSTOP, int LQMAX, bool LAZY>
+// forward rounds on blocks of size 2^LB down to block size 2^LSTOP, in each
+// of NBUF buffers; ends with a barrier (none if there is no round)
+template <int LB, int LSTOP, int LQMAX, bool LAZY, int NBUF = 1>
 __device__ __forceinline__ void dif_lds_upto(const Arith<LAZY>& A, u32* const* bufs, int n_el, const PrimeTables& T,
                                              int tid, int nthr) {
   if constexpr (LB > LSTOP) {
     constexpr int LQ = round_lq<LB, LQMAX>();
-    dif_round_lds<LB, LQ, LAZY, 1>(A, bufs, n_el, T, tid, nthr);
+    dif_round_lds<LB, LQ, LAZY, NBUF>(A, bufs, n_el, T, tid, nthr);
     __syncthreads();
-    dif_lds_upto<LB - LQ, LSTOP, LQMAX, LAZY>(A, bufs, n_el, T, tid, nthr);
+    dif_lds_upto<LB - LQ, LSTOP, LQMAX, LAZY, NBUF>(A, bufs, n_el, T, tid, nthr);
   }
 }
 
@@ -388,4 +390,38 @@ __device__ __forceinline__ void dit_regs_to_lds(const Arith<LAZY>& A, u32* buf, 
   }
   __syncthreads();
   if constexpr (LB > LQL) dit_lds_from<LB, LQL, LQMAX, LAZY>(A, buf, n_el, T, tid, nthr);
+}
+
+// ---------------------------------------------------------------------------
+// The outermost round of a transform of size B = 2^LB done in registers, for
+// a thread that holds x[s] = element tid + (B/Q) s, Q = 2^LQ (the layout of a
+// coalesced load by B/Q threads).  Forward: DFT over s, then slot t times
+// w_B^{tid rev(t)}; slot t then belongs at position tid + (B/Q) t, the start
+// of the Q sub-blocks of size B/Q (the first round of dif_lds, without LDS).
+template <int LB, int LQ, bool LAZY>
+__device__ __forceinline__ void dif_top_reg(const Arith<LAZY>& A, u32 (&x)[1 << LQ], const PrimeTables& T, int tid) {
+  constexpr int Q = 1 << LQ;
+  dif_reg<Q>(A, x, T.pf);
+  const uint4* tw = reinterpret_cast<const uint4*>(T.rf[LQ - 1] + (1 << LB) + tid * Q);
+#pragma unroll
+  for (int k = 0; k < Q / 2; ++k) {
+    const uint4 v = tw[k];
+    if (k > 0) x[2 * k] = A.mul(x[2 * k], make_uint2(v.x, v.y));
+    x[2 * k + 1] = A.mul(x[2 * k + 1], make_uint2(v.z, v.w));
+  }
+}
+
+// Mirror of dif_top_reg (the last round of dit_lds, unscaled): x[t] holds
+// position tid + (B/Q) t; on return x[s] is element tid + (B/Q) s.
+template <int LB, int LQ, bool LAZY>
+__device__ __forceinline__ void dit_top_reg(const Arith<LAZY>& A, u32 (&x)[1 << LQ], const PrimeTables& T, int tid) {
+  constexpr int Q = 1 << LQ;
+  const uint4* tw = reinterpret_cast<const uint4*>(T.ri[LQ - 1] + (1 << LB) + tid * Q);
+#pragma unroll
+  for (int k = 0; k < Q / 2; ++k) {
+    const uint4 v = tw[k];
+    if (k > 0) x[2 * k] = A.mul(x[2 * k], make_uint2(v.x, v.y));
+    x[2 * k + 1] = A.mul(x[2 * k + 1], make_uint2(v.z, v.w));
+  }
+  dit_reg<Q>(A, x, T.pi);
 }

@@ -169,16 +169,16 @@ DevCtx* ctx_current(pm_status* st) {
 pm_status ensure_prime_tables(DevCtx* c, int pidx) {
   if (c->prime_mem[pidx]) return PM_OK;
   const PrimeInfo& P = prime_info(pidx);
-  // pf, pi, ph, iv, then six round tables (Q = 8, 16, 32; both directions)
+  // pf, pi, ph, iv, then the round tables (Q = 2 .. 32; both directions)
   const size_t head = 2 * (size_t)kPyrSize + kHalfSize + kInvPow;
   const size_t head_al = (head + 63) & ~(size_t)63;
-  const size_t n = head_al + 6 * (size_t)kPyrSize;
+  const size_t n = head_al + 2 * kRoundTables * (size_t)kPyrSize;
   uint2* mem = nullptr;
   if (hipMalloc(&mem, n * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
   k_fill_pyramids<<<kPyrSize / 256, 256>>>(mem, P.p, P.g);
-  for (int q = 0; q < 3; ++q) {
-    k_fill_round_table<<<kPyrSize / 256, 256>>>(mem + head_al + (2 * q) * kPyrSize, P.p, P.g, q + 3, 0);
-    k_fill_round_table<<<kPyrSize / 256, 256>>>(mem + head_al + (2 * q + 1) * kPyrSize, P.p, P.g, q + 3, 1);
+  for (int q = 0; q < kRoundTables; ++q) {
+    k_fill_round_table<<<kPyrSize / 256, 256>>>(mem + head_al + (2 * q) * kPyrSize, P.p, P.g, q + 1, 0);
+    k_fill_round_table<<<kPyrSize / 256, 256>>>(mem + head_al + (2 * q + 1) * kPyrSize, P.p, P.g, q + 1, 1);
   }
   if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     hipFree(mem);
@@ -189,7 +189,7 @@ pm_status ensure_prime_tables(DevCtx* c, int pidx) {
   c->tabs[pidx].pi = mem + kPyrSize;
   c->tabs[pidx].ph = mem + 2 * kPyrSize;
   c->tabs[pidx].iv = mem + 2 * kPyrSize + kHalfSize;
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < kRoundTables; ++q) {
     c->tabs[pidx].rf[q] = mem + head_al + (2 * q) * kPyrSize;
     c->tabs[pidx].ri[q] = mem + head_al + (2 * q + 1) * kPyrSize;
   }

@@ -25,6 +25,7 @@ pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const vo
 void plan_cache_set(long lc, u32 p, const Plan& P);
 bool plan_cache_get(long lc, u32 p, Plan* P);
 Plan default_plan(long lc, int pidx);
+void plan_epoch_bump();
 
 struct DbRow {
   long lc;
@@ -388,6 +389,7 @@ pm_status pm_model_train(const float* init, int steps, float lr, float* losses) 
   g_model.mean = (float)mean;
   g_model.std = (float)sd;
   g_model.ok = true;
+  plan_epoch_bump();
   return PM_OK;
 }
 
@@ -407,6 +409,7 @@ pm_status pm_model_set(const float* params, float mean, float sd) {
   g_model.mean = mean;
   g_model.std = sd;
   g_model.ok = true;
+  plan_epoch_bump();
   return PM_OK;
 }
 
@@ -457,6 +460,7 @@ pm_status pm_model_load(const char* path) {
   M.ok = true;
   std::lock_guard<std::mutex> lk(g_model_mu);
   g_model = M;
+  plan_epoch_bump();
   return PM_OK;
 }
 

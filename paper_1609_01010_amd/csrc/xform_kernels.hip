@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(1024) k_lds_xform(const u32* in, int zin, u32*
         if (t < ma) {
           u32 v = x[t];
           if constexpr (S > 1) {
-            if (t > 0) v = A.mul(v, T.rf[LRA - 3][N + j * RA + t]);
+            if (t > 0) v = A.mul(v, T.rf[LRA - 1][N + j * RA + t]);
           }
           sm[lds_ix(j + S * t)] = v;
         }
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(1024) k_lds_xform(const u32* in, int zin, u32*
         if (t < ma) {
           v = sm[lds_ix(j + S * t)];
           if constexpr (S > 1) {
-            if (t > 0) v = A.mul(v, T.ri[LRA - 3][N + j * RA + t]);
+            if (t > 0) v = A.mul(v, T.ri[LRA - 1][N + j * RA + t]);
           }
         }
         x[t] = v;
@@ -109,7 +109,7 @@ static hipError_t lds_xform_inst(const Plan& P, const u32* in, long zin, u32* ou
   if (nthr > 1024) nthr = 1024;
   const size_t lds = (size_t)N * sizeof(u32);
   auto kern = k_lds_xform<LN, LRA, LAZY>;
-  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  ensure_lds_attr((const void*)kern, lds);
   TraceScope ts(s, "lds_xform");
   kern<<<1, nthr, lds, s>>>(in, (int)zin, out, (int)nout, P.ma, dir, natural, mp, T, sc, err);
   return hipGetLastError();
@@ -201,7 +201,7 @@ static hipError_t row_xform_inst(const Plan& P, const u32* in, u32* out, long no
   const int rows = P.ma << P.logRB;
   const size_t lds = (size_t)C * sizeof(u32);
   auto kern = k_row_xform<LC, LNT, LAZY>;
-  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  ensure_lds_attr((const void*)kern, lds);
   TraceScope ts(s, "row_xform");
   kern<<<rows, 1 << LNT, lds, s>>>(in, out, nout, dir, P.logRA + P.logRB, mp, T, W);
   return hipGetLastError();
