@@ -16,6 +16,45 @@
 typedef uint32_t u32;
 typedef uint64_t u64;
 
+// Address spaces of device memory.  Pointers that reach a kernel inside a job
+// descriptor are generic to the compiler, which then emits flat accesses
+// (these also hold up waits for LDS results).  Every access to device memory
+// names its space instead: gld/gst for data in global memory, cld for the
+// twiddle tables, which no kernel writes; wave-uniform reads of those become
+// scalar loads.
+#define PM_GMEM __attribute__((address_space(1)))
+#define PM_CMEM __attribute__((address_space(4)))
+
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  static_assert(__is_arithmetic(T), "scalar types only");
+  return *(const PM_GMEM T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  static_assert(__is_arithmetic(T), "scalar types only");
+  *(PM_GMEM T*)p = v;
+}
+__device__ __forceinline__ uint32_t cld(const uint32_t* p) { return *(const PM_CMEM uint32_t*)p; }
+__device__ __forceinline__ uint2 cld(const uint2* p) {
+  const PM_CMEM uint2* q = (const PM_CMEM uint2*)p;
+  return make_uint2(q->x, q->y);
+}
+__device__ __forceinline__ uint4 cld(const uint4* p) {
+  const PM_CMEM uint4* q = (const PM_CMEM uint4*)p;
+  return make_uint4(q->x, q->y, q->z, q->w);
+}
+
+// Hide a pointer's value from the optimiser: loads through the result are
+// neither merged with loads before this point nor hoisted above it.  Used at
+// phase boundaries of long kernels so that the table entries held in scalar
+// registers are those of one phase only.
+template <typename T>
+__device__ __forceinline__ const T* fresh(const T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 struct ModP {
   u32 p;     // the prime
   u32 p2;    // 2p

@@ -205,19 +205,10 @@ hipError_t launch_crt_carry(const u32* r1, const u32* r2, const u32* r3, long lc
   u32* sums = (u32*)ws;
   u32* bmap = sums + nl;
   u32* cin = bmap + nblk;
-  {
-    TraceScope ts(s, "crt_sums");
-    k_crt_sums<<<(unsigned)nblk, kCrtThreads, 0, s>>>(r1, r2, r3, lc, nl, K, sums, bmap);
-  }
-  {
-    TraceScope ts(s, "carry_scan");
-    k_carry_scan<<<1, 1024, 0, s>>>(bmap, (int)nblk, cin);
-  }
-  {
-    TraceScope ts(s, "carry_apply");
-    k_carry_apply<<<(unsigned)nblk, kCrtThreads, 0, s>>>(sums, nl, cin, out);
-  }
-  return hipGetLastError();
+  hipError_t e = launch("crt_sums", k_crt_sums, (unsigned)nblk, kCrtThreads, 0, s, r1, r2, r3, lc, nl, K, sums, bmap);
+  if (e == hipSuccess) e = launch("carry_scan", k_carry_scan, 1, 1024, 0, s, bmap, (int)nblk, cin);
+  if (e == hipSuccess) e = launch("carry_apply", k_carry_apply, (unsigned)nblk, kCrtThreads, 0, s, sums, nl, cin, out);
+  return e;
 }
 
 // widen 16-bit limbs to 32-bit words (inputs of the one-work-group plans)
@@ -227,9 +218,7 @@ __global__ void k_widen(const uint16_t* __restrict__ in, long n, u32* __restrict
 }
 
 hipError_t launch_widen(const uint16_t* in, long n, u32* out, hipStream_t s) {
-  TraceScope ts(s, "widen");
-  k_widen<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, n, out);
-  return hipGetLastError();
+  return launch("widen", k_widen, (unsigned)((n + 255) / 256), 256, 0, s, in, n, out);
 }
 
 }  // namespace pm

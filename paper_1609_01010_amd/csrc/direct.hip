@@ -46,12 +46,8 @@ __global__ void __launch_bounds__(64) k_direct(const u32* __restrict__ a, int la
 hipError_t launch_direct(const u32* a, long la, const u32* b, long lb, u32* c, int pidx, int* err, hipStream_t s) {
   const PrimeInfo& P = prime_info(pidx);
   const ModP mp = modp_of(P);
-  TraceScope ts(s, "direct");
-  if (P.lazy)
-    k_direct<true><<<1, 64, 0, s>>>(a, (int)la, b, (int)lb, c, mp, err);
-  else
-    k_direct<false><<<1, 64, 0, s>>>(a, (int)la, b, (int)lb, c, mp, err);
-  return hipGetLastError();
+  if (P.lazy) return launch("direct", k_direct<true>, 1, 64, 0, s, a, (int)la, b, (int)lb, c, mp, err);
+  return launch("direct", k_direct<false>, 1, 64, 0, s, a, (int)la, b, (int)lb, c, mp, err);
 }
 
 }  // namespace pm

@@ -52,116 +52,154 @@ __global__ void __launch_bounds__(64) k_col_fwd1(JobRef jr, int logC) {
 #pragma unroll
   for (int s = 0; s < RA; ++s) {
     const long pos = C * s + j2;
-    x[s] = pos < z ? (u32)in[pos] : 0u;
+    x[s] = pos < z ? (u32)gld(in + pos) : 0u;
     bad |= x[s] >= J.mp.p;
   }
   if (bad) atomicOr(J.err, 1);
   dif_reg<RA>(A, x, J.T.pf);
 #pragma unroll
   for (int t = 0; t < RA; ++t)
-    if (t < J.ma) out[C * t + j2] = x[t];
+    if (t < J.ma) gst(out + C * t + j2, x[t]);
 }
 
-// four-step column pass (forward), two sub-rounds (R = RA * RB): a work-group
-// owns W adjacent columns.  Sub-round 1: thread (c, j1b) transforms rows
-// j1b + RB e (e < RA) and twiddles by w_R^{j1b k1a}; sub-round 2: thread
-// (c, ta) transforms the RB values of block ta, giving output row
-// t = ta RB + tb.  Only blocks ta < ma are carried into sub-round 2.
+// ---------------------------------------------------------------------------
+// four-step column passes for R = RA RB > 32 rows.  A work-group of
+// NT = W R / 16 threads owns W adjacent columns (an [R][W] LDS tile) and runs
+// their length-R transforms as rounds of radix 2^LQ <= 16, each thread taking
+// 16 / 2^LQ (column, group) tasks per round, lanes along the columns: so
+// every thread holds 16 values per round, and the first round (straight
+// from global memory) has 16 loads per thread in flight.  The last round
+// writes global memory.  Only rows below mr = ma RB are kept (the relaxed
+// TFT): blocks that start at or beyond mr are skipped.
 
-template <int LRA, int LRB, int LW, bool LAZY, typename TIn>
-__global__ void __launch_bounds__(1024) k_col_fwd2(JobRef jr, int logC) {
-  constexpr int RA = 1 << LRA, RB = 1 << LRB, W = 1 << LW, R = RA * RB;
-  extern __shared__ u32 sm[];  // [RA][RB][W]
+// radix (log2) of round k (outermost first) of a length-2^LR column transform
+template <int LR, int K>
+constexpr int col_round_lq() {
+  constexpr int seq[11][3] = {{0, 0, 0}, {1, 0, 0}, {2, 0, 0}, {3, 0, 0}, {4, 0, 0}, {2, 3, 0},
+                              {3, 3, 0}, {3, 4, 0}, {4, 4, 0}, {3, 3, 3}, {4, 3, 3}};
+  return seq[LR][K];
+}
+
+// DIF round of radix 2^LQ over the blocks of 2^LB rows that start below mr;
+// FROM_GLOBAL: the input is the operand in global memory (rows beyond its
+// length are zero), else LDS; TO_GLOBAL: output rows below mr go to `out`,
+// else back to LDS
+template <int LB, int LQ, bool FROM_GLOBAL, bool TO_GLOBAL, bool LAZY, typename TIn>
+__device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
+                                              int tid, int nthr, const TIn* __restrict__ in, long z, long C, long col0,
+                                              u32* __restrict__ out, bool& bad) {
+  constexpr int Q = 1 << LQ;
+  constexpr int LS = LB - LQ;
+  constexpr int K = 16 / Q;
+  const int ntask = (((mr + (1 << LB) - 1) >> LB) << LS) << lw;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int task = tid + k * nthr;
+    if (task < ntask) {
+      const int c = task & ((1 << lw) - 1);
+      const int g = task >> lw;
+      const int j = g & ((1 << LS) - 1);
+      const int base = ((g >> LS) << LB) + j;
+      u32 x[Q];
+#pragma unroll
+      for (int s = 0; s < Q; ++s) {
+        const int row = base + (s << LS);
+        if constexpr (FROM_GLOBAL) {
+          const long pos = C * row + col0 + c;
+          x[s] = pos < z ? (u32)gld(in + pos) : 0u;
+          bad |= x[s] >= A.p;
+        } else {
+          x[s] = sm[(row << lw) + c];
+        }
+      }
+      dif_reg<Q>(A, x, T.pf);
+      const uint2* tw = T.rf[LQ - 1] + (1 << LB) + j * Q;
+#pragma unroll
+      for (int t = 0; t < Q; ++t) {
+        const int row = base + (t << LS);
+        u32 v = x[t];
+        if (LS > 0 && t > 0) v = A.mul(v, cld(tw + t));
+        if constexpr (TO_GLOBAL) {
+          if (row < mr) gst(out + C * row + col0 + c, v);
+        } else {
+          sm[(row << lw) + c] = v;
+        }
+      }
+    }
+  }
+}
+
+// rounds K.. of the forward column transform on blocks of 2^LB rows; a
+// barrier separates consecutive rounds
+template <int LR, int K, int LB, bool LAZY, typename TIn>
+__device__ __forceinline__ void col_dif_rounds(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
+                                               int tid, int nthr, const TIn* in, long z, long C, long col0, u32* out,
+                                               bool& bad) {
+  constexpr int LQ = col_round_lq<LR, K>();
+  constexpr bool first = K == 0;
+  constexpr bool last = LB == LQ;
+  col_dif_round<LB, LQ, first, last, LAZY, TIn>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, bad);
+  if constexpr (!last) {
+    __syncthreads();
+    col_dif_rounds<LR, K + 1, LB - LQ, LAZY, TIn>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, bad);
+  }
+}
+
+template <int LR, bool LAZY, typename TIn>
+__global__ void __launch_bounds__(1024) k_col_fwdr(JobRef jr, int logC, int lw) {
+  extern __shared__ u32 sm[];  // [R][W]
   const ConvJob J = load_job(jr);
-  const long C = 1l << logC;
-  const long c0 = (long)blockIdx.x * W;
   const Arith<LAZY> A(J.mp);
   const TIn* __restrict__ in = (const TIn*)(blockIdx.y ? J.b : J.a);
   const long z = blockIdx.y ? J.lb : J.la;
   u32* __restrict__ out = blockIdx.y ? J.Tb : J.Ta;
-  const int ma = J.ma;
-  const int tid = threadIdx.x, nthr = blockDim.x;
   bool bad = false;
-  for (int task = tid; task < W * RB; task += nthr) {
-    const int c = task & (W - 1);
-    const int j1b = task >> LW;
-    u32 x[RA];
-#pragma unroll
-    for (int e = 0; e < RA; ++e) {
-      const long pos = C * (j1b + RB * e) + c0 + c;
-      x[e] = pos < z ? (u32)in[pos] : 0u;
-      bad |= x[e] >= J.mp.p;
-    }
-    dif_reg<RA>(A, x, J.T.pf);
-    uint2 tw[RA];
-    load_tw<RA>(tw, J.T.rf[LRA - 1] + R + j1b * RA);
-#pragma unroll
-    for (int ta = 0; ta < RA; ++ta) {
-      if (ta < ma) {
-        u32 v = x[ta];
-        if (ta > 0) v = A.mul(v, tw[ta]);
-        sm[(ta * RB + j1b) * W + c] = v;
-      }
-    }
-  }
+  col_dif_rounds<LR, 0, LR, LAZY, TIn>(A, sm, lw, J.rows, J.T, threadIdx.x, blockDim.x, in, z, 1l << logC,
+                                       (long)blockIdx.x << lw, out, bad);
   if (bad) atomicOr(J.err, 1);
-  __syncthreads();
-  for (int task = tid; task < W * ma; task += nthr) {
-    const int c = task & (W - 1);
-    const int ta = task >> LW;
-    u32 x[RB];
-#pragma unroll
-    for (int j1b = 0; j1b < RB; ++j1b) x[j1b] = sm[(ta * RB + j1b) * W + c];
-    dif_reg<RB>(A, x, J.T.pf);
-#pragma unroll
-    for (int tb = 0; tb < RB; ++tb) out[C * (ta * RB + tb) + c0 + c] = x[tb];
-  }
 }
 
-// Columns per work-group of the two-sub-round passes: W RB = 1024 first-
-// round tasks (one per thread) unless the LDS tile W R words would exceed
-// 64 KB, and at least 32 columns (128-byte row segments); at most 128 KB.
-template <int LRA, int LRB>
-constexpr int col_lw() {
-  constexpr int a = 10 - LRB;
-  constexpr int b = 14 - LRA - LRB;
-  constexpr int w = a < b ? a : b;
-  return w < 5 ? 5 : w;
+// Columns per work-group: 32 (128-byte row segments) unless the tile of R
+// rows would exceed 64 KB, and 16 when the grid would otherwise have fewer
+// work-groups than the chip has compute units.
+inline int col_lw(int logR, int logC, long groups) {
+  int lw = 5;
+  if (logR + lw > 14) lw = 14 - logR;
+  if (lw > logC) lw = logC;
+  while (lw > 4 && (groups << (logC - lw)) < 256) --lw;
+  return lw;
 }
-template <int LRA, int LRB>
-constexpr int col_threads() {
-  constexpr int n = (1 << col_lw<LRA, LRB>()) << LRB;
-  return n > 1024 ? 1024 : n;
+inline int col_threads(int logR, int lw) {
+  const int n = 1 << (lw + logR - 4);
+  return n < 64 ? 64 : n;
 }
 
-template <int LRA, int LRB, typename TIn>
-static hipError_t col_fwd2_launch(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
-  constexpr int LW = col_lw<LRA, LRB>();
+template <int LR, typename TIn>
+static hipError_t col_fwdr_launch(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
+  const int lw = col_lw(LR, P.logC, (long)nops * njobs);
   const long C = 1l << P.logC;
-  if (C < (1l << LW)) return hipErrorInvalidValue;
-  const size_t lds = ((size_t)1 << (LW + LRA + LRB)) * sizeof(u32);
-  auto kern = k_col_fwd2<LRA, LRB, LW, kLazy, TIn>;
+  if (C < (1l << lw) || col_threads(LR, lw) > 1024) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)1 << (lw + LR)) * sizeof(u32);
+  auto kern = k_col_fwdr<LR, kLazy, TIn>;
   ensure_lds_attr((const void*)kern, lds);
-  TraceScope ts(s, "col_fwd");
-  kern<<<dim3((unsigned)(C >> LW), nops, njobs), col_threads<LRA, LRB>(), lds, s>>>(jr, P.logC);
-  return hipGetLastError();
+  return launch("col_fwd", kern, dim3((unsigned)(C >> lw), nops, njobs), col_threads(LR, lw), lds, s, jr, P.logC,
+                lw);
 }
 
 template <int LRA, typename TIn>
 static hipError_t col_fwd_ra(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
   const long C = 1l << P.logC;
   if (P.logRB == 0) {
-    TraceScope ts(s, "col_fwd");
-    k_col_fwd1<LRA, kLazy, TIn><<<dim3((unsigned)((C + 63) / 64), nops, njobs), 64, 0, s>>>(jr, P.logC);
-    return hipGetLastError();
+    return launch("col_fwd", k_col_fwd1<LRA, kLazy, TIn>, dim3((unsigned)((C + 63) / 64), nops, njobs), 64, 0, s, jr,
+                  P.logC);
   }
   if constexpr (LRA >= 4) {
     switch (P.logRB) {
-      case 1: return col_fwd2_launch<LRA, 1, TIn>(P, nops, jr, njobs, s);
-      case 2: return col_fwd2_launch<LRA, 2, TIn>(P, nops, jr, njobs, s);
-      case 3: return col_fwd2_launch<LRA, 3, TIn>(P, nops, jr, njobs, s);
-      case 4: return col_fwd2_launch<LRA, 4, TIn>(P, nops, jr, njobs, s);
-      case 5: return col_fwd2_launch<LRA, 5, TIn>(P, nops, jr, njobs, s);
+      case 1: return col_fwdr_launch<LRA + 1, TIn>(P, nops, jr, njobs, s);
+      case 2: return col_fwdr_launch<LRA + 2, TIn>(P, nops, jr, njobs, s);
+      case 3: return col_fwdr_launch<LRA + 3, TIn>(P, nops, jr, njobs, s);
+      case 4: return col_fwdr_launch<LRA + 4, TIn>(P, nops, jr, njobs, s);
+      case 5: return col_fwdr_launch<LRA + 5, TIn>(P, nops, jr, njobs, s);
       default: break;
     }
   }
@@ -202,28 +240,6 @@ hipError_t PM_SUFFIX(launch_col_fwd)(const Plan& P, int in_type, int nops, const
 // in LDS at once so their rounds share barriers; NB = 1 (the largest rows)
 // transforms them one after the other in one buffer.
 
-template <int LC, int LE, bool LAZY>
-__device__ __forceinline__ void row_twist_fwd(const Arith<LAZY>& A, u32 (&x)[1 << LE], uint2 g,
-                                              const uint2* __restrict__ f, const PrimeTables& T, int tid) {
-#pragma unroll
-  for (int e = 0; e < (1 << LE); ++e) x[e] = A.mul(A.mul(x[e], g), f[e]);
-  dif_top_reg<LC, LE, LAZY>(A, x, T, tid);
-}
-
-template <int LQL, int EPT, bool LAZY>
-__device__ __forceinline__ void row_last_fwd(const Arith<LAZY>& A, const u32* buf, u32 (&x)[EPT],
-                                             const PrimeTables& T, int tid, int nthr) {
-  constexpr int QL = 1 << LQL;
-#pragma unroll
-  for (int u = 0; u < EPT / QL; ++u) {
-    u32 y[QL];
-    lds_load_contig<QL>(buf, (tid + nthr * u) * QL, y);
-    dif_reg<QL>(A, y, T.pf);
-#pragma unroll
-    for (int t = 0; t < QL; ++t) x[u * QL + t] = y[t];
-  }
-}
-
 template <int LC, int LQ, int LNT, int NB, bool LAZY>
 __global__ void __launch_bounds__(1 << LNT) k_row_conv(JobRef jr, int logR) {
   constexpr int C = 1 << LC;
@@ -245,47 +261,51 @@ __global__ void __launch_bounds__(1 << LNT) k_row_conv(JobRef jr, int logR) {
   const long off = (long)row * C;
   u32* Ta = J.Ta;
   const u32* __restrict__ Tb = J.Tb;
-  const uint2 gf = J.W.gf[k1 * (u32)tid];
+  const uint2 gf = cld(J.W.gf + k1 * (u32)tid);
   const uint2* ff = J.W.ff + (size_t)k1 * EPT;
   // b's row is fetched up front (its latency hides behind a's rounds) unless
   // 1024 threads leave too few registers to hold it meanwhile
-  constexpr bool kPrefetchB = NB == 2 || LNT < 10;
+  constexpr bool kPrefetchB = NB == 2;
+  PrimeTables T = J.T;
   u32 xa[EPT], xb[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
-    xa[e] = Ta[off + tid + NT * e];
-    if constexpr (kPrefetchB) xb[e] = Tb[off + tid + NT * e];
+    xa[e] = gld(Ta + off + tid + NT * e);
+    if constexpr (kPrefetchB) xb[e] = gld(Tb + off + tid + NT * e);
   }
-  row_twist_fwd<LC, LE, LAZY>(A, xa, gf, ff, J.T, tid);
+  row_twist_fwd<LC, LE, LAZY>(A, xa, gf, ff, T, tid);
 #pragma unroll
   for (int t = 0; t < EPT; ++t) sa[lds_ix(tid + NT * t)] = xa[t];
   if constexpr (NB == 2) {
-    row_twist_fwd<LC, LE, LAZY>(A, xb, gf, ff, J.T, tid);
+    row_twist_fwd<LC, LE, LAZY>(A, xb, gf, ff, T, tid);
 #pragma unroll
     for (int t = 0; t < EPT; ++t) sb[lds_ix(tid + NT * t)] = xb[t];
   }
   __syncthreads();
   if constexpr (NB == 2) {
     u32* bufs[2] = {sa, sb};
-    dif_lds_upto<LNT, LQL, LQ, LAZY, 2>(A, bufs, C, J.T, tid, NT);
-    row_last_fwd<LQL, EPT, LAZY>(A, sa, xa, J.T, tid, NT);
-    row_last_fwd<LQL, EPT, LAZY>(A, sb, xb, J.T, tid, NT);
+    dif_lds_upto<LNT, LQL, LQ, LAZY, 2>(A, bufs, C, T, tid, NT);
+    row_last_fwd<LQL, EPT, LAZY>(A, sa, xa, T, tid, NT);
+    row_last_fwd<LQL, EPT, LAZY>(A, sb, xb, T, tid, NT);
   } else {
     u32* bufs[1] = {sa};
-    dif_lds_upto<LNT, LQL, LQ, LAZY, 1>(A, bufs, C, J.T, tid, NT);
-    row_last_fwd<LQL, EPT, LAZY>(A, sa, xa, J.T, tid, NT);
+    dif_lds_upto<LNT, LQL, LQ, LAZY, 1>(A, bufs, C, T, tid, NT);
+    row_last_fwd<LQL, EPT, LAZY>(A, sa, xa, T, tid, NT);
+    T = fresh(T);
+    ff = fresh(ff);
     if constexpr (!kPrefetchB) {
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) xb[e] = Tb[off + tid + NT * e];
+      for (int e = 0; e < EPT; ++e) xb[e] = gld(Tb + off + tid + NT * e);
     }
     __syncthreads();
-    row_twist_fwd<LC, LE, LAZY>(A, xb, gf, ff, J.T, tid);
+    row_twist_fwd<LC, LE, LAZY>(A, xb, gf, ff, T, tid);
 #pragma unroll
     for (int t = 0; t < EPT; ++t) sa[lds_ix(tid + NT * t)] = xb[t];
     __syncthreads();
-    dif_lds_upto<LNT, LQL, LQ, LAZY, 1>(A, bufs, C, J.T, tid, NT);
-    row_last_fwd<LQL, EPT, LAZY>(A, sa, xb, J.T, tid, NT);
+    dif_lds_upto<LNT, LQL, LQ, LAZY, 1>(A, bufs, C, T, tid, NT);
+    row_last_fwd<LQL, EPT, LAZY>(A, sa, xb, T, tid, NT);
   }
+  T = fresh(T);
   // pointwise product and the innermost inverse round; each thread writes
   // back exactly the LDS words it read last, so no barrier is needed first
 #pragma unroll
@@ -293,18 +313,18 @@ __global__ void __launch_bounds__(1 << LNT) k_row_conv(JobRef jr, int logR) {
     u32 y[QL];
 #pragma unroll
     for (int t = 0; t < QL; ++t) y[t] = A.mont(xa[u * QL + t], xb[u * QL + t]);
-    dit_reg<QL>(A, y, J.T.pi);
+    dit_reg<QL>(A, y, T.pi);
     lds_store_contig<QL>(sa, (tid + NT * u) * QL, y);
   }
   __syncthreads();
-  dit_lds_from<LNT, LQL, LQ, LAZY>(A, sa, C, J.T, tid, NT);
+  dit_lds_from<LNT, LQL, LQ, LAZY>(A, sa, C, T, tid, NT);
 #pragma unroll
   for (int t = 0; t < EPT; ++t) xa[t] = sa[lds_ix(tid + NT * t)];
-  dit_top_reg<LC, LE, LAZY>(A, xa, J.T, tid);
-  const uint2 gi = J.W.gi[k1 * (u32)tid];
+  dit_top_reg<LC, LE, LAZY>(A, xa, T, tid);
+  const uint2 gi = cld(J.W.gi + k1 * (u32)tid);
   const uint2* fi = J.W.fi + (size_t)k1 * EPT;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) Ta[off + tid + NT * e] = A.mul(A.mul(xa[e], gi), fi[e]);
+  for (int e = 0; e < EPT; ++e) gst(Ta + off + tid + NT * e, A.mul(A.mul(xa[e], gi), cld(fi + e)));
 }
 
 template <int LC, int LNT>
@@ -315,9 +335,7 @@ static hipError_t row_conv_inst(const Plan& P, int max_rows, const JobRef& jr, i
   const size_t lds = (size_t)NB * C * sizeof(u32);
   auto kern = P.lq == 3 ? k_row_conv<LC, 3, LNT, NB, kLazy> : k_row_conv<LC, 4, LNT, NB, kLazy>;
   ensure_lds_attr((const void*)kern, lds);
-  TraceScope ts(s, "row_conv");
-  kern<<<dim3(max_rows, 1, njobs), 1 << LNT, lds, s>>>(jr, logR);
-  return hipGetLastError();
+  return launch("row_conv", kern, dim3(max_rows, 1, njobs), 1 << LNT, lds, s, jr, logR);
 }
 
 template <int LC>
@@ -366,51 +384,95 @@ __global__ void __launch_bounds__(64) k_col_inv1(JobRef jr, int logC) {
   const int ma = J.ma;
   u32 x[RA];
 #pragma unroll
-  for (int t = 0; t < RA; ++t) x[t] = t < ma ? Tc[C * t + j2] : 0u;
+  for (int t = 0; t < RA; ++t) x[t] = t < ma ? gld(Tc + C * t + j2) : 0u;
   inv_column<RA, LAZY>(A, x, ma, J.T);
 #pragma unroll
   for (int s = 0; s < RA; ++s) {
     const long pos = C * s + j2;
-    if (s < ma && pos < J.lc) c[pos] = A.canon(x[s]);
+    if (s < ma && pos < J.lc) gst(c + pos, A.canon(x[s]));
   }
 }
 
-// two sub-rounds: inverse of k_col_fwd2
-template <int LRA, int LRB, int LW, bool LAZY>
-__global__ void __launch_bounds__(1024) k_col_inv2(JobRef jr, int logC) {
-  constexpr int RA = 1 << LRA, RB = 1 << LRB, W = 1 << LW, R = RA * RB;
-  extern __shared__ u32 sm[];  // [RA][RB][W]
+// DIT round of radix 2^LQ over the blocks of 2^LB rows below mr (all whole);
+// FROM_GLOBAL: the input rows come from `in` (the innermost round), else LDS
+template <int LB, int LQ, bool FROM_GLOBAL, bool LAZY>
+__device__ __forceinline__ void col_dit_round(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
+                                              int tid, int nthr, const u32* __restrict__ in, long C, long col0) {
+  constexpr int Q = 1 << LQ;
+  constexpr int LS = LB - LQ;
+  constexpr int K = 16 / Q;
+  const int ntask = ((mr >> LB) << LS) << lw;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int task = tid + k * nthr;
+    if (task < ntask) {
+      const int c = task & ((1 << lw) - 1);
+      const int g = task >> lw;
+      const int j = g & ((1 << LS) - 1);
+      const int base = ((g >> LS) << LB) + j;
+      const uint2* tw = T.ri[LQ - 1] + (1 << LB) + j * Q;
+      u32 x[Q];
+#pragma unroll
+      for (int t = 0; t < Q; ++t) {
+        const int row = base + (t << LS);
+        u32 v = FROM_GLOBAL ? gld(in + C * row + col0 + c) : sm[(row << lw) + c];
+        if (LS > 0 && t > 0) v = A.mul(v, cld(tw + t));
+        x[t] = v;
+      }
+      dit_reg<Q>(A, x, T.pi);
+#pragma unroll
+      for (int s = 0; s < Q; ++s) sm[((base + (s << LS)) << lw) + c] = x[s];
+    }
+  }
+}
+
+// inverse rounds of the length-RB blocks: the mirror of the forward split of
+// LRB (rounds K, K-1, .., 0, innermost first); each ends with a barrier
+template <int LRB, int K, int LB, bool LAZY>
+__device__ __forceinline__ void col_dit_rounds(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
+                                               int tid, int nthr, const u32* in, long C, long col0) {
+  constexpr int LQ = col_round_lq<LRB, K>();
+  if constexpr (LQ > 0) {
+    constexpr bool first = LB == 0;
+    col_dit_round<LB + LQ, LQ, first, LAZY>(A, sm, lw, mr, T, tid, nthr, in, C, col0);
+    __syncthreads();
+    if constexpr (K > 0) col_dit_rounds<LRB, K - 1, LB + LQ, LAZY>(A, sm, lw, mr, T, tid, nthr, in, C, col0);
+  }
+}
+
+template <int LR>
+constexpr int col_last_round() {
+  return col_round_lq<LR, 2>() ? 2 : (col_round_lq<LR, 1>() ? 1 : 0);
+}
+
+// Inverse column pass: the length-RB inverses of the blocks below mr (the
+// innermost round straight from global memory), then per column and j1b
+// the truncated inverse of radix RA with ma known values, written to the
+// output coefficients.
+template <int LRA, int LRB, bool LAZY>
+__global__ void __launch_bounds__(1024) k_col_invr(JobRef jr, int logC, int lw) {
+  constexpr int RA = 1 << LRA, RB = 1 << LRB, R = RA * RB;
+  extern __shared__ u32 sm[];  // [R][W]
   const ConvJob J = load_job(jr);
   const long C = 1l << logC;
-  const long c0 = (long)blockIdx.x * W;
+  const int W = 1 << lw;
+  const long c0 = (long)blockIdx.x << lw;
   const Arith<LAZY> A(J.mp);
-  const u32* __restrict__ Tc = J.Ta;
   u32* __restrict__ c = J.c;
   const int ma = J.ma;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int task = tid; task < W * ma; task += nthr) {
+  col_dit_rounds<LRB, col_last_round<LRB>(), 0, LAZY>(A, sm, lw, ma << LRB, J.T, tid, nthr, J.Ta, C, c0);
+  for (int task = tid; task < (W << LRB); task += nthr) {
     const int cc = task & (W - 1);
-    const int ta = task >> LW;
-    u32 x[RB];
-#pragma unroll
-    for (int tb = 0; tb < RB; ++tb) x[tb] = Tc[C * (ta * RB + tb) + c0 + cc];
-    dit_reg<RB>(A, x, J.T.pi);
-#pragma unroll
-    for (int j1b = 0; j1b < RB; ++j1b) sm[(ta * RB + j1b) * W + cc] = x[j1b];
-  }
-  __syncthreads();
-  for (int task = tid; task < W * RB; task += nthr) {
-    const int cc = task & (W - 1);
-    const int j1b = task >> LW;
-    uint2 tw[RA];
-    load_tw<RA>(tw, J.T.ri[LRA - 1] + R + j1b * RA);
+    const int j1b = task >> lw;
+    const uint2* tw = J.T.ri[LRA - 1] + R + j1b * RA;
     u32 x[RA];
 #pragma unroll
     for (int ta = 0; ta < RA; ++ta) {
       u32 v = 0;
       if (ta < ma) {
-        v = sm[(ta * RB + j1b) * W + cc];
-        if (ta > 0) v = A.mul(v, tw[ta]);
+        v = sm[((ta * RB + j1b) << lw) + cc];
+        if (ta > 0) v = A.mul(v, cld(tw + ta));
       }
       x[ta] = v;
     }
@@ -418,39 +480,36 @@ __global__ void __launch_bounds__(1024) k_col_inv2(JobRef jr, int logC) {
 #pragma unroll
     for (int e = 0; e < RA; ++e) {
       const long pos = C * (j1b + RB * e) + c0 + cc;
-      if (e < ma && pos < J.lc) c[pos] = A.canon(x[e]);
+      if (e < ma && pos < J.lc) gst(c + pos, A.canon(x[e]));
     }
   }
 }
 
 template <int LRA, int LRB>
-static hipError_t col_inv2_launch(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
-  constexpr int LW = col_lw<LRA, LRB>();
+static hipError_t col_invr_launch(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
+  const int lw = col_lw(LRA + LRB, P.logC, (long)njobs);
   const long C = 1l << P.logC;
-  if (C < (1l << LW)) return hipErrorInvalidValue;
-  const size_t lds = ((size_t)1 << (LW + LRA + LRB)) * sizeof(u32);
-  auto kern = k_col_inv2<LRA, LRB, LW, kLazy>;
+  if (C < (1l << lw) || col_threads(LRA + LRB, lw) > 1024) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)1 << (lw + LRA + LRB)) * sizeof(u32);
+  auto kern = k_col_invr<LRA, LRB, kLazy>;
   ensure_lds_attr((const void*)kern, lds);
-  TraceScope ts(s, "col_inv");
-  kern<<<dim3((unsigned)(C >> LW), 1, njobs), col_threads<LRA, LRB>(), lds, s>>>(jr, P.logC);
-  return hipGetLastError();
+  return launch("col_inv", kern, dim3((unsigned)(C >> lw), 1, njobs), col_threads(LRA + LRB, lw), lds, s, jr,
+                P.logC, lw);
 }
 
 template <int LRA>
 static hipError_t col_inv_ra(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
   const long C = 1l << P.logC;
   if (P.logRB == 0) {
-    TraceScope ts(s, "col_inv");
-    k_col_inv1<LRA, kLazy><<<dim3((unsigned)((C + 63) / 64), 1, njobs), 64, 0, s>>>(jr, P.logC);
-    return hipGetLastError();
+    return launch("col_inv", k_col_inv1<LRA, kLazy>, dim3((unsigned)((C + 63) / 64), 1, njobs), 64, 0, s, jr, P.logC);
   }
   if constexpr (LRA >= 4) {
     switch (P.logRB) {
-      case 1: return col_inv2_launch<LRA, 1>(P, jr, njobs, s);
-      case 2: return col_inv2_launch<LRA, 2>(P, jr, njobs, s);
-      case 3: return col_inv2_launch<LRA, 3>(P, jr, njobs, s);
-      case 4: return col_inv2_launch<LRA, 4>(P, jr, njobs, s);
-      case 5: return col_inv2_launch<LRA, 5>(P, jr, njobs, s);
+      case 1: return col_invr_launch<LRA, 1>(P, jr, njobs, s);
+      case 2: return col_invr_launch<LRA, 2>(P, jr, njobs, s);
+      case 3: return col_invr_launch<LRA, 3>(P, jr, njobs, s);
+      case 4: return col_invr_launch<LRA, 4>(P, jr, njobs, s);
+      case 5: return col_invr_launch<LRA, 5>(P, jr, njobs, s);
       default: break;
     }
   }

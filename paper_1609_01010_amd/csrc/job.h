@@ -36,7 +36,17 @@ struct JobRef {
   const ConvJob* many;
 };
 
+// the descriptor array is read through the constant space (wave-uniform
+// scalar loads); it is never written while kernels run
 __device__ __forceinline__ ConvJob load_job(const JobRef& r) {
-  if (r.many) return r.many[blockIdx.z];
+  if (r.many) {
+    static_assert(sizeof(ConvJob) % 4 == 0, "descriptor copied as words");
+    ConvJob J;
+    const PM_CMEM uint32_t* s = (const PM_CMEM uint32_t*)(r.many + blockIdx.z);
+    uint32_t* d = reinterpret_cast<uint32_t*>(&J);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(ConvJob) / 4); ++i) d[i] = s[i];
+    return J;
+  }
   return r.one;
 }

@@ -53,19 +53,19 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   bool bad = false;
 
-  for (int j = tid; j < S; j += nthr) {
-    uint2 tw[RA];
-    if constexpr (S > 1) load_tw<RA>(tw, T.rf[LRA - 1] + N + j * RA);
-#pragma unroll
-    for (int op = 0; op < 2; ++op) {
-      const u32* in = op ? b : a;
-      const int len = op ? lb : la;
-      u32* out = op ? sb : sa;
+  // operands one after the other: the twiddles of a column are read again
+  // (from cache) rather than held in registers across both
+  for (int op = 0; op < 2; ++op) {
+    const u32* in = op ? b : a;
+    const int len = op ? lb : la;
+    u32* out = op ? sb : sa;
+    for (int j = tid; j < S; j += nthr) {
+      const uint2* tw = T.rf[LRA - 1] + N + j * RA;
       u32 x[RA];
 #pragma unroll
       for (int s = 0; s < RA; ++s) {
         const int pos = j + S * s;
-        x[s] = pos < len ? in[pos] : 0u;
+        x[s] = pos < len ? gld(in + pos) : 0u;
         bad |= x[s] >= J.mp.p;
       }
       dif_reg<RA>(A, x, T.pf);
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
         if (t < ma) {
           u32 v = x[t];
           if constexpr (S > 1) {
-            if (t > 0) v = A.mul(v, tw[t]);
+            if (t > 0) v = A.mul(v, cld(tw + t));
           }
           out[lds_ix(j + S * t)] = v;
         }
@@ -84,18 +84,15 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
   if (bad) atomicOr(J.err, 1);
   __syncthreads();
   const int nel = ma * S;
+  constexpr int LQL = last_lb<LS, LQ>();
   u32* bufs[2] = {sa, sb};
-  dif_lds<LS, LQ, LAZY, 2>(A, bufs, nel, T, tid, nthr);
-  for (int i = tid; i < nel; i += nthr) {
-    const int k = lds_ix(i);
-    sa[k] = A.mul(A.mont(sa[k], sb[k]), J.sc);
-  }
+  dif_lds_upto<LS, LQL, LQ, LAZY, 2>(A, bufs, nel, T, tid, nthr);
+  conv_inner<LQL, LAZY>(A, sa, sb, nel, T, tid, nthr, J.sc);
   __syncthreads();
-  dit_lds<LS, LQ, LAZY>(A, sa, nel, T, tid, nthr);
+  dit_lds_from<LS, LQL, LQ, LAZY>(A, sa, nel, T, tid, nthr);
   u32* __restrict__ c = J.c;
   for (int j = tid; j < S; j += nthr) {
-    uint2 tw[RA];
-    if constexpr (S > 1) load_tw<RA>(tw, T.ri[LRA - 1] + N + j * RA);
+    const uint2* tw = T.ri[LRA - 1] + N + j * RA;
     u32 x[RA];
 #pragma unroll
     for (int t = 0; t < RA; ++t) {
@@ -103,7 +100,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
       if (t < ma) {
         v = sa[lds_ix(j + S * t)];
         if constexpr (S > 1) {
-          if (t > 0) v = A.mul(v, tw[t]);
+          if (t > 0) v = A.mul(v, cld(tw + t));
         }
       }
       x[t] = v;
@@ -112,7 +109,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
 #pragma unroll
     for (int s = 0; s < RA; ++s) {
       const int pos = j + S * s;
-      if (s < ma && pos < lc) c[pos] = A.canon(x[s]);
+      if (s < ma && pos < lc) gst(c + pos, A.canon(x[s]));
     }
   }
 }
@@ -129,9 +126,7 @@ static hipError_t lds_conv_inst(const JobRef& jr, int njobs, hipStream_t s) {
   const size_t lds = 2 * (size_t)N * sizeof(u32);
   auto kern = k_lds_conv<LN, LRA, 4, kLazy>;
   ensure_lds_attr((const void*)kern, lds);
-  TraceScope ts(s, "lds_conv");
-  kern<<<dim3(1, 1, njobs), lds_conv_threads(LN), lds, s>>>(jr);
-  return hipGetLastError();
+  return launch("lds_conv", kern, dim3(1, 1, njobs), lds_conv_threads(LN), lds, s, jr);
 }
 
 template <int LN>

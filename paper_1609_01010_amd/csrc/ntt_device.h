@@ -37,6 +37,21 @@ struct PrimeTables {
   const uint2* ri[kRoundTables];
 };
 
+// the same tables, reads not merged with those before this point (see fresh)
+__device__ __forceinline__ PrimeTables fresh(const PrimeTables& T) {
+  PrimeTables R;
+  R.pf = fresh(T.pf);
+  R.pi = fresh(T.pi);
+  R.ph = fresh(T.ph);
+  R.iv = fresh(T.iv);
+#pragma unroll
+  for (int q = 0; q < kRoundTables; ++q) {
+    R.rf[q] = fresh(T.rf[q]);
+    R.ri[q] = fresh(T.ri[q]);
+  }
+  return R;
+}
+
 // ---------------------------------------------------------------------------
 // In-register transforms of size Q (compile time), values x[0..Q).
 
@@ -52,7 +67,7 @@ __device__ __forceinline__ void dif_reg(const Arith<LAZY>& A, u32* x, const uint
         if (i == 0)
           bfly_dif1(A, x[blk + i], x[blk + i + h]);
         else
-          bfly_dif(A, x[blk + i], x[blk + i + h], pf[2 * h + i]);
+          bfly_dif(A, x[blk + i], x[blk + i + h], cld(pf + 2 * h + i));
       }
     }
   }
@@ -70,7 +85,7 @@ __device__ __forceinline__ void dit_reg(const Arith<LAZY>& A, u32* x, const uint
         if (i == 0)
           bfly_dit1(A, x[blk + i], x[blk + i + h]);
         else
-          bfly_dit(A, x[blk + i], x[blk + i + h], pi[2 * h + i]);
+          bfly_dit(A, x[blk + i], x[blk + i + h], cld(pi + 2 * h + i));
       }
     }
   }
@@ -101,7 +116,7 @@ struct ItftReg {
         // full scale-1 inverse of the left half
         dit_reg_off<h, OFF>(A, v, T.pi);
         if constexpr (h > 1) {
-          const uint2 ih = T.iv[ilog2c(h)];
+          const uint2 ih = cld(T.iv + ilog2c(h));
 #pragma unroll
           for (int i = 0; i < h; ++i) v[OFF + i] = A.mul(v[OFF + i], ih);
         }
@@ -109,14 +124,14 @@ struct ItftReg {
         for (int i = MK - h; i < h; ++i) {
           u32 a = A.sub(v[OFF + i], v[OFF + h + i]);
           u32 d = A.subraw(a, v[OFF + h + i]);
-          v[OFF + h + i] = (i == 0) ? A.red(d) : A.mul(d, T.pf[N + i]);
+          v[OFF + h + i] = (i == 0) ? A.red(d) : A.mul(d, cld(T.pf + N + i));
           v[OFF + i] = a;
         }
         ItftReg<h, MK - h, OFF + h, LAZY>::run(A, v, T);
-        const uint2 half = T.iv[1];
+        const uint2 half = cld(T.iv + 1);
 #pragma unroll
         for (int i = 0; i < MK - h; ++i) {
-          u32 t = A.mul(v[OFF + h + i], T.ph[N + i]);
+          u32 t = A.mul(v[OFF + h + i], cld(T.ph + N + i));
           u32 u = A.mul(v[OFF + i], half);
           v[OFF + i] = A.add(u, t);
           v[OFF + h + i] = A.sub(u, t);
@@ -142,7 +157,7 @@ struct ItftReg {
           if (i == 0)
             bfly_dit1(A, v[O + blk + i], v[O + blk + i + hh]);
           else
-            bfly_dit(A, v[O + blk + i], v[O + blk + i + hh], pi[2 * hh + i]);
+            bfly_dit(A, v[O + blk + i], v[O + blk + i + hh], cld(pi + 2 * hh + i));
         }
       }
     }
@@ -182,7 +197,7 @@ __device__ __forceinline__ void load_tw(uint2 (&tw)[Q], const uint2* __restrict_
   const uint4* q = reinterpret_cast<const uint4*>(p);
 #pragma unroll
   for (int t = 0; t < Q / 2; ++t) {
-    const uint4 v = q[t];
+    const uint4 v = cld(q + t);
     tw[2 * t] = make_uint2(v.x, v.y);
     tw[2 * t + 1] = make_uint2(v.z, v.w);
   }
@@ -281,10 +296,12 @@ __device__ __forceinline__ void dit_round_lds(const Arith<LAZY>& A, u32* buf, in
   }
 }
 
-// radix of the round that starts at block size 2^LB
+// radix of the round that starts at block size 2^LB: the remainder of LB
+// modulo LQMAX first, then rounds of radix 2^LQMAX, so that the innermost
+// round (contiguous groups) is a full one
 template <int LB, int LQMAX>
 constexpr int round_lq() {
-  return LB < LQMAX ? LB : LQMAX;
+  return LB % LQMAX == 0 ? LQMAX : LB % LQMAX;
 }
 
 // forward transform of every block of size 2^LB in the buffers (n_el
@@ -341,55 +358,29 @@ __device__ __forceinline__ void dit_lds_from(const Arith<LAZY>& A, u32* buf, int
 // log2 of the block size of the last round of a transform of size 2^LB
 template <int LB, int LQMAX>
 constexpr int last_lb() {
-  if constexpr (LB <= LQMAX)
-    return LB;
-  else
-    return last_lb<LB - LQMAX, LQMAX>();
+  return LB <= LQMAX ? LB : LQMAX;
 }
 
-// All rounds but the last on LDS, then the last round (contiguous groups of
-// Q = 2^last_lb) into registers: x[u Q + t] is slot t of group tid + nthr u.
-// Requires n_el = nthr * EPT.  Ends without a barrier (the caller's next LDS
-// write must be preceded by one).
-template <int LB, int LQMAX, bool LAZY, int EPT>
-__device__ __forceinline__ void dif_lds_to_regs(const Arith<LAZY>& A, u32* buf, int n_el, const PrimeTables& T,
-                                                int tid, int nthr, u32 (&x)[EPT]) {
-  constexpr int LQL = last_lb<LB, LQMAX>();
-  constexpr int QL = 1 << LQL;
-  if constexpr (LB > LQL) {
-    u32* bufs[1] = {buf};
-    // rounds down to block size 2^LQL
-    dif_lds_upto<LB, LQL, LQMAX, LAZY>(A, bufs, n_el, T, tid, nthr);
+// The innermost forward round of two buffers, their pointwise product
+// (Montgomery, then times sc) and the innermost inverse round, fused: each
+// contiguous group of 2^LQL words is read from both buffers by one thread and
+// the result written back over the first, so no barrier separates the three
+// steps.  Needs a barrier before (the rounds above) and after.
+template <int LQL, bool LAZY>
+__device__ __forceinline__ void conv_inner(const Arith<LAZY>& A, u32* sa, const u32* sb, int n_el,
+                                           const PrimeTables& T, int tid, int nthr, uint2 sc) {
+  constexpr int Q = 1 << LQL;
+  for (int g = tid; g < (n_el >> LQL); g += nthr) {
+    u32 x[Q], y[Q];
+    lds_load_contig<Q>(sa, g * Q, x);
+    lds_load_contig<Q>(sb, g * Q, y);
+    dif_reg<Q>(A, x, T.pf);
+    dif_reg<Q>(A, y, T.pf);
+#pragma unroll
+    for (int t = 0; t < Q; ++t) x[t] = A.mul(A.mont(x[t], y[t]), sc);
+    dit_reg<Q>(A, x, T.pi);
+    lds_store_contig<Q>(sa, g * Q, x);
   }
-#pragma unroll
-  for (int u = 0; u < EPT / QL; ++u) {
-    const int g = tid + nthr * u;
-    u32 y[QL];
-    lds_load_contig<QL>(buf, g * QL, y);
-    dif_reg<QL>(A, y, T.pf);
-#pragma unroll
-    for (int t = 0; t < QL; ++t) x[u * QL + t] = y[t];
-  }
-}
-
-// Mirror of dif_lds_to_regs: first inverse round from registers to LDS,
-// then the remaining inverse rounds; ends with a barrier.
-template <int LB, int LQMAX, bool LAZY, int EPT>
-__device__ __forceinline__ void dit_regs_to_lds(const Arith<LAZY>& A, u32* buf, int n_el, const PrimeTables& T,
-                                                int tid, int nthr, u32 (&x)[EPT]) {
-  constexpr int LQL = last_lb<LB, LQMAX>();
-  constexpr int QL = 1 << LQL;
-#pragma unroll
-  for (int u = 0; u < EPT / QL; ++u) {
-    const int g = tid + nthr * u;
-    u32 y[QL];
-#pragma unroll
-    for (int t = 0; t < QL; ++t) y[t] = x[u * QL + t];
-    dit_reg<QL>(A, y, T.pi);
-    lds_store_contig<QL>(buf, g * QL, y);
-  }
-  __syncthreads();
-  if constexpr (LB > LQL) dit_lds_from<LB, LQL, LQMAX, LAZY>(A, buf, n_el, T, tid, nthr);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,7 +396,7 @@ __device__ __forceinline__ void dif_top_reg(const Arith<LAZY>& A, u32 (&x)[1 << 
   const uint4* tw = reinterpret_cast<const uint4*>(T.rf[LQ - 1] + (1 << LB) + tid * Q);
 #pragma unroll
   for (int k = 0; k < Q / 2; ++k) {
-    const uint4 v = tw[k];
+    const uint4 v = cld(tw + k);
     if (k > 0) x[2 * k] = A.mul(x[2 * k], make_uint2(v.x, v.y));
     x[2 * k + 1] = A.mul(x[2 * k + 1], make_uint2(v.z, v.w));
   }
@@ -419,9 +410,39 @@ __device__ __forceinline__ void dit_top_reg(const Arith<LAZY>& A, u32 (&x)[1 << 
   const uint4* tw = reinterpret_cast<const uint4*>(T.ri[LQ - 1] + (1 << LB) + tid * Q);
 #pragma unroll
   for (int k = 0; k < Q / 2; ++k) {
-    const uint4 v = tw[k];
+    const uint4 v = cld(tw + k);
     if (k > 0) x[2 * k] = A.mul(x[2 * k], make_uint2(v.x, v.y));
     x[2 * k + 1] = A.mul(x[2 * k + 1], make_uint2(v.z, v.w));
   }
   dit_reg<Q>(A, x, T.pi);
+}
+
+// ---------------------------------------------------------------------------
+// Four-step row helpers.  A row of C = 2^LC words is held by NT threads,
+// thread tid owning elements tid + NT e (e < EPT = 2^LE, a coalesced load).
+
+// Twiddle element j2 = tid + NT e by g * f[e] (g = w_L^{k1 tid}, f[e] =
+// w_L^{k1 NT e}), then the outermost round in registers (dif_top_reg).
+template <int LC, int LE, bool LAZY>
+__device__ __forceinline__ void row_twist_fwd(const Arith<LAZY>& A, u32 (&x)[1 << LE], uint2 g,
+                                              const uint2* __restrict__ f, const PrimeTables& T, int tid) {
+#pragma unroll
+  for (int e = 0; e < (1 << LE); ++e) x[e] = A.mul(A.mul(x[e], g), cld(f + e));
+  dif_top_reg<LC, LE, LAZY>(A, x, T, tid);
+}
+
+// The innermost forward round from LDS into registers: x[u Q + t] is slot t
+// of the contiguous group tid + nthr u (Q = 2^LQL).
+template <int LQL, int EPT, bool LAZY>
+__device__ __forceinline__ void row_last_fwd(const Arith<LAZY>& A, const u32* buf, u32 (&x)[EPT],
+                                             const PrimeTables& T, int tid, int nthr) {
+  constexpr int QL = 1 << LQL;
+#pragma unroll
+  for (int u = 0; u < EPT / QL; ++u) {
+    u32 y[QL];
+    lds_load_contig<QL>(buf, (tid + nthr * u) * QL, y);
+    dif_reg<QL>(A, y, T.pf);
+#pragma unroll
+    for (int t = 0; t < QL; ++t) x[u * QL + t] = y[t];
+  }
 }

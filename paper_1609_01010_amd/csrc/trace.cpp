@@ -1,6 +1,7 @@
-// Kernel tracing: when enabled, every library kernel launch is bracketed by
-// two HIP events on its stream; pm_trace_query aggregates the durations by
-// kernel name.  Off by default (one relaxed load per launch).
+// Kernel tracing: when enabled, every library kernel launch carries a start
+// and a stop event (graph launches are bracketed by two); pm_trace_query
+// aggregates the durations by kernel name.  Off by default (one relaxed load
+// per launch).
 #include "trace.h"
 
 #include <atomic>
@@ -37,6 +38,20 @@ static hipEvent_t take_event() {
 }
 
 bool trace_on() { return g_on.load(std::memory_order_relaxed) && !g_suppress; }
+
+bool trace_begin(const char* name, hipEvent_t* start, hipEvent_t* stop) {
+  if (!trace_on()) return false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Rec r;
+  r.name = name;
+  r.a = take_event();
+  r.b = take_event();
+  if (!r.a || !r.b) return false;
+  g_recs.push_back(r);
+  *start = r.a;
+  *stop = r.b;
+  return true;
+}
 
 TraceScope::TraceScope(hipStream_t s_, const char* name) : s(s_), slot(-1) {
   if (!trace_on()) return;

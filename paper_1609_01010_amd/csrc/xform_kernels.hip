@@ -110,9 +110,7 @@ static hipError_t lds_xform_inst(const Plan& P, const u32* in, long zin, u32* ou
   const size_t lds = (size_t)N * sizeof(u32);
   auto kern = k_lds_xform<LN, LRA, LAZY>;
   ensure_lds_attr((const void*)kern, lds);
-  TraceScope ts(s, "lds_xform");
-  kern<<<1, nthr, lds, s>>>(in, (int)zin, out, (int)nout, P.ma, dir, natural, mp, T, sc, err);
-  return hipGetLastError();
+  return launch("lds_xform", kern, 1, nthr, lds, s, in, (int)zin, out, (int)nout, P.ma, dir, natural, mp, T, sc, err);
 }
 
 template <int LN, bool LAZY>
@@ -144,52 +142,88 @@ hipError_t PM_SUFFIX(launch_lds_xform)(const Plan& P, const u32* in, long zin, u
 // ---------------------------------------------------------------------------
 // four-step row transforms (one operand): forward = twiddle by w_L^{j2 k1}
 // then DIF; inverse = DIT, then untwiddle by w_L^{-j2 k1} times the scale
-// folded into the row tables.
+// folded into the row tables.  As in the convolution's row pass, the
+// outermost round runs in registers beside the coalesced load (forward) or
+// store (inverse) and the innermost one beside the contiguous store (forward)
+// or load (inverse); the rounds between use LDS.
 
-template <int LC, int LNT, bool LAZY>
-__global__ void __launch_bounds__(1 << LNT) k_row_xform(const u32* in, u32* out, long nout, int dir, int logR, ModP mp,
-                                                        PrimeTables T, RowTables W) {
+template <int LC, int LNT, int LQ, bool LAZY>
+__global__ void __launch_bounds__(1 << LNT) k_row_fwd(const u32* in, u32* out, long nout, int logR, ModP mp,
+                                                      PrimeTables T, RowTables W) {
   constexpr int C = 1 << LC;
   constexpr int NT = 1 << LNT;
-  constexpr int EPT = C / NT;
+  constexpr int LE = LC - LNT;
+  constexpr int EPT = 1 << LE;
+  constexpr int LQL = last_lb<LNT, LQ>();
+  constexpr int QL = 1 << LQL;
   extern __shared__ u32 sm[];
   const Arith<LAZY> A(mp);
   const int tid = threadIdx.x;
   const int row = blockIdx.x;
   const u32 k1 = bitrev_n((u32)row, logR);
   const long off = (long)row * C;
-  if (dir == 0) {
-    const uint2 gf = W.gf[k1 * (u32)tid];
-    const uint2* ff = W.ff + (size_t)k1 * EPT;
+  const uint2 gf = cld(W.gf + k1 * (u32)tid);
+  const uint2* ff = W.ff + (size_t)k1 * EPT;
+  u32 x[EPT];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int i = tid + NT * e;
-      sm[lds_ix(i)] = A.mul(A.mul(in[off + i], gf), ff[e]);
-    }
-    __syncthreads();
-    u32* bufs[1] = {sm};
-    dif_lds<LC, 4, LAZY, 1>(A, bufs, C, T, tid, NT);
+  for (int e = 0; e < EPT; ++e) x[e] = in[off + tid + NT * e];
+  row_twist_fwd<LC, LE, LAZY>(A, x, gf, ff, T, tid);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int i = tid + NT * e;
-      if (off + i < nout) out[off + i] = A.canon(sm[lds_ix(i)]);
-    }
-  } else {
-    const uint2 gi = W.gi[k1 * (u32)tid];
-    const uint2* fi = W.fi + (size_t)k1 * EPT;
+  for (int t = 0; t < EPT; ++t) sm[lds_ix(tid + NT * t)] = x[t];
+  __syncthreads();
+  u32* bufs[1] = {sm};
+  dif_lds_upto<LNT, LQL, LQ, LAZY, 1>(A, bufs, C, T, tid, NT);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int i = tid + NT * e;
-      sm[lds_ix(i)] = in[off + i];
-    }
-    __syncthreads();
-    dit_lds<LC, 4, LAZY>(A, sm, C, T, tid, NT);
+  for (int u = 0; u < EPT / QL; ++u) {
+    const long base = off + (long)(tid + NT * u) * QL;
+    u32 y[QL];
+    lds_load_contig<QL>(sm, (tid + NT * u) * QL, y);
+    dif_reg<QL>(A, y, T.pf);
+    if (base + QL <= nout) {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int i = tid + NT * e;
-      out[off + i] = A.mul(A.mul(sm[lds_ix(i)], gi), fi[e]);
+      for (int t = 0; t < QL; ++t) out[base + t] = A.canon(y[t]);
+    } else {
+#pragma unroll
+      for (int t = 0; t < QL; ++t)
+        if (base + t < nout) out[base + t] = A.canon(y[t]);
     }
   }
+}
+
+template <int LC, int LNT, int LQ, bool LAZY>
+__global__ void __launch_bounds__(1 << LNT) k_row_inv(const u32* in, u32* out, int logR, ModP mp, PrimeTables T,
+                                                      RowTables W) {
+  constexpr int C = 1 << LC;
+  constexpr int NT = 1 << LNT;
+  constexpr int LE = LC - LNT;
+  constexpr int EPT = 1 << LE;
+  constexpr int LQL = last_lb<LNT, LQ>();
+  constexpr int QL = 1 << LQL;
+  extern __shared__ u32 sm[];
+  const Arith<LAZY> A(mp);
+  const int tid = threadIdx.x;
+  const int row = blockIdx.x;
+  const u32 k1 = bitrev_n((u32)row, logR);
+  const long off = (long)row * C;
+#pragma unroll
+  for (int u = 0; u < EPT / QL; ++u) {
+    const long base = off + (long)(tid + NT * u) * QL;
+    u32 y[QL];
+#pragma unroll
+    for (int t = 0; t < QL; ++t) y[t] = in[base + t];
+    dit_reg<QL>(A, y, T.pi);
+    lds_store_contig<QL>(sm, (tid + NT * u) * QL, y);
+  }
+  __syncthreads();
+  dit_lds_from<LNT, LQL, LQ, LAZY>(A, sm, C, T, tid, NT);
+  u32 x[EPT];
+#pragma unroll
+  for (int t = 0; t < EPT; ++t) x[t] = sm[lds_ix(tid + NT * t)];
+  dit_top_reg<LC, LE, LAZY>(A, x, T, tid);
+  const uint2 gi = cld(W.gi + k1 * (u32)tid);
+  const uint2* fi = W.fi + (size_t)k1 * EPT;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) out[off + tid + NT * e] = A.mul(A.mul(x[e], gi), cld(fi + e));
 }
 
 template <int LC, bool LAZY>
@@ -199,12 +233,16 @@ static hipError_t row_xform_inst(const Plan& P, const u32* in, u32* out, long no
   constexpr int LNT = LC - 5 < 6 ? 6 : (LC - 5 > 9 ? 9 : LC - 5);
   if (plan_row_lnt(P) != LNT) return hipErrorInvalidValue;
   const int rows = P.ma << P.logRB;
+  const int logR = P.logRA + P.logRB;
   const size_t lds = (size_t)C * sizeof(u32);
-  auto kern = k_row_xform<LC, LNT, LAZY>;
+  if (dir == 0) {
+    auto kern = k_row_fwd<LC, LNT, 3, LAZY>;
+    ensure_lds_attr((const void*)kern, lds);
+    return launch("row_xform", kern, rows, 1 << LNT, lds, s, in, out, nout, logR, mp, T, W);
+  }
+  auto kern = k_row_inv<LC, LNT, 3, LAZY>;
   ensure_lds_attr((const void*)kern, lds);
-  TraceScope ts(s, "row_xform");
-  kern<<<rows, 1 << LNT, lds, s>>>(in, out, nout, dir, P.logRA + P.logRB, mp, T, W);
-  return hipGetLastError();
+  return launch("row_xform", kern, rows, 1 << LNT, lds, s, in, out, logR, mp, T, W);
 }
 
 hipError_t PM_SUFFIX(launch_row_xform)(const Plan& P, const u32* in, u32* out, long nout, int dir, int pidx,
@@ -242,9 +280,7 @@ __global__ void k_permute(const u32* __restrict__ in, u32* __restrict__ out, int
 
 hipError_t launch_permute(const u32* in, u32* out, int logR, int logC, int to_natural, hipStream_t s) {
   const long n = 1l << (logR + logC);
-  TraceScope ts(s, "permute");
-  k_permute<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, out, logR, logC, to_natural);
-  return hipGetLastError();
+  return launch("permute", k_permute, (unsigned)((n + 255) / 256), 256, 0, s, in, out, logR, logC, to_natural);
 }
 
 #endif
