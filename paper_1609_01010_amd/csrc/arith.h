@@ -82,6 +82,8 @@ struct Arith {
     return LAZY ? r : min(r, r - p);
   }
   __device__ __forceinline__ u32 mul(u32 x, uint2 wp) const { return mul(x, wp.x, wp.y); }
+  // the same, left in [0, 2p): only for a value that is multiplied again
+  __device__ __forceinline__ u32 mul_raw(u32 x, uint2 wp) const { return x * wp.x - __umulhi(x, wp.y) * p; }
   // a * b * 2^-32 mod p for a, b in [0, K); result in [0, K)
   __device__ __forceinline__ u32 mont(u32 a, u32 b) const {
     u32 lo = a * b;
@@ -90,6 +92,12 @@ struct Arith {
     u32 t = __umulhi(m, p);
     u32 r = hi + t + (lo != 0u ? 1u : 0u);  // (a*b + m*p) / 2^32 < 2p
     return LAZY ? r : min(r, r - p);
+  }
+  // the same, left in [0, 2p): only for a value that is multiplied again
+  __device__ __forceinline__ u32 mont_raw(u32 a, u32 b) const {
+    u32 lo = a * b;
+    u32 m = lo * ninv;
+    return __umulhi(a, b) + __umulhi(m, p) + (lo != 0u ? 1u : 0u);
   }
   // any value in [0, K) -> canonical [0, p)
   __device__ __forceinline__ u32 canon(u32 x) const { return LAZY ? min(x, x - p) : x; }
@@ -110,6 +118,14 @@ __device__ __forceinline__ void bfly_dif1(const Arith<LAZY>& A, u32& a, u32& b) 
   b = A.sub(a, b);
   a = s;
 }
+// the same, outputs left in [0, 2K) (a + b and a - b + K): only where both
+// are multiplied next (Shoup accepts any 32-bit input)
+template <bool LAZY>
+__device__ __forceinline__ void bfly_dif1_raw(const Arith<LAZY>& A, u32& a, u32& b) {
+  u32 s = a + b;
+  b = A.subraw(a, b);
+  a = s;
+}
 template <bool LAZY>
 __device__ __forceinline__ void bfly_dit(const Arith<LAZY>& A, u32& a, u32& b, uint2 w) {
   u32 t = A.mul(b, w);
@@ -121,6 +137,20 @@ __device__ __forceinline__ void bfly_dit1(const Arith<LAZY>& A, u32& a, u32& b) 
   u32 t = b;
   b = A.sub(a, t);
   a = A.add(a, t);
+}
+// DIT butterflies with outputs left in [0, 2K): only where both are
+// multiplied next
+template <bool LAZY>
+__device__ __forceinline__ void bfly_dit_raw(const Arith<LAZY>& A, u32& a, u32& b, uint2 w) {
+  u32 t = A.mul(b, w);
+  b = A.subraw(a, t);
+  a = a + t;
+}
+template <bool LAZY>
+__device__ __forceinline__ void bfly_dit1_raw(const Arith<LAZY>& A, u32& a, u32& b) {
+  u32 t = b;
+  b = A.subraw(a, t);
+  a = a + t;
 }
 
 __host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }

@@ -75,12 +75,13 @@ struct BatchState {
   size_t staging_cap = 0;
   hipEvent_t staged = nullptr;  // the last upload from `staging` has completed
 };
-std::map<int, BatchState*> g_batch;
+// one state per (device, stream): batches on different streams may overlap
+std::map<std::pair<int, hipStream_t>, BatchState*> g_batch;
 
 constexpr int kBranches = 4;
 
-pm_status batch_state(DevCtx* c, BatchState** out) {
-  auto it = g_batch.find(c->dev);
+pm_status batch_state(DevCtx* c, hipStream_t s, BatchState** out) {
+  auto it = g_batch.find({c->dev, s});
   if (it != g_batch.end()) {
     *out = it->second;
     return PM_OK;
@@ -91,7 +92,7 @@ pm_status batch_state(DevCtx* c, BatchState** out) {
   for (auto& s : b->branches)
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PM_EDEVICE;
   if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) return PM_EDEVICE;
-  g_batch[c->dev] = b;
+  g_batch[{c->dev, s}] = b;
   *out = b;
   return PM_OK;
 }
@@ -172,13 +173,18 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
   if (!c) return st;
   std::lock_guard<std::mutex> lk(c->mu);
   BatchState* B;
-  st = batch_state(c, &B);
+  st = batch_state(c, s, &B);
   if (st) return st;
+  void* ws_cur = nullptr;
+  {
+    auto it = c->ws.find(s);
+    if (it != c->ws.end()) ws_cur = it->second.first;
+  }
 
   // fast path: the same shape as the previous batch
   {
     LastShape& L = B->last;
-    bool same = L.graph && L.key.size() == 3 * count && L.epoch == plan_epoch() && L.ws == c->ws;
+    bool same = L.graph && L.key.size() == 3 * count && L.epoch == plan_epoch() && L.ws == ws_cur;
     for (size_t i = 0; same && i < count; ++i)
       same = L.key[3 * i] == probs[i].len_a && L.key[3 * i + 1] == probs[i].len_b && L.key[3 * i + 2] == probs[i].p;
     if (same) {
@@ -219,15 +225,16 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
     groups[class_key(plans[i], prime_info(pidx[i]).lazy)].push_back(i);
     wsb += (plan_workspace_bytes(plans[i]) + 255) & ~(size_t)255;
   }
+  void* wsp = nullptr;
   if (wsb) {
-    st = ensure_workspace(c, wsb);
+    st = stream_workspace(c, s, wsb, &wsp);
     if (st) return st;
   }
   std::vector<ClassRun> runs;
   std::vector<ConvJob> jobs;
   std::vector<int> order;
   jobs.reserve(count);
-  char* ws = (char*)c->ws;
+  char* ws = (char*)wsp;
   for (auto& kv : groups) {
     ClassRun r;
     r.key = kv.first;
@@ -305,7 +312,7 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
       L.key[3 * i + 2] = probs[i].p;
     }
     L.epoch = plan_epoch();
-    L.ws = c->ws;
+    L.ws = wsp;
     L.jobs = jobs;
     L.order = order;
     L.direct = direct;

@@ -43,7 +43,8 @@ bool plan_valid(const Plan& P, long lc, int pidx) {
     if (P.logC < 10 || P.logC > 14) return false;
     if (P.logRB < 0 || P.logRB > 5 || (P.logRB > 0 && P.logRA < 4)) return false;
     const int lnt = plan_row_lnt(P);
-    if (lnt < 6 || lnt > 10 || P.logC - lnt < 4 || P.logC - lnt > 6) return false;
+    if (lnt < 6 || lnt > 10 || P.logC - lnt < 3 || P.logC - lnt > 6) return false;
+    if (P.logC - lnt == 3 && P.lq == 4) return false;  // 8 values per thread: innermost radix 8
     return P.logL == P.logRA + P.logRB + P.logC;
   }
   return false;
@@ -352,11 +353,12 @@ static pm_status product_with(const uint32_t* a, size_t len_a, const uint32_t* b
   Plan P = given ? *given : choose_plan(lc, pidx, ctx, (hipStream_t)stream);
   if (!plan_valid(P, lc, pidx)) return given ? PM_EINVAL : PM_ETOOLARGE;
   const size_t wsb = plan_workspace_bytes(P);
+  void* ws = nullptr;
   if (wsb) {
-    st = ensure_workspace(ctx, wsb);
+    st = stream_workspace(ctx, (hipStream_t)stream, wsb, &ws);
     if (st) return st;
   }
-  return run_product(ctx, P, a, (long)len_a, b, (long)len_b, 0, c, lc, pidx, ctx->ws, (hipStream_t)stream);
+  return run_product(ctx, P, a, (long)len_a, b, (long)len_b, 0, c, lc, pidx, ws, (hipStream_t)stream);
 }
 
 pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p, uint32_t* c,
@@ -477,12 +479,13 @@ pm_status pm_ntt(const uint32_t* x, uint32_t* y, size_t n, uint32_t p, int inver
   if (P.kind == PLAN_LDS)
     return dev_status(launch_lds_xform(P, x, (long)n, y, (long)n, inverse ? 1 : 0, 1, pidx, c->tabs[pidx], ninv,
                                        c->errflag, s));
-  st = ensure_workspace(c, n * sizeof(u32));
+  void* wsp = nullptr;
+  st = stream_workspace(c, s, n * sizeof(u32), &wsp);
   if (st) return st;
   RowTables S;
   st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), inverse ? ninv.x : 1u, &S);
   if (st) return st;
-  u32* T = (u32*)c->ws;
+  u32* T = (u32*)wsp;
   const int logR = P.logRA + P.logRB;
   hipError_t e;
   JobRef jr;
@@ -516,12 +519,13 @@ pm_status pm_tft(const uint32_t* x, size_t z, size_t L, size_t n, uint32_t p, ui
   if (P.kind == PLAN_LDS)
     return dev_status(
         launch_lds_xform(P, x, (long)z, out, (long)n, 0, 0, pidx, c->tabs[pidx], one, c->errflag, s));
-  st = ensure_workspace(c, (size_t)plan_nprime(P) * sizeof(u32));
+  void* wsp = nullptr;
+  st = stream_workspace(c, s, (size_t)plan_nprime(P) * sizeof(u32), &wsp);
   if (st) return st;
   RowTables S;
   st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), 1u, &S);
   if (st) return st;
-  u32* T = (u32*)c->ws;
+  u32* T = (u32*)wsp;
   JobRef jr;
   jr.many = nullptr;
   st = make_job(c, P, pidx, x, (long)z, nullptr, 0, out, (long)n, T, nullptr, &jr.one);
@@ -547,12 +551,13 @@ pm_status pm_itft(const uint32_t* v, size_t L, size_t n, uint32_t p, uint32_t* o
   const uint2 sc = h_shoup(full ? 1u : (u32)(1u << P.logRA), PI.p);
   if (P.kind == PLAN_LDS)
     return dev_status(launch_lds_xform(P, v, (long)n, out, (long)n, 1, 0, pidx, c->tabs[pidx], sc, c->errflag, s));
-  st = ensure_workspace(c, (size_t)plan_nprime(P) * sizeof(u32));
+  void* wsp = nullptr;
+  st = stream_workspace(c, s, (size_t)plan_nprime(P) * sizeof(u32), &wsp);
   if (st) return st;
   RowTables S;
   st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), sc.x, &S);
   if (st) return st;
-  u32* T = (u32*)c->ws;
+  u32* T = (u32*)wsp;
   JobRef jr;
   jr.many = nullptr;
   st = make_job(c, P, pidx, v, (long)n, nullptr, 0, out, (long)n, T, nullptr, &jr.one);
@@ -592,9 +597,10 @@ pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb,
   const size_t res_b = al((size_t)lc * 4);
   const size_t wid_b = widen ? al((na + nb) * 4) : 0;
   const size_t total = 3 * res_b + wid_b + al(pw) + al(crt_workspace_bytes(nl));
-  st = ensure_workspace(c, total);
+  void* wsp = nullptr;
+  st = stream_workspace(c, s, total, &wsp);
   if (st) return st;
-  char* base = (char*)c->ws;
+  char* base = (char*)wsp;
   u32* res[3] = {(u32*)base, (u32*)(base + res_b), (u32*)(base + 2 * res_b)};
   u32* wa = (u32*)(base + 3 * res_b);
   u32* wb = wa + na;

@@ -112,7 +112,7 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
           x[s] = sm[(row << lw) + c];
         }
       }
-      dif_reg<Q>(A, x, T.pf);
+      dif_reg<Q, LAZY, (LS > 0)>(A, x, T.pf);
       const uint2* tw = T.rf[LQ - 1] + (1 << LB) + j * Q;
 #pragma unroll
       for (int t = 0; t < Q; ++t) {
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(1 << LNT) k_row_conv(JobRef jr, int logR) {
   const uint2 gi = cld(J.W.gi + k1 * (u32)tid);
   const uint2* fi = J.W.fi + (size_t)k1 * EPT;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) gst(Ta + off + tid + NT * e, A.mul(A.mul(xa[e], gi), cld(fi + e)));
+  for (int e = 0; e < EPT; ++e) gst(Ta + off + tid + NT * e, A.mul(A.mul_raw(xa[e], gi), cld(fi + e)));
 }
 
 template <int LC, int LNT>
@@ -333,7 +333,10 @@ static hipError_t row_conv_inst(const Plan& P, int max_rows, const JobRef& jr, i
   constexpr int NB = LC <= 13 ? 2 : 1;
   const int logR = P.logRA + P.logRB;
   const size_t lds = (size_t)NB * C * sizeof(u32);
-  auto kern = P.lq == 3 ? k_row_conv<LC, 3, LNT, NB, kLazy> : k_row_conv<LC, 4, LNT, NB, kLazy>;
+  auto kern = k_row_conv<LC, 3, LNT, NB, kLazy>;
+  if constexpr (LC - LNT >= 4) {
+    if (P.lq == 4) kern = k_row_conv<LC, 4, LNT, NB, kLazy>;
+  }
   ensure_lds_attr((const void*)kern, lds);
   return launch("row_conv", kern, dim3(max_rows, 1, njobs), 1 << LNT, lds, s, jr, logR);
 }
@@ -343,7 +346,7 @@ static hipError_t row_conv_lc(const Plan& P, int max_rows, const JobRef& jr, int
   switch (plan_row_lnt(P)) {
 #define PM_NT(n)                                                               \
   case n:                                                                      \
-    if constexpr (LC - n >= 4 && LC - n <= 6 && n >= 6 && n <= 10)             \
+    if constexpr (LC - n >= 3 && LC - n <= 6 && n >= 6 && n <= 10)             \
       return row_conv_inst<LC, n>(P, max_rows, jr, njobs, s);                  \
     break;
     PM_NT(6) PM_NT(7) PM_NT(8) PM_NT(9) PM_NT(10)

@@ -62,14 +62,16 @@ struct DevCtx {
   PrimeTables tabs[kNumPrimes];
   std::map<RowKey, std::pair<uint2*, RowTables>> rowtw;
   int* errflag = nullptr;  // device word: bit 0 = input not reduced
-  void* ws = nullptr;      // workspace
-  size_t ws_bytes = 0;
+  // workspace per stream: calls on different streams may run concurrently,
+  // calls on one stream are ordered by it
+  std::map<hipStream_t, std::pair<void*, size_t>> ws;
   std::mutex mu;
 };
 
 DevCtx* ctx_current(pm_status* st);
 pm_status ensure_prime_tables(DevCtx* c, int pidx);
-pm_status ensure_workspace(DevCtx* c, size_t bytes);
+// the workspace of stream s, grown to at least `bytes`
+pm_status stream_workspace(DevCtx* c, hipStream_t s, size_t bytes, void** out);
 // scale: the value multiplied into the inverse factors (1 for none)
 pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, RowTables* out);
 

@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
         x[s] = pos < len ? gld(in + pos) : 0u;
         bad |= x[s] >= J.mp.p;
       }
-      dif_reg<RA>(A, x, T.pf);
+      dif_reg<RA, LAZY, (S > 1)>(A, x, T.pf);
 #pragma unroll
       for (int t = 0; t < RA; ++t) {
         if (t < ma) {

@@ -55,8 +55,10 @@ __device__ __forceinline__ PrimeTables fresh(const PrimeTables& T) {
 // ---------------------------------------------------------------------------
 // In-register transforms of size Q (compile time), values x[0..Q).
 
-// forward DIF: natural in, bit-reversed out
-template <int Q, bool LAZY>
+// forward DIF: natural in, bit-reversed out.  RAW_TAIL: outputs 1..Q-1 are
+// left in [0, 2K) (for a caller that multiplies each of them next); output 0
+// is always reduced.
+template <int Q, bool LAZY, bool RAW_TAIL = false>
 __device__ __forceinline__ void dif_reg(const Arith<LAZY>& A, u32* x, const uint2* __restrict__ pf) {
 #pragma unroll
   for (int h = Q / 2; h >= 1; h >>= 1) {
@@ -64,17 +66,25 @@ __device__ __forceinline__ void dif_reg(const Arith<LAZY>& A, u32* x, const uint
     for (int blk = 0; blk < Q; blk += 2 * h) {
 #pragma unroll
       for (int i = 0; i < h; ++i) {
-        if (i == 0)
-          bfly_dif1(A, x[blk + i], x[blk + i + h]);
-        else
+        if (i != 0)
           bfly_dif(A, x[blk + i], x[blk + i + h], cld(pf + 2 * h + i));
+        else if (RAW_TAIL && h == 1 && blk > 0)
+          bfly_dif1_raw(A, x[blk], x[blk + 1]);
+        else if (RAW_TAIL && h == 1) {
+          const u32 a = x[0], b = x[1];
+          x[0] = A.add(a, b);
+          x[1] = A.subraw(a, b);
+        } else
+          bfly_dif1(A, x[blk + i], x[blk + i + h]);
       }
     }
   }
 }
 
-// inverse DIT, unscaled (returns Q * x): bit-reversed in, natural out
-template <int Q, bool LAZY>
+// inverse DIT, unscaled (returns Q * x): bit-reversed in, natural out.
+// RAW_OUT: all outputs left in [0, 2K) (for a caller that multiplies each of
+// them next).
+template <int Q, bool LAZY, bool RAW_OUT = false>
 __device__ __forceinline__ void dit_reg(const Arith<LAZY>& A, u32* x, const uint2* __restrict__ pi) {
 #pragma unroll
   for (int h = 1; h < Q; h <<= 1) {
@@ -82,7 +92,12 @@ __device__ __forceinline__ void dit_reg(const Arith<LAZY>& A, u32* x, const uint
     for (int blk = 0; blk < Q; blk += 2 * h) {
 #pragma unroll
       for (int i = 0; i < h; ++i) {
-        if (i == 0)
+        if (RAW_OUT && 2 * h == Q) {
+          if (i == 0)
+            bfly_dit1_raw(A, x[blk + i], x[blk + i + h]);
+          else
+            bfly_dit_raw(A, x[blk + i], x[blk + i + h], cld(pi + 2 * h + i));
+        } else if (i == 0)
           bfly_dit1(A, x[blk + i], x[blk + i + h]);
         else
           bfly_dit(A, x[blk + i], x[blk + i + h], cld(pi + 2 * h + i));
@@ -253,7 +268,7 @@ __device__ __forceinline__ void dif_round_lds(const Arith<LAZY>& A, u32* const* 
 #pragma unroll
         for (int s = 0; s < Q; ++s) x[s] = buf[lds_ix(base + S * s)];
       }
-      dif_reg<Q>(A, x, T.pf);
+      dif_reg<Q, LAZY, (S > 1)>(A, x, T.pf);
       if constexpr (S > 1) {
 #pragma unroll
         for (int t = 1; t < Q; ++t) x[t] = A.mul(x[t], tw[t]);
@@ -377,7 +392,7 @@ __device__ __forceinline__ void conv_inner(const Arith<LAZY>& A, u32* sa, const 
     dif_reg<Q>(A, x, T.pf);
     dif_reg<Q>(A, y, T.pf);
 #pragma unroll
-    for (int t = 0; t < Q; ++t) x[t] = A.mul(A.mont(x[t], y[t]), sc);
+    for (int t = 0; t < Q; ++t) x[t] = A.mul(A.mont_raw(x[t], y[t]), sc);
     dit_reg<Q>(A, x, T.pi);
     lds_store_contig<Q>(sa, g * Q, x);
   }
@@ -392,7 +407,7 @@ __device__ __forceinline__ void conv_inner(const Arith<LAZY>& A, u32* sa, const 
 template <int LB, int LQ, bool LAZY>
 __device__ __forceinline__ void dif_top_reg(const Arith<LAZY>& A, u32 (&x)[1 << LQ], const PrimeTables& T, int tid) {
   constexpr int Q = 1 << LQ;
-  dif_reg<Q>(A, x, T.pf);
+  dif_reg<Q, LAZY, true>(A, x, T.pf);
   const uint4* tw = reinterpret_cast<const uint4*>(T.rf[LQ - 1] + (1 << LB) + tid * Q);
 #pragma unroll
   for (int k = 0; k < Q / 2; ++k) {
@@ -403,7 +418,8 @@ __device__ __forceinline__ void dif_top_reg(const Arith<LAZY>& A, u32 (&x)[1 << 
 }
 
 // Mirror of dif_top_reg (the last round of dit_lds, unscaled): x[t] holds
-// position tid + (B/Q) t; on return x[s] is element tid + (B/Q) s.
+// position tid + (B/Q) t; on return x[s] is element tid + (B/Q) s, left in
+// [0, 2K) (every caller multiplies it by its untwiddle next).
 template <int LB, int LQ, bool LAZY>
 __device__ __forceinline__ void dit_top_reg(const Arith<LAZY>& A, u32 (&x)[1 << LQ], const PrimeTables& T, int tid) {
   constexpr int Q = 1 << LQ;
@@ -414,7 +430,7 @@ __device__ __forceinline__ void dit_top_reg(const Arith<LAZY>& A, u32 (&x)[1 << 
     if (k > 0) x[2 * k] = A.mul(x[2 * k], make_uint2(v.x, v.y));
     x[2 * k + 1] = A.mul(x[2 * k + 1], make_uint2(v.z, v.w));
   }
-  dit_reg<Q>(A, x, T.pi);
+  dit_reg<Q, LAZY, true>(A, x, T.pi);
 }
 
 // ---------------------------------------------------------------------------
@@ -427,7 +443,7 @@ template <int LC, int LE, bool LAZY>
 __device__ __forceinline__ void row_twist_fwd(const Arith<LAZY>& A, u32 (&x)[1 << LE], uint2 g,
                                               const uint2* __restrict__ f, const PrimeTables& T, int tid) {
 #pragma unroll
-  for (int e = 0; e < (1 << LE); ++e) x[e] = A.mul(A.mul(x[e], g), cld(f + e));
+  for (int e = 0; e < (1 << LE); ++e) x[e] = A.mul(A.mul_raw(x[e], g), cld(f + e));
   dif_top_reg<LC, LE, LAZY>(A, x, T, tid);
 }
 

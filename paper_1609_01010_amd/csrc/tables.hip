@@ -233,17 +233,21 @@ pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 s
   return PM_OK;
 }
 
-pm_status ensure_workspace(DevCtx* c, size_t bytes) {
-  if (c->ws_bytes >= bytes) return PM_OK;
-  if (c->ws) {
-    if (hipDeviceSynchronize() != hipSuccess) return PM_EDEVICE;
-    hipFree(c->ws);
-    c->ws = nullptr;
-    c->ws_bytes = 0;
+pm_status stream_workspace(DevCtx* c, hipStream_t s, size_t bytes, void** out) {
+  auto& w = c->ws[s];
+  if (w.second < bytes) {
+    if (w.first) {
+      // work already queued on s may still use the old buffer
+      if (hipStreamSynchronize(s) != hipSuccess) return PM_EDEVICE;
+      hipFree(w.first);
+      w.first = nullptr;
+      w.second = 0;
+    }
+    size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+    if (hipMalloc(&w.first, want) != hipSuccess) return PM_ENOMEM;
+    w.second = want;
   }
-  size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
-  if (hipMalloc(&c->ws, want) != hipSuccess) return PM_ENOMEM;
-  c->ws_bytes = want;
+  *out = w.first;
   return PM_OK;
 }
 

@@ -102,18 +102,19 @@ static pm_status tune_inputs(long lc, u32 p, TuneBufs* T, hipStream_t s) {
 static pm_status time_plan(DevCtx* c, const Plan& P, long lc, int pidx, const TuneBufs& B, int reps, hipStream_t s,
                            double* us) {
   const size_t wsb = plan_workspace_bytes(P);
+  void* ws = nullptr;
   if (wsb) {
-    pm_status st = ensure_workspace(c, wsb);
+    pm_status st = stream_workspace(c, s, wsb, &ws);
     if (st) return st;
   }
-  pm_status st = run_product(c, P, B.a, B.la, B.b, B.lb, 0, B.c, lc, pidx, c->ws, s);
+  pm_status st = run_product(c, P, B.a, B.la, B.b, B.lb, 0, B.c, lc, pidx, ws, s);
   if (st) return st;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) || hipEventCreate(&e1)) return PM_EDEVICE;
   std::vector<float> t;
   for (int r = 0; r < reps && st == PM_OK; ++r) {
     hipEventRecord(e0, s);
-    st = run_product(c, P, B.a, B.la, B.b, B.lb, 0, B.c, lc, pidx, c->ws, s);
+    st = run_product(c, P, B.a, B.la, B.b, B.lb, 0, B.c, lc, pidx, ws, s);
     hipEventRecord(e1, s);
     if (hipEventSynchronize(e1) != hipSuccess) st = PM_EDEVICE;
     float ms = 0;

@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(1 << LNT) k_row_inv(const u32* in, u32* out, i
   const uint2 gi = cld(W.gi + k1 * (u32)tid);
   const uint2* fi = W.fi + (size_t)k1 * EPT;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) out[off + tid + NT * e] = A.mul(A.mul(x[e], gi), cld(fi + e));
+  for (int e = 0; e < EPT; ++e) out[off + tid + NT * e] = A.mul(A.mul_raw(x[e], gi), cld(fi + e));
 }
 
 template <int LC, bool LAZY>

@@ -224,6 +224,38 @@ def test_batch_uneven_4096(gpu_lib):
             assert np.array_equal(got[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
 
 
+def test_products_on_concurrent_streams(gpu_lib):
+    """Products and batches issued on two streams without synchronising
+    between them: each stream has its own workspace, so every result is exact."""
+    import torch
+
+    pm = gpu_lib
+    p = 2013265921
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    pairs = [inputs.poly_pair((130, k), la, lb, p) for k, (la, lb) in enumerate(((300000, 200001), (150000, 150000),
+                                                                                  (70001, 9000), (4096, 4096)))]
+    dpairs = [(dev(a), dev(b)) for a, b in pairs]
+    items = inputs.batch_uneven(count=64, lo=1, hi=30000, tag=(131,))
+    ditems = [(dev(it.a), dev(it.b), it.p) for it in items]
+    torch.cuda.synchronize()
+    say("case: two streams, 4 products x 3 rounds + one batch each")
+    outs = []
+    for rnd in range(3):
+        for k, (da, db) in enumerate(dpairs):
+            s = s1 if (k + rnd) % 2 == 0 else s2
+            with torch.cuda.stream(s):
+                outs.append((k, pm.poly_mul(da, db, p, stream=s)))
+    b1 = pm.poly_mul_batch(ditems[:32], stream=s1)
+    b2 = pm.poly_mul_batch(ditems[32:], stream=s2)
+    torch.cuda.synchronize()
+    assert pm.stream_check() == 0
+    for k, c in outs:
+        a, b = pairs[k]
+        assert np.array_equal(host(c), op.poly_mul_ntt(a, b, p, inputs.PRIMES[p])), k
+    for it, c in zip(items, b1 + b2):
+        assert np.array_equal(host(c), op.poly_mul_ntt(it.a, it.b, it.p, inputs.PRIMES[it.p]))
+
+
 def test_not_reduced_input_is_reported(gpu_lib):
     pm = gpu_lib
     p = 998244353
