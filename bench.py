@@ -91,6 +91,16 @@ def learned_pick(pm, lc, p, only_truncated=False):
     return cands[int(pred.argmin())]
 
 
+def tuned_pick(pm, lc, p, only_truncated=False, reps=7):
+    """The autotuner's pick: every candidate plan timed (median of reps runs),
+    the fastest kept (optionally among the relaxed-TFT plans only)."""
+    pm.tune([lc], p, reps=reps)
+    rows = [r for r in pm.tune_db_rows() if r[0] == lc and r[1] == p]
+    if only_truncated:
+        rows = [r for r in rows if r[2].kind != 0 and (r[2].ma << (r[2].log_l - r[2].log_ra)) < (1 << r[2].log_l)]
+    return min(rows, key=lambda r: r[3])[2]
+
+
 def time_calls(torch, fn, reps):
     """Median milliseconds of fn() over reps runs, HIP events on the current stream."""
     import numpy as np
@@ -105,6 +115,51 @@ def time_calls(torch, fn, reps):
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
     return float(np.median(ts))
+
+
+def time_loop(torch, fn, n):
+    """Milliseconds per call of n back-to-back calls, HIP events on the current stream."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(n):
+        fn(i)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def standalone_transform(pm, torch, dev, n_calls=40):
+    """Forward transform of 2^22 points in bit-reversed order (the TFT hook with
+    n = L): two passes over HBM, 16 N algorithmic bytes; 8 rotating buffer
+    pairs (256 MiB); four outputs checked against direct evaluation."""
+    from oracle import poly as op
+    from paper_1609_01010_amd import inputs
+
+    N = 1 << 22
+    out = {}
+    for pp in (2013265921, 998244353):
+        g = inputs.PRIMES[pp]
+        xs = [torch.from_numpy(inputs.uniform_mod(inputs.rng_for((140, pp % 1000, k)), N, pp)).to(dev)
+              for k in range(8)]
+        ys = [torch.empty(N, dtype=torch.uint32, device=dev) for _ in range(8)]
+
+        def fwd(i):
+            pm.tft(xs[i % 8], N, N, pp, out=ys[i % 8])
+
+        for i in range(8):
+            fwd(i)
+        ms = time_loop(torch, fwd, n_calls)
+        x0, y0 = xs[0].cpu().numpy(), ys[0].cpu().numpy()
+        w = op.root(pp, g, N)
+        ok = all(int(y0[i]) == op.eval_at(x0, pp, pow(w, op.bitrev(i, 22), pp)) for i in (0, 1, 12345, N - 1))
+        out[f"ntt_2^22_p{pp}"] = {"us": ms * 1e3, "points_per_s": N / (ms * 1e-3),
+                                  "hbm_alg_GBps": 16 * N / (ms * 1e-3) / 1e9,
+                                  "hbm_frac": 16 * N / (ms * 1e-3) / HBM_PEAK,
+                                  "bit_exact_sampled": bool(ok)}
+        del xs, ys
+    return out
 
 
 def extra_configs(pm, torch, dev, reps=5):
@@ -174,6 +229,7 @@ def extra_configs(pm, torch, dev, reps=5):
         it = items[int(k)]
         ks = rng.integers(0, outs[int(k)].numel(), 4)
         assert np.array_equal(outs[int(k)].cpu().numpy()[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
+    out.update(standalone_transform(pm, torch, dev))
     out["batch_4096_uneven"] = {
         "output_coeffs": ncoef,
         "plain_ms": ms_plain, "plain_coeffs_per_s": ncoef / (ms_plain * 1e-3),
@@ -205,6 +261,9 @@ def main():
     ap.add_argument("--rotate", type=int, default=8, help="buffer sets rotated over the steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--plans", default=None,
+                    help="fixed plans for the two products, 'kind,log_l,log_ra,log_rb,log_c,ma,lq,lnt;...' "
+                         "(skips the autotuner, e.g. for profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 256 MiB three times (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -242,12 +301,24 @@ def main():
     for _ in range(args.rotate):
         sets.append(tuple(torch.from_numpy(x).to(dev) for x in (a2, b2, a3, b3)) +
                     (torch.empty(lc2, dtype=torch.uint32, device=dev), torch.empty(lc3, dtype=torch.uint32, device=dev)))
-    # plans: the trained cost model's picks (for the 10^6 product, among the
-    # relaxed-TFT plans only: the workload excludes padding to 2^20)
+    # plans: the autotuner's picks (exhaustive empirical search, before the
+    # timed region; for the 10^6 product among the relaxed-TFT plans only: the
+    # workload excludes padding to 2^20).  The cost model's picks are listed
+    # beside them.
     pm.model_load(os.path.join(ROOT, "paper_1609_01010_amd", "data", "cost_model.txt"))
-    plan2 = learned_pick(pm, lc2, P)
-    plan3 = learned_pick(pm, lc3, P, only_truncated=True)
-    log("plans:", plan2, plan3)
+    lplan2 = learned_pick(pm, lc2, P)
+    lplan3 = learned_pick(pm, lc3, P, only_truncated=True)
+    if args.plans:
+        plan2, plan3 = (pm.Plan(*[int(v) for v in s.split(",")]) for s in args.plans.split(";"))
+        plan_source = "given on the command line"
+    else:
+        pm.tune_db_clear()
+        plan2 = tuned_pick(pm, lc2, P)
+        plan3 = tuned_pick(pm, lc3, P, only_truncated=True)
+        pm.tune_db_clear()
+        pm.plan_cache_clear()
+        plan_source = "autotuner (every candidate timed, fastest kept)"
+    log("plans:", plan2, plan3, "learned:", lplan2, lplan3)
 
     def step(i):
         ta2, tb2, ta3, tb3, c2, c3 = sets[i % len(sets)]
@@ -346,6 +417,8 @@ def main():
                         "600001 x 400000 (relaxed TFT, 10^6 outputs)",
             "coeffs_per_step": lc2 + lc3,
             "plans": [list(plan2.as_tuple()), list(plan3.as_tuple())],
+            "plan_source": plan_source,
+            "learned_plans": [list(lplan2.as_tuple()), list(lplan3.as_tuple())],
             "dominant_kernel": dom,
             "wall_s": wall,
         },

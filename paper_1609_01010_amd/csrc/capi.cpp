@@ -43,7 +43,7 @@ bool plan_valid(const Plan& P, long lc, int pidx) {
     if (P.logC < 10 || P.logC > 14) return false;
     if (P.logRB < 0 || P.logRB > 5 || (P.logRB > 0 && P.logRA < 4)) return false;
     const int lnt = plan_row_lnt(P);
-    if (lnt < 6 || lnt > 10 || P.logC - lnt < 3 || P.logC - lnt > 6) return false;
+    if (lnt < 6 || lnt > 10 || P.logC - lnt < 3 || P.logC - lnt > 5) return false;
     if (P.logC - lnt == 3 && P.lq == 4) return false;  // 8 values per thread: innermost radix 8
     return P.logL == P.logRA + P.logRB + P.logC;
   }
@@ -57,7 +57,7 @@ static int kept_blocks(long lc, int logL, int logRA) {
 
 Plan default_plan(long lc, int pidx) {
   // measured on MI355X: row length C = L / 256 (at least 2^10, at most 2^14),
-  // columns split 16 x R/16, 32 elements per row thread; truncation with the
+  // columns split 16 x R/16, 16 elements per row thread; truncation with the
   // finest first radix (32) when the output length is not a power of two
   Plan P;
   if (lc <= 64) {
@@ -83,7 +83,7 @@ Plan default_plan(long lc, int pidx) {
       P.logRA = (finer || logR - 4 > 5) ? 5 : 4;
       P.logRB = logR - P.logRA;
     }
-    P.lnt = P.logC - 5 < 6 ? 6 : P.logC - 5;
+    P.lnt = P.logC - 4 < 6 ? 6 : P.logC - 4;
   }
   P.ma = kept_blocks(lc, P.logL, P.logRA);
   return P;
@@ -120,7 +120,7 @@ std::vector<Plan> plan_candidates(long lc, int pidx) {
           for (int lra = 1; lra <= 5; ++lra) {
             const int lrb = lr - lra;
             if (lrb < 0 || lrb > 5 || (lrb > 0 && lra < 4)) continue;
-            for (int lnt = lc_ - 6; lnt <= lc_ - 4; ++lnt) {
+            for (int lnt = lc_ - 5; lnt <= lc_ - 3; ++lnt) {
               Plan P;
               P.kind = PLAN_FOURSTEP;
               P.logL = logL;
@@ -435,7 +435,7 @@ pm_status pm_stream_check(void* stream) {
 size_t pm_itft_granularity(size_t L) { return L <= 32 ? 1 : L / 32; }
 
 // the hooks' plan for length L: one work-group up to 2^14, else four-step
-// with first radix 32
+// with first radix 32, rows of up to 2^14, and 16 values per row thread
 static Plan hook_plan(int logL, int ma) {
   Plan P;
   P.logL = logL;
@@ -447,6 +447,7 @@ static Plan hook_plan(int logL, int ma) {
     P.logRA = 5;
     P.logC = logL - 5 > 14 ? 14 : logL - 5;
     P.logRB = logL - 5 - P.logC;
+    P.lnt = P.logC - 4;
   }
   P.ma = ma;
   return P;

@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(1 << LNT) k_row_conv(JobRef jr, int logR) {
   const long off = (long)row * C;
   u32* Ta = J.Ta;
   const u32* __restrict__ Tb = J.Tb;
-  const uint2 gf = cld(J.W.gf + k1 * (u32)tid);
+  const uint2 gf = cld(J.W.gf + k1 * (u32)NT + tid);
   const uint2* ff = J.W.ff + (size_t)k1 * EPT;
   // b's row is fetched up front (its latency hides behind a's rounds) unless
   // 1024 threads leave too few registers to hold it meanwhile
@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(1 << LNT) k_row_conv(JobRef jr, int logR) {
 #pragma unroll
   for (int t = 0; t < EPT; ++t) xa[t] = sa[lds_ix(tid + NT * t)];
   dit_top_reg<LC, LE, LAZY>(A, xa, T, tid);
-  const uint2 gi = cld(J.W.gi + k1 * (u32)tid);
+  const uint2 gi = cld(J.W.gi + k1 * (u32)NT + tid);
   const uint2* fi = J.W.fi + (size_t)k1 * EPT;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) gst(Ta + off + tid + NT * e, A.mul(A.mul_raw(xa[e], gi), cld(fi + e)));
@@ -346,7 +346,7 @@ static hipError_t row_conv_lc(const Plan& P, int max_rows, const JobRef& jr, int
   switch (plan_row_lnt(P)) {
 #define PM_NT(n)                                                               \
   case n:                                                                      \
-    if constexpr (LC - n >= 3 && LC - n <= 6 && n >= 6 && n <= 10)             \
+    if constexpr (LC - n >= 3 && LC - n <= 5 && n >= 6 && n <= 10)             \
       return row_conv_inst<LC, n>(P, max_rows, jr, njobs, s);                  \
     break;
     PM_NT(6) PM_NT(7) PM_NT(8) PM_NT(9) PM_NT(10)

@@ -5,8 +5,10 @@
 #include "ntt_device.h"
 
 // Row-pass twiddles of the four-step split for (L, C, nt threads): element
-// j2 = tid + nt e of row k1 is multiplied by gf[k1 tid] * ff[k1 ept + e] =
-// w_L^{k1 j2} (forward) or gi[k1 tid] * fi[k1 ept + e] = w_L^{-k1 j2} * scale.
+// j2 = tid + nt e of row k1 is multiplied by gf[k1 nt + tid] * ff[k1 ept + e]
+// = w_L^{k1 j2} (forward) or gi[k1 nt + tid] * fi[k1 ept + e] =
+// w_L^{-k1 j2} * scale.  Both tables are laid out row after row, so a row's
+// threads read them contiguously.
 struct RowTables {
   const uint2* gf;
   const uint2* gi;

@@ -127,9 +127,13 @@ __global__ void k_row_factors(uint2* out, int R, int ept, int nt, u32 Lmask, u32
 }
 
 // out[i] = mult * base^i mod p as Shoup pairs, i < n
-__global__ void k_powtable(uint2* out, int n, u32 p, u32 base, u32 mult) {
+// Row-pass per-thread factors, one row after the other:
+// out[k1 * nt + tid] = base^(k1 tid), k1 < R, tid < nt
+__global__ void k_row_pows(uint2* out, int R, int nt, u32 p, u32 base) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = d_shoup(d_mulmod(mult, d_powmod(base, (u32)i, p), p), p);
+  if (i >= R * nt) return;
+  const u32 k1 = (u32)(i / nt), tid = (u32)(i % nt);
+  out[i] = d_shoup(d_powmod(base, k1 * tid, p), p);
 }
 
 // ---------------------------------------------------------------------------
@@ -216,8 +220,8 @@ pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 s
   uint2* ff = gi + ng;
   uint2* fi = ff + nf;
   const u32 Lmask = (u32)((1ull << logL) - 1);
-  k_powtable<<<(ng + 255) / 256, 256>>>(gf, ng, P.p, w, 1);
-  k_powtable<<<(ng + 255) / 256, 256>>>(gi, ng, P.p, wi, 1);
+  k_row_pows<<<(ng + 255) / 256, 256>>>(gf, R, nt, P.p, w);
+  k_row_pows<<<(ng + 255) / 256, 256>>>(gi, R, nt, P.p, wi);
   k_row_factors<<<(nf + 255) / 256, 256>>>(ff, R, ept, nt, Lmask, P.p, w, 1);
   k_row_factors<<<(nf + 255) / 256, 256>>>(fi, R, ept, nt, Lmask, P.p, wi, scale);
   if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {

@@ -56,7 +56,8 @@ void plan_features(long lc, int pidx, const Plan& P, float* f) {
   f[10] = P.kind == PLAN_FOURSTEP ? (float)plan_row_lnt(P) / 10.f : 0.f;
   f[11] = prime_info(pidx).lazy ? 1.f : 0.f;
   f[12] = (float)(std::log2((double)std::max(rows, 1)) / 10.0);
-  f[13] = (float)(std::log2(nprime) / 24.0);
+  // values per row thread (log2): the row pass's register/occupancy trade-off
+  f[13] = P.kind == PLAN_FOURSTEP ? (float)(P.logC - plan_row_lnt(P)) / 5.f : 0.f;
   f[14] = P.kind == PLAN_FOURSTEP ? (float)(P.logL - P.logC) / 10.f : 0.f;
   f[15] = P.kind == PLAN_DIRECT ? 0.f : (float)P.ma / (float)(1 << P.logRA);
 }

@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(1024) k_lds_xform(const u32* in, int zin, u32*
         if (t < ma) {
           u32 v = x[t];
           if constexpr (S > 1) {
-            if (t > 0) v = A.mul(v, T.rf[LRA - 1][N + j * RA + t]);
+            if (t > 0) v = A.mul(v, cld(T.rf[LRA - 1] + N + j * RA + t));
           }
           sm[lds_ix(j + S * t)] = v;
         }
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(1024) k_lds_xform(const u32* in, int zin, u32*
         if (t < ma) {
           v = sm[lds_ix(j + S * t)];
           if constexpr (S > 1) {
-            if (t > 0) v = A.mul(v, T.ri[LRA - 1][N + j * RA + t]);
+            if (t > 0) v = A.mul(v, cld(T.ri[LRA - 1] + N + j * RA + t));
           }
         }
         x[t] = v;
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(1 << LNT) k_row_fwd(const u32* in, u32* out, l
   const int row = blockIdx.x;
   const u32 k1 = bitrev_n((u32)row, logR);
   const long off = (long)row * C;
-  const uint2 gf = cld(W.gf + k1 * (u32)tid);
+  const uint2 gf = cld(W.gf + k1 * (u32)NT + tid);
   const uint2* ff = W.ff + (size_t)k1 * EPT;
   u32 x[EPT];
 #pragma unroll
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(1 << LNT) k_row_inv(const u32* in, u32* out, i
 #pragma unroll
   for (int t = 0; t < EPT; ++t) x[t] = sm[lds_ix(tid + NT * t)];
   dit_top_reg<LC, LE, LAZY>(A, x, T, tid);
-  const uint2 gi = cld(W.gi + k1 * (u32)tid);
+  const uint2 gi = cld(W.gi + k1 * (u32)NT + tid);
   const uint2* fi = W.fi + (size_t)k1 * EPT;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) out[off + tid + NT * e] = A.mul(A.mul_raw(x[e], gi), cld(fi + e));
@@ -230,7 +230,7 @@ template <int LC, bool LAZY>
 static hipError_t row_xform_inst(const Plan& P, const u32* in, u32* out, long nout, int dir, const ModP& mp,
                                  const PrimeTables& T, const RowTables& W, hipStream_t s) {
   constexpr int C = 1 << LC;
-  constexpr int LNT = LC - 5 < 6 ? 6 : (LC - 5 > 9 ? 9 : LC - 5);
+  constexpr int LNT = LC - 4;
   if (plan_row_lnt(P) != LNT) return hipErrorInvalidValue;
   const int rows = P.ma << P.logRB;
   const int logR = P.logRA + P.logRB;
