@@ -230,6 +230,23 @@ def extra_configs(pm, torch, dev, reps=5):
         ks = rng.integers(0, outs[int(k)].numel(), 4)
         assert np.array_equal(outs[int(k)].cpu().numpy()[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
     out.update(standalone_transform(pm, torch, dev))
+
+    # products in the two factors of eq. 13 at n = 2^21: the operands of the
+    # headline's 2^21 x 2^21 product, reduced mod x^n - 1 / x^n + 1 (length-n
+    # transforms, no padding)
+    a2, b2, pp = inputs.large_pow2_product()
+    n21 = a2.size
+    ra, rb = torch.from_numpy(a2).to(dev), torch.from_numpy(b2).to(dev)
+    rc = torch.empty(n21, dtype=torch.uint32, device=dev)
+    for name, fn in (("cyclic", pm.cyclic_mul), ("negacyclic", pm.negacyclic_mul)):
+        fn(ra, rb, n21, pp, out=rc)
+        ms = time_loop(torch, lambda i: fn(ra, rb, n21, pp, out=rc), 20)
+        ks = np.array([0, 1, n21 // 2, n21 - 2])
+        lin = op.poly_mul_sample(a2, b2, pp, np.concatenate([ks, ks + n21])).astype(np.int64)
+        sign = 1 if name == "cyclic" else -1
+        want = (lin[:4] + sign * lin[4:]) % pp
+        ok = np.array_equal(rc.cpu().numpy()[ks], want.astype(np.uint32))
+        out[f"{name}_2^21_p{pp}"] = {"us": ms * 1e3, "coeffs_per_s": n21 / (ms * 1e-3), "bit_exact_sampled": bool(ok)}
     out["batch_4096_uneven"] = {
         "output_coeffs": ncoef,
         "plain_ms": ms_plain, "plain_coeffs_per_s": ncoef / (ms_plain * 1e-3),

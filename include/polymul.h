@@ -69,6 +69,27 @@ pm_status pm_init(void);
 pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p, uint32_t* c,
                       void* stream);
 
+/*
+ * Products in the quotient rings of the factorisation of eq. 13:
+ *   pm_cyclic_mul:     c = a b mod (x^n - 1), the circular convolution
+ *                      (Def. 4, eq. 5): c_i = sum_{j+k = i mod n} a_j b_k;
+ *   pm_negacyclic_mul: c = a b mod (x^n + 1), the nega-circular one:
+ *                      c_i = sum_{j+k = i} a_j b_k - sum_{j+k = i+n} a_j b_k.
+ * n is a power of two; len_a, len_b <= n (missing coefficients are zero);
+ * c receives n outputs, canonical.  The circular product is one length-n
+ * transform per operand, the pointwise product and one inverse (the
+ * convolution theorem without padding, diagram 9); the nega-circular one is
+ * the same on inputs twisted by psi^j (psi a primitive 2n-th root of unity,
+ * psi^n = -1) with the output untwisted by psi^-j; the twists are folded into
+ * the passes that read and write HBM and into the four-step row factors.
+ * Requires n (cyclic) or 2n (nega-circular) to divide p - 1 and n <= 2^24;
+ * n <= 64 uses the defining sums.  Errors as pm_poly_mul.
+ */
+pm_status pm_cyclic_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, size_t n, uint32_t p,
+                        uint32_t* c, void* stream);
+pm_status pm_negacyclic_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, size_t n, uint32_t p,
+                            uint32_t* c, void* stream);
+
 /* One problem of a batch; all pointers are device pointers. */
 typedef struct {
   const uint32_t* a;

@@ -43,6 +43,8 @@ def lib():
             L.orc_polymul_sample.restype = None
             L.orc_cyclic.argtypes = [u32p, u32p, i64, u32, u32p]
             L.orc_cyclic.restype = None
+            L.orc_negacyclic.argtypes = [u32p, u32p, i64, u32, u32p]
+            L.orc_negacyclic.restype = None
             L.orc_eval.argtypes = [u32p, i64, u32, u32]
             L.orc_eval.restype = u32
             L.orc_ntt.argtypes = [u32p, i64, u32, u32, ctypes.c_int]

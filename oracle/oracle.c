@@ -10,6 +10,8 @@
  *                         the same sum as the linear convolution, Def. 3, eq. 3)
  *   - orc_polymul_sample: the same sum, for a chosen set of output indices k
  *   - orc_cyclic:         (u (*) v)_i = sum_k u_k v_{(i-k) mod N} (Def. 4, eq. 5)
+ *   - orc_negacyclic:     the product in R[x]/(x^N + 1), the second factor of
+ *                         eq. 13: sum_{k<=i} u_k v_{i-k} - sum_{k>i} u_k v_{N+i-k}
  *   - orc_ntt:            X_k = sum_j x_j w^{jk} (evaluation at w^0..w^{N-1},
  *                         section 3, convolution theorem), by the iterative
  *                         radix-2 Cooley-Tukey algorithm; inverse scaled by N^-1
@@ -70,6 +72,16 @@ void orc_cyclic(const uint32_t* u, const uint32_t* v, int64_t n, uint32_t p, uin
     u128 acc = 0;
     for (int64_t k = 0; k < n; ++k) acc += (uint64_t)u[k] * v[((i - k) % n + n) % n];
     out[i] = (uint32_t)(acc % p);
+  }
+}
+
+void orc_negacyclic(const uint32_t* u, const uint32_t* v, int64_t n, uint32_t p, uint32_t* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    u128 pos = 0, neg = 0;
+    for (int64_t k = 0; k <= i; ++k) pos += (uint64_t)u[k] * v[i - k];
+    for (int64_t k = i + 1; k < n; ++k) neg += (uint64_t)u[k] * v[n + i - k];
+    out[i] = (uint32_t)(((pos % p) + p - (neg % p)) % p);
   }
 }
 

@@ -118,6 +118,29 @@ def cyclic_conv(u, v, p: int) -> np.ndarray:
     return out
 
 
+def negacyclic_conv(u, v, p: int) -> np.ndarray:
+    """u v mod (x^N + 1) mod p by its defining sums (the nega-circular factor of eq. 13)."""
+    u = _as_u32(u)
+    v = _as_u32(v)
+    if u.size != v.size:
+        raise ValueError("lengths differ")
+    out = np.zeros(u.size, dtype=np.uint32)
+    lib().orc_negacyclic(_ptr(u), _ptr(v), u.size, p, _ptr(out))
+    return out
+
+
+def fold(c, n: int, p: int, sign: int) -> np.ndarray:
+    """Reduce the coefficients c of a polynomial mod x^n - sign (sign = +1 or -1):
+    out_i = sum_m sign^m c_{i + m n} mod p."""
+    c = np.asarray(c, dtype=np.int64)
+    out = np.zeros(n, dtype=np.int64)
+    for m in range(0, (c.size + n - 1) // n):
+        blk = c[m * n:(m + 1) * n]
+        s = 1 if (sign == 1 or m % 2 == 0) else -1
+        out[:blk.size] = (out[:blk.size] + s * blk) % p
+    return (out % p).astype(np.uint32)
+
+
 def eval_at(a, p: int, x: int) -> int:
     """a(x) mod p by Horner's rule."""
     a = _as_u32(a)

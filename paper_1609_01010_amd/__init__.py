@@ -79,6 +79,8 @@ SIGNATURES = {
     "pm_init": (_int, []),
     "pm_poly_mul": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, _vp]),
     "pm_poly_mul_batch": (_int, [ctypes.POINTER(Problem), _sz, _vp]),
+    "pm_cyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
+    "pm_negacyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
     "pm_int_mul": (_int, [_vp, _sz, _vp, _sz, _vp, _vp]),
     "pm_ntt": (_int, [_vp, _vp, _sz, _u32, _int, _vp]),
     "pm_tft": (_int, [_vp, _sz, _sz, _sz, _u32, _vp, _vp]),
@@ -191,6 +193,25 @@ def poly_mul(a, b, p: int, out=None, plan: Plan | None = None, stream=None):
     else:
         _check(lib().pm_poly_mul_plan(*args, ctypes.byref(plan), _stream(stream)), "pm_poly_mul_plan")
     return out
+
+
+def _ring_mul(fn, a, b, n: int, p: int, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint32, device=a.device)
+    _check(getattr(lib(), fn)(_dev_ptr(a, torch.uint32, "a"), a.numel(), _dev_ptr(b, torch.uint32, "b"), b.numel(), n,
+                              p, _dev_ptr(out, torch.uint32, "out"), _stream(stream)), fn)
+    return out
+
+
+def cyclic_mul(a, b, n: int, p: int, out=None, stream=None):
+    """a b mod (x^n - 1) mod p (the circular convolution); n a power of two."""
+    return _ring_mul("pm_cyclic_mul", a, b, n, p, out, stream)
+
+
+def negacyclic_mul(a, b, n: int, p: int, out=None, stream=None):
+    """a b mod (x^n + 1) mod p (the nega-circular convolution); n a power of two."""
+    return _ring_mul("pm_negacyclic_mul", a, b, n, p, out, stream)
 
 
 class PreparedBatch:

@@ -19,7 +19,7 @@ bool plan_valid(const Plan& P, long lc, int pidx);
 Plan choose_plan(long lc, int pidx, DevCtx* c, hipStream_t s);
 size_t plan_workspace_bytes(const Plan& P);
 pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
-                   long lc, u32* Ta, u32* Tb, ConvJob* J);
+                   long lc, u32* Ta, u32* Tb, ConvJob* J, int ring);
 pm_status launch_class(const Plan& P, bool lazy, int in_type, const JobRef& jr, int njobs, int max_rows,
                        hipStream_t s);
 void trace_suppress(bool on);
@@ -254,7 +254,7 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
         ws += (w + 255) & ~(size_t)255;
       }
       ConvJob J;
-      st = make_job(c, plans[i], pidx[i], q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, lc, Ta, Tb, &J);
+      st = make_job(c, plans[i], pidx[i], q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, lc, Ta, Tb, &J, 0);
       if (st) return st;
       r.max_rows = std::max(r.max_rows, J.rows);
       jobs.push_back(J);

@@ -230,8 +230,10 @@ size_t plan_workspace_bytes(const Plan& P) {
 
 // Fill the job of one product with plan P (tables are built on first use).
 // Ta/Tb: the four-step workspace (n' words each) or null for other plans.
+// ring: 0 the product in Z/pZ[x] (or, with lc = L, the circular one), 2 the
+// nega-circular product (inputs twisted by psi^j, outputs untwisted).
 pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
-                   long lc, u32* Ta, u32* Tb, ConvJob* J) {
+                   long lc, u32* Ta, u32* Tb, ConvJob* J, int ring) {
   pm_status st = ensure_prime_tables(c, pidx);
   if (st) return st;
   const PrimeInfo& PI = prime_info(pidx);
@@ -251,7 +253,11 @@ pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, c
   J->err = c->errflag;
   if (P.kind == PLAN_DIRECT) return PM_OK;
   J->sc = conv_scale(P, pidx);
-  if (P.kind == PLAN_FOURSTEP) return get_row_tables(c, pidx, P.logL, P.logC, plan_row_lnt(P), J->sc.x, &J->W);
+  if (ring == 2) {
+    st = get_twist_tables(c, pidx, P.logL, P.kind == PLAN_FOURSTEP ? P.logC : 0, &J->twf, &J->twi);
+    if (st) return st;
+  }
+  if (P.kind == PLAN_FOURSTEP) return get_row_tables(c, pidx, P.logL, P.logC, plan_row_lnt(P), J->sc.x, ring == 2, &J->W);
   return PM_OK;
 }
 
@@ -282,9 +288,46 @@ pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const vo
   u32* Tb = Ta ? Ta + plan_nprime(P) : nullptr;
   JobRef jr;
   jr.many = nullptr;
-  pm_status st = make_job(c, P, pidx, a, la, b, lb, out, lc, Ta, Tb, &jr.one);
+  pm_status st = make_job(c, P, pidx, a, la, b, lb, out, lc, Ta, Tb, &jr.one, 0);
   if (st) return st;
   return launch_class(P, prime_info(pidx).lazy, in_type, jr, 1, jr.one.rows, s);
+}
+
+// Products mod x^n - 1 (ring 1) and x^n + 1 (ring 2): length-n transforms,
+// no padding; the nega-circular twist is carried by the job (make_job).
+static pm_status ring_product(int ring, const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, size_t n,
+                              uint32_t p, uint32_t* c, void* stream) {
+  if (!a || !b || !c || len_a == 0 || len_b == 0 || n < 1 || (n & (n - 1)) || len_a > n || len_b > n)
+    return PM_EINVAL;
+  const int pidx = prime_index(p);
+  if (pidx < 0) return PM_EUNSUPPORTED;
+  const PrimeInfo& PI = prime_info(pidx);
+  const int logn = ceil_log2((long)n);
+  if (logn + (ring == 2 ? 1 : 0) > PI.two_adic || logn > 24) return PM_ETOOLARGE;
+  pm_status st;
+  DevCtx* ctx = ctx_current(&st);
+  if (!ctx) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t s = (hipStream_t)stream;
+  if (n <= 64)
+    return dev_status(
+        launch_direct_ring(a, (long)len_a, b, (long)len_b, (long)n, ring == 2, c, pidx, ctx->errflag, s));
+  // a plan for output length n transforms exactly n points (n' = L = n)
+  const Plan P = choose_plan((long)n, pidx, ctx, s);
+  if (P.kind == PLAN_DIRECT || !plan_valid(P, (long)n, pidx) || plan_nprime(P) != (long)n) return PM_ETOOLARGE;
+  const size_t wsb = plan_workspace_bytes(P);
+  void* ws = nullptr;
+  if (wsb) {
+    st = stream_workspace(ctx, s, wsb, &ws);
+    if (st) return st;
+  }
+  u32* Ta = P.kind == PLAN_FOURSTEP ? (u32*)ws : nullptr;
+  u32* Tb = Ta ? Ta + plan_nprime(P) : nullptr;
+  JobRef jr;
+  jr.many = nullptr;
+  st = make_job(ctx, P, pidx, a, (long)len_a, b, (long)len_b, c, (long)n, Ta, Tb, &jr.one, ring);
+  if (st) return st;
+  return launch_class(P, PI.lazy, 0, jr, 1, jr.one.rows, s);
 }
 
 }  // namespace pm
@@ -364,6 +407,16 @@ static pm_status product_with(const uint32_t* a, size_t len_a, const uint32_t* b
 pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p, uint32_t* c,
                       void* stream) {
   return product_with(a, len_a, b, len_b, p, c, nullptr, stream);
+}
+
+pm_status pm_cyclic_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, size_t n, uint32_t p,
+                        uint32_t* c, void* stream) {
+  return ring_product(1, a, len_a, b, len_b, n, p, c, stream);
+}
+
+pm_status pm_negacyclic_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, size_t n, uint32_t p,
+                            uint32_t* c, void* stream) {
+  return ring_product(2, a, len_a, b, len_b, n, p, c, stream);
 }
 
 pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
@@ -484,14 +537,14 @@ pm_status pm_ntt(const uint32_t* x, uint32_t* y, size_t n, uint32_t p, int inver
   st = stream_workspace(c, s, n * sizeof(u32), &wsp);
   if (st) return st;
   RowTables S;
-  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), inverse ? ninv.x : 1u, &S);
+  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), inverse ? ninv.x : 1u, 0, &S);
   if (st) return st;
   u32* T = (u32*)wsp;
   const int logR = P.logRA + P.logRB;
   hipError_t e;
   JobRef jr;
   jr.many = nullptr;
-  st = make_job(c, P, pidx, x, (long)n, nullptr, 0, y, (long)n, T, nullptr, &jr.one);
+  st = make_job(c, P, pidx, x, (long)n, nullptr, 0, y, (long)n, T, nullptr, &jr.one, 0);
   if (st) return st;
   const bool lazy = prime_info(pidx).lazy;
   if (!inverse) {
@@ -524,12 +577,12 @@ pm_status pm_tft(const uint32_t* x, size_t z, size_t L, size_t n, uint32_t p, ui
   st = stream_workspace(c, s, (size_t)plan_nprime(P) * sizeof(u32), &wsp);
   if (st) return st;
   RowTables S;
-  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), 1u, &S);
+  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), 1u, 0, &S);
   if (st) return st;
   u32* T = (u32*)wsp;
   JobRef jr;
   jr.many = nullptr;
-  st = make_job(c, P, pidx, x, (long)z, nullptr, 0, out, (long)n, T, nullptr, &jr.one);
+  st = make_job(c, P, pidx, x, (long)z, nullptr, 0, out, (long)n, T, nullptr, &jr.one, 0);
   if (st) return st;
   hipError_t e = launch_col_fwd(P, prime_info(pidx).lazy, 0, 1, jr, 1, s);
   if (e == hipSuccess) e = launch_row_xform(P, T, out, (long)n, 0, pidx, c->tabs[pidx], S, s);
@@ -556,12 +609,12 @@ pm_status pm_itft(const uint32_t* v, size_t L, size_t n, uint32_t p, uint32_t* o
   st = stream_workspace(c, s, (size_t)plan_nprime(P) * sizeof(u32), &wsp);
   if (st) return st;
   RowTables S;
-  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), sc.x, &S);
+  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), sc.x, 0, &S);
   if (st) return st;
   u32* T = (u32*)wsp;
   JobRef jr;
   jr.many = nullptr;
-  st = make_job(c, P, pidx, v, (long)n, nullptr, 0, out, (long)n, T, nullptr, &jr.one);
+  st = make_job(c, P, pidx, v, (long)n, nullptr, 0, out, (long)n, T, nullptr, &jr.one, 0);
   if (st) return st;
   hipError_t e = launch_row_xform(P, v, T, (long)n, 1, pidx, c->tabs[pidx], S, s);
   if (e == hipSuccess) e = launch_col_inv(P, prime_info(pidx).lazy, jr, 1, s);

@@ -43,6 +43,38 @@ __global__ void __launch_bounds__(64) k_direct(const u32* __restrict__ a, int la
   c[k] = (u32)(acc % mp.p);
 }
 
+// products in Z/pZ[x]/(x^n - 1) (NEG = false, the circular convolution of
+// eq. 5) and Z/pZ[x]/(x^n + 1) (NEG = true) by their defining sums, n <= 64:
+// c_i = sum_{j+k = i} a_j b_k +- sum_{j+k = i+n} a_j b_k
+template <bool NEG>
+__global__ void __launch_bounds__(64) k_direct_ring(const u32* __restrict__ a, int la, const u32* __restrict__ b,
+                                                   int lb, int n, u32* __restrict__ c, ModP mp, int* err) {
+  const int i = threadIdx.x;
+  if (i >= n) return;
+  u64 pos = 0, neg = 0;  // < 64 terms each below 2^31
+  for (int j = 0; j < la; ++j) {
+    int k = i - j;
+    const bool wrap = k < 0;
+    if (wrap) k += n;
+    if (k >= lb) continue;
+    const u32 x = a[j], y = b[k];
+    if (x >= mp.p || y >= mp.p) atomicOr(err, 1);
+    const u64 t = (u64)x * y % mp.p;
+    if (NEG && wrap)
+      neg += t;
+    else
+      pos += t;
+  }
+  c[i] = (u32)((pos % mp.p + mp.p - neg % mp.p) % mp.p);
+}
+
+hipError_t launch_direct_ring(const u32* a, long la, const u32* b, long lb, long n, bool negacyclic, u32* c, int pidx,
+                              int* err, hipStream_t s) {
+  const ModP mp = modp_of(prime_info(pidx));
+  if (negacyclic) return launch("direct", k_direct_ring<true>, 1, 64, 0, s, a, (int)la, b, (int)lb, (int)n, c, mp, err);
+  return launch("direct", k_direct_ring<false>, 1, 64, 0, s, a, (int)la, b, (int)lb, (int)n, c, mp, err);
+}
+
 hipError_t launch_direct(const u32* a, long la, const u32* b, long lb, u32* c, int pidx, int* err, hipStream_t s) {
   const PrimeInfo& P = prime_info(pidx);
   const ModP mp = modp_of(P);

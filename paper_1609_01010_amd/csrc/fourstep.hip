@@ -54,6 +54,7 @@ __global__ void __launch_bounds__(64) k_col_fwd1(JobRef jr, int logC) {
     const long pos = C * s + j2;
     x[s] = pos < z ? (u32)gld(in + pos) : 0u;
     bad |= x[s] >= J.mp.p;
+    if (J.twf) x[s] = A.mul(x[s], cld(J.twf + s));
   }
   if (bad) atomicOr(J.err, 1);
   dif_reg<RA>(A, x, J.T.pf);
@@ -87,7 +88,7 @@ constexpr int col_round_lq() {
 template <int LB, int LQ, bool FROM_GLOBAL, bool TO_GLOBAL, bool LAZY, typename TIn>
 __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
                                               int tid, int nthr, const TIn* __restrict__ in, long z, long C, long col0,
-                                              u32* __restrict__ out, bool& bad) {
+                                              u32* __restrict__ out, const uint2* twf, bool& bad) {
   constexpr int Q = 1 << LQ;
   constexpr int LS = LB - LQ;
   constexpr int K = 16 / Q;
@@ -108,6 +109,7 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
           const long pos = C * row + col0 + c;
           x[s] = pos < z ? (u32)gld(in + pos) : 0u;
           bad |= x[s] >= A.p;
+          if (twf) x[s] = A.mul(x[s], cld(twf + row));
         } else {
           x[s] = sm[(row << lw) + c];
         }
@@ -134,14 +136,14 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
 template <int LR, int K, int LB, bool LAZY, typename TIn>
 __device__ __forceinline__ void col_dif_rounds(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
                                                int tid, int nthr, const TIn* in, long z, long C, long col0, u32* out,
-                                               bool& bad) {
+                                               const uint2* twf, bool& bad) {
   constexpr int LQ = col_round_lq<LR, K>();
   constexpr bool first = K == 0;
   constexpr bool last = LB == LQ;
-  col_dif_round<LB, LQ, first, last, LAZY, TIn>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, bad);
+  col_dif_round<LB, LQ, first, last, LAZY, TIn>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, twf, bad);
   if constexpr (!last) {
     __syncthreads();
-    col_dif_rounds<LR, K + 1, LB - LQ, LAZY, TIn>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, bad);
+    col_dif_rounds<LR, K + 1, LB - LQ, LAZY, TIn>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, twf, bad);
   }
 }
 
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(1024) k_col_fwdr(JobRef jr, int logC, int lw) 
   u32* __restrict__ out = blockIdx.y ? J.Tb : J.Ta;
   bool bad = false;
   col_dif_rounds<LR, 0, LR, LAZY, TIn>(A, sm, lw, J.rows, J.T, threadIdx.x, blockDim.x, in, z, 1l << logC,
-                                       (long)blockIdx.x << lw, out, bad);
+                                       (long)blockIdx.x << lw, out, J.twf, bad);
   if (bad) atomicOr(J.err, 1);
 }
 
@@ -392,7 +394,7 @@ __global__ void __launch_bounds__(64) k_col_inv1(JobRef jr, int logC) {
 #pragma unroll
   for (int s = 0; s < RA; ++s) {
     const long pos = C * s + j2;
-    if (s < ma && pos < J.lc) gst(c + pos, A.canon(x[s]));
+    if (s < ma && pos < J.lc) gst(c + pos, A.canon(J.twi ? A.mul(x[s], cld(J.twi + s)) : x[s]));
   }
 }
 
@@ -483,7 +485,7 @@ __global__ void __launch_bounds__(1024) k_col_invr(JobRef jr, int logC, int lw) 
 #pragma unroll
     for (int e = 0; e < RA; ++e) {
       const long pos = C * (j1b + RB * e) + c0 + cc;
-      if (e < ma && pos < J.lc) gst(c + pos, A.canon(x[e]));
+      if (e < ma && pos < J.lc) gst(c + pos, A.canon(J.twi ? A.mul(x[e], cld(J.twi + j1b + RB * e)) : x[e]));
     }
   }
 }

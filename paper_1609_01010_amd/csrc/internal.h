@@ -47,12 +47,14 @@ uint2 h_shoup(u32 w, u32 p);  // (w, floor(w 2^32 / p))
 struct RowKey {
   int pidx, logL, logC, lnt;
   u32 scale;
+  int twist;  // 1: the twisted transform of the nega-circular product
   bool operator<(const RowKey& o) const {
     if (pidx != o.pidx) return pidx < o.pidx;
     if (logL != o.logL) return logL < o.logL;
     if (logC != o.logC) return logC < o.logC;
     if (lnt != o.lnt) return lnt < o.lnt;
-    return scale < o.scale;
+    if (scale != o.scale) return scale < o.scale;
+    return twist < o.twist;
   }
 };
 
@@ -73,7 +75,10 @@ pm_status ensure_prime_tables(DevCtx* c, int pidx);
 // the workspace of stream s, grown to at least `bytes`
 pm_status stream_workspace(DevCtx* c, hipStream_t s, size_t bytes, void** out);
 // scale: the value multiplied into the inverse factors (1 for none)
-pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, RowTables* out);
+pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, int twist, RowTables* out);
+// powers psi^(i s) and psi^(-i s), i < L / s, of a primitive 2L-th root of
+// unity psi, stride s = 2^log_stride (the nega-circular product's twist)
+pm_status get_twist_tables(DevCtx* c, int pidx, int logL, int log_stride, const uint2** fwd, const uint2** inv);
 
 inline ModP modp_of(const PrimeInfo& P) { return ModP{P.p, 2u * P.p, P.ninv}; }
 
@@ -102,6 +107,8 @@ inline long plan_nprime(const Plan& P) { return (long)P.ma << (P.logL - P.logRA)
 
 // ---- launchers (return hipSuccess or the launch error) --------------------
 hipError_t launch_direct(const u32* a, long la, const u32* b, long lb, u32* c, int pidx, int* err, hipStream_t s);
+hipError_t launch_direct_ring(const u32* a, long la, const u32* b, long lb, long n, bool negacyclic, u32* c, int pidx,
+                              int* err, hipStream_t s);
 // Convolution launches over njobs jobs of one plan class (jobs in jr: the
 // single inline job, or a device array indexed by blockIdx.z).
 hipError_t launch_lds_conv(const Plan& P, bool lazy, const JobRef& jr, int njobs, hipStream_t s);

@@ -31,6 +31,11 @@ struct ConvJob {
   RowTables W;     // four-step row twiddles (scale folded into fi)
   uint2 sc;        // one-work-group plans: inverse scale (times 2^32)
   int* err;        // device error word
+  // nega-circular products (null otherwise): the input twist psi^(s i) and
+  // the output untwist psi^(-s i) by row index i of the pass that reads the
+  // operands / writes the result (s = C for four-step plans, 1 otherwise)
+  const uint2* twf;
+  const uint2* twi;
 };
 
 struct JobRef {

@@ -67,6 +67,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
         const int pos = j + S * s;
         x[s] = pos < len ? gld(in + pos) : 0u;
         bad |= x[s] >= J.mp.p;
+        if (J.twf) x[s] = A.mul(x[s], cld(J.twf + pos));
       }
       dif_reg<RA, LAZY, (S > 1)>(A, x, T.pf);
 #pragma unroll
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
 #pragma unroll
     for (int s = 0; s < RA; ++s) {
       const int pos = j + S * s;
-      if (s < ma && pos < lc) gst(c + pos, A.canon(x[s]));
+      if (s < ma && pos < lc) gst(c + pos, A.canon(J.twi ? A.mul(x[s], cld(J.twi + pos)) : x[s]));
     }
   }
 }

@@ -117,23 +117,31 @@ __global__ void k_fill_round_table(uint2* out, u32 p, u32 g, int lq, int inverse
   out[idx] = d_shoup(d_powmod(w, e, p), p);
 }
 
-// Row-pass twiddle factors: out[k1 * ept + e] = mult * wL^{(k1 * nt * e) mod L}
-__global__ void k_row_factors(uint2* out, int R, int ept, int nt, u32 Lmask, u32 p, u32 wL, u32 mult) {
+// Row-pass twiddle factors.  With kf = kmul k1 + kadd (k1 for the cyclic
+// transform, 2 k1 + 1 for the twisted one of the nega-circular product):
+//   out[k1 * ept + e] = mult * base^((nt e kf) mod ord)     (k_row_factors)
+//   out[k1 * nt + tid] = base^(tid kf)                       (k_row_pows)
+// ord is the order of base (a power of two).
+__global__ void k_row_factors(uint2* out, int R, int ept, int nt, u32 ord_mask, u32 p, u32 base, u32 mult, u32 kmul,
+                              u32 kadd) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R * ept) return;
-  const u32 k1 = (u32)(i / ept), e = (u32)(i % ept);
-  const u32 ex = (u32)(((u64)k1 * (u32)nt * e) & Lmask);
-  out[i] = d_shoup(d_mulmod(mult, d_powmod(wL, ex, p), p), p);
+  const u64 k1 = (u64)(i / ept), e = (u64)(i % ept);
+  const u32 ex = (u32)(((u64)nt * e * (kmul * k1 + kadd)) & ord_mask);
+  out[i] = d_shoup(d_mulmod(mult, d_powmod(base, ex, p), p), p);
 }
 
-// out[i] = mult * base^i mod p as Shoup pairs, i < n
-// Row-pass per-thread factors, one row after the other:
-// out[k1 * nt + tid] = base^(k1 tid), k1 < R, tid < nt
-__global__ void k_row_pows(uint2* out, int R, int nt, u32 p, u32 base) {
+__global__ void k_row_pows(uint2* out, int R, int nt, u32 ord_mask, u32 p, u32 base, u32 kmul, u32 kadd) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R * nt) return;
-  const u32 k1 = (u32)(i / nt), tid = (u32)(i % nt);
-  out[i] = d_shoup(d_powmod(base, k1 * tid, p), p);
+  const u64 k1 = (u64)(i / nt), tid = (u64)(i % nt);
+  out[i] = d_shoup(d_powmod(base, (u32)((tid * (kmul * k1 + kadd)) & ord_mask), p), p);
+}
+
+// out[i] = base^i as Shoup pairs, i < n
+__global__ void k_pows(uint2* out, int n, u32 p, u32 base) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = d_shoup(d_powmod(base, (u32)i, p), p);
 }
 
 // ---------------------------------------------------------------------------
@@ -200,8 +208,8 @@ pm_status ensure_prime_tables(DevCtx* c, int pidx) {
   return PM_OK;
 }
 
-pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, RowTables* out) {
-  const RowKey key{pidx, logL, logC, lnt, scale};
+pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, int twist, RowTables* out) {
+  const RowKey key{pidx, logL, logC, lnt, scale, twist};
   auto it = c->rowtw.find(key);
   if (it != c->rowtw.end()) {
     *out = it->second.second;
@@ -210,20 +218,24 @@ pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 s
   const PrimeInfo& P = prime_info(pidx);
   const int R = 1 << (logL - logC), nt = 1 << lnt, ept = 1 << (logC - lnt);
   const int ng = R * nt, nf = R * ept;
+  if (twist && logL + 1 > P.two_adic) return PM_ETOOLARGE;
   uint2* mem = nullptr;
   if (hipMalloc(&mem, 2 * (size_t)(ng + nf) * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
-  const u32 w = h_powmod(P.g, (P.p - 1) >> logL, P.p);
+  // cyclic: w_L^(j2 k1); twisted: psi^(j2 (2 k1 + 1)) with psi^2 = w_L
+  const int lord = twist ? logL + 1 : logL;
+  const u32 w = h_powmod(P.g, (P.p - 1) >> lord, P.p);
   const u32 wi = h_inv(w, P.p);
+  const u32 mask = (u32)((1ull << lord) - 1);
+  const u32 kmul = twist ? 2 : 1, kadd = twist ? 1 : 0;
   RowTables W;
   uint2* gf = mem;
   uint2* gi = gf + ng;
   uint2* ff = gi + ng;
   uint2* fi = ff + nf;
-  const u32 Lmask = (u32)((1ull << logL) - 1);
-  k_row_pows<<<(ng + 255) / 256, 256>>>(gf, R, nt, P.p, w);
-  k_row_pows<<<(ng + 255) / 256, 256>>>(gi, R, nt, P.p, wi);
-  k_row_factors<<<(nf + 255) / 256, 256>>>(ff, R, ept, nt, Lmask, P.p, w, 1);
-  k_row_factors<<<(nf + 255) / 256, 256>>>(fi, R, ept, nt, Lmask, P.p, wi, scale);
+  k_row_pows<<<(ng + 255) / 256, 256>>>(gf, R, nt, mask, P.p, w, kmul, kadd);
+  k_row_pows<<<(ng + 255) / 256, 256>>>(gi, R, nt, mask, P.p, wi, kmul, kadd);
+  k_row_factors<<<(nf + 255) / 256, 256>>>(ff, R, ept, nt, mask, P.p, w, 1, kmul, kadd);
+  k_row_factors<<<(nf + 255) / 256, 256>>>(fi, R, ept, nt, mask, P.p, wi, scale, kmul, kadd);
   if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     hipFree(mem);
     return PM_EDEVICE;
@@ -234,6 +246,34 @@ pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 s
   W.fi = fi;
   c->rowtw[key] = std::make_pair(mem, W);
   *out = W;
+  return PM_OK;
+}
+
+pm_status get_twist_tables(DevCtx* c, int pidx, int logL, int log_stride, const uint2** fwd, const uint2** inv) {
+  const RowKey key{pidx, logL, log_stride, -1, 0u, 1};
+  auto it = c->rowtw.find(key);
+  if (it == c->rowtw.end()) {
+    const PrimeInfo& P = prime_info(pidx);
+    if (logL + 1 > P.two_adic) return PM_ETOOLARGE;
+    const int n = 1 << (logL - log_stride);
+    uint2* mem = nullptr;
+    if (hipMalloc(&mem, 2 * (size_t)n * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
+    // psi, a primitive 2L-th root of unity (psi^L = -1), raised to the stride
+    const u32 psi = h_powmod(P.g, (P.p - 1) >> (logL + 1), P.p);
+    const u32 base = h_powmod(psi, 1u << log_stride, P.p);
+    k_pows<<<(n + 255) / 256, 256>>>(mem, n, P.p, base);
+    k_pows<<<(n + 255) / 256, 256>>>(mem + n, n, P.p, h_inv(base, P.p));
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      hipFree(mem);
+      return PM_EDEVICE;
+    }
+    RowTables W{};
+    W.gf = mem;
+    W.gi = mem + n;
+    it = c->rowtw.emplace(key, std::make_pair(mem, W)).first;
+  }
+  *fwd = it->second.second.gf;
+  *inv = it->second.second.gi;
   return PM_OK;
 }
 

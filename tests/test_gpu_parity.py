@@ -224,6 +224,48 @@ def test_batch_uneven_4096(gpu_lib):
             assert np.array_equal(got[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
 
 
+@pytest.mark.parametrize("p,g", PRIMES)
+def test_cyclic_and_negacyclic_products(gpu_lib, p, g):
+    """Products mod x^n - 1 and x^n + 1 (eq. 5 and the factors of eq. 13) for the
+    defining-sum, one-work-group and four-step plans, operands shorter than n
+    included: against the linear product reduced mod x^n -+ 1, and for small n
+    against the oracle's defining sums directly."""
+    pm = gpu_lib
+    cases = ((4, 4, 3), (64, 64, 30), (128, 128, 128), (2048, 1000, 2048), (16384, 16384, 16384),
+             (32768, 32768, 20000), (1 << 17, 1 << 17, 1 << 17), (1 << 20, 1 << 20, 777777))
+    for k, (n, la, lb) in enumerate(cases):
+        say("case:", p, n, la, lb)
+        a, b = inputs.poly_pair((150, k, p % 1000), la, lb, p)
+        lin = op.poly_mul(a, b, p) if la * lb <= 1 << 24 else op.poly_mul_ntt(a, b, p, g)
+        got_c = host(pm.cyclic_mul(dev(a), dev(b), n, p))
+        got_n = host(pm.negacyclic_mul(dev(a), dev(b), n, p))
+        assert pm.stream_check() == 0
+        assert np.array_equal(got_c, op.fold(lin, n, p, +1)), ("cyclic", n)
+        assert np.array_equal(got_n, op.fold(lin, n, p, -1)), ("negacyclic", n)
+        if n <= 2048:
+            ap = np.zeros(n, np.uint32)
+            bp = np.zeros(n, np.uint32)
+            ap[:la], bp[:lb] = a, b
+            assert np.array_equal(got_c, op.cyclic_conv(ap, bp, p))
+            assert np.array_equal(got_n, op.negacyclic_conv(ap, bp, p))
+
+
+def test_ring_product_errors(gpu_lib):
+    pm = gpu_lib
+    p = 998244353
+    x = dev(np.ones(100, np.uint32))
+    for fn in (pm.cyclic_mul, pm.negacyclic_mul):
+        with pytest.raises(pm.PolymulError) as e:
+            fn(x, x, 96, p)  # not a power of two
+        assert e.value.status == pm.PM_EINVAL
+        with pytest.raises(pm.PolymulError) as e:
+            fn(x, x, 64, p)  # operands longer than n
+        assert e.value.status == pm.PM_EINVAL
+    with pytest.raises(pm.PolymulError) as e:
+        pm.negacyclic_mul(x, x, 1 << 23, p)  # 2n does not divide p - 1
+    assert e.value.status == pm.PM_ETOOLARGE
+
+
 def test_products_on_concurrent_streams(gpu_lib):
     """Products and batches issued on two streams without synchronising
     between them: each stream has its own workspace, so every result is exact."""

@@ -197,6 +197,68 @@ def test_cyclic_conv_is_product_mod_xn_minus_1():
     assert [int(t) for t in op.cyclic_conv(u, v, p)] == fold
 
 
+def test_negacyclic_conv_is_product_mod_xn_plus_1():
+    """The nega-circular factor of eq. 13: the product reduced mod x^N + 1
+    (x^N = -1), against the product by Kronecker substitution."""
+    p = 2013265921
+    rng = random.Random(31)
+    for n in (1, 2, 7, 23, 64):
+        u = [rng.randrange(p) for _ in range(n)]
+        v = [rng.randrange(p) for _ in range(n)]
+        full = kronecker_product(u, v, p)
+        fold = [0] * n
+        for k, c in enumerate(full):
+            fold[k % n] += c if (k // n) % 2 == 0 else -c
+        assert [int(t) for t in op.negacyclic_conv(u, v, p)] == [f % p for f in fold]
+
+
+def test_negacyclic_closed_forms():
+    """x^(N-1) x = x^N = -1 mod x^N + 1 (and +1 mod x^N - 1); x^i x^j = x^(i+j)
+    below N in both rings."""
+    p, n = 998244353, 16
+    u = [0] * n
+    v = [0] * n
+    u[n - 1], v[1] = 1, 1
+    neg = op.negacyclic_conv(u, v, p)
+    cyc = op.cyclic_conv(u, v, p)
+    assert int(neg[0]) == p - 1 and not neg[1:].any()
+    assert int(cyc[0]) == 1 and not cyc[1:].any()
+    u = [0] * n
+    u[5] = 1
+    v = [0] * n
+    v[7] = 3
+    assert [int(t) for t in op.negacyclic_conv(u, v, p)] == [3 if i == 12 else 0 for i in range(n)]
+
+
+def test_eq13_split_of_the_circular_product():
+    """eq. 13: Z[x]/(x^2n - 1) = Z[x]/(x^n - 1) x Z[x]/(x^n + 1).  The circular
+    product of length 2n, reduced mod x^n - 1 and mod x^n + 1, equals the
+    circular and the nega-circular products of the reduced operands."""
+    p = 469762049
+    rng = np.random.default_rng(32)
+    n = 32
+    u = rng.integers(0, p, 2 * n, dtype=np.uint32)
+    v = rng.integers(0, p, 2 * n, dtype=np.uint32)
+    w = op.cyclic_conv(u, v, p)
+    assert np.array_equal(op.fold(w, n, p, +1), op.cyclic_conv(op.fold(u, n, p, +1), op.fold(v, n, p, +1), p))
+    assert np.array_equal(op.fold(w, n, p, -1), op.negacyclic_conv(op.fold(u, n, p, -1), op.fold(v, n, p, -1), p))
+
+
+def test_negacyclic_agrees_at_odd_powers_of_psi():
+    """The roots of x^N + 1 are the odd powers of a primitive 2N-th root of
+    unity psi; there the nega-circular product equals a(x) b(x)."""
+    p, g = 2013265921, 31
+    n = 64
+    rng = np.random.default_rng(33)
+    u = rng.integers(0, p, n, dtype=np.uint32)
+    v = rng.integers(0, p, n, dtype=np.uint32)
+    c = op.negacyclic_conv(u, v, p)
+    psi = op.root(p, g, 2 * n)
+    for k in (0, 1, 5, 63):
+        x = pow(psi, 2 * k + 1, p)
+        assert op.eval_at(c, p, x) == op.eval_at(u, p, x) * op.eval_at(v, p, x) % p
+
+
 def test_large_ntt_roundtrip_and_theorem():
     p, g = 2013265921, 31
     rng = np.random.default_rng(5)
