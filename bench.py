@@ -231,6 +231,17 @@ def extra_configs(pm, torch, dev, reps=5):
         assert np.array_equal(outs[int(k)].cpu().numpy()[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
     out.update(standalone_transform(pm, torch, dev))
 
+    # a bivariate product by Kronecker substitution: 1024 x 1024 coefficients
+    # times 1024 x 1024 (2047^2 outputs, one 2^22 transform)
+    rng = inputs.rng_for(141)
+    ma = torch.from_numpy(inputs.uniform_mod(rng, 1 << 20, 2013265921).reshape(1024, 1024)).to(dev)
+    mb = torch.from_numpy(inputs.uniform_mod(rng, 1 << 20, 2013265921).reshape(1024, 1024)).to(dev)
+    mc = torch.empty((2047, 2047), dtype=torch.uint32, device=dev)
+    pm.poly_mul_multi(ma, mb, 2013265921, out=mc)
+    ms = time_loop(torch, lambda i: pm.poly_mul_multi(ma, mb, 2013265921, out=mc), 20)
+    out["bivariate_1024^2_x_1024^2_p2013265921"] = {"us": ms * 1e3, "coeffs_per_s": 2047 * 2047 / (ms * 1e-3)}
+    del ma, mb, mc
+
     # products in the two factors of eq. 13 at n = 2^21: the operands of the
     # headline's 2^21 x 2^21 product, reduced mod x^n - 1 / x^n + 1 (length-n
     # transforms, no padding)

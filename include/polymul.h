@@ -90,6 +90,20 @@ pm_status pm_cyclic_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size
 pm_status pm_negacyclic_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, size_t n, uint32_t p,
                             uint32_t* c, void* stream);
 
+/*
+ * Dense multivariate product (section 1: multivariate products reduce to
+ * univariate ones), here by Kronecker substitution: one univariate
+ * product (pm_poly_mul) of the operands packed with the strides of the
+ * product's box.  a is row-major over the box dims_a[0] x .. x
+ * dims_a[nvars-1] (dims_a[i] = 1 + the degree of a in variable i, the last
+ * variable fastest); likewise b.  c receives the product row-major over
+ * dims_a[i] + dims_b[i] - 1.  dims_a, dims_b: HOST arrays; 1 <= nvars <= 8.
+ * The packed operands live in the stream's workspace.  Requires the product's
+ * number of coefficients to be a supported transform length (as pm_poly_mul).
+ */
+pm_status pm_poly_mul_multi(const uint32_t* a, const size_t* dims_a, const uint32_t* b, const size_t* dims_b,
+                            int nvars, uint32_t p, uint32_t* c, void* stream);
+
 /* One problem of a batch; all pointers are device pointers. */
 typedef struct {
   const uint32_t* a;

@@ -129,6 +129,31 @@ def negacyclic_conv(u, v, p: int) -> np.ndarray:
     return out
 
 
+def poly_mul_multi(a, b, p: int) -> np.ndarray:
+    """Dense multivariate product by its definition: c[e + f] += a[e] b[f] mod p
+    (arrays indexed by exponent vectors, one axis per variable)."""
+    a = np.asarray(a, dtype=np.int64)
+    b = np.asarray(b, dtype=np.int64)
+    c = np.zeros(tuple(x + y - 1 for x, y in zip(a.shape, b.shape)), dtype=np.int64)
+    for e in np.ndindex(*a.shape):
+        if a[e]:
+            box = tuple(slice(ei, ei + bi) for ei, bi in zip(e, b.shape))
+            c[box] = (c[box] + a[e] * b) % p
+    return c.astype(np.uint32)
+
+
+def eval_multi(a, p: int, xs) -> int:
+    """a(x_1, .., x_k) mod p for an array a indexed by exponent vectors."""
+    a = np.asarray(a, dtype=np.int64)
+    total = 0
+    for e in np.ndindex(*a.shape):
+        t = int(a[e])
+        for ei, x in zip(e, xs):
+            t = t * pow(x, ei, p) % p
+        total = (total + t) % p
+    return total
+
+
 def fold(c, n: int, p: int, sign: int) -> np.ndarray:
     """Reduce the coefficients c of a polynomial mod x^n - sign (sign = +1 or -1):
     out_i = sum_m sign^m c_{i + m n} mod p."""

@@ -80,6 +80,7 @@ SIGNATURES = {
     "pm_poly_mul": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, _vp]),
     "pm_poly_mul_batch": (_int, [ctypes.POINTER(Problem), _sz, _vp]),
     "pm_cyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
+    "pm_poly_mul_multi": (_int, [_vp, ctypes.POINTER(_sz), _vp, ctypes.POINTER(_sz), _int, _u32, _vp, _vp]),
     "pm_negacyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
     "pm_int_mul": (_int, [_vp, _sz, _vp, _sz, _vp, _vp]),
     "pm_ntt": (_int, [_vp, _vp, _sz, _u32, _int, _vp]),
@@ -192,6 +193,24 @@ def poly_mul(a, b, p: int, out=None, plan: Plan | None = None, stream=None):
         _check(lib().pm_poly_mul(*args, _stream(stream)), "pm_poly_mul")
     else:
         _check(lib().pm_poly_mul_plan(*args, ctypes.byref(plan), _stream(stream)), "pm_poly_mul_plan")
+    return out
+
+
+def poly_mul_multi(a, b, p: int, out=None, stream=None):
+    """Dense multivariate product by Kronecker substitution.  a, b: uint32 device
+    tensors with one dimension per variable (1 + the degree in it); returns the
+    product, of shape a.shape[i] + b.shape[i] - 1."""
+    torch = _torch()
+    nv = a.dim()
+    if b.dim() != nv:
+        raise ValueError("a and b need the same number of variables")
+    shape = tuple(x + y - 1 for x, y in zip(a.shape, b.shape))
+    if out is None:
+        out = torch.empty(shape, dtype=torch.uint32, device=a.device)
+    da = (_sz * max(nv, 1))(*a.shape)
+    db = (_sz * max(nv, 1))(*b.shape)
+    _check(lib().pm_poly_mul_multi(_dev_ptr(a, torch.uint32, "a"), da, _dev_ptr(b, torch.uint32, "b"), db, nv, p,
+                                   _dev_ptr(out, torch.uint32, "out"), _stream(stream)), "pm_poly_mul_multi")
     return out
 
 

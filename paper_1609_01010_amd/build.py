@@ -28,6 +28,7 @@ SOURCES = [
     ("xform_kernels.hip", ["-DPM_LAZY=0"]),
     ("xform_kernels.hip", ["-DPM_LAZY=1"]),
     ("crt.hip", []),
+    ("kronecker.hip", []),
     ("dispatch.cpp", []),
     ("capi.cpp", []),
     ("batch.cpp", []),

@@ -57,8 +57,9 @@ static int kept_blocks(long lc, int logL, int logRA) {
 
 Plan default_plan(long lc, int pidx) {
   // measured on MI355X: row length C = L / 256 (at least 2^10, at most 2^14),
-  // columns split 16 x R/16, 16 elements per row thread; truncation with the
-  // finest first radix (32) when the output length is not a power of two
+  // columns split 16 x R/16, 16 elements per row thread, LDS rounds of radix
+  // 8 in the rows; truncation with the finest first radix (32) when the
+  // output length is not a power of two
   Plan P;
   if (lc <= 64) {
     P.kind = PLAN_DIRECT;
@@ -84,6 +85,7 @@ Plan default_plan(long lc, int pidx) {
       P.logRB = logR - P.logRA;
     }
     P.lnt = P.logC - 4 < 6 ? 6 : P.logC - 4;
+    P.lq = 3;
   }
   P.ma = kept_blocks(lc, P.logL, P.logRA);
   return P;
@@ -313,7 +315,14 @@ static pm_status ring_product(int ring, const uint32_t* a, size_t len_a, const u
     return dev_status(
         launch_direct_ring(a, (long)len_a, b, (long)len_b, (long)n, ring == 2, c, pidx, ctx->errflag, s));
   // a plan for output length n transforms exactly n points (n' = L = n)
-  const Plan P = choose_plan((long)n, pidx, ctx, s);
+  Plan P = choose_plan((long)n, pidx, ctx, s);
+  if (ring == 2) {
+    P.twist = 1;
+    if (P.kind == PLAN_LDS) {  // the twisted one-work-group kernels exist for the first radix 16
+      P.logRA = 4;
+      P.ma = 16;
+    }
+  }
   if (P.kind == PLAN_DIRECT || !plan_valid(P, (long)n, pidx) || plan_nprime(P) != (long)n) return PM_ETOOLARGE;
   const size_t wsb = plan_workspace_bytes(P);
   void* ws = nullptr;
@@ -407,6 +416,49 @@ static pm_status product_with(const uint32_t* a, size_t len_a, const uint32_t* b
 pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p, uint32_t* c,
                       void* stream) {
   return product_with(a, len_a, b, len_b, p, c, nullptr, stream);
+}
+
+pm_status pm_poly_mul_multi(const uint32_t* a, const size_t* dims_a, const uint32_t* b, const size_t* dims_b,
+                            int nvars, uint32_t p, uint32_t* c, void* stream) {
+  if (!a || !b || !c || !dims_a || !dims_b || nvars < 1 || nvars > kKronMaxVars) return PM_EINVAL;
+  long da[kKronMaxVars], db[kKronMaxVars], dc[kKronMaxVars];
+  long total = 1;
+  for (int i = 0; i < nvars; ++i) {
+    if (dims_a[i] < 1 || dims_b[i] < 1 || dims_a[i] > (1ul << 24) || dims_b[i] > (1ul << 24)) return PM_EINVAL;
+    da[i] = (long)dims_a[i];
+    db[i] = (long)dims_b[i];
+    dc[i] = da[i] + db[i] - 1;
+    total *= dc[i];
+    if (total > (1l << 24)) return PM_ETOOLARGE;
+  }
+  // packed lengths: 1 + sum (d_i - 1) s_i with s_i the product's strides
+  long la = 1, lb = 1, stride = 1;
+  for (int i = nvars - 1; i >= 0; --i) {
+    la += (da[i] - 1) * stride;
+    lb += (db[i] - 1) * stride;
+    stride *= dc[i];
+  }
+  int pidx;
+  long lc;
+  pm_status st = check_product_args(a, (size_t)la, b, (size_t)lb, p, c, &pidx, &lc);
+  if (st) return st;
+  DevCtx* ctx = ctx_current(&st);
+  if (!ctx) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t s = (hipStream_t)stream;
+  const Plan P = choose_plan(lc, pidx, ctx, s);
+  if (!plan_valid(P, lc, pidx)) return PM_ETOOLARGE;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t pa = al((size_t)la * 4), pb = al((size_t)lb * 4);
+  void* ws = nullptr;
+  st = stream_workspace(ctx, s, pa + pb + plan_workspace_bytes(P), &ws);
+  if (st) return st;
+  u32* ka = (u32*)ws;
+  u32* kb = (u32*)((char*)ws + pa);
+  hipError_t e = launch_kron_pack(a, nvars, da, dc, la, ka, s);
+  if (e == hipSuccess) e = launch_kron_pack(b, nvars, db, dc, lb, kb, s);
+  if (e != hipSuccess) return dev_status(e);
+  return run_product(ctx, P, ka, la, kb, lb, 0, c, lc, pidx, (char*)ws + pa + pb, s);
 }
 
 pm_status pm_cyclic_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, size_t n, uint32_t p,

@@ -36,7 +36,7 @@ constexpr bool kLazy = PM_LAZY != 0;
 // length), transforms in registers and keeps output rows t < ma.
 // blockIdx.y selects the operand, blockIdx.z the job.
 
-template <int LRA, bool LAZY, typename TIn>
+template <int LRA, bool LAZY, typename TIn, bool TWIST>
 __global__ void __launch_bounds__(64) k_col_fwd1(JobRef jr, int logC) {
   constexpr int RA = 1 << LRA;
   const ConvJob J = load_job(jr);
@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(64) k_col_fwd1(JobRef jr, int logC) {
     const long pos = C * s + j2;
     x[s] = pos < z ? (u32)gld(in + pos) : 0u;
     bad |= x[s] >= J.mp.p;
-    if (J.twf) x[s] = A.mul(x[s], cld(J.twf + s));
+    if constexpr (TWIST) x[s] = A.mul(x[s], cld(J.twf + s));
   }
   if (bad) atomicOr(J.err, 1);
   dif_reg<RA>(A, x, J.T.pf);
@@ -85,7 +85,7 @@ constexpr int col_round_lq() {
 // FROM_GLOBAL: the input is the operand in global memory (rows beyond its
 // length are zero), else LDS; TO_GLOBAL: output rows below mr go to `out`,
 // else back to LDS
-template <int LB, int LQ, bool FROM_GLOBAL, bool TO_GLOBAL, bool LAZY, typename TIn>
+template <int LB, int LQ, bool FROM_GLOBAL, bool TO_GLOBAL, bool LAZY, typename TIn, bool TWIST>
 __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
                                               int tid, int nthr, const TIn* __restrict__ in, long z, long C, long col0,
                                               u32* __restrict__ out, const uint2* twf, bool& bad) {
@@ -109,7 +109,7 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
           const long pos = C * row + col0 + c;
           x[s] = pos < z ? (u32)gld(in + pos) : 0u;
           bad |= x[s] >= A.p;
-          if (twf) x[s] = A.mul(x[s], cld(twf + row));
+          if constexpr (TWIST) x[s] = A.mul(x[s], cld(twf + row));
         } else {
           x[s] = sm[(row << lw) + c];
         }
@@ -133,21 +133,21 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
 
 // rounds K.. of the forward column transform on blocks of 2^LB rows; a
 // barrier separates consecutive rounds
-template <int LR, int K, int LB, bool LAZY, typename TIn>
+template <int LR, int K, int LB, bool LAZY, typename TIn, bool TWIST>
 __device__ __forceinline__ void col_dif_rounds(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
                                                int tid, int nthr, const TIn* in, long z, long C, long col0, u32* out,
                                                const uint2* twf, bool& bad) {
   constexpr int LQ = col_round_lq<LR, K>();
   constexpr bool first = K == 0;
   constexpr bool last = LB == LQ;
-  col_dif_round<LB, LQ, first, last, LAZY, TIn>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, twf, bad);
+  col_dif_round<LB, LQ, first, last, LAZY, TIn, TWIST>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, twf, bad);
   if constexpr (!last) {
     __syncthreads();
-    col_dif_rounds<LR, K + 1, LB - LQ, LAZY, TIn>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, twf, bad);
+    col_dif_rounds<LR, K + 1, LB - LQ, LAZY, TIn, TWIST>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, twf, bad);
   }
 }
 
-template <int LR, bool LAZY, typename TIn>
+template <int LR, bool LAZY, typename TIn, bool TWIST>
 __global__ void __launch_bounds__(1024) k_col_fwdr(JobRef jr, int logC, int lw) {
   extern __shared__ u32 sm[];  // [R][W]
   const ConvJob J = load_job(jr);
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(1024) k_col_fwdr(JobRef jr, int logC, int lw) 
   const long z = blockIdx.y ? J.lb : J.la;
   u32* __restrict__ out = blockIdx.y ? J.Tb : J.Ta;
   bool bad = false;
-  col_dif_rounds<LR, 0, LR, LAZY, TIn>(A, sm, lw, J.rows, J.T, threadIdx.x, blockDim.x, in, z, 1l << logC,
+  col_dif_rounds<LR, 0, LR, LAZY, TIn, TWIST>(A, sm, lw, J.rows, J.T, threadIdx.x, blockDim.x, in, z, 1l << logC,
                                        (long)blockIdx.x << lw, out, J.twf, bad);
   if (bad) atomicOr(J.err, 1);
 }
@@ -176,46 +176,46 @@ inline int col_threads(int logR, int lw) {
   return n < 64 ? 64 : n;
 }
 
-template <int LR, typename TIn>
+template <int LR, typename TIn, bool TWIST>
 static hipError_t col_fwdr_launch(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
   const int lw = col_lw(LR, P.logC, (long)nops * njobs);
   const long C = 1l << P.logC;
   if (C < (1l << lw) || col_threads(LR, lw) > 1024) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << (lw + LR)) * sizeof(u32);
-  auto kern = k_col_fwdr<LR, kLazy, TIn>;
+  auto kern = k_col_fwdr<LR, kLazy, TIn, TWIST>;
   ensure_lds_attr((const void*)kern, lds);
   return launch("col_fwd", kern, dim3((unsigned)(C >> lw), nops, njobs), col_threads(LR, lw), lds, s, jr, P.logC,
                 lw);
 }
 
-template <int LRA, typename TIn>
+template <int LRA, typename TIn, bool TWIST>
 static hipError_t col_fwd_ra(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
   const long C = 1l << P.logC;
   if (P.logRB == 0) {
-    return launch("col_fwd", k_col_fwd1<LRA, kLazy, TIn>, dim3((unsigned)((C + 63) / 64), nops, njobs), 64, 0, s, jr,
-                  P.logC);
+    return launch("col_fwd", k_col_fwd1<LRA, kLazy, TIn, TWIST>, dim3((unsigned)((C + 63) / 64), nops, njobs), 64, 0,
+                  s, jr, P.logC);
   }
   if constexpr (LRA >= 4) {
     switch (P.logRB) {
-      case 1: return col_fwdr_launch<LRA + 1, TIn>(P, nops, jr, njobs, s);
-      case 2: return col_fwdr_launch<LRA + 2, TIn>(P, nops, jr, njobs, s);
-      case 3: return col_fwdr_launch<LRA + 3, TIn>(P, nops, jr, njobs, s);
-      case 4: return col_fwdr_launch<LRA + 4, TIn>(P, nops, jr, njobs, s);
-      case 5: return col_fwdr_launch<LRA + 5, TIn>(P, nops, jr, njobs, s);
+      case 1: return col_fwdr_launch<LRA + 1, TIn, TWIST>(P, nops, jr, njobs, s);
+      case 2: return col_fwdr_launch<LRA + 2, TIn, TWIST>(P, nops, jr, njobs, s);
+      case 3: return col_fwdr_launch<LRA + 3, TIn, TWIST>(P, nops, jr, njobs, s);
+      case 4: return col_fwdr_launch<LRA + 4, TIn, TWIST>(P, nops, jr, njobs, s);
+      case 5: return col_fwdr_launch<LRA + 5, TIn, TWIST>(P, nops, jr, njobs, s);
       default: break;
     }
   }
   return hipErrorInvalidValue;
 }
 
-template <typename TIn>
+template <typename TIn, bool TWIST>
 static hipError_t col_fwd_t(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
   switch (P.logRA) {
-    case 1: return col_fwd_ra<1, TIn>(P, nops, jr, njobs, s);
-    case 2: return col_fwd_ra<2, TIn>(P, nops, jr, njobs, s);
-    case 3: return col_fwd_ra<3, TIn>(P, nops, jr, njobs, s);
-    case 4: return col_fwd_ra<4, TIn>(P, nops, jr, njobs, s);
-    case 5: return col_fwd_ra<5, TIn>(P, nops, jr, njobs, s);
+    case 1: return col_fwd_ra<1, TIn, TWIST>(P, nops, jr, njobs, s);
+    case 2: return col_fwd_ra<2, TIn, TWIST>(P, nops, jr, njobs, s);
+    case 3: return col_fwd_ra<3, TIn, TWIST>(P, nops, jr, njobs, s);
+    case 4: return col_fwd_ra<4, TIn, TWIST>(P, nops, jr, njobs, s);
+    case 5: return col_fwd_ra<5, TIn, TWIST>(P, nops, jr, njobs, s);
     default: break;
   }
   return hipErrorInvalidValue;
@@ -223,8 +223,9 @@ static hipError_t col_fwd_t(const Plan& P, int nops, const JobRef& jr, int njobs
 
 hipError_t PM_SUFFIX(launch_col_fwd)(const Plan& P, int in_type, int nops, const JobRef& jr, int njobs,
                                      hipStream_t s) {
-  if (in_type == 1) return col_fwd_t<uint16_t>(P, nops, jr, njobs, s);
-  return col_fwd_t<u32>(P, nops, jr, njobs, s);
+  if (in_type == 1) return P.twist ? hipErrorInvalidValue : col_fwd_t<uint16_t, false>(P, nops, jr, njobs, s);
+  if (P.twist) return col_fwd_t<u32, true>(P, nops, jr, njobs, s);
+  return col_fwd_t<u32, false>(P, nops, jr, njobs, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -376,7 +377,7 @@ hipError_t PM_SUFFIX(launch_row_conv)(const Plan& P, int max_rows, const JobRef&
 // column j2 gathers rows t < ma, inverts (full length-RA inverse, or the
 // truncated inverse with ma known values), writes coefficients j1 < ma.
 
-template <int LRA, bool LAZY>
+template <int LRA, bool LAZY, bool TWIST>
 __global__ void __launch_bounds__(64) k_col_inv1(JobRef jr, int logC) {
   constexpr int RA = 1 << LRA;
   const ConvJob J = load_job(jr);
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(64) k_col_inv1(JobRef jr, int logC) {
 #pragma unroll
   for (int s = 0; s < RA; ++s) {
     const long pos = C * s + j2;
-    if (s < ma && pos < J.lc) gst(c + pos, A.canon(J.twi ? A.mul(x[s], cld(J.twi + s)) : x[s]));
+    if (s < ma && pos < J.lc) gst(c + pos, A.canon(TWIST ? A.mul(x[s], cld(J.twi + s)) : x[s]));
   }
 }
 
@@ -454,7 +455,7 @@ constexpr int col_last_round() {
 // innermost round straight from global memory), then per column and j1b
 // the truncated inverse of radix RA with ma known values, written to the
 // output coefficients.
-template <int LRA, int LRB, bool LAZY>
+template <int LRA, int LRB, bool LAZY, bool TWIST>
 __global__ void __launch_bounds__(1024) k_col_invr(JobRef jr, int logC, int lw) {
   constexpr int RA = 1 << LRA, RB = 1 << LRB, R = RA * RB;
   extern __shared__ u32 sm[];  // [R][W]
@@ -485,52 +486,58 @@ __global__ void __launch_bounds__(1024) k_col_invr(JobRef jr, int logC, int lw) 
 #pragma unroll
     for (int e = 0; e < RA; ++e) {
       const long pos = C * (j1b + RB * e) + c0 + cc;
-      if (e < ma && pos < J.lc) gst(c + pos, A.canon(J.twi ? A.mul(x[e], cld(J.twi + j1b + RB * e)) : x[e]));
+      if (e < ma && pos < J.lc) gst(c + pos, A.canon(TWIST ? A.mul(x[e], cld(J.twi + j1b + RB * e)) : x[e]));
     }
   }
 }
 
-template <int LRA, int LRB>
+template <int LRA, int LRB, bool TWIST>
 static hipError_t col_invr_launch(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
   const int lw = col_lw(LRA + LRB, P.logC, (long)njobs);
   const long C = 1l << P.logC;
   if (C < (1l << lw) || col_threads(LRA + LRB, lw) > 1024) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << (lw + LRA + LRB)) * sizeof(u32);
-  auto kern = k_col_invr<LRA, LRB, kLazy>;
+  auto kern = k_col_invr<LRA, LRB, kLazy, TWIST>;
   ensure_lds_attr((const void*)kern, lds);
   return launch("col_inv", kern, dim3((unsigned)(C >> lw), 1, njobs), col_threads(LRA + LRB, lw), lds, s, jr,
                 P.logC, lw);
 }
 
-template <int LRA>
+template <int LRA, bool TWIST>
 static hipError_t col_inv_ra(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
   const long C = 1l << P.logC;
   if (P.logRB == 0) {
-    return launch("col_inv", k_col_inv1<LRA, kLazy>, dim3((unsigned)((C + 63) / 64), 1, njobs), 64, 0, s, jr, P.logC);
+    return launch("col_inv", k_col_inv1<LRA, kLazy, TWIST>, dim3((unsigned)((C + 63) / 64), 1, njobs), 64, 0, s, jr,
+                  P.logC);
   }
   if constexpr (LRA >= 4) {
     switch (P.logRB) {
-      case 1: return col_invr_launch<LRA, 1>(P, jr, njobs, s);
-      case 2: return col_invr_launch<LRA, 2>(P, jr, njobs, s);
-      case 3: return col_invr_launch<LRA, 3>(P, jr, njobs, s);
-      case 4: return col_invr_launch<LRA, 4>(P, jr, njobs, s);
-      case 5: return col_invr_launch<LRA, 5>(P, jr, njobs, s);
+      case 1: return col_invr_launch<LRA, 1, TWIST>(P, jr, njobs, s);
+      case 2: return col_invr_launch<LRA, 2, TWIST>(P, jr, njobs, s);
+      case 3: return col_invr_launch<LRA, 3, TWIST>(P, jr, njobs, s);
+      case 4: return col_invr_launch<LRA, 4, TWIST>(P, jr, njobs, s);
+      case 5: return col_invr_launch<LRA, 5, TWIST>(P, jr, njobs, s);
       default: break;
     }
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t PM_SUFFIX(launch_col_inv)(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
+template <bool TWIST>
+static hipError_t col_inv_t(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
   switch (P.logRA) {
-    case 1: return col_inv_ra<1>(P, jr, njobs, s);
-    case 2: return col_inv_ra<2>(P, jr, njobs, s);
-    case 3: return col_inv_ra<3>(P, jr, njobs, s);
-    case 4: return col_inv_ra<4>(P, jr, njobs, s);
-    case 5: return col_inv_ra<5>(P, jr, njobs, s);
+    case 1: return col_inv_ra<1, TWIST>(P, jr, njobs, s);
+    case 2: return col_inv_ra<2, TWIST>(P, jr, njobs, s);
+    case 3: return col_inv_ra<3, TWIST>(P, jr, njobs, s);
+    case 4: return col_inv_ra<4, TWIST>(P, jr, njobs, s);
+    case 5: return col_inv_ra<5, TWIST>(P, jr, njobs, s);
     default: break;
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t PM_SUFFIX(launch_col_inv)(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
+  return P.twist ? col_inv_t<true>(P, jr, njobs, s) : col_inv_t<false>(P, jr, njobs, s);
 }
 
 }  // namespace pm

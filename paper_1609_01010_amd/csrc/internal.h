@@ -94,6 +94,7 @@ struct Plan {
   int ma = 1;     // kept blocks of the first radix, 1..RA
   int lq = 4;     // log radix of the LDS rounds
   int lnt = 0;    // log2 threads of the row pass (0: the default for logC)
+  int twist = 0;  // nega-circular product: the passes twist the operands and untwist the result
 };
 
 // threads of the four-step row pass
@@ -107,6 +108,9 @@ inline long plan_nprime(const Plan& P) { return (long)P.ma << (P.logL - P.logRA)
 
 // ---- launchers (return hipSuccess or the launch error) --------------------
 hipError_t launch_direct(const u32* a, long la, const u32* b, long lb, u32* c, int pidx, int* err, hipStream_t s);
+constexpr int kKronMaxVars = 8;
+hipError_t launch_kron_pack(const u32* a, int nv, const long* da, const long* dc, long n_out, u32* out,
+                            hipStream_t s);
 hipError_t launch_direct_ring(const u32* a, long la, const u32* b, long lb, long n, bool negacyclic, u32* c, int pidx,
                               int* err, hipStream_t s);
 // Convolution launches over njobs jobs of one plan class (jobs in jr: the

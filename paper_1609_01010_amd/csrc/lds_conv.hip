@@ -35,7 +35,7 @@ constexpr bool kLazy = PM_LAZY != 0;
 // registers straight from global memory and keeps the first ma of its RA
 // output blocks; the remaining rounds transform those blocks in LDS.
 
-template <int LN, int LRA, int LQ, bool LAZY>
+template <int LN, int LRA, int LQ, bool LAZY, bool TWIST>
 __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
   constexpr int N = 1 << LN;
   constexpr int RA = 1 << LRA;
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
         const int pos = j + S * s;
         x[s] = pos < len ? gld(in + pos) : 0u;
         bad |= x[s] >= J.mp.p;
-        if (J.twf) x[s] = A.mul(x[s], cld(J.twf + pos));
+        if constexpr (TWIST) x[s] = A.mul(x[s], cld(J.twf + pos));
       }
       dif_reg<RA, LAZY, (S > 1)>(A, x, T.pf);
 #pragma unroll
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
 #pragma unroll
     for (int s = 0; s < RA; ++s) {
       const int pos = j + S * s;
-      if (s < ma && pos < lc) gst(c + pos, A.canon(J.twi ? A.mul(x[s], cld(J.twi + pos)) : x[s]));
+      if (s < ma && pos < lc) gst(c + pos, A.canon(TWIST ? A.mul(x[s], cld(J.twi + pos)) : x[s]));
     }
   }
 }
@@ -121,21 +121,23 @@ inline int lds_conv_threads(int ln) {
   return nthr < 64 ? 64 : (nthr > 1024 ? 1024 : nthr);
 }
 
-template <int LN, int LRA>
+template <int LN, int LRA, bool TWIST>
 static hipError_t lds_conv_inst(const JobRef& jr, int njobs, hipStream_t s) {
   constexpr int N = 1 << LN;
   const size_t lds = 2 * (size_t)N * sizeof(u32);
-  auto kern = k_lds_conv<LN, LRA, 4, kLazy>;
+  auto kern = k_lds_conv<LN, LRA, 4, kLazy, TWIST>;
   ensure_lds_attr((const void*)kern, lds);
   return launch("lds_conv", kern, dim3(1, 1, njobs), lds_conv_threads(LN), lds, s, jr);
 }
 
+// the nega-circular products (twisted) use the first radix 16 only
 template <int LN>
 static hipError_t lds_conv_ra(const Plan& P, const JobRef& jr, int njobs, hipStream_t s) {
+  if (P.twist) return P.logRA == 4 ? lds_conv_inst<LN, 4, true>(jr, njobs, s) : hipErrorInvalidValue;
   switch (P.logRA) {
 #define PM_RA(r)                                                                    \
   case r:                                                                           \
-    if constexpr (r <= LN) return lds_conv_inst<LN, r>(jr, njobs, s);               \
+    if constexpr (r <= LN) return lds_conv_inst<LN, r, false>(jr, njobs, s);        \
     break;
     PM_RA(3) PM_RA(4) PM_RA(5)
 #undef PM_RA

@@ -250,6 +250,48 @@ def test_cyclic_and_negacyclic_products(gpu_lib, p, g):
             assert np.array_equal(got_n, op.negacyclic_conv(ap, bp, p))
 
 
+def _eval2(c, p, x, y):
+    """c(x, y) mod p for a 2-D coefficient array, vectorised with exact int64 steps."""
+    c = np.asarray(c, dtype=np.int64)
+    yp = np.array([pow(y, j, p) for j in range(c.shape[1])], dtype=np.int64)
+    xp = np.array([pow(x, i, p) for i in range(c.shape[0])], dtype=np.int64)
+    rows = ((c * yp[None, :]) % p).sum(axis=1) % p
+    return int(((rows * xp) % p).sum() % p)
+
+
+def test_multivariate_products(gpu_lib):
+    """Kronecker substitution: against the multivariate definition on small
+    boxes (one to four variables), and a 1024 x 1024 by 1024 x 1024 bivariate
+    product (2047^2 coefficients, a 2^22 transform) against evaluation at
+    random points."""
+    pm = gpu_lib
+    rng = np.random.default_rng(160)
+    for p in (998244353, 2013265921):
+        for k, (sa, sb) in enumerate((((1000,), (777,)), ((30, 40), (25, 17)), ((5, 6, 7), (4, 3, 9)),
+                                      ((3, 2, 4, 5), (2, 5, 3, 2)), ((1, 64), (1, 1)), ((40, 1), (1, 33)))):
+            say("case: multivariate", p, sa, sb)
+            a = rng.integers(0, p, sa, dtype=np.uint32)
+            b = rng.integers(0, p, sb, dtype=np.uint32)
+            got = host(pm.poly_mul_multi(dev(a), dev(b), p))
+            assert pm.stream_check() == 0
+            assert np.array_equal(got, op.poly_mul_multi(a, b, p)), (sa, sb)
+    p = 2013265921
+    say("case: multivariate 1024^2 x 1024^2")
+    a = rng.integers(0, p, (1024, 1024), dtype=np.uint32)
+    b = rng.integers(0, p, (1024, 1024), dtype=np.uint32)
+    got = host(pm.poly_mul_multi(dev(a), dev(b), p))
+    assert got.shape == (2047, 2047) and pm.stream_check() == 0
+    for _ in range(4):
+        x, y = (int(t) for t in rng.integers(1, p, 2))
+        assert _eval2(got, p, x, y) == _eval2(a, p, x, y) * _eval2(b, p, x, y) % p
+    # one row of the result by the definition: c[i, :] = sum_r a[r, :] * b[i - r, :]
+    i = 700
+    row = np.zeros(2047, dtype=np.int64)
+    for r in range(max(0, i - 1023), min(i, 1023) + 1):
+        row = (row + op.poly_mul(a[r], b[i - r], p).astype(np.int64)) % p
+    assert np.array_equal(got[i], row.astype(np.uint32))
+
+
 def test_ring_product_errors(gpu_lib):
     pm = gpu_lib
     p = 998244353

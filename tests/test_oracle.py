@@ -259,6 +259,29 @@ def test_negacyclic_agrees_at_odd_powers_of_psi():
         assert op.eval_at(c, p, x) == op.eval_at(u, p, x) * op.eval_at(v, p, x) % p
 
 
+def test_multivariate_product_pins():
+    """The multivariate product by definition: one variable reduces to the
+    univariate schoolbook product; (1+x)^m (1+y)^n has binomial products as
+    coefficients; and the product agrees with a(x) b(x) at random points."""
+    p = 167772161
+    rng = np.random.default_rng(34)
+    a = rng.integers(0, p, 37, dtype=np.uint32)
+    b = rng.integers(0, p, 21, dtype=np.uint32)
+    assert np.array_equal(op.poly_mul_multi(a, b, p), op.poly_mul(a, b, p))
+    m, n = 6, 9
+    ax = np.array([[math.comb(m, i) * math.comb(n, j) % p for j in range(n + 1)] for i in range(m + 1)])
+    c = op.poly_mul_multi(ax, ax, p)
+    want = [[math.comb(2 * m, i) * math.comb(2 * n, j) % p for j in range(2 * n + 1)] for i in range(2 * m + 1)]
+    assert np.array_equal(c, np.array(want, dtype=np.uint32))
+    a = rng.integers(0, p, (3, 4, 5), dtype=np.uint32)
+    b = rng.integers(0, p, (2, 6, 3), dtype=np.uint32)
+    c = op.poly_mul_multi(a, b, p)
+    assert c.shape == (4, 9, 7)
+    for _ in range(3):
+        xs = [int(t) for t in rng.integers(1, p, 3)]
+        assert op.eval_multi(c, p, xs) == op.eval_multi(a, p, xs) * op.eval_multi(b, p, xs) % p
+
+
 def test_large_ntt_roundtrip_and_theorem():
     p, g = 2013265921, 31
     rng = np.random.default_rng(5)
