@@ -202,6 +202,21 @@ def dft_direct(x, p: int, g: int, inverse: bool = False) -> list:
     return out
 
 
+def dft_eval(x, p: int, g: int, inverse: bool = False, ks=None) -> np.ndarray:
+    """X_k = x(w^k) mod p for a length N = len(x) dividing p - 1, any N (section
+    3: the transform evaluates x at w^0 .. w^{N-1}, w = g^((p-1)/N)); with
+    inverse, x(w^-k) N^-1.  Only the indices ks (all by default), each by
+    Horner's rule: O(N) per value."""
+    x = _as_u32(x)
+    n = x.size
+    w = root(p, g, n, inverse)
+    ks = range(n) if ks is None else ks
+    out = np.array([eval_at(x, p, pow(w, int(k), p)) for k in ks], dtype=np.uint64)
+    if inverse:
+        out = out * pow(n, p - 2, p) % p
+    return out.astype(np.uint32)
+
+
 def ntt(x, p: int, g: int, inverse: bool = False) -> np.ndarray:
     """Length-N transform in natural order by the iterative radix-2 algorithm
     (C); inverse includes N^-1.  Pinned against dft_direct."""

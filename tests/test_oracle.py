@@ -183,6 +183,83 @@ def test_dft_direct_is_evaluation():
     assert op.dft_direct(x, p, g) == [op.eval_at_py(x, p, pow(w, k, p)) for k in range(8)]
 
 
+# lengths N = q 2^k with q an odd factor of p - 1, per prime
+MIXED_LENGTHS = {2013265921: (3, 6, 10, 12, 15, 20, 24, 30, 48, 96),
+                 998244353: (7, 14, 17, 28, 34, 56, 68, 112),
+                 469762049: (7, 14, 28, 56),
+                 167772161: (5, 10, 20, 40, 80)}
+
+
+def _prime_factors(n):
+    f, d = set(), 2
+    while d * d <= n:
+        while n % d == 0:
+            f.add(d)
+            n //= d
+        d += 1
+    if n > 1:
+        f.add(n)
+    return f
+
+
+def check_dft_any_length(dft):
+    """Pins of a transform dft(x, p, g, inverse) of any length N | p - 1."""
+    rng = random.Random(11)
+    for p, g in PRIMES:
+        for n in MIXED_LENGTHS[p]:
+            w = op.root(p, g, n)
+            # w has order exactly n
+            assert pow(w, n, p) == 1 and all(pow(w, n // r, p) != 1 for r in _prime_factors(n))
+            # closed forms: delta_0 -> all ones; delta_1 -> w^k; all ones -> n delta_0
+            # (the geometric sum over the n-th roots vanishes only for a root of order n)
+            d0 = [1] + [0] * (n - 1)
+            d1 = [0, 1] + [0] * (n - 2)
+            assert [int(v) for v in dft(d0, p, g, False)] == [1] * n
+            assert [int(v) for v in dft(d1, p, g, False)] == [pow(w, k, p) for k in range(n)]
+            assert [int(v) for v in dft([1] * n, p, g, False)] == [n % p] + [0] * (n - 1)
+            # the convolution theorem (eq. 8) with the circular convolution's defining sums
+            u = [rng.randrange(p) for _ in range(n)]
+            v = [rng.randrange(p) for _ in range(n)]
+            fu, fv = dft(u, p, g, False), dft(v, p, g, False)
+            lhs = [int(t) for t in dft(op.cyclic_conv(u, v, p), p, g, False)]
+            assert lhs == [int(a) * int(b) % p for a, b in zip(fu, fv)]
+            # the inverse undoes the transform, factor n^-1 included
+            assert [int(t) for t in dft(fu, p, g, True)] == u
+        # power-of-two lengths: the radix-2 algorithm
+        x = [rng.randrange(p) for _ in range(64)]
+        assert [int(t) for t in dft(x, p, g, False)] == [int(t) for t in op.ntt(x, p, g)]
+
+
+def test_dft_any_length_pins():
+    check_dft_any_length(op.dft_eval)
+
+
+def _dft_root_of_half_order(x, p, g, inverse):
+    n = len(x)
+    m = n // 2 if n % 2 == 0 else n
+    w = op.root(p, g, m, inverse)
+    out = [op.eval_at(x, p, pow(w, k, p)) for k in range(n)]
+    return [v * pow(n, p - 2, p) % p for v in out] if inverse else out
+
+
+def _dft_no_scale(x, p, g, inverse):
+    y = op.dft_eval(x, p, g, inverse)
+    return [int(v) * len(x) % p for v in y] if inverse else y
+
+
+def _dft_shifted_index(x, p, g, inverse):
+    n = len(x)
+    w = op.root(p, g, n, inverse)
+    out = [op.eval_at(x, p, pow(w, k + 1, p)) for k in range(n)]
+    return [v * pow(n, p - 2, p) % p for v in out] if inverse else out
+
+
+@pytest.mark.parametrize("mutant", [_dft_root_of_half_order, _dft_no_scale, _dft_shifted_index])
+def test_dft_any_length_pins_catch_mistakes(mutant):
+    with pytest.raises(AssertionError):
+        check_dft_any_length(mutant)
+
+
 def test_cyclic_conv_is_product_mod_xn_minus_1():
     """Def. 4: circular convolution = product reduced mod x^N - 1."""
     p = 469762049
