@@ -258,6 +258,28 @@ def extra_configs(pm, torch, dev, reps=5):
         want = (lin[:4] + sign * lin[4:]) % pp
         ok = np.array_equal(rc.cpu().numpy()[ks], want.astype(np.uint32))
         out[f"{name}_2^21_p{pp}"] = {"us": ms * 1e3, "coeffs_per_s": n21 / (ms * 1e-3), "bit_exact_sampled": bool(ok)}
+    # general radix: products of length q 2^k - 1 through the length-q 2^k
+    # circular convolution (prime-factor split, q rows of 2^k), beside the
+    # same product by the autotuned power-of-two plans (relaxed TFT)
+    for q, k in ((3, 20), (5, 18), (15, 16)):
+        la = (q << k) // 2
+        lb = (q << k) - la
+        ma_, mb_ = inputs.poly_pair((163, q), la, lb, pp)
+        lcm = la + lb - 1
+        xa, xb = torch.from_numpy(ma_).to(dev), torch.from_numpy(mb_).to(dev)
+        xc = torch.empty(lcm, dtype=torch.uint32, device=dev)
+        pm.poly_mul_mixed(xa, xb, pp, q, out=xc)
+        ms_mixed = time_loop(torch, lambda i: pm.poly_mul_mixed(xa, xb, pp, q, out=xc), 20)
+        ks = np.array([0, 1, lcm // 3, lcm - 1])
+        ok = np.array_equal(xc.cpu().numpy()[ks], op.poly_mul_sample(ma_, mb_, pp, ks))
+        plan = tuned_pick(pm, lcm, pp)
+        pm.tune_db_clear()
+        pm.poly_mul(xa, xb, pp, out=xc, plan=plan)
+        ms_pow2 = time_loop(torch, lambda i: pm.poly_mul(xa, xb, pp, out=xc, plan=plan), 20)
+        out[f"mixed_radix_{q}x2^{k}_p{pp}"] = {
+            "lc": lcm, "us": ms_mixed * 1e3, "coeffs_per_s": lcm / (ms_mixed * 1e-3),
+            "pow2_tuned_us": ms_pow2 * 1e3, "pow2_plan": list(plan.as_tuple()), "bit_exact_sampled": bool(ok)}
+        del xa, xb, xc
     out["batch_4096_uneven"] = {
         "output_coeffs": ncoef,
         "plain_ms": ms_plain, "plain_coeffs_per_s": ncoef / (ms_plain * 1e-3),
@@ -267,18 +289,19 @@ def extra_configs(pm, torch, dev, reps=5):
     return out
 
 
-def traffic_from_profiles(kernel_src_hash):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter runs, if they were taken on the current kernel source."""
+def counters_from_profiles(kernel_src_hash):
+    """HBM bytes per launch and VALU utilisation of the dominant kernel from the
+    committed rocprofv3 counter runs, if they were taken on the current kernel
+    source (else None, None)."""
     path = os.path.join(ROOT, "profiles", "row_conv_counters.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except OSError:
-        return None
+        return None, None
     if d.get("source_sha256") != kernel_src_hash:
-        return None
-    return d.get("hbm_bytes_per_launch")
+        return None, None
+    return d.get("hbm_bytes_per_launch"), d.get("valu")
 
 
 def main():
@@ -406,7 +429,7 @@ def main():
     src += open(os.path.join(ROOT, "paper_1609_01010_amd", "csrc", "arith.h"), "rb").read()
     src_hash = hashlib.sha256(src).hexdigest()
     achieved = per_launch_slots / (row["avg_us"] * 1e-6)
-    traffic = traffic_from_profiles(src_hash)
+    traffic, valu = counters_from_profiles(src_hash)
     roofline = {
         "kernel": "row_conv",
         "bound": "alu",
@@ -415,6 +438,7 @@ def main():
         "unit": "Tslot/s",
         "frac": achieved / ALU_PEAK,
         "traffic": traffic,
+        "valu_counters": valu,
         "algorithmic_slots_per_launch": per_launch_slots,
         "hbm_achieved_GBps": per_launch_bytes / (row["avg_us"] * 1e-6) / 1e9,
         "hbm_frac": per_launch_bytes / (row["avg_us"] * 1e-6) / HBM_PEAK,

@@ -91,6 +91,20 @@ pm_status pm_negacyclic_mul(const uint32_t* a, size_t len_a, const uint32_t* b, 
                             uint32_t* c, void* stream);
 
 /*
+ * The product a * b mod p (as pm_poly_mul) through a circular convolution of
+ * length N = q 2^k >= len_a + len_b - 1, q odd (general radix: section 1,
+ * the smoothing of the power-of-two staircase by transforms of other
+ * lengths): the prime-factor split of the length-N convolution into q
+ * circular products of length 2^k by a length-q transform, and back.  q in
+ * {3, 5, 7, 15, 17} dividing p - 1 (see pm_ntt), else PM_EUNSUPPORTED;
+ * 2^k <= 2^24 and within p's 2-adic order, else PM_ETOOLARGE.  The q rows of
+ * each operand and of the result live in the stream's workspace (3 N words).
+ * Other errors as pm_poly_mul.
+ */
+pm_status pm_poly_mul_mixed(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p, uint32_t q,
+                            uint32_t* c, void* stream);
+
+/*
  * Dense multivariate product (section 1: multivariate products reduce to
  * univariate ones), here by Kronecker substitution: one univariate
  * product (pm_poly_mul) of the operands packed with the strides of the
@@ -136,9 +150,15 @@ pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb,
 
 /*
  * Length-n modular DFT (section 3: evaluation at w^0 .. w^{n-1}, with
- * w = g^((p-1)/n)), natural order in and out, n a power of two, 2 <= n.
- * inverse != 0 computes the inverse transform including the factor n^-1.
- * x: n inputs; y: n outputs (may equal x).
+ * w = g^((p-1)/n)), natural order in and out, 2 <= n.  n is a power of two,
+ * or n = q 2^k with q in {3, 5, 7, 15, 17} (the general-size transforms of
+ * the library generator that section 1 builds on): then q must divide p - 1
+ * (3, 5, 15 for 2013265921; 7, 17 for 998244353; 7 for 469762049; 5 for
+ * 167772161) and is split off by the prime-factor algorithm.  inverse != 0
+ * computes the inverse transform including the factor n^-1.  x: n inputs;
+ * y: n outputs (may equal x).  Errors: PM_EUNSUPPORTED for an odd part of n
+ * that is not supported for p, PM_ETOOLARGE for 2^k beyond p's 2-adic order
+ * or 2^24.
  */
 pm_status pm_ntt(const uint32_t* x, uint32_t* y, size_t n, uint32_t p, int inverse, void* stream);
 

@@ -80,6 +80,7 @@ SIGNATURES = {
     "pm_poly_mul": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, _vp]),
     "pm_poly_mul_batch": (_int, [ctypes.POINTER(Problem), _sz, _vp]),
     "pm_cyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
+    "pm_poly_mul_mixed": (_int, [_vp, _sz, _vp, _sz, _u32, _u32, _vp, _vp]),
     "pm_poly_mul_multi": (_int, [_vp, ctypes.POINTER(_sz), _vp, ctypes.POINTER(_sz), _int, _u32, _vp, _vp]),
     "pm_negacyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
     "pm_int_mul": (_int, [_vp, _sz, _vp, _sz, _vp, _vp]),
@@ -231,6 +232,19 @@ def cyclic_mul(a, b, n: int, p: int, out=None, stream=None):
 def negacyclic_mul(a, b, n: int, p: int, out=None, stream=None):
     """a b mod (x^n + 1) mod p (the nega-circular convolution); n a power of two."""
     return _ring_mul("pm_negacyclic_mul", a, b, n, p, out, stream)
+
+
+def poly_mul_mixed(a, b, p: int, q: int, out=None, stream=None):
+    """a * b mod p through a circular convolution of length q 2^k >= la + lb - 1
+    (q odd, dividing p - 1)."""
+    torch = _torch()
+    lc = a.numel() + b.numel() - 1
+    if out is None:
+        out = torch.empty(lc, dtype=torch.uint32, device=a.device)
+    _check(lib().pm_poly_mul_mixed(_dev_ptr(a, torch.uint32, "a"), a.numel(), _dev_ptr(b, torch.uint32, "b"),
+                                   b.numel(), p, q, _dev_ptr(out, torch.uint32, "out"), _stream(stream)),
+           "pm_poly_mul_mixed")
+    return out
 
 
 class PreparedBatch:

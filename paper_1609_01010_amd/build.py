@@ -29,6 +29,7 @@ SOURCES = [
     ("xform_kernels.hip", ["-DPM_LAZY=1"]),
     ("crt.hip", []),
     ("kronecker.hip", []),
+    ("mixed.hip", []),
     ("dispatch.cpp", []),
     ("capi.cpp", []),
     ("batch.cpp", []),

@@ -295,6 +295,46 @@ pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const vo
   return launch_class(P, prime_info(pidx).lazy, in_type, jr, 1, jr.one.rows, s);
 }
 
+// `rows` circular products of length n (Def. 4, eq. 5): row r of C is
+// row r of A times row r of B mod x^n - 1, rows n words apart; P is the plan
+// for length n (n' = L = n), Ta and Tb its four-step workspace.
+static pm_status cyclic_rows(DevCtx* ctx, int pidx, const Plan& P, const u32* A, const u32* B, u32* C, int rows,
+                             long n, u32* Ta, u32* Tb, hipStream_t s) {
+  const bool lazy = prime_info(pidx).lazy;
+  for (int r = 0; r < rows; ++r) {
+    const long o = (long)r * n;
+    if (n <= 64) {
+      const hipError_t e = launch_direct_ring(A + o, n, B + o, n, n, false, C + o, pidx, ctx->errflag, s);
+      if (e != hipSuccess) return PM_EDEVICE;
+      continue;
+    }
+    JobRef jr;
+    jr.many = nullptr;
+    pm_status st = make_job(ctx, P, pidx, A + o, n, B + o, n, C + o, n, Ta, Tb, &jr.one, 1);
+    if (st) return st;
+    st = launch_class(P, lazy, 0, jr, 1, jr.one.rows, s);
+    if (st) return st;
+  }
+  return PM_OK;
+}
+
+// the plan of the length-n circular product: the plan for output length n,
+// which transforms exactly n points (n' = L = n); twist selects the
+// nega-circular variant
+static pm_status ring_plan(long n, int pidx, DevCtx* ctx, hipStream_t s, int twist, Plan* out) {
+  Plan P = choose_plan(n, pidx, ctx, s);
+  if (twist) {
+    P.twist = 1;
+    if (P.kind == PLAN_LDS) {  // the twisted one-work-group kernels exist for the first radix 16
+      P.logRA = 4;
+      P.ma = 16;
+    }
+  }
+  if (P.kind == PLAN_DIRECT || !plan_valid(P, n, pidx) || plan_nprime(P) != n) return PM_ETOOLARGE;
+  *out = P;
+  return PM_OK;
+}
+
 // Products mod x^n - 1 (ring 1) and x^n + 1 (ring 2): length-n transforms,
 // no padding; the nega-circular twist is carried by the job (make_job).
 static pm_status ring_product(int ring, const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, size_t n,
@@ -314,16 +354,9 @@ static pm_status ring_product(int ring, const uint32_t* a, size_t len_a, const u
   if (n <= 64)
     return dev_status(
         launch_direct_ring(a, (long)len_a, b, (long)len_b, (long)n, ring == 2, c, pidx, ctx->errflag, s));
-  // a plan for output length n transforms exactly n points (n' = L = n)
-  Plan P = choose_plan((long)n, pidx, ctx, s);
-  if (ring == 2) {
-    P.twist = 1;
-    if (P.kind == PLAN_LDS) {  // the twisted one-work-group kernels exist for the first radix 16
-      P.logRA = 4;
-      P.ma = 16;
-    }
-  }
-  if (P.kind == PLAN_DIRECT || !plan_valid(P, (long)n, pidx) || plan_nprime(P) != (long)n) return PM_ETOOLARGE;
+  Plan P;
+  st = ring_plan((long)n, pidx, ctx, s, ring == 2, &P);
+  if (st) return st;
   const size_t wsb = plan_workspace_bytes(P);
   void* ws = nullptr;
   if (wsb) {
@@ -337,6 +370,53 @@ static pm_status ring_product(int ring, const uint32_t* a, size_t len_a, const u
   st = make_job(ctx, P, pidx, a, (long)len_a, b, (long)len_b, c, (long)n, Ta, Tb, &jr.one, ring);
   if (st) return st;
   return launch_class(P, PI.lazy, 0, jr, 1, jr.one.rows, s);
+}
+
+
+// Product through the length-N = q M circular convolution, q odd: the split
+// into q rows (length-q transform over j mod q), q circular products of
+// length M, and the merge (inverse length-q transform, factor q^-1) into the
+// lc = la + lb - 1 outputs; N >= lc makes the circular product the product.
+static pm_status mixed_product(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
+                               uint32_t q, uint32_t* c, void* stream) {
+  if (!a || !b || !c || len_a == 0 || len_b == 0) return PM_EINVAL;
+  const int pidx = prime_index(p);
+  if (pidx < 0) return PM_EUNSUPPORTED;
+  const PrimeInfo& PI = prime_info(pidx);
+  if (!mixed_q_supported((int)q) || (PI.p - 1) % q) return PM_EUNSUPPORTED;
+  const long lc = (long)(len_a + len_b - 1);
+  long M = 1;
+  while ((long)q * M < lc) M <<= 1;
+  const int logM = ceil_log2(M);
+  if (logM > PI.two_adic || logM > 24) return PM_ETOOLARGE;
+  pm_status st;
+  DevCtx* ctx = ctx_current(&st);
+  if (!ctx) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t s = (hipStream_t)stream;
+  st = ensure_prime_tables(ctx, pidx);
+  if (st) return st;
+  Plan P;
+  if (M > 64) {
+    st = ring_plan(M, pidx, ctx, s, 0, &P);
+    if (st) return st;
+  }
+  const size_t rows_words = (size_t)q * M;
+  const size_t wsb = 3 * rows_words * sizeof(u32) + (M > 64 ? plan_workspace_bytes(P) : 0);
+  void* ws = nullptr;
+  st = stream_workspace(ctx, s, wsb, &ws);
+  if (st) return st;
+  u32* A = (u32*)ws;
+  u32* B = A + rows_words;
+  u32* C = B + rows_words;
+  u32* Ta = M > 64 && P.kind == PLAN_FOURSTEP ? C + rows_words : nullptr;
+  u32* Tb = Ta ? Ta + plan_nprime(P) : nullptr;
+  hipError_t e = launch_mixed_split(a, (long)len_a, (int)q, M, A, pidx, ctx->errflag, s);
+  if (e == hipSuccess) e = launch_mixed_split(b, (long)len_b, (int)q, M, B, pidx, ctx->errflag, s);
+  if (e != hipSuccess) return PM_EDEVICE;
+  st = cyclic_rows(ctx, pidx, P, A, B, C, (int)q, M, Ta, Tb, s);
+  if (st) return st;
+  return dev_status(launch_mixed_merge(C, (int)q, M, c, lc, pidx, s));
 }
 
 }  // namespace pm
@@ -471,6 +551,11 @@ pm_status pm_negacyclic_mul(const uint32_t* a, size_t len_a, const uint32_t* b, 
   return ring_product(2, a, len_a, b, len_b, n, p, c, stream);
 }
 
+pm_status pm_poly_mul_mixed(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
+                            uint32_t q, uint32_t* c, void* stream) {
+  return mixed_product(a, len_a, b, len_b, p, q, c, stream);
+}
+
 pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
                            uint32_t* c, const pm_plan* plan, void* stream) {
   if (!plan) return PM_EINVAL;
@@ -570,45 +655,92 @@ static pm_status hook_setup(size_t L, uint32_t p, int* pidx, int* logL, DevCtx**
   return ensure_prime_tables(*ctx, *pidx);
 }
 
+// natural-order length-n transform, n = 2^logL >= 2, on an acquired context;
+// T: n words of workspace (four-step lengths)
+static pm_status ntt_pow2(DevCtx* c, int pidx, int logL, const u32* x, u32* y, long n, int inverse, u32* T,
+                          hipStream_t s) {
+  const PrimeInfo& PI = prime_info(pidx);
+  Plan P = hook_plan(logL, 0);
+  P.ma = 1 << P.logRA;
+  const uint2 ninv = h_shoup(h_inv((u32)(n % PI.p), PI.p), PI.p);
+  if (P.kind == PLAN_LDS)
+    return dev_status(
+        launch_lds_xform(P, x, n, y, n, inverse ? 1 : 0, 1, pidx, c->tabs[pidx], ninv, c->errflag, s));
+  RowTables S;
+  pm_status st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), inverse ? ninv.x : 1u, 0, &S);
+  if (st) return st;
+  const int logR = P.logRA + P.logRB;
+  hipError_t e;
+  JobRef jr;
+  jr.many = nullptr;
+  st = make_job(c, P, pidx, x, n, nullptr, 0, y, n, T, nullptr, &jr.one, 0);
+  if (st) return st;
+  if (!inverse) {
+    e = launch_col_fwd(P, PI.lazy, 0, 1, jr, 1, s);
+    if (e == hipSuccess) e = launch_row_xform(P, T, T, n, 0, pidx, c->tabs[pidx], S, s);
+    if (e == hipSuccess) e = launch_permute(T, y, logR, P.logC, 1, s);
+  } else {
+    e = launch_permute(x, T, logR, P.logC, 0, s);
+    if (e == hipSuccess) e = launch_row_xform(P, T, T, n, 1, pidx, c->tabs[pidx], S, s);
+    if (e == hipSuccess) e = launch_col_inv(P, PI.lazy, jr, 1, s);
+  }
+  return dev_status(e);
+}
+
+// length n = q M, q odd: the prime-factor split into q natural-order
+// length-M transforms (mixed.hip states the index maps)
+static pm_status ntt_mixed(const uint32_t* x, uint32_t* y, size_t n, uint32_t p, int inverse, void* stream) {
+  long M = (long)(n & (~n + 1));  // the largest power of two dividing n
+  const int q = (int)(n / (size_t)M);
+  const int pidx = prime_index(p);
+  if (pidx < 0) return PM_EUNSUPPORTED;
+  const PrimeInfo& PI = prime_info(pidx);
+  if (!mixed_q_supported(q) || (PI.p - 1) % (u32)q) return PM_EUNSUPPORTED;
+  const int logM = ceil_log2(M);
+  if (logM > PI.two_adic || logM > 24) return PM_ETOOLARGE;
+  pm_status st;
+  DevCtx* c = ctx_current(&st);
+  if (!c) return st;
+  st = ensure_prime_tables(c, pidx);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  void* wsp = nullptr;
+  st = stream_workspace(c, s, (2 * (size_t)n + (size_t)M) * sizeof(u32), &wsp);
+  if (st) return st;
+  u32* R1 = (u32*)wsp;
+  u32* R2 = R1 + n;
+  u32* T = R2 + n;
+  hipError_t e = inverse ? launch_mixed_perm(x, q, M, R1, 0, s)
+                         : launch_mixed_split(x, (long)n, q, M, R1, pidx, c->errflag, s);
+  if (e != hipSuccess) return PM_EDEVICE;
+  u32* rows = R1;
+  if (M > 1) {
+    for (int k1 = 0; k1 < q; ++k1) {
+      st = ntt_pow2(c, pidx, logM, R1 + (long)k1 * M, R2 + (long)k1 * M, M, inverse, T, s);
+      if (st) return st;
+    }
+    rows = R2;
+  }
+  return dev_status(inverse ? launch_mixed_merge(rows, q, M, y, (long)n, pidx, s)
+                            : launch_mixed_perm(rows, q, M, y, 1, s));
+}
+
 pm_status pm_ntt(const uint32_t* x, uint32_t* y, size_t n, uint32_t p, int inverse, void* stream) {
   if (!x || !y || n < 2) return PM_EINVAL;
+  if (n & (n - 1)) return ntt_mixed(x, y, n, p, inverse, stream);
   int pidx, logL;
   DevCtx* c;
   pm_status st = hook_setup(n, p, &pidx, &logL, &c);
   if (st) return st;
   std::lock_guard<std::mutex> lk(c->mu);
-  const PrimeInfo& PI = prime_info(pidx);
   hipStream_t s = (hipStream_t)stream;
-  Plan P = hook_plan(logL, 0);
-  P.ma = 1 << P.logRA;
-  const uint2 ninv = h_shoup(h_inv((u32)(n % PI.p), PI.p), PI.p);
-  if (P.kind == PLAN_LDS)
-    return dev_status(launch_lds_xform(P, x, (long)n, y, (long)n, inverse ? 1 : 0, 1, pidx, c->tabs[pidx], ninv,
-                                       c->errflag, s));
   void* wsp = nullptr;
-  st = stream_workspace(c, s, n * sizeof(u32), &wsp);
-  if (st) return st;
-  RowTables S;
-  st = get_row_tables(c, pidx, logL, P.logC, plan_row_lnt(P), inverse ? ninv.x : 1u, 0, &S);
-  if (st) return st;
-  u32* T = (u32*)wsp;
-  const int logR = P.logRA + P.logRB;
-  hipError_t e;
-  JobRef jr;
-  jr.many = nullptr;
-  st = make_job(c, P, pidx, x, (long)n, nullptr, 0, y, (long)n, T, nullptr, &jr.one, 0);
-  if (st) return st;
-  const bool lazy = prime_info(pidx).lazy;
-  if (!inverse) {
-    e = launch_col_fwd(P, lazy, 0, 1, jr, 1, s);
-    if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 0, pidx, c->tabs[pidx], S, s);
-    if (e == hipSuccess) e = launch_permute(T, y, logR, P.logC, 1, s);
-  } else {
-    e = launch_permute(x, T, logR, P.logC, 0, s);
-    if (e == hipSuccess) e = launch_row_xform(P, T, T, (long)n, 1, pidx, c->tabs[pidx], S, s);
-    if (e == hipSuccess) e = launch_col_inv(P, lazy, jr, 1, s);
+  if (logL > 14) {
+    st = stream_workspace(c, s, n * sizeof(u32), &wsp);
+    if (st) return st;
   }
-  return dev_status(e);
+  return ntt_pow2(c, pidx, logL, x, y, (long)n, inverse, (u32*)wsp, s);
 }
 
 pm_status pm_tft(const uint32_t* x, size_t z, size_t L, size_t n, uint32_t p, uint32_t* out, void* stream) {

@@ -57,7 +57,18 @@ def test_host_validation_without_device(L):
     assert L.pm_poly_mul(fake, 1 << 23, fake, 1 << 23, 998244353, fake, null) == 3
     assert L.pm_int_mul(fake, 1 << 23, fake, 1 << 23, fake, null) == 3
     assert L.pm_int_mul(null, 3, fake, 3, fake, null) == 1
-    assert L.pm_ntt(fake, fake, 3, 998244353, 0, null) == 1           # not a power of two
+    assert L.pm_ntt(fake, fake, 1, 998244353, 0, null) == 1           # n < 2
+    assert L.pm_ntt(fake, fake, 3, 998244353, 0, null) == 2           # 3 does not divide p - 1
+    assert L.pm_ntt(fake, fake, 18, 2013265921, 0, null) == 2         # odd part 9: no kernels
+    assert L.pm_ntt(fake, fake, 3 << 25, 2013265921, 0, null) == 3    # 2^25 > 2^24
+    assert L.pm_ntt(fake, fake, 7 << 24, 998244353, 0, null) == 3     # 2^24 > 2^23, the 2-adic order
+    # general-radix product
+    assert L.pm_poly_mul_mixed(null, 4, fake, 4, 2013265921, 3, fake, null) == 1
+    assert L.pm_poly_mul_mixed(fake, 4, fake, 0, 2013265921, 3, fake, null) == 1
+    assert L.pm_poly_mul_mixed(fake, 4, fake, 4, 998244353, 3, fake, null) == 2
+    assert L.pm_poly_mul_mixed(fake, 4, fake, 4, 2013265921, 9, fake, null) == 2
+    assert L.pm_poly_mul_mixed(fake, 4, fake, 4, 1000000007, 3, fake, null) == 2
+    assert L.pm_poly_mul_mixed(fake, 7 << 23, fake, 7 << 23, 998244353, 7, fake, null) == 3
     assert L.pm_tft(fake, 5, 4, 2, 998244353, fake, null) == 1        # z > L
     assert L.pm_itft(fake, 1 << 10, 33, 998244353, fake, null) == 1   # n not a multiple of L/32
     assert L.pm_set_policy(7) == 1

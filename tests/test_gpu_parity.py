@@ -250,6 +250,89 @@ def test_cyclic_and_negacyclic_products(gpu_lib, p, g):
             assert np.array_equal(got_n, op.negacyclic_conv(ap, bp, p))
 
 
+# odd factors q of p - 1 with kernels for the prime-factor split
+MIXED_Q = {2013265921: (3, 5, 15), 998244353: (7, 17), 469762049: (7,), 167772161: (5,)}
+
+
+@pytest.mark.parametrize("p,g", PRIMES)
+def test_mixed_length_ntt(gpu_lib, p, g):
+    """Transforms of length n = q 2^k (q odd, q | p - 1) by the prime-factor
+    split: every output against the evaluation definition up to n = 8192,
+    sampled outputs (first, last and 64 random) beyond; the inverse against
+    the same definition and the exact round trip."""
+    pm = gpu_lib
+    for q in MIXED_Q[p]:
+        for k in (0, 1, 3, 6, 9, 12, 15, 17):
+            n = q << k
+            say("case: mixed ntt", p, q, n)
+            x = inputs.uniform_mod(inputs.rng_for((160, q, k, p % 1000)), n, p)
+            X = host(pm.ntt(dev(x), p))
+            Y = host(pm.ntt(dev(x), p, inverse=True))
+            assert pm.stream_check() == 0
+            if n <= 8192:
+                ks = list(range(n))
+            else:
+                ks = sorted(set([0, 1, n - 1] + random.Random(n).sample(range(n), 64)))
+            assert np.array_equal(X[ks], op.dft_eval(x, p, g, ks=ks)), (q, n)
+            assert np.array_equal(Y[ks], op.dft_eval(x, p, g, inverse=True, ks=ks)), (q, n)
+            assert np.array_equal(host(pm.ntt(dev(X), p, inverse=True)), x), (q, n)
+
+
+@pytest.mark.parametrize("p,g", PRIMES)
+def test_mixed_radix_products(gpu_lib, p, g):
+    """Products through circular convolutions of length q 2^k >= la + lb - 1:
+    rows by the defining sums (2^k <= 64), one work-group and four-step rows,
+    ragged lengths; every output against the schoolbook oracle."""
+    pm = gpu_lib
+    shapes = [(1, 1), (2, 1), (10, 7), (40, 30), (100, 93), (1000, 537), (5000, 4001), (20000, 13001),
+              (70000, 30001)]
+    for q in MIXED_Q[p]:
+        for i, (la, lb) in enumerate(shapes):
+            say("case: mixed product", p, q, la, lb)
+            a, b = inputs.poly_pair((161, q, i, p % 1000), la, lb, p)
+            got = host(pm.poly_mul_mixed(dev(a), dev(b), p, q))
+            assert pm.stream_check() == 0
+            assert np.array_equal(got, op.poly_mul(a, b, p)), (q, la, lb)
+
+
+def test_mixed_radix_product_large_sampled(gpu_lib):
+    """3 * 2^19 x 3 * 2^19 mod 2013265921 through length 3 * 2^20 (rows of 2^20,
+    four-step), and 600001 x 400000 through length 5 * 2^18: 256 sampled outputs
+    each against the oracle's defining sum."""
+    pm = gpu_lib
+    p = 2013265921
+    for q, la, lb in ((3, 3 << 19, 3 << 19), (5, 600001, 400000)):
+        say("case: mixed product large", q, la, lb)
+        a, b = inputs.poly_pair((162, q), la, lb, p)
+        got = host(pm.poly_mul_mixed(dev(a), dev(b), p, q))
+        assert pm.stream_check() == 0
+        rng = random.Random(q)
+        ks = sorted(set([0, got.size - 1] + rng.sample(range(got.size), 256)))
+        assert np.array_equal(got[ks], op.poly_mul_sample(a, b, p, ks))
+
+
+def test_mixed_radix_errors(gpu_lib):
+    import ctypes
+
+    pm = gpu_lib
+    x = dev(np.ones(100, np.uint32))
+    for p, q in ((998244353, 3), (2013265921, 7), (2013265921, 9), (167772161, 1)):
+        with pytest.raises(pm.PolymulError) as e:
+            pm.poly_mul_mixed(x, x, p, q)
+        assert e.value.status == pm.PM_EUNSUPPORTED, (p, q)
+    with pytest.raises(pm.PolymulError) as e:
+        pm.ntt(dev(np.ones(18, np.uint32)), 2013265921)  # odd part 9
+    assert e.value.status == pm.PM_EUNSUPPORTED
+    # 3 * 2^25: the power-of-two part is beyond 2^24; rejected before any launch
+    st = pm.lib().pm_ntt(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()), 3 << 25, 2013265921, 0, None)
+    assert st == pm.PM_ETOOLARGE
+    a = np.full(3000, 5, dtype=np.uint32)
+    a[1234] = 2013265921  # not canonical
+    pm.poly_mul_mixed(dev(a), x, 2013265921, 3)
+    assert pm.stream_check() == pm.PM_ENOTREDUCED
+    assert pm.stream_check() == 0
+
+
 def _eval2(c, p, x, y):
     """c(x, y) mod p for a 2-D coefficient array, vectorised with exact int64 steps."""
     c = np.asarray(c, dtype=np.int64)
