@@ -297,25 +297,27 @@ pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const vo
 
 // `rows` circular products of length n (Def. 4, eq. 5): row r of C is
 // row r of A times row r of B mod x^n - 1, rows n words apart; P is the plan
-// for length n (n' = L = n), Ta and Tb its four-step workspace.
+// for length n (n' = L = n).  Beyond the defining sums (n <= 64) every pass
+// runs once over all rows: `jobs` receives the rows' descriptors (device
+// memory, rows entries) and Ta, Tb hold rows * n words each.
 static pm_status cyclic_rows(DevCtx* ctx, int pidx, const Plan& P, const u32* A, const u32* B, u32* C, int rows,
-                             long n, u32* Ta, u32* Tb, hipStream_t s) {
-  const bool lazy = prime_info(pidx).lazy;
-  for (int r = 0; r < rows; ++r) {
-    const long o = (long)r * n;
-    if (n <= 64) {
+                             long n, ConvJob* jobs, u32* Ta, u32* Tb, hipStream_t s) {
+  if (n <= 64) {
+    for (int r = 0; r < rows; ++r) {
+      const long o = (long)r * n;
       const hipError_t e = launch_direct_ring(A + o, n, B + o, n, n, false, C + o, pidx, ctx->errflag, s);
       if (e != hipSuccess) return PM_EDEVICE;
-      continue;
     }
-    JobRef jr;
-    jr.many = nullptr;
-    pm_status st = make_job(ctx, P, pidx, A + o, n, B + o, n, C + o, n, Ta, Tb, &jr.one, 1);
-    if (st) return st;
-    st = launch_class(P, lazy, 0, jr, 1, jr.one.rows, s);
-    if (st) return st;
+    return PM_OK;
   }
-  return PM_OK;
+  ConvJob base;
+  pm_status st = make_job(ctx, P, pidx, A, n, B, n, C, n, Ta, Tb, &base, 1);
+  if (st) return st;
+  if (launch_row_jobs(base, n, n, rows, jobs, s) != hipSuccess) return PM_EDEVICE;
+  JobRef jr;
+  jr.one = base;
+  jr.many = jobs;
+  return launch_class(P, prime_info(pidx).lazy, 0, jr, rows, base.rows, s);
 }
 
 // the plan of the length-n circular product: the plan for output length n,
@@ -400,21 +402,39 @@ static pm_status mixed_product(const uint32_t* a, size_t len_a, const uint32_t* 
   if (M > 64) {
     st = ring_plan(M, pidx, ctx, s, 0, &P);
     if (st) return st;
+    // the q rows run side by side, but a one-work-group plan would still give
+    // each row a single compute unit: from 2^12 on, rows of 2^10 instead
+    if (P.kind == PLAN_LDS && logM >= 12) {
+      Plan F;
+      F.kind = PLAN_FOURSTEP;
+      F.logL = logM;
+      F.logC = 10;
+      F.logRA = logM - 10;
+      F.logRB = 0;
+      F.ma = 1 << F.logRA;
+      F.lq = 3;
+      F.lnt = 6;
+      if (plan_valid(F, M, pidx)) P = F;
+    }
   }
+  // workspace: the rows' job descriptors, then A, B, C (q rows of M each),
+  // then the four-step workspace of every row
   const size_t rows_words = (size_t)q * M;
-  const size_t wsb = 3 * rows_words * sizeof(u32) + (M > 64 ? plan_workspace_bytes(P) : 0);
+  const size_t job_bytes = (q * sizeof(ConvJob) + 255) / 256 * 256;
+  const bool fourstep = M > 64 && P.kind == PLAN_FOURSTEP;
+  const size_t wsb = job_bytes + (fourstep ? 5 : 3) * rows_words * sizeof(u32);
   void* ws = nullptr;
   st = stream_workspace(ctx, s, wsb, &ws);
   if (st) return st;
-  u32* A = (u32*)ws;
+  ConvJob* jobs = (ConvJob*)ws;
+  u32* A = (u32*)((char*)ws + job_bytes);
   u32* B = A + rows_words;
   u32* C = B + rows_words;
-  u32* Ta = M > 64 && P.kind == PLAN_FOURSTEP ? C + rows_words : nullptr;
-  u32* Tb = Ta ? Ta + plan_nprime(P) : nullptr;
-  hipError_t e = launch_mixed_split(a, (long)len_a, (int)q, M, A, pidx, ctx->errflag, s);
-  if (e == hipSuccess) e = launch_mixed_split(b, (long)len_b, (int)q, M, B, pidx, ctx->errflag, s);
-  if (e != hipSuccess) return PM_EDEVICE;
-  st = cyclic_rows(ctx, pidx, P, A, B, C, (int)q, M, Ta, Tb, s);
+  u32* Ta = fourstep ? C + rows_words : nullptr;
+  u32* Tb = fourstep ? Ta + rows_words : nullptr;
+  if (launch_mixed_split(a, (long)len_a, A, b, (long)len_b, B, (int)q, M, pidx, ctx->errflag, s) != hipSuccess)
+    return PM_EDEVICE;
+  st = cyclic_rows(ctx, pidx, P, A, B, C, (int)q, M, jobs, Ta, Tb, s);
   if (st) return st;
   return dev_status(launch_mixed_merge(C, (int)q, M, c, lc, pidx, s));
 }
@@ -712,7 +732,7 @@ static pm_status ntt_mixed(const uint32_t* x, uint32_t* y, size_t n, uint32_t p,
   u32* R2 = R1 + n;
   u32* T = R2 + n;
   hipError_t e = inverse ? launch_mixed_perm(x, q, M, R1, 0, s)
-                         : launch_mixed_split(x, (long)n, q, M, R1, pidx, c->errflag, s);
+                         : launch_mixed_split(x, (long)n, R1, nullptr, 0, nullptr, q, M, pidx, c->errflag, s);
   if (e != hipSuccess) return PM_EDEVICE;
   u32* rows = R1;
   if (M > 1) {

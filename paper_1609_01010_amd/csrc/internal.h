@@ -115,10 +115,14 @@ hipError_t launch_direct_ring(const u32* a, long la, const u32* b, long lb, long
                               int* err, hipStream_t s);
 // mixed-radix lengths N = q M (q odd, M a power of two): q in {3, 5, 7, 15, 17}
 bool mixed_q_supported(int q);
-// x (lx values, zero beyond) -> q rows of M: the length-q transform over j mod q
-hipError_t launch_mixed_split(const u32* x, long lx, int q, long M, u32* rows, int pidx, int* err, hipStream_t s);
+// x (lx values, zero beyond) -> q rows of M: the length-q transform over j mod q;
+// one launch for one operand (x1 null) or two
+hipError_t launch_mixed_split(const u32* x0, long lx0, u32* rows0, const u32* x1, long lx1, u32* rows1, int q, long M,
+                              int pidx, int* err, hipStream_t s);
 // q rows of M -> y_j, j < ly: the inverse length-q transform times q^-1
 hipError_t launch_mixed_merge(const u32* rows, int q, long M, u32* y, long ly, int pidx, hipStream_t s);
+// q <= 64 job descriptors: base advanced by r * stride (a, b, c) and r * tstride (Ta, Tb)
+hipError_t launch_row_jobs(const ConvJob& base, long stride, long tstride, int q, ConvJob* out, hipStream_t s);
 // rows[k1][k2] <-> flat[(M k1 + q k2) mod N]
 hipError_t launch_mixed_perm(const u32* in, int q, long M, u32* out, int to_flat, hipStream_t s);
 // Convolution launches over njobs jobs of one plan class (jobs in jr: the

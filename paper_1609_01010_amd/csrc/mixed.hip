@@ -61,9 +61,14 @@ __device__ __forceinline__ void dft_q(const Arith<false>& A, const u32 (&x)[Q], 
   }
 }
 
+// blockIdx.y selects the operand: (x0, lx0) into rows0 or (x1, lx1) into rows1
 template <int Q>
-__global__ void __launch_bounds__(256) k_mixed_split(const u32* __restrict__ x, long lx, long M, u32* __restrict__ rows,
-                                                     MixedRoots R, ModP mp, int* err) {
+__global__ void __launch_bounds__(256) k_mixed_split(const u32* __restrict__ x0, long lx0, u32* __restrict__ rows0,
+                                                     const u32* __restrict__ x1, long lx1, u32* __restrict__ rows1,
+                                                     long M, MixedRoots R, ModP mp, int* err) {
+  const u32* __restrict__ x = blockIdx.y ? x1 : x0;
+  const long lx = blockIdx.y ? lx1 : lx0;
+  u32* __restrict__ rows = blockIdx.y ? rows1 : rows0;
   __shared__ uint2 vt[Q];
   if (threadIdx.x < Q) vt[threadIdx.x] = R.v[threadIdx.x];
   __syncthreads();
@@ -138,6 +143,26 @@ __global__ void __launch_bounds__(256) k_mixed_perm(const u32* __restrict__ in, 
   }
 }
 
+// Descriptors of the q row products, so that each pass of the circular
+// products runs once over all rows (blockIdx.z selects the row): job r is
+// `base` with its operands and result advanced by r * stride words and its
+// four-step workspace by r * tstride words.
+__global__ void k_row_jobs(ConvJob base, long stride, long tstride, int q, ConvJob* __restrict__ out) {
+  const int r = threadIdx.x;
+  if (r >= q) return;
+  ConvJob J = base;
+  J.a = (const u32*)base.a + r * stride;
+  J.b = (const u32*)base.b + r * stride;
+  J.c = base.c + r * stride;
+  if (base.Ta) J.Ta = base.Ta + r * tstride;
+  if (base.Tb) J.Tb = base.Tb + r * tstride;
+  out[r] = J;
+}
+
+hipError_t launch_row_jobs(const ConvJob& base, long stride, long tstride, int q, ConvJob* out, hipStream_t s) {
+  return launch("row_jobs", k_row_jobs, 1, 64, 0, s, base, stride, tstride, q, out);
+}
+
 static unsigned mixed_blocks(long M) {
   long b = (M + 255) / 256;
   return (unsigned)(b > 4096 ? 4096 : b);
@@ -171,11 +196,14 @@ bool mixed_q_supported(int q) { return q == 3 || q == 5 || q == 7 || q == 15 || 
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_mixed_split(const u32* x, long lx, int q, long M, u32* rows, int pidx, int* err, hipStream_t s) {
+hipError_t launch_mixed_split(const u32* x0, long lx0, u32* rows0, const u32* x1, long lx1, u32* rows1, int q, long M,
+                              int pidx, int* err, hipStream_t s) {
   const PrimeInfo& P = prime_info(pidx);
   const MixedRoots R = mixed_roots(P, q, M, 0, 1);
   const ModP mp = modp_of(P);
-#define PM_SPLIT(Q) return launch("mixed_split", k_mixed_split<Q>, mixed_blocks(M), 256, 0, s, x, lx, M, rows, R, mp, err)
+  const dim3 grid(mixed_blocks(M), x1 ? 2 : 1);
+#define PM_SPLIT(Q) \
+  return launch("mixed_split", k_mixed_split<Q>, grid, 256, 0, s, x0, lx0, rows0, x1, lx1, rows1, M, R, mp, err)
   PM_MIXED_DISPATCH(q, PM_SPLIT)
 #undef PM_SPLIT
 }
