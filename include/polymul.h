@@ -138,6 +138,38 @@ typedef struct {
 pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream);
 
 /*
+ * Workspace.  Products, transforms and batches keep their intermediate
+ * arrays (the four-step passes' n' words per operand, the integer product's
+ * residues and carry state) in one workspace per stream, which the library
+ * allocates with hipMalloc on first use and grows as needed (growing waits
+ * for the stream).  Callers that manage device memory themselves supply it:
+ *
+ *   pm_workspace_query:        bytes pm_poly_mul(len_a, len_b, p) needs under
+ *                              the current policy and plan cache (the largest
+ *                              over the candidate plans when the policy is
+ *                              exhaustive); 0 for one-work-group and
+ *                              defining-sum plans.
+ *   pm_batch_workspace_query:  bytes pm_poly_mul_batch needs for these
+ *                              problems (host array).
+ *   pm_int_mul_workspace_query: bytes pm_int_mul(na, nb) needs.
+ *   pm_set_workspace:          use the caller's device memory [ptr, ptr +
+ *                              bytes) as the workspace of `stream` on the
+ *                              current device from now on; a call that needs
+ *                              more returns PM_ENOMEM and launches nothing.
+ *                              ptr = NULL returns the stream to the library's
+ *                              own workspace.  The caller keeps the memory
+ *                              alive, and does not touch it, while work
+ *                              queued on the stream may use it.  Twiddle
+ *                              tables are still allocated by the library,
+ *                              once per device and prime.
+ * The queries need no device and validate their arguments as the calls do.
+ */
+pm_status pm_workspace_query(size_t len_a, size_t len_b, uint32_t p, size_t* bytes);
+pm_status pm_batch_workspace_query(const pm_problem* probs, size_t count, size_t* bytes);
+pm_status pm_int_mul_workspace_query(size_t na, size_t nb, size_t* bytes);
+pm_status pm_set_workspace(void* stream, void* ptr, size_t bytes);
+
+/*
  * Integer product by the three-primes algorithm (section 1): A and B are
  * little-endian integers of na and nb 16-bit limbs (A = sum a_i 2^{16 i}).
  * The limb sequences are multiplied as polynomials modulo 469762049,

@@ -81,6 +81,10 @@ SIGNATURES = {
     "pm_poly_mul_batch": (_int, [ctypes.POINTER(Problem), _sz, _vp]),
     "pm_cyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
     "pm_poly_mul_mixed": (_int, [_vp, _sz, _vp, _sz, _u32, _u32, _vp, _vp]),
+    "pm_workspace_query": (_int, [_sz, _sz, _u32, ctypes.POINTER(ctypes.c_size_t)]),
+    "pm_batch_workspace_query": (_int, [ctypes.POINTER(Problem), _sz, ctypes.POINTER(ctypes.c_size_t)]),
+    "pm_int_mul_workspace_query": (_int, [_sz, _sz, ctypes.POINTER(ctypes.c_size_t)]),
+    "pm_set_workspace": (_int, [_vp, _vp, _sz]),
     "pm_poly_mul_multi": (_int, [_vp, ctypes.POINTER(_sz), _vp, ctypes.POINTER(_sz), _int, _u32, _vp, _vp]),
     "pm_negacyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
     "pm_int_mul": (_int, [_vp, _sz, _vp, _sz, _vp, _vp]),
@@ -245,6 +249,39 @@ def poly_mul_mixed(a, b, p: int, q: int, out=None, stream=None):
                                    b.numel(), p, q, _dev_ptr(out, torch.uint32, "out"), _stream(stream)),
            "pm_poly_mul_mixed")
     return out
+
+
+def workspace_query(len_a: int, len_b: int, p: int) -> int:
+    """Workspace bytes of a product of these lengths under the current plans."""
+    n = ctypes.c_size_t(0)
+    _check(lib().pm_workspace_query(len_a, len_b, p, ctypes.byref(n)), "pm_workspace_query")
+    return n.value
+
+
+def int_mul_workspace_query(na: int, nb: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().pm_int_mul_workspace_query(na, nb, ctypes.byref(n)), "pm_int_mul_workspace_query")
+    return n.value
+
+
+def batch_workspace_query(problems) -> int:
+    """problems: list of (a, b, p) uint32 device tensors."""
+    arr = (Problem * max(len(problems), 1))()
+    for i, (a, b, p) in enumerate(problems):
+        arr[i].a, arr[i].len_a, arr[i].b, arr[i].len_b, arr[i].p = a.data_ptr(), a.numel(), b.data_ptr(), b.numel(), p
+        arr[i].c = a.data_ptr()  # not written: the query only validates and sizes
+    n = ctypes.c_size_t(0)
+    _check(lib().pm_batch_workspace_query(arr, len(problems), ctypes.byref(n)), "pm_batch_workspace_query")
+    return n.value
+
+
+def set_workspace(buf, stream=None):
+    """Use the device tensor buf as the stream's workspace (None: the library's own)."""
+    if buf is None:
+        _check(lib().pm_set_workspace(_stream(stream), None, 0), "pm_set_workspace")
+    else:
+        _check(lib().pm_set_workspace(_stream(stream), ctypes.c_void_p(buf.data_ptr()),
+                                      buf.numel() * buf.element_size()), "pm_set_workspace")
 
 
 class PreparedBatch:

@@ -151,13 +151,10 @@ pm_status capture_graph(BatchState* B, const std::vector<ClassRun>& runs, ConvJo
 
 using namespace pm;
 
-extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream) {
-  if (!probs && count) return PM_EINVAL;
-  if (count == 0) return PM_OK;
-  if (count > 65535) return PM_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  std::vector<Plan> plans(count);
-  std::vector<int> pidx(count);
+// validate the problems and pick their plans (cache, cost model or default)
+static pm_status batch_plans(const pm_problem* probs, size_t count, std::vector<Plan>& plans, std::vector<int>& pidx) {
+  plans.resize(count);
+  pidx.resize(count);
   for (size_t i = 0; i < count; ++i) {
     const pm_problem& q = probs[i];
     if (!q.a || !q.b || !q.c || q.len_a == 0 || q.len_b == 0) return PM_EINVAL;
@@ -168,6 +165,38 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
     plans[i] = choose_plan(lc, pidx[i], nullptr, 0);
     if (!plan_valid(plans[i], lc, pidx[i])) return PM_ETOOLARGE;
   }
+  return PM_OK;
+}
+
+// the batch's workspace: every four-step item's, each rounded up to 256 bytes
+static size_t batch_workspace_bytes(const std::vector<Plan>& plans) {
+  size_t wsb = 0;
+  for (const Plan& P : plans)
+    if (P.kind != PLAN_DIRECT) wsb += (plan_workspace_bytes(P) + 255) & ~(size_t)255;
+  return wsb;
+}
+
+extern "C" pm_status pm_batch_workspace_query(const pm_problem* probs, size_t count, size_t* bytes) {
+  if ((!probs && count) || !bytes || count > 65535) return PM_EINVAL;
+  std::vector<Plan> plans;
+  std::vector<int> pidx;
+  const pm_status st = batch_plans(probs, count, plans, pidx);
+  if (st) return st;
+  *bytes = batch_workspace_bytes(plans);
+  return PM_OK;
+}
+
+extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream) {
+  if (!probs && count) return PM_EINVAL;
+  if (count == 0) return PM_OK;
+  if (count > 65535) return PM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<Plan> plans;
+  std::vector<int> pidx;
+  {
+    const pm_status st0 = batch_plans(probs, count, plans, pidx);
+    if (st0) return st0;
+  }
   pm_status st;
   DevCtx* c = ctx_current(&st);
   if (!c) return st;
@@ -175,11 +204,7 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
   BatchState* B;
   st = batch_state(c, s, &B);
   if (st) return st;
-  void* ws_cur = nullptr;
-  {
-    auto it = c->ws.find(s);
-    if (it != c->ws.end()) ws_cur = it->second.first;
-  }
+  void* ws_cur = stream_workspace_current(c, s);
 
   // fast path: the same shape as the previous batch
   {
@@ -216,14 +241,13 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
   // classes, largest transforms first
   std::map<ClassKey, std::vector<size_t>> groups;
   std::vector<size_t> direct;
-  size_t wsb = 0;
+  const size_t wsb = batch_workspace_bytes(plans);
   for (size_t i = 0; i < count; ++i) {
     if (plans[i].kind == PLAN_DIRECT) {
       direct.push_back(i);
       continue;
     }
     groups[class_key(plans[i], prime_info(pidx[i]).lazy)].push_back(i);
-    wsb += (plan_workspace_bytes(plans[i]) + 255) & ~(size_t)255;
   }
   void* wsp = nullptr;
   if (wsb) {

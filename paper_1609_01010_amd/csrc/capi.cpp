@@ -1,5 +1,6 @@
 // The C ABI (include/polymul.h): argument validation, plan choice, workspace,
 // and the launch sequences of the product, the hooks and the integer product.
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 
@@ -518,6 +519,38 @@ pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t
   return product_with(a, len_a, b, len_b, p, c, nullptr, stream);
 }
 
+pm_status pm_workspace_query(size_t len_a, size_t len_b, uint32_t p, size_t* bytes) {
+  if (!bytes) return PM_EINVAL;
+  int pidx;
+  long lc;
+  const uint32_t one = 1;
+  pm_status st = check_product_args(&one, len_a, &one, len_b, p, &one, &pidx, &lc);
+  if (st) return st;
+  size_t w = 0;
+  if (g_policy == PM_POLICY_EXHAUSTIVE) {
+    // the plan is picked by timing at call time: any candidate may win
+    for (const Plan& P : plan_candidates(lc, pidx)) w = std::max(w, plan_workspace_bytes(P));
+  }
+  const Plan P = choose_plan(lc, pidx);
+  if (!plan_valid(P, lc, pidx)) return PM_ETOOLARGE;
+  *bytes = std::max(w, plan_workspace_bytes(P));
+  return PM_OK;
+}
+
+pm_status pm_set_workspace(void* stream, void* ptr, size_t bytes) {
+  if (ptr && bytes == 0) return PM_EINVAL;
+  pm_status st;
+  DevCtx* c = ctx_current(&st);
+  if (!c) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  if (ptr)
+    c->user_ws[s] = std::make_pair(ptr, bytes);
+  else
+    c->user_ws.erase(s);
+  return PM_OK;
+}
+
 pm_status pm_poly_mul_multi(const uint32_t* a, const size_t* dims_a, const uint32_t* b, const size_t* dims_b,
                             int nvars, uint32_t p, uint32_t* c, void* stream) {
   if (!a || !b || !c || !dims_a || !dims_b || nvars < 1 || nvars > kKronMaxVars) return PM_EINVAL;
@@ -827,6 +860,45 @@ pm_status pm_itft(const uint32_t* v, size_t L, size_t n, uint32_t p, uint32_t* o
 
 // ---- three-primes integer product -----------------------------------------------
 
+static const u32 kIntPrimes[3] = {469762049u, 998244353u, 167772161u};
+
+// The integer product's plans and workspace: three residue arrays, the
+// widened operands when a plan needs 32-bit input, the largest plan
+// workspace, the carry state.
+struct IntLayout {
+  Plan plans[3];
+  bool widen = false;
+  size_t res_b = 0, wid_b = 0, pw = 0, total = 0;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static pm_status int_mul_layout(size_t na, size_t nb, IntLayout* L) {
+  const long lc = (long)(na + nb - 1);
+  if (ceil_log2(lc) > 23) return PM_ETOOLARGE;
+  for (int i = 0; i < 3; ++i) {
+    const int pidx = prime_index(kIntPrimes[i]);
+    L->plans[i] = choose_plan(lc, pidx);
+    if (!plan_valid(L->plans[i], lc, pidx)) return PM_ETOOLARGE;
+    if (L->plans[i].kind != PLAN_FOURSTEP) L->widen = true;
+    const size_t w = plan_workspace_bytes(L->plans[i]);
+    if (w > L->pw) L->pw = w;
+  }
+  L->res_b = align256((size_t)lc * 4);
+  L->wid_b = L->widen ? align256((na + nb) * 4) : 0;
+  L->total = 3 * L->res_b + L->wid_b + align256(L->pw) + align256(crt_workspace_bytes((long)(na + nb)));
+  return PM_OK;
+}
+
+pm_status pm_int_mul_workspace_query(size_t na, size_t nb, size_t* bytes) {
+  if (!bytes || na == 0 || nb == 0) return PM_EINVAL;
+  IntLayout L;
+  const pm_status st = int_mul_layout(na, nb, &L);
+  if (st) return st;
+  *bytes = L.total;
+  return PM_OK;
+}
+
 pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint16_t* out, void* stream) {
   if (!a || !b || !out || na == 0 || nb == 0) return PM_EINVAL;
   const long lc = (long)(na + nb - 1);
@@ -836,25 +908,14 @@ pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb,
   if (!c) return st;
   std::lock_guard<std::mutex> lk(c->mu);
   hipStream_t s = (hipStream_t)stream;
-  static const u32 kIntPrimes[3] = {469762049u, 998244353u, 167772161u};
   const long nl = (long)(na + nb);
-  // workspace: three residue arrays, the widened operands when a plan needs
-  // 32-bit input, the largest plan workspace, the carry state
-  Plan plans[3];
-  size_t pw = 0;
-  bool widen = false;
-  for (int i = 0; i < 3; ++i) {
-    const int pidx = prime_index(kIntPrimes[i]);
-    plans[i] = choose_plan(lc, pidx);
-    if (!plan_valid(plans[i], lc, pidx)) return PM_ETOOLARGE;
-    if (plans[i].kind != PLAN_FOURSTEP) widen = true;
-    size_t w = plan_workspace_bytes(plans[i]);
-    if (w > pw) pw = w;
-  }
-  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t res_b = al((size_t)lc * 4);
-  const size_t wid_b = widen ? al((na + nb) * 4) : 0;
-  const size_t total = 3 * res_b + wid_b + al(pw) + al(crt_workspace_bytes(nl));
+  IntLayout LY;
+  st = int_mul_layout(na, nb, &LY);
+  if (st) return st;
+  const Plan* plans = LY.plans;
+  const bool widen = LY.widen;
+  const size_t res_b = LY.res_b, wid_b = LY.wid_b, pw = LY.pw, total = LY.total;
+  auto al = align256;
   void* wsp = nullptr;
   st = stream_workspace(c, s, total, &wsp);
   if (st) return st;

@@ -67,13 +67,18 @@ struct DevCtx {
   // workspace per stream: calls on different streams may run concurrently,
   // calls on one stream are ordered by it
   std::map<hipStream_t, std::pair<void*, size_t>> ws;
+  // caller-owned workspace per stream (pm_set_workspace): used instead of ws
+  std::map<hipStream_t, std::pair<void*, size_t>> user_ws;
   std::mutex mu;
 };
 
 DevCtx* ctx_current(pm_status* st);
 pm_status ensure_prime_tables(DevCtx* c, int pidx);
-// the workspace of stream s, grown to at least `bytes`
+// the workspace of stream s, grown to at least `bytes`; a caller-owned one
+// (pm_set_workspace) is never grown: PM_ENOMEM if it is smaller
 pm_status stream_workspace(DevCtx* c, hipStream_t s, size_t bytes, void** out);
+// the workspace stream s uses now (null if none yet)
+void* stream_workspace_current(DevCtx* c, hipStream_t s);
 // scale: the value multiplied into the inverse factors (1 for none)
 pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, int twist, RowTables* out);
 // powers psi^(i s) and psi^(-i s), i < L / s, of a primitive 2L-th root of

@@ -277,7 +277,20 @@ pm_status get_twist_tables(DevCtx* c, int pidx, int logL, int log_stride, const 
   return PM_OK;
 }
 
+void* stream_workspace_current(DevCtx* c, hipStream_t s) {
+  auto u = c->user_ws.find(s);
+  if (u != c->user_ws.end()) return u->second.first;
+  auto it = c->ws.find(s);
+  return it != c->ws.end() ? it->second.first : nullptr;
+}
+
 pm_status stream_workspace(DevCtx* c, hipStream_t s, size_t bytes, void** out) {
+  auto u = c->user_ws.find(s);
+  if (u != c->user_ws.end()) {
+    if (u->second.second < bytes) return PM_ENOMEM;
+    *out = u->second.first;
+    return PM_OK;
+  }
   auto& w = c->ws[s];
   if (w.second < bytes) {
     if (w.first) {

@@ -74,6 +74,39 @@ def test_host_validation_without_device(L):
     assert L.pm_set_policy(7) == 1
 
 
+def test_workspace_queries_on_host(L):
+    """The queries need no device: sizes follow from the plans alone."""
+    import paper_1609_01010_amd as pm
+
+    n = ctypes.c_size_t(0)
+    assert L.pm_workspace_query(1024, 1024, 998244353, ctypes.byref(n)) == 0 and n.value == 0  # one work-group
+    assert L.pm_workspace_query(1 << 21, 1 << 21, 2013265921, ctypes.byref(n)) == 0
+    assert n.value == 2 * 4 * (1 << 22)  # two operands of n' = L words
+    for la, lb in ((600001, 400000), (70001, 9000), (40, 30)):
+        assert L.pm_workspace_query(la, lb, 2013265921, ctypes.byref(n)) == 0
+        P = pm.plan_for(la + lb - 1, 2013265921)
+        want = 2 * 4 * (P.ma << (P.log_l - P.log_ra)) if P.kind == 2 else 0
+        assert n.value == want, (la, lb, P)
+    assert L.pm_workspace_query(4, 4, 1000000007, ctypes.byref(n)) == 2
+    assert L.pm_workspace_query(0, 4, 998244353, ctypes.byref(n)) == 1
+    assert L.pm_workspace_query(4, 4, 998244353, None) == 1
+    assert L.pm_workspace_query(1 << 23, 1 << 23, 998244353, ctypes.byref(n)) == 3
+    assert L.pm_int_mul_workspace_query(1 << 21, 1 << 21, ctypes.byref(n)) == 0
+    assert n.value >= 3 * 4 * ((1 << 22) - 1) + 2 * (1 << 22)  # three residue arrays and the limb sums
+    assert L.pm_int_mul_workspace_query(1 << 23, 1 << 23, ctypes.byref(n)) == 3
+    # a batch needs the sum of its four-step items' workspaces (each rounded to 256 bytes)
+    lens = [(100, 50), (5000, 4000), (70001, 9000), (300000, 20001), (40, 30)]
+    probs = (pm.Problem * len(lens))()
+    want = 0
+    for i, (la, lb) in enumerate(lens):
+        probs[i].a, probs[i].len_a, probs[i].b, probs[i].len_b = 4096, la, 4096, lb
+        probs[i].p, probs[i].c = 998244353, 4096
+        assert L.pm_workspace_query(la, lb, 998244353, ctypes.byref(n)) == 0
+        want += (n.value + 255) // 256 * 256
+    assert L.pm_batch_workspace_query(probs, len(lens), ctypes.byref(n)) == 0
+    assert n.value == want and want > 0
+
+
 def test_granularity(L):
     assert L.pm_itft_granularity(16) == 1
     assert L.pm_itft_granularity(32) == 1

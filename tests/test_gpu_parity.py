@@ -423,6 +423,60 @@ def test_products_on_concurrent_streams(gpu_lib):
         assert np.array_equal(host(c), op.poly_mul_ntt(it.a, it.b, it.p, inputs.PRIMES[it.p]))
 
 
+def test_caller_owned_workspace(gpu_lib):
+    """Products, an integer product and a batch on a stream whose workspace
+    the caller supplied (sized by the queries): exact results; a workspace
+    that is too small is refused with PM_ENOMEM before anything runs, and the
+    stream returns to the library's own workspace afterwards."""
+    import torch
+
+    pm = gpu_lib
+    p = 2013265921
+    s = torch.cuda.Stream()
+    pairs = [inputs.poly_pair((170, k), la, lb, p) for k, (la, lb) in enumerate(((600001, 400000), (1 << 20, 1 << 20),
+                                                                                  (70001, 9000), (1000, 999)))]
+    ia, ib = inputs.int_operands(1 << 12, tag=171)
+    items = inputs.batch_uneven(count=40, lo=1, hi=40000, tag=(172,))
+    dpairs = [(dev(a), dev(b)) for a, b in pairs]
+    ditems = [(dev(it.a), dev(it.b), it.p) for it in items]
+    need = max([pm.workspace_query(a.size, b.size, p) for a, b in pairs] +
+               [pm.int_mul_workspace_query(ia.size, ib.size), pm.batch_workspace_query(ditems)])
+    say("case: caller workspace of", need, "bytes")
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    pm.set_workspace(buf, stream=s)
+    try:
+        with torch.cuda.stream(s):
+            outs = [pm.poly_mul(da, db, p, stream=s) for da, db in dpairs]
+            ic = pm.int_mul(dev(ia, np.uint16), dev(ib, np.uint16), stream=s)
+            bouts = pm.poly_mul_batch(ditems, stream=s)
+        s.synchronize()
+        assert pm.stream_check() == 0
+        for (a, b), c in zip(pairs, outs):
+            assert np.array_equal(host(c), op.poly_mul_ntt(a, b, p, inputs.PRIMES[p]))
+        assert np.array_equal(host(ic), op.int_mul(ia, ib))
+        for it, c in zip(items, bouts):
+            assert np.array_equal(host(c), op.poly_mul_ntt(it.a, it.b, it.p, inputs.PRIMES[it.p]))
+        # too small for the 2^20 x 2^20 product: refused, nothing written
+        small = pm.workspace_query(1 << 20, 1 << 20, p) - 4096
+        pm.set_workspace(buf[:small], stream=s)
+        da, db = dpairs[1]
+        sentinel = torch.full((da.numel() + db.numel() - 1,), 7, dtype=torch.uint32, device="cuda")
+        torch.cuda.synchronize()
+        with pytest.raises(pm.PolymulError) as e:
+            pm.poly_mul(da, db, p, out=sentinel, stream=s)
+        assert e.value.status == pm.PM_ENOMEM
+        s.synchronize()
+        assert bool((sentinel == 7).all())
+    finally:
+        pm.set_workspace(None, stream=s)
+    with torch.cuda.stream(s):
+        c = pm.poly_mul(*dpairs[1], p, stream=s)
+    s.synchronize()
+    a, b = pairs[1]
+    assert np.array_equal(host(c), op.poly_mul_ntt(a, b, p, inputs.PRIMES[p]))
+
+
 def test_not_reduced_input_is_reported(gpu_lib):
     pm = gpu_lib
     p = 998244353
