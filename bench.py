@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 P = 2013265921
+G = 31                                 # a primitive root mod P
 CU, LANES, CLOCK = 256, 64, 2.4e9
 ALU_PEAK = CU * LANES * CLOCK          # 32-bit VALU issue slots per second
 HBM_PEAK = 8.0e12                      # bytes per second
@@ -51,6 +52,17 @@ def row_conv_units(plan, n_rows_elems):
     return per_el * n_rows_elems, 12 * n_rows_elems
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    """Bytes read plus written per second by a device-to-device copy of 1 GiB
+    (the attainable HBM rate the roofline fractions are also quoted against)."""
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = time_loop(torch, lambda i: dst.copy_(src), reps)
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3)
+
+
 def cpu_baseline(a2, b2, a3, b3, target_s=10.0):
     """The oracle's defining sum timed on a bounded sample of output coefficients."""
     import numpy as np
@@ -71,6 +83,13 @@ def cpu_baseline(a2, b2, a3, b3, target_s=10.0):
     dt, cnt = run(64)
     n = int(min(200000, max(64, 64 * target_s / max(dt, 1e-3))))
     dt, cnt = run(n)
+    # the oracle's O(n log n) route (textbook radix-2 transforms, OpenMP over
+    # the blocks of each level) on the whole step, for scale
+    t0 = time.perf_counter()
+    op.poly_mul_ntt(a2, b2, P, G)
+    op.poly_mul_ntt(a3, b3, P, G)
+    dt_ntt = time.perf_counter() - t0
+    lc_step = a2.size + b2.size - 1 + a3.size + b3.size - 1
     return {
         "value": cnt / dt,
         "unit": "coeffs/s",
@@ -78,6 +97,8 @@ def cpu_baseline(a2, b2, a3, b3, target_s=10.0):
         "kind": "oracle",
         "sample": f"{cnt} output coefficients ({n} of the 2^21 x 2^21 product, {cnt - n} of the 600001 x 400000 "
                   f"product) by the schoolbook sum c_k = sum a_i b_(k-i) mod p, OpenMP over k; {dt:.1f} s",
+        "ntt_route": {"value": lc_step / dt_ntt, "unit": "coeffs/s", "cores": threads,
+                      "sample": f"one whole step (both products) by the oracle's radix-2 transforms; {dt_ntt:.2f} s"},
     }
 
 
@@ -130,7 +151,7 @@ def time_loop(torch, fn, n):
     return e0.elapsed_time(e1) / n
 
 
-def standalone_transform(pm, torch, dev, n_calls=40):
+def standalone_transform(pm, torch, dev, copy_bw, n_calls=40):
     """Forward transform of 2^22 points in bit-reversed order (the TFT hook with
     n = L): two passes over HBM, 16 N algorithmic bytes; 8 rotating buffer
     pairs (256 MiB); four outputs checked against direct evaluation."""
@@ -157,12 +178,13 @@ def standalone_transform(pm, torch, dev, n_calls=40):
         out[f"ntt_2^22_p{pp}"] = {"us": ms * 1e3, "points_per_s": N / (ms * 1e-3),
                                   "hbm_alg_GBps": 16 * N / (ms * 1e-3) / 1e9,
                                   "hbm_frac": 16 * N / (ms * 1e-3) / HBM_PEAK,
+                                  "hbm_frac_vs_copy": 16 * N / (ms * 1e-3) / copy_bw,
                                   "bit_exact_sampled": bool(ok)}
         del xs, ys
     return out
 
 
-def extra_configs(pm, torch, dev, reps=5):
+def extra_configs(pm, torch, dev, copy_bw, reps=5):
     """The other workloads, each timed on its own: the 1024 x 1024 product,
     the three-primes integer product of two 2^21-limb integers, and the batch
     of 4096 uneven products, plain (a loop of single products with the
@@ -229,7 +251,7 @@ def extra_configs(pm, torch, dev, reps=5):
         it = items[int(k)]
         ks = rng.integers(0, outs[int(k)].numel(), 4)
         assert np.array_equal(outs[int(k)].cpu().numpy()[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
-    out.update(standalone_transform(pm, torch, dev))
+    out.update(standalone_transform(pm, torch, dev, copy_bw))
 
     # a bivariate product by Kronecker substitution: 1024 x 1024 coefficients
     # times 1024 x 1024 (2047^2 outputs, one 2^22 transform)
@@ -309,7 +331,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--rotate", type=int, default=8, help="buffer sets rotated over the steps")
+    ap.add_argument("--rotate", type=int, default=16,
+                    help="buffer sets rotated over the steps (16 sets = 640 MiB, over twice the 256 MB MALL)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--plans", default=None,
@@ -417,6 +440,7 @@ def main():
         kernels[name] = {"launches": n, "avg_us": 1e3 * tot / max(n, 1), "share": tot / gpu_ms}
     pm.trace_reset()
     dom = max(kernels, key=lambda k: kernels[k]["share"])
+    copy_bw = copy_bandwidth(torch, dev)
     row = kernels.get("row_conv")
     rows2 = plan2.ma << plan2.log_rb
     rows3 = plan3.ma << plan3.log_rb
@@ -442,6 +466,8 @@ def main():
         "algorithmic_slots_per_launch": per_launch_slots,
         "hbm_achieved_GBps": per_launch_bytes / (row["avg_us"] * 1e-6) / 1e9,
         "hbm_frac": per_launch_bytes / (row["avg_us"] * 1e-6) / HBM_PEAK,
+        "hbm_frac_vs_copy": per_launch_bytes / (row["avg_us"] * 1e-6) / copy_bw,
+        "copy_GBps": copy_bw / 1e9,
     }
     cpu = None
     if not args.no_cpu_baseline:
@@ -450,7 +476,7 @@ def main():
     if not args.no_extra:
         del sets
         torch.cuda.empty_cache()
-        extra = extra_configs(pm, torch, dev)
+        extra = extra_configs(pm, torch, dev, copy_bw)
     out = {
         "metric": "conv coefficients/s",
         "value": value,
