@@ -27,6 +27,23 @@ constexpr int kHalfSize = 1 << (kHalfLog + 1);
 constexpr int kInvPow = 33;
 constexpr int kRoundTables = 6;  // radices 2 .. 64
 
+// Completion matrices of truncated inverses (itft_fill): for Q = 2^q,
+// q = kFillMinLog .. kFillMaxLog, and d = 1 .. kFillMax unknown outputs, the
+// d x (Q - d) matrix K, row-major, with x[Q - d + r] = sum_k K[r][k] x[k].
+constexpr int kFillMax = 3;
+constexpr int kFillMinLog = 3;
+constexpr int kFillMaxLog = 5;
+__host__ __device__ constexpr int fill_offset(int lq, int d) {
+  int off = 0;
+  for (int q = kFillMinLog; q <= kFillMaxLog + 1; ++q)
+    for (int e = 1; e <= kFillMax; ++e) {
+      if (q == lq && e == d) return off;
+      off += e * ((1 << q) - e);
+    }
+  return off;
+}
+constexpr int kFillSize = fill_offset(kFillMaxLog + 1, 1);
+
 // all per-prime constants the kernels read, in one device allocation
 struct PrimeTables {
   const uint2* pf;
@@ -35,6 +52,7 @@ struct PrimeTables {
   const uint2* iv;
   const uint2* rf[kRoundTables];
   const uint2* ri[kRoundTables];
+  const uint2* kx;  // completion matrices (kFillSize pairs)
 };
 
 // the same tables, reads not merged with those before this point (see fresh)
@@ -44,6 +62,7 @@ __device__ __forceinline__ PrimeTables fresh(const PrimeTables& T) {
   R.pi = fresh(T.pi);
   R.ph = fresh(T.ph);
   R.iv = fresh(T.iv);
+  R.kx = fresh(T.kx);
 #pragma unroll
   for (int q = 0; q < kRoundTables; ++q) {
     R.rf[q] = fresh(T.rf[q]);
@@ -179,6 +198,31 @@ struct ItftReg {
   }
 };
 
+// The same inverse when only d = Q - M outputs are unknown (d small): the
+// coefficients at j >= M are zero, and these d equations fix the unknown
+// outputs as linear combinations of the known ones, x[M + r] = sum_k K[r][k]
+// x[k] (K = -G_m^-1 G_k from the inverse transform matrix G, computed on the
+// host).  Then one full inverse network and the factor Q^-1.  Same contract
+// as ItftReg; more arithmetic than the recursion, but every step has the full
+// network's independent butterflies instead of a chain of shrinking
+// transforms, which is what limits a thread that runs the recursion alone.
+template <int Q, int M, bool LAZY>
+__device__ __forceinline__ void itft_fill(const Arith<LAZY>& A, u32* v, const PrimeTables& T) {
+  constexpr int D = Q - M;
+  const uint2* K = T.kx + fill_offset(ilog2c(Q), D);
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    u32 acc = A.mul(v[0], cld(K + r * M));
+#pragma unroll
+    for (int k = 1; k < M; ++k) acc = A.add(acc, A.mul(v[k], cld(K + r * M + k)));
+    v[M + r] = acc;
+  }
+  dit_reg<Q>(A, v, T.pi);
+  const uint2 qi = cld(T.iv + ilog2c(Q));
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = A.mul(v[j], qi);
+}
+
 // Dispatch on the runtime number of known outputs m (1 <= m <= Q).  m == Q is
 // the full inverse, returned unscaled (Q * x); m < Q returns scale 1.
 template <int Q, bool LAZY, int M = 1>
@@ -187,7 +231,10 @@ __device__ __forceinline__ void inv_column(const Arith<LAZY>& A, u32* v, int m, 
     dit_reg<Q>(A, v, T.pi);
   } else {
     if (m == M) {
-      ItftReg<Q, M, 0, LAZY>::run(A, v, T);
+      if constexpr (Q >= (1 << kFillMinLog) && Q <= (1 << kFillMaxLog) && Q - M <= kFillMax)
+        itft_fill<Q, M, LAZY>(A, v, T);
+      else
+        ItftReg<Q, M, 0, LAZY>::run(A, v, T);
     } else {
       inv_column<Q, LAZY, M + 1>(A, v, m, T);
     }

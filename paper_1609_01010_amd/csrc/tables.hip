@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include <vector>
+
 #include "internal.h"
 
 namespace pm {
@@ -178,13 +180,68 @@ DevCtx* ctx_current(pm_status* st) {
   return c;
 }
 
+// Completion matrices of truncated inverses (the kx table): the inverse
+// transform of size Q = 2^q maps bit-reversed outputs x to Q z with
+// G[j][t] = w_Q^{-j rev_q(t)}.  When z_j = 0 for j >= M = Q - d, the rows
+// j >= M give G_m x_miss + G_k x_known = 0, so K = -G_m^-1 G_k (G_m: the
+// columns t >= M, invertible as a Vandermonde matrix at distinct points,
+// scaled); Gauss-Jordan elimination mod p.
+static void fill_completion(const PrimeInfo& P, std::vector<uint2>& out) {
+  out.assign(kFillSize, make_uint2(0, 0));
+  const u32 p = P.p;
+  for (int lq = kFillMinLog; lq <= kFillMaxLog; ++lq) {
+    const int Q = 1 << lq;
+    const u32 wi = h_inv(h_powmod(P.g, (p - 1) / (u32)Q, p), p);
+    auto rev = [lq](int t) {
+      int r = 0;
+      for (int b = 0; b < lq; ++b) r |= ((t >> b) & 1) << (lq - 1 - b);
+      return r;
+    };
+    for (int d = 1; d <= kFillMax; ++d) {
+      const int M = Q - d;
+      // augmented rows [G_m | -G_k] for j = M .. Q-1
+      std::vector<std::vector<u32>> a(d, std::vector<u32>(Q));
+      for (int r = 0; r < d; ++r) {
+        const int j = M + r;
+        for (int t = 0; t < Q; ++t) {
+          const u32 gv = h_powmod(wi, (u64)j * (u64)rev(t), p);
+          if (t >= M)
+            a[r][t - M] = gv;
+          else
+            a[r][d + t] = gv ? p - gv : 0u;
+        }
+      }
+      for (int col = 0; col < d; ++col) {
+        int piv = col;
+        while (piv < d && a[piv][col] == 0) ++piv;
+        if (piv == d) continue;  // not reached: G_m is invertible
+        std::swap(a[piv], a[col]);
+        const u32 inv = h_inv(a[col][col], p);
+        for (auto& v : a[col]) v = h_mulmod(v, inv, p);
+        for (int r = 0; r < d; ++r) {
+          if (r == col || a[r][col] == 0) continue;
+          const u32 f = a[r][col];
+          for (int k = 0; k < Q; ++k) a[r][k] = (u32)((a[r][k] + (u64)(p - h_mulmod(f, a[col][k], p))) % p);
+        }
+      }
+      uint2* K = out.data() + fill_offset(lq, d);
+      for (int r = 0; r < d; ++r)
+        for (int k = 0; k < M; ++k) K[r * M + k] = h_shoup(a[r][d + k], p);
+    }
+  }
+}
+
 pm_status ensure_prime_tables(DevCtx* c, int pidx) {
   if (c->prime_mem[pidx]) return PM_OK;
   const PrimeInfo& P = prime_info(pidx);
-  // pf, pi, ph, iv, then the round tables (Q = 2 .. 32; both directions)
+  // pf, pi, ph, iv, then the round tables (Q = 2 .. 32; both directions),
+  // then the completion matrices
   const size_t head = 2 * (size_t)kPyrSize + kHalfSize + kInvPow;
   const size_t head_al = (head + 63) & ~(size_t)63;
-  const size_t n = head_al + 2 * kRoundTables * (size_t)kPyrSize;
+  const size_t kx_at = head_al + 2 * kRoundTables * (size_t)kPyrSize;
+  const size_t n = kx_at + kFillSize;
+  std::vector<uint2> kx;
+  fill_completion(P, kx);
   uint2* mem = nullptr;
   if (hipMalloc(&mem, n * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
   k_fill_pyramids<<<kPyrSize / 256, 256>>>(mem, P.p, P.g);
@@ -192,7 +249,8 @@ pm_status ensure_prime_tables(DevCtx* c, int pidx) {
     k_fill_round_table<<<kPyrSize / 256, 256>>>(mem + head_al + (2 * q) * kPyrSize, P.p, P.g, q + 1, 0);
     k_fill_round_table<<<kPyrSize / 256, 256>>>(mem + head_al + (2 * q + 1) * kPyrSize, P.p, P.g, q + 1, 1);
   }
-  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(mem + kx_at, kx.data(), kFillSize * sizeof(uint2), hipMemcpyHostToDevice) != hipSuccess) {
     hipFree(mem);
     return PM_EDEVICE;
   }
@@ -205,6 +263,7 @@ pm_status ensure_prime_tables(DevCtx* c, int pidx) {
     c->tabs[pidx].rf[q] = mem + head_al + (2 * q) * kPyrSize;
     c->tabs[pidx].ri[q] = mem + head_al + (2 * q + 1) * kPyrSize;
   }
+  c->tabs[pidx].kx = mem + kx_at;
   return PM_OK;
 }
 

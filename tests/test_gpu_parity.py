@@ -88,6 +88,45 @@ def test_every_candidate_plan_agrees(gpu_lib):
                 assert np.array_equal(got, want), (p, lc, P)
 
 
+@pytest.mark.parametrize("p", [998244353, 2013265921])
+def test_truncated_inverse_near_full(gpu_lib, p):
+    """Relaxed plans that keep all but d = 0..4 blocks of the first radix
+    (RA = 8, 16, 32): the truncated inverse completes the d missing values
+    from the known ones for d <= 3 and runs the recursion for d = 4; every
+    kernel family (one work-group, four-step with and without a second
+    column radix) against the schoolbook oracle."""
+    pm = gpu_lib
+    seen = set()
+    for logL in (11, 13, 16):
+        L = 1 << logL
+        for lra in (3, 4, 5):
+            RA = 1 << lra
+            for d in range(5):
+                lc = (RA - d) * (L // RA) - 3  # needs RA - d blocks of L / RA
+                la, lb = inputs.split_output_length(lc)
+                a, b = None, None
+                for P in pm.plan_candidates(lc, p):
+                    if P.kind == 0 or P.log_ra != lra or P.ma != RA - d:
+                        continue
+                    fam = (P.kind, P.log_rb > 0, lra, d)
+                    if fam in seen:
+                        continue
+                    seen.add(fam)
+                    if a is None:
+                        a, b = inputs.poly_pair((103, lc, p % 1000), la, lb, p)
+                        want = op.poly_mul(a, b, p)
+                    say("case: near-full truncation", p, lc, P)
+                    assert np.array_equal(_product(pm, a, b, p, plan=P), want), (p, lc, P)
+    # every family and d <= 3 reached: one work-group, and four-step with RB = 1
+    # and with RB > 1 (which needs RA >= 16)
+    for fam in ((1, False), (2, False), (2, True)):
+        for lra in (3, 4, 5):
+            if fam == (2, True) and lra < 4:
+                continue
+            for d in range(4):
+                assert (fam + (lra, d)) in seen, (fam, lra, d)
+
+
 def test_large_power_of_two_product_sampled(gpu_lib):
     """2^21 x 2^21 mod 2013265921 (transform 2^22): sampled coefficients by the
     defining sum, 16 random points by evaluation."""
