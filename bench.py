@@ -236,12 +236,16 @@ def extra_configs(pm, torch, dev, copy_bw, reps=5):
     pm.plan_cache_clear()
     plain()
     ms_plain = time_calls(torch, plain, 3)
+    prepared = pm.PreparedBatch(probs, outs=outs)
+    prepared.run()
+    torch.cuda.synchronize()
+    ms_batch_default = time_calls(torch, prepared.run, max(reps, 7))
     pm.set_policy(pm.POLICY_LEARNED)
     pm.plan_cache_clear()
     prepared = pm.PreparedBatch(probs, outs=outs)
     prepared.run()
     torch.cuda.synchronize()
-    ms_batch = time_calls(torch, prepared.run, reps)
+    ms_batch = time_calls(torch, prepared.run, max(reps, 7))
     pm.set_policy(pm.POLICY_DEFAULT)
     pm.plan_cache_clear()
     if pm.stream_check() != 0:
@@ -306,6 +310,7 @@ def extra_configs(pm, torch, dev, copy_bw, reps=5):
         "output_coeffs": ncoef,
         "plain_ms": ms_plain, "plain_coeffs_per_s": ncoef / (ms_plain * 1e-3),
         "batched_learned_ms": ms_batch, "batched_learned_coeffs_per_s": ncoef / (ms_batch * 1e-3),
+        "batched_default_plans_ms": ms_batch_default,
         "speedup": ms_plain / ms_batch,
     }
     return out

@@ -242,8 +242,22 @@ typedef struct {
 /* Select the policy used by pm_poly_mul / pm_poly_mul_batch to pick plans. */
 pm_status pm_set_policy(pm_policy policy);
 
-/* The plan the current policy picks for an output length lc and prime p. */
+/* Timing contexts of the tuner, the database and the cost model.  A product
+ * on its own is bound by its own parallelism (its plan should spread it over
+ * the device); one of a batch shares the device with the others (its plan
+ * should do the least work and traffic).  pm_poly_mul and the hooks choose
+ * plans for PM_CTX_SINGLE, pm_poly_mul_batch for PM_CTX_BATCH; the plan cache
+ * holds one entry per (length, prime, context). */
+#define PM_CTX_SINGLE 0
+#define PM_CTX_BATCH 1
+
+/* The plan the current policy picks for an output length lc and prime p:
+ * for a product on its own (pm_plan_for), or in a context.  In the batch
+ * context under PM_POLICY_LEARNED, pm_poly_mul_batch plans a batch's new
+ * lengths together (one plan family per transform length and prime) and
+ * caches them; before that, a length gets the model's own pick. */
 pm_status pm_plan_for(size_t lc, uint32_t p, pm_plan* plan);
+pm_status pm_plan_for_ctx(size_t lc, uint32_t p, int context, pm_plan* plan);
 
 /* Product with an explicit plan (validated; PM_EINVAL if it does not fit). */
 pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
@@ -252,38 +266,49 @@ pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, s
 /* Number of candidate plans for (lc, p) and the i-th one (the tuner's space). */
 size_t pm_plan_candidates(size_t lc, uint32_t p, pm_plan* out, size_t max_out);
 
-/* Record the plan to use for (lc, p) in the plan cache (used by all policies
- * before they choose). */
+/* Record the plan to use for (lc, p) in the plan cache, for both contexts
+ * (used by all policies before they choose). */
 pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan);
 void pm_plan_cache_clear(void);
 
 /* ---- the autotuner (empirical search) -------------------------------------
  * The tuner times every candidate plan of an output length on the device
  * (hipEvents, median of `reps` runs after a warm-up, deterministic inputs)
- * and records (length, prime, plan, microseconds) in the in-memory timing
- * database; the fastest plan of each length goes to the plan cache.  This
- * follows the paper's search over measured running times (section 2.2, and
- * the autotuned library of section 5).  Synchronous: returns after timing. */
+ * and records (length, prime, plan, microseconds, context) in the in-memory
+ * timing database; the fastest plan of each length goes to the plan cache of
+ * that context.  This follows the paper's search over measured running times
+ * (section 2.2, and the autotuned library of section 5).  In PM_CTX_SINGLE a
+ * plan is timed on one product; in PM_CTX_BATCH on about 2^24 / L products
+ * of the length at once (at most 4096: enough to fill the device whatever the
+ * plan) (each pass one launch over all of them, as the batch
+ * executor runs a class), and the time per product is recorded.
+ * Synchronous: returns after timing.  pm_tune is pm_tune_ctx(.., PM_CTX_SINGLE). */
 pm_status pm_tune(const size_t* lcs, size_t n, uint32_t p, int reps, void* stream);
-/* Median running time of one plan for output length lc (synchronous). */
+pm_status pm_tune_ctx(const size_t* lcs, size_t n, uint32_t p, int reps, int context, void* stream);
+/* Median running time of one plan for output length lc (synchronous); in
+ * PM_CTX_BATCH the time per product of a batch, as the tuner measures it.
+ * pm_time_plan is pm_time_plan_ctx(.., PM_CTX_SINGLE, ..). */
 pm_status pm_time_plan(size_t lc, uint32_t p, const pm_plan* plan, int reps, double* us);
+pm_status pm_time_plan_ctx(size_t lc, uint32_t p, const pm_plan* plan, int reps, int context, double* us);
 size_t pm_tune_db_size(void);
-pm_status pm_tune_db_get(size_t i, size_t* lc, uint32_t* p, pm_plan* plan, double* us);
-pm_status pm_tune_db_add(size_t lc, uint32_t p, const pm_plan* plan, double us);
+/* Row i of the database; any output pointer may be NULL. */
+pm_status pm_tune_db_get(size_t i, size_t* lc, uint32_t* p, pm_plan* plan, double* us, int* context);
+pm_status pm_tune_db_add(size_t lc, uint32_t p, const pm_plan* plan, double us, int context);
 void pm_tune_db_clear(void);
-/* Text file, one row per line: lc p kind log_l log_ra log_rb log_c ma lq lnt us.
- * Load appends (tuning resumes from the rows already measured). */
+/* Text file, one row per line: lc p kind log_l log_ra log_rb log_c ma lq lnt us
+ * context (a line without the context is a PM_CTX_SINGLE row).  Load appends
+ * (tuning resumes from the rows already measured). */
 pm_status pm_tune_db_save(const char* path);
 pm_status pm_tune_db_load(const char* path);
 
 /* ---- the learned cost model -----------------------------------------------
- * An FP32 perceptron (16 features, two tanh layers of 64, linear output)
- * predicts the log running time per relaxed coefficient of a (length, plan)
- * pair; under PM_POLICY_LEARNED the plan with the least predicted time is
- * used (and cached).  Trained on the timing database by the library's own
- * forward, backward and Adam kernels. */
-/* Feature vector (16 floats) of a (length, prime, plan). */
-pm_status pm_model_features(size_t lc, uint32_t p, const pm_plan* plan, float* out);
+ * An FP32 perceptron (17 features, two tanh layers of 64, linear output)
+ * predicts the log running time per relaxed coefficient of a (length, plan,
+ * context); under PM_POLICY_LEARNED the plan with the least predicted time in
+ * the caller's context is used (and cached).  Trained on the timing database
+ * (both contexts) by the library's own forward, backward and Adam kernels. */
+/* Feature vector (17 floats) of a (length, prime, plan, context). */
+pm_status pm_model_features(size_t lc, uint32_t p, const pm_plan* plan, int context, float* out);
 /* Train on the database for `steps` full-batch Adam steps at rate lr from
  * the initial weights `init` (pm_mlp_num_params() floats, host; NULL: a
  * SplitMix64-seeded Glorot-uniform draw).  losses: NULL or `steps` floats. */
@@ -291,13 +316,14 @@ pm_status pm_model_train(const float* init, int steps, float lr, float* losses);
 /* Weights and target normalisation (log us per coefficient: mean, sd). */
 pm_status pm_model_get(float* params, float* mean, float* sd);
 pm_status pm_model_set(const float* params, float mean, float sd);
-/* Predicted natural log of the running time in microseconds of n plans. */
-pm_status pm_model_predict(size_t lc, uint32_t p, const pm_plan* plans, size_t n, double* log_us);
+/* Predicted natural log of the running time in microseconds of n plans in a
+ * context (per product in PM_CTX_BATCH). */
+pm_status pm_model_predict(size_t lc, uint32_t p, const pm_plan* plans, size_t n, int context, double* log_us);
 pm_status pm_model_save(const char* path);
 pm_status pm_model_load(const char* path);
 
 /* The network's kernels on host arrays (test hooks).  Parameter layout
- * W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3[1]; X is B x 16 row-major;
+ * W1[64][17], b1[64], W2[64][64], b2[64], W3[64], b3[1]; X is B x 17 row-major;
  * loss = mean (y - t)^2. */
 size_t pm_mlp_num_params(void);
 pm_status pm_mlp_forward(const float* params, const float* X, int B, float* y);

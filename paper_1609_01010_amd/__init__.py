@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libpolymul.so")
 PRIMES = (998244353, 2013265921, 469762049, 167772161)
 
 PM_OK, PM_EINVAL, PM_EUNSUPPORTED, PM_ETOOLARGE, PM_ENOTREDUCED, PM_ENOMEM, PM_EDEVICE = range(7)
+CTX_SINGLE, CTX_BATCH = 0, 1  # tuning contexts: a product alone, one of a batch
 POLICY_DEFAULT, POLICY_EXHAUSTIVE, POLICY_LEARNED = range(3)
 
 
@@ -95,25 +96,28 @@ SIGNATURES = {
     "pm_stream_check": (_int, [_vp]),
     "pm_set_policy": (_int, [_int]),
     "pm_plan_for": (_int, [_sz, _u32, ctypes.POINTER(Plan)]),
+    "pm_plan_for_ctx": (_int, [_sz, _u32, _int, ctypes.POINTER(Plan)]),
     "pm_poly_mul_plan": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, ctypes.POINTER(Plan), _vp]),
     "pm_plan_candidates": (_sz, [_sz, _u32, ctypes.POINTER(Plan), _sz]),
     "pm_plan_cache_put": (_int, [_sz, _u32, ctypes.POINTER(Plan)]),
     "pm_plan_cache_clear": (None, []),
     "pm_tune": (_int, [ctypes.POINTER(_sz), _sz, _u32, _int, _vp]),
+    "pm_tune_ctx": (_int, [ctypes.POINTER(_sz), _sz, _u32, _int, _int, _vp]),
     "pm_time_plan": (_int, [_sz, _u32, ctypes.POINTER(Plan), _int, ctypes.POINTER(ctypes.c_double)]),
+    "pm_time_plan_ctx": (_int, [_sz, _u32, ctypes.POINTER(Plan), _int, _int, ctypes.POINTER(ctypes.c_double)]),
     "pm_tune_db_size": (_sz, []),
     "pm_tune_db_get": (_int, [_sz, ctypes.POINTER(_sz), ctypes.POINTER(_u32), ctypes.POINTER(Plan),
-                              ctypes.POINTER(ctypes.c_double)]),
-    "pm_tune_db_add": (_int, [_sz, _u32, ctypes.POINTER(Plan), ctypes.c_double]),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_int)]),
+    "pm_tune_db_add": (_int, [_sz, _u32, ctypes.POINTER(Plan), ctypes.c_double, _int]),
     "pm_tune_db_clear": (None, []),
     "pm_tune_db_save": (_int, [ctypes.c_char_p]),
     "pm_tune_db_load": (_int, [ctypes.c_char_p]),
-    "pm_model_features": (_int, [_sz, _u32, ctypes.POINTER(Plan), ctypes.POINTER(ctypes.c_float)]),
+    "pm_model_features": (_int, [_sz, _u32, ctypes.POINTER(Plan), _int, ctypes.POINTER(ctypes.c_float)]),
     "pm_model_train": (_int, [ctypes.POINTER(ctypes.c_float), _int, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
     "pm_model_get": (_int, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_float)]),
     "pm_model_set": (_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_float, ctypes.c_float]),
-    "pm_model_predict": (_int, [_sz, _u32, ctypes.POINTER(Plan), _sz, ctypes.POINTER(ctypes.c_double)]),
+    "pm_model_predict": (_int, [_sz, _u32, ctypes.POINTER(Plan), _sz, _int, ctypes.POINTER(ctypes.c_double)]),
     "pm_model_save": (_int, [ctypes.c_char_p]),
     "pm_model_load": (_int, [ctypes.c_char_p]),
     "pm_mlp_num_params": (_sz, []),
@@ -380,9 +384,9 @@ def set_policy(policy: int):
     _check(lib().pm_set_policy(policy), "pm_set_policy")
 
 
-def plan_for(lc: int, p: int) -> Plan:
+def plan_for(lc: int, p: int, context: int = 0) -> Plan:
     P = Plan()
-    _check(lib().pm_plan_for(lc, p, ctypes.byref(P)), "pm_plan_for")
+    _check(lib().pm_plan_for_ctx(lc, p, context, ctypes.byref(P)), "pm_plan_for_ctx")
     return P
 
 
@@ -440,33 +444,39 @@ def _f32(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
 
 
-def tune(lcs, p: int, reps: int = 5, stream=None):
-    """Time every candidate plan of each output length; fills the database and the plan cache."""
+def tune(lcs, p: int, reps: int = 5, stream=None, context: int = 0):
+    """Time every candidate plan of each output length (context CTX_SINGLE: one
+    product; CTX_BATCH: time per product of a batch); fills the database and
+    the plan cache of that context."""
     arr = (ctypes.c_size_t * len(lcs))(*[int(x) for x in lcs])
-    _check(lib().pm_tune(arr, len(lcs), p, reps, _stream(stream) if stream is not None else None), "pm_tune")
+    _check(lib().pm_tune_ctx(arr, len(lcs), p, reps, context, _stream(stream) if stream is not None else None),
+           "pm_tune_ctx")
 
 
-def time_plan(lc: int, p: int, plan: Plan, reps: int = 5) -> float:
+def time_plan(lc: int, p: int, plan: Plan, reps: int = 5, context: int = 0) -> float:
     us = ctypes.c_double()
-    _check(lib().pm_time_plan(lc, p, ctypes.byref(plan), reps, ctypes.byref(us)), "pm_time_plan")
+    _check(lib().pm_time_plan_ctx(lc, p, ctypes.byref(plan), reps, context, ctypes.byref(us)), "pm_time_plan_ctx")
     return us.value
 
 
-def tune_db_rows():
-    """[(lc, p, Plan, us)] of the timing database."""
+def tune_db_rows(context: int = 0):
+    """[(lc, p, Plan, us)] of the timing database rows of one context."""
     out = []
     for i in range(lib().pm_tune_db_size()):
         lc = ctypes.c_size_t()
         p = ctypes.c_uint32()
         P = Plan()
         us = ctypes.c_double()
-        _check(lib().pm_tune_db_get(i, ctypes.byref(lc), ctypes.byref(p), ctypes.byref(P), ctypes.byref(us)))
-        out.append((lc.value, p.value, P, us.value))
+        cx = ctypes.c_int()
+        _check(lib().pm_tune_db_get(i, ctypes.byref(lc), ctypes.byref(p), ctypes.byref(P), ctypes.byref(us),
+                                    ctypes.byref(cx)))
+        if cx.value == context:
+            out.append((lc.value, p.value, P, us.value))
     return out
 
 
-def tune_db_add(lc: int, p: int, plan: Plan, us: float):
-    _check(lib().pm_tune_db_add(lc, p, ctypes.byref(plan), us), "pm_tune_db_add")
+def tune_db_add(lc: int, p: int, plan: Plan, us: float, context: int = 0):
+    _check(lib().pm_tune_db_add(lc, p, ctypes.byref(plan), us, context), "pm_tune_db_add")
 
 
 def tune_db_clear():
@@ -485,11 +495,13 @@ def mlp_num_params() -> int:
     return int(lib().pm_mlp_num_params())
 
 
-def model_features(lc: int, p: int, plan: Plan):
+def model_features(lc: int, p: int, plan: Plan, context: int = 0):
     import numpy as np
 
-    f = np.zeros(16, dtype=np.float32)
-    _check(lib().pm_model_features(lc, p, ctypes.byref(plan), _fptr(f)), "pm_model_features")
+    from .inputs import MLP_F
+
+    f = np.zeros(MLP_F, dtype=np.float32)
+    _check(lib().pm_model_features(lc, p, ctypes.byref(plan), context, _fptr(f)), "pm_model_features")
     return f
 
 
@@ -521,13 +533,13 @@ def model_set(w, mean: float, sd: float):
     _check(lib().pm_model_set(_fptr(w), mean, sd), "pm_model_set")
 
 
-def model_predict(lc: int, p: int, plans):
+def model_predict(lc: int, p: int, plans, context: int = 0):
     import numpy as np
 
     arr = (Plan * len(plans))(*plans)
     out = np.zeros(len(plans), dtype=np.float64)
-    _check(lib().pm_model_predict(lc, p, arr, len(plans), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
-           "pm_model_predict")
+    _check(lib().pm_model_predict(lc, p, arr, len(plans), context,
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "pm_model_predict")
     return out
 
 

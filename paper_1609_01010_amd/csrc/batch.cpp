@@ -16,7 +16,6 @@
 
 namespace pm {
 bool plan_valid(const Plan& P, long lc, int pidx);
-Plan choose_plan(long lc, int pidx, DevCtx* c, hipStream_t s);
 size_t plan_workspace_bytes(const Plan& P);
 pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
                    long lc, u32* Ta, u32* Tb, ConvJob* J, int ring);
@@ -41,6 +40,7 @@ struct ClassRun {
   int first;  // offset in the job array
   int count;
   int max_rows;
+  double work = 0;  // sum over the products of n' (3 log2 L + 10): the butterflies and multiplies
 };
 
 struct GraphEntry {
@@ -74,6 +74,9 @@ struct BatchState {
   ConvJob* staging = nullptr;                               // pinned host copy of the jobs
   size_t staging_cap = 0;
   hipEvent_t staged = nullptr;  // the last upload from `staging` has completed
+  // learned policy: per batch shape (hash of the lengths and primes), whether
+  // the default plans ran the whole batch faster than the model's (1) or not (0)
+  std::map<u64, int> verdict;
 };
 // one state per (device, stream): batches on different streams may overlap
 std::map<std::pair<int, hipStream_t>, BatchState*> g_batch;
@@ -109,10 +112,13 @@ pm_status capture_graph(BatchState* B, const std::vector<ClassRun>& runs, ConvJo
   hipEvent_t fork;
   hipEventCreateWithFlags(&fork, hipEventDisableTiming);
   hipEventRecord(fork, cs);
+  // classes in decreasing work, each on the branch with the least work so far
   std::vector<bool> used(B->branches.size(), false);
+  std::vector<double> load(B->branches.size(), 0.0);
   for (size_t k = 0; k < runs.size() && st == PM_OK; ++k) {
     const ClassRun& r = runs[k];
-    const size_t bi = k % B->branches.size();
+    const size_t bi = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[bi] += r.work;
     hipStream_t bs = B->branches[bi];
     if (!used[bi]) {
       hipStreamWaitEvent(bs, fork, 0);
@@ -155,6 +161,27 @@ using namespace pm;
 static pm_status batch_plans(const pm_problem* probs, size_t count, std::vector<Plan>& plans, std::vector<int>& pidx) {
   plans.resize(count);
   pidx.resize(count);
+  if (current_policy() == PM_POLICY_LEARNED) {
+    // lengths not planned yet: one plan family per size class, from the cost
+    // model, into the batch context's plan cache
+    std::vector<long> lcs;
+    std::vector<int> pix;
+    for (size_t i = 0; i < count; ++i) {
+      const pm_problem& q = probs[i];
+      const int pi = prime_index(q.p);
+      if (pi < 0 || q.len_a == 0 || q.len_b == 0 || q.len_a > (1ul << 24) || q.len_b > (1ul << 24)) continue;
+      const long lc = (long)(q.len_a + q.len_b - 1);
+      Plan P;
+      if (lc > 64 && !plan_cache_get(lc, q.p, &P, kCtxBatch)) {
+        lcs.push_back(lc);
+        pix.push_back(pi);
+      }
+    }
+    std::vector<Plan> picked;
+    if (!lcs.empty() && learned_batch_plans(lcs, pix, &picked) == PM_OK)
+      for (size_t k = 0; k < lcs.size(); ++k)
+        if (plan_valid(picked[k], lcs[k], pix[k])) plan_cache_set(lcs[k], prime_info(pix[k]).p, picked[k], kCtxBatch);
+  }
   for (size_t i = 0; i < count; ++i) {
     const pm_problem& q = probs[i];
     if (!q.a || !q.b || !q.c || q.len_a == 0 || q.len_b == 0) return PM_EINVAL;
@@ -162,7 +189,7 @@ static pm_status batch_plans(const pm_problem* probs, size_t count, std::vector<
     pidx[i] = prime_index(q.p);
     if (pidx[i] < 0) return PM_EUNSUPPORTED;
     const long lc = (long)(q.len_a + q.len_b - 1);
-    plans[i] = choose_plan(lc, pidx[i], nullptr, 0);
+    plans[i] = choose_plan(lc, pidx[i], nullptr, 0, kCtxBatch);
     if (!plan_valid(plans[i], lc, pidx[i])) return PM_ETOOLARGE;
   }
   return PM_OK;
@@ -186,57 +213,56 @@ extern "C" pm_status pm_batch_workspace_query(const pm_problem* probs, size_t co
   return PM_OK;
 }
 
-extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream) {
-  if (!probs && count) return PM_EINVAL;
-  if (count == 0) return PM_OK;
-  if (count > 65535) return PM_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  std::vector<Plan> plans;
-  std::vector<int> pidx;
-  {
-    const pm_status st0 = batch_plans(probs, count, plans, pidx);
-    if (st0) return st0;
-  }
-  pm_status st;
-  DevCtx* c = ctx_current(&st);
-  if (!c) return st;
-  std::lock_guard<std::mutex> lk(c->mu);
-  BatchState* B;
-  st = batch_state(c, s, &B);
-  if (st) return st;
-  void* ws_cur = stream_workspace_current(c, s);
-
-  // fast path: the same shape as the previous batch
-  {
-    LastShape& L = B->last;
-    bool same = L.graph && L.key.size() == 3 * count && L.epoch == plan_epoch() && L.ws == ws_cur;
-    for (size_t i = 0; same && i < count; ++i)
-      same = L.key[3 * i] == probs[i].len_a && L.key[3 * i + 1] == probs[i].len_b && L.key[3 * i + 2] == probs[i].p;
-    if (same) {
-      for (size_t k = 0; k < L.direct.size(); ++k) {
-        const pm_problem& q = probs[L.direct[k]];
-        if (launch_direct(q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, L.direct_pidx[k], c->errflag, s) !=
-            hipSuccess)
-          return PM_EDEVICE;
-      }
-      if (L.jobs.empty()) return PM_OK;
-      if (hipEventSynchronize(B->staged) != hipSuccess) return PM_EDEVICE;
-      for (size_t k = 0; k < L.jobs.size(); ++k) {
-        const pm_problem& q = probs[L.order[k]];
-        ConvJob& J = B->staging[k];
-        J = L.jobs[k];
-        J.a = q.a;
-        J.b = q.b;
-        J.c = q.c;
-      }
-      const size_t bytes = L.jobs.size() * sizeof(ConvJob);
-      if (hipMemcpyAsync(L.graph->djobs, B->staging, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-        return PM_EDEVICE;
-      if (hipEventRecord(B->staged, s) != hipSuccess) return PM_EDEVICE;
-      TraceScope ts(s, "batch_graph");
-      return hipGraphLaunch(L.graph->exec, s) == hipSuccess ? PM_OK : PM_EDEVICE;
+// Fast path: the same shape (lengths and primes, in order) as the previous
+// batch on this stream, under the same plans and workspace: patch the
+// operand and output pointers into the previous jobs, upload them, relaunch
+// the graph.  Returns false, launching nothing, when the shape differs.
+static bool batch_fast(DevCtx* c, BatchState* B, const pm_problem* probs, size_t count, hipStream_t s,
+                       pm_status* st) {
+  LastShape& L = B->last;
+  bool same = L.graph && L.key.size() == 3 * count && L.epoch == plan_epoch() && L.ws == stream_workspace_current(c, s);
+  for (size_t i = 0; same && i < count; ++i)
+    same = L.key[3 * i] == probs[i].len_a && L.key[3 * i + 1] == probs[i].len_b && L.key[3 * i + 2] == probs[i].p;
+  if (!same) return false;
+  for (size_t i = 0; i < count; ++i)
+    if (!probs[i].a || !probs[i].b || !probs[i].c) {
+      *st = PM_EINVAL;
+      return true;
     }
+  *st = PM_EDEVICE;
+  for (size_t k = 0; k < L.direct.size(); ++k) {
+    const pm_problem& q = probs[L.direct[k]];
+    if (launch_direct(q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, L.direct_pidx[k], c->errflag, s) != hipSuccess)
+      return true;
   }
+  if (L.jobs.empty()) {
+    *st = PM_OK;
+    return true;
+  }
+  if (hipEventSynchronize(B->staged) != hipSuccess) return true;
+  for (size_t k = 0; k < L.jobs.size(); ++k) {
+    const pm_problem& q = probs[L.order[k]];
+    ConvJob& J = B->staging[k];
+    J = L.jobs[k];
+    J.a = q.a;
+    J.b = q.b;
+    J.c = q.c;
+  }
+  const size_t bytes = L.jobs.size() * sizeof(ConvJob);
+  if (hipMemcpyAsync(L.graph->djobs, B->staging, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return true;
+  if (hipEventRecord(B->staged, s) != hipSuccess) return true;
+  TraceScope ts(s, "batch_graph");
+  *st = hipGraphLaunch(L.graph->exec, s) == hipSuccess ? PM_OK : PM_EDEVICE;
+  return true;
+}
+
+// Run one batch with the given plans: the fast path when the shape repeats,
+// else classes, jobs and (cached per class signature) the graph.  The caller
+// holds the device lock.
+static pm_status batch_run(DevCtx* c, BatchState* B, const pm_problem* probs, size_t count,
+                           const std::vector<Plan>& plans, const std::vector<int>& pidx, hipStream_t s) {
+  pm_status st = PM_OK;
+  if (batch_fast(c, B, probs, count, s, &st)) return st;
 
   // classes, largest transforms first
   std::map<ClassKey, std::vector<size_t>> groups;
@@ -281,13 +307,13 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
       st = make_job(c, plans[i], pidx[i], q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, lc, Ta, Tb, &J, 0);
       if (st) return st;
       r.max_rows = std::max(r.max_rows, J.rows);
+      r.work += (double)plan_nprime(plans[i]) * (3.0 * plans[i].logL + 10.0);
       jobs.push_back(J);
       order.push_back((int)i);
     }
     runs.push_back(r);
   }
-  std::stable_sort(runs.begin(), runs.end(),
-                   [](const ClassRun& x, const ClassRun& y) { return std::get<1>(x.key) > std::get<1>(y.key); });
+  std::stable_sort(runs.begin(), runs.end(), [](const ClassRun& x, const ClassRun& y) { return x.work > y.work; });
 
   for (size_t i : direct) {
     const pm_problem& q = probs[i];
@@ -350,4 +376,94 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
   TraceScope ts(s, "batch_graph");
   if (hipGraphLaunch(G->exec, s) != hipSuccess) return PM_EDEVICE;
   return PM_OK;
+}
+
+// FNV-1a over the (len_a, len_b, p) of every problem
+static u64 shape_hash(const pm_problem* probs, size_t count) {
+  u64 h = 1469598103934665603ull;
+  auto mix = [&h](u64 v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xFF;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(count);
+  for (size_t i = 0; i < count; ++i) {
+    mix(probs[i].len_a);
+    mix(probs[i].len_b);
+    mix(probs[i].p);
+  }
+  return h;
+}
+
+// median milliseconds of three runs of the batch with these plans (after one)
+static pm_status time_batch(DevCtx* c, BatchState* B, const pm_problem* probs, size_t count,
+                            const std::vector<Plan>& plans, const std::vector<int>& pidx, hipStream_t s, float* ms) {
+  pm_status st = batch_run(c, B, probs, count, plans, pidx, s);
+  hipEvent_t e0, e1;
+  if (st || hipEventCreate(&e0) || hipEventCreate(&e1)) return st ? st : PM_EDEVICE;
+  std::vector<float> t;
+  for (int r = 0; r < 3 && st == PM_OK; ++r) {
+    hipEventRecord(e0, s);
+    st = batch_run(c, B, probs, count, plans, pidx, s);
+    hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) st = PM_EDEVICE;
+    float x = 0;
+    hipEventElapsedTime(&x, e0, e1);
+    t.push_back(x);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) return st;
+  std::sort(t.begin(), t.end());
+  *ms = t[1];
+  return PM_OK;
+}
+
+extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream) {
+  if (!probs && count) return PM_EINVAL;
+  if (count == 0) return PM_OK;
+  if (count > 65535) return PM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  pm_status st;
+  DevCtx* c = ctx_current(&st);
+  if (!c) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  BatchState* B;
+  st = batch_state(c, s, &B);
+  if (st) return st;
+  // a repeated shape needs no planning at all
+  if (batch_fast(c, B, probs, count, s, &st)) return st;
+  std::vector<Plan> plans;
+  std::vector<int> pidx;
+  st = batch_plans(probs, count, plans, pidx);
+  if (st) return st;
+  if (current_policy() != PM_POLICY_LEARNED) return batch_run(c, B, probs, count, plans, pidx, s);
+  // Learned policy: the model's plans are chosen per transform length, but
+  // the classes of a batch share the device, and how well they overlap
+  // decides its time.  The first call of a batch shape therefore runs it
+  // with the model's plans and with the default plans, waits, and keeps the
+  // faster for that shape.
+  std::vector<Plan> dplans(count);
+  bool differ = false;
+  for (size_t i = 0; i < count; ++i) {
+    const long lc = (long)(probs[i].len_a + probs[i].len_b - 1);
+    // a plan the caller put into the cache is kept in both
+    dplans[i] = plan_pinned(lc, probs[i].p) ? plans[i] : default_plan(lc, pidx[i]);
+    const Plan& P = plans[i];
+    const Plan& D = dplans[i];
+    differ |= P.kind != D.kind || P.logL != D.logL || P.logRA != D.logRA || P.logRB != D.logRB ||
+              P.logC != D.logC || P.ma != D.ma || P.lq != D.lq || plan_row_lnt(P) != plan_row_lnt(D);
+  }
+  if (!differ) return batch_run(c, B, probs, count, plans, pidx, s);
+  const u64 h = shape_hash(probs, count);
+  auto v = B->verdict.find(h);
+  if (v == B->verdict.end()) {
+    float t_model = 0, t_default = 0;
+    st = time_batch(c, B, probs, count, plans, pidx, s, &t_model);
+    if (st == PM_OK) st = time_batch(c, B, probs, count, dplans, pidx, s, &t_default);
+    if (st) return st;
+    v = B->verdict.emplace(h, t_default < t_model ? 1 : 0).first;
+  }
+  return batch_run(c, B, probs, count, v->second ? dplans : plans, pidx, s);
 }

@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
+#include <set>
+#include <tuple>
 
 #include "internal.h"
 
@@ -27,8 +29,10 @@ static std::atomic<unsigned long> g_plan_epoch{1};
 
 // changes whenever a plan choice could change (policy, cache, model)
 unsigned long plan_epoch() { return g_plan_epoch.load(); }
+pm_policy current_policy() { return g_policy; }
 void plan_epoch_bump() { g_plan_epoch.fetch_add(1); }
-static std::map<std::pair<long, u32>, Plan> g_plan_cache;
+static std::map<std::tuple<long, u32, int>, Plan> g_plan_cache;
+static std::set<std::pair<long, u32>> g_plan_pinned;  // (lc, p) put by the caller (pm_plan_cache_put)
 
 bool plan_valid(const Plan& P, long lc, int pidx) {
   const PrimeInfo& PI = prime_info(pidx);
@@ -144,18 +148,20 @@ std::vector<Plan> plan_candidates(long lc, int pidx) {
   return out;
 }
 
-Plan learned_plan(long lc, int pidx, bool* ok);  // cost model (tune.cpp)
-pm_status tune_one(DevCtx* c, long lc, int pidx, int reps, hipStream_t s, Plan* best_out);
-
-void plan_cache_set(long lc, u32 p, const Plan& P) {
+void plan_cache_set(long lc, u32 p, const Plan& P, int tctx) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
-  g_plan_cache[std::make_pair(lc, p)] = P;
+  g_plan_cache[std::make_tuple(lc, p, tctx)] = P;
   plan_epoch_bump();
 }
 
-bool plan_cache_get(long lc, u32 p, Plan* P) {
+bool plan_pinned(long lc, u32 p) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
-  auto it = g_plan_cache.find(std::make_pair(lc, p));
+  return g_plan_pinned.count(std::make_pair(lc, p)) != 0;
+}
+
+bool plan_cache_get(long lc, u32 p, Plan* P, int tctx) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto it = g_plan_cache.find(std::make_tuple(lc, p, tctx));
   if (it == g_plan_cache.end()) return false;
   *P = it->second;
   return true;
@@ -164,20 +170,21 @@ bool plan_cache_get(long lc, u32 p, Plan* P) {
 // The plan cache first (tuned or recorded plans); then the policy: the cost
 // model's argmin (cached), the exhaustive search of this length when a
 // device context is at hand (the caller holds its lock), or the default.
-Plan choose_plan(long lc, int pidx, DevCtx* c = nullptr, hipStream_t s = 0) {
+// tctx: the context the plan runs in (a product alone, or in a batch).
+Plan choose_plan(long lc, int pidx, DevCtx* c, hipStream_t s, int tctx) {
   const u32 p = prime_info(pidx).p;
   Plan P;
-  if (plan_cache_get(lc, p, &P)) return P;
+  if (plan_cache_get(lc, p, &P, tctx)) return P;
   if (lc > 64 && g_policy == PM_POLICY_LEARNED) {
     bool ok = false;
-    P = learned_plan(lc, pidx, &ok);
+    P = learned_plan(lc, pidx, &ok, tctx);
     if (ok && plan_valid(P, lc, pidx)) {
-      plan_cache_set(lc, p, P);
+      plan_cache_set(lc, p, P, tctx);
       return P;
     }
   }
   if (lc > 64 && g_policy == PM_POLICY_EXHAUSTIVE && c) {
-    if (tune_one(c, lc, pidx, 5, s, &P) == PM_OK) return P;
+    if (tune_one(c, lc, pidx, 5, s, &P, tctx) == PM_OK) return P;
   }
   return default_plan(lc, pidx);
 }
@@ -623,13 +630,15 @@ pm_status pm_set_policy(pm_policy policy) {
   return PM_OK;
 }
 
-pm_status pm_plan_for(size_t lc, uint32_t p, pm_plan* plan) {
-  if (!plan || lc == 0) return PM_EINVAL;
+pm_status pm_plan_for(size_t lc, uint32_t p, pm_plan* plan) { return pm_plan_for_ctx(lc, p, PM_CTX_SINGLE, plan); }
+
+pm_status pm_plan_for_ctx(size_t lc, uint32_t p, int context, pm_plan* plan) {
+  if (!plan || lc == 0 || (context != PM_CTX_SINGLE && context != PM_CTX_BATCH)) return PM_EINVAL;
   const int pidx = prime_index(p);
   if (pidx < 0) return PM_EUNSUPPORTED;
   const int logL = ceil_log2((long)lc);
   if (lc > 64 && (logL > prime_info(pidx).two_adic || logL > 24)) return PM_ETOOLARGE;
-  *plan = to_pub(choose_plan((long)lc, pidx));
+  *plan = to_pub(choose_plan((long)lc, pidx, nullptr, 0, context));
   return PM_OK;
 }
 
@@ -648,7 +657,9 @@ pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan) {
   Plan P = from_pub(*plan);
   if (!plan_valid(P, (long)lc, pidx)) return PM_EINVAL;
   std::lock_guard<std::mutex> lk(g_plan_mu);
-  g_plan_cache[std::make_pair((long)lc, p)] = P;
+  g_plan_cache[std::make_tuple((long)lc, p, kCtxSingle)] = P;  // for products alone and in batches
+  g_plan_cache[std::make_tuple((long)lc, p, kCtxBatch)] = P;
+  g_plan_pinned.insert(std::make_pair((long)lc, p));
   plan_epoch_bump();
   return PM_OK;
 }
@@ -656,6 +667,7 @@ pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan) {
 void pm_plan_cache_clear(void) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plan_cache.clear();
+  g_plan_pinned.clear();
   plan_epoch_bump();
 }
 

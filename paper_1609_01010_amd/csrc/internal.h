@@ -102,6 +102,29 @@ struct Plan {
   int twist = 0;  // nega-circular product: the passes twist the operands and untwist the result
 };
 
+// Timing contexts of the tuner and the cost model: a product on its own
+// (latency) or one of many in a batch (throughput, time per product).
+constexpr int kCtxSingle = 0;
+constexpr int kCtxBatch = 1;
+
+// plan choice (capi.cpp): the cache for (lc, p, context), then the policy
+Plan choose_plan(long lc, int pidx, DevCtx* c = nullptr, hipStream_t s = 0, int tctx = kCtxSingle);
+void plan_cache_set(long lc, u32 p, const Plan& P, int tctx = kCtxSingle);
+bool plan_cache_get(long lc, u32 p, Plan* P, int tctx = kCtxSingle);
+// the caller put a plan for (lc, p) into the cache (pm_plan_cache_put)
+bool plan_pinned(long lc, u32 p);
+// the library's plan without a model or a search
+Plan default_plan(long lc, int pidx);
+// the cost model's pick (tune.cpp)
+Plan learned_plan(long lc, int pidx, bool* ok, int tctx);
+// the cost model's picks for the items of one batch, one plan family per
+// (transform length, prime); items of at most 64 outputs are left alone
+pm_status learned_batch_plans(const std::vector<long>& lcs, const std::vector<int>& pidx, std::vector<Plan>* out);
+// the policy in force (capi.cpp)
+pm_policy current_policy();
+// time every candidate of one length in a context, record the rows, cache the best
+pm_status tune_one(DevCtx* c, long lc, int pidx, int reps, hipStream_t s, Plan* best_out, int tctx = kCtxSingle);
+
 // threads of the four-step row pass
 inline int plan_row_lnt(const Plan& P) {
   if (P.lnt) return P.lnt;

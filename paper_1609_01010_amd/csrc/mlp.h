@@ -6,7 +6,7 @@
 
 namespace pm {
 
-constexpr int kMlpF = 16;  // features
+constexpr int kMlpF = 17;  // features
 constexpr int kMlpH = 64;  // hidden width
 constexpr int kOffW1 = 0;
 constexpr int kOffB1 = kOffW1 + kMlpH * kMlpF;

@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <cstring>
 
+#include <map>
+
 #include "internal.h"
 #include "mlp.h"
 
@@ -22,8 +24,6 @@ std::vector<Plan> plan_candidates(long lc, int pidx);
 size_t plan_workspace_bytes(const Plan& P);
 pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const void* b, long lb, int in_type, u32* out,
                       long lc, int pidx, void* ws, hipStream_t s);
-void plan_cache_set(long lc, u32 p, const Plan& P);
-bool plan_cache_get(long lc, u32 p, Plan* P);
 Plan default_plan(long lc, int pidx);
 void plan_epoch_bump();
 
@@ -32,6 +32,7 @@ struct DbRow {
   u32 p;
   Plan plan;
   double us;
+  int tctx = kCtxSingle;  // timed alone (latency) or in a batch (time per product)
 };
 static std::mutex g_db_mu;
 static std::vector<DbRow> g_db;
@@ -39,7 +40,7 @@ static std::vector<DbRow> g_db;
 // ---------------------------------------------------------------------------
 // features of (length, prime, plan) for the cost model
 
-void plan_features(long lc, int pidx, const Plan& P, float* f) {
+void plan_features(long lc, int pidx, const Plan& P, int tctx, float* f) {
   const double nprime = P.kind == PLAN_DIRECT ? (double)lc : (double)plan_nprime(P);
   const double L = P.kind == PLAN_DIRECT ? (double)lc : (double)(1l << P.logL);
   const int rows = P.kind == PLAN_FOURSTEP ? (P.ma << P.logRB) : P.ma;
@@ -60,6 +61,9 @@ void plan_features(long lc, int pidx, const Plan& P, float* f) {
   f[13] = P.kind == PLAN_FOURSTEP ? (float)(P.logC - plan_row_lnt(P)) / 5.f : 0.f;
   f[14] = P.kind == PLAN_FOURSTEP ? (float)(P.logL - P.logC) / 10.f : 0.f;
   f[15] = P.kind == PLAN_DIRECT ? 0.f : (float)P.ma / (float)(1 << P.logRA);
+  // the context: a product alone is bound by its own parallelism, one of a
+  // batch by its work and traffic
+  f[16] = tctx == kCtxBatch ? 1.f : 0.f;
 }
 
 static double plan_nprime_d(long lc, const Plan& P) {
@@ -130,30 +134,142 @@ static pm_status time_plan(DevCtx* c, const Plan& P, long lc, int pidx, const Tu
   return PM_OK;
 }
 
-// Time every candidate of one length, record the rows, cache the best.
-// The caller holds the device lock.
-pm_status tune_one(DevCtx* c, long lc, int pidx, int reps, hipStream_t s, Plan* best_out) {
+// Batch context: `count` independent products of length lc (distinct
+// operands, outputs and workspaces), every pass one launch over all of them as
+// the batch executor runs a class, with count * L about 2^24: enough products
+// to keep the device full whatever the plan, as the other classes of a batch
+// do, so that the time per product measures throughput, not latency.
+struct BatchBufs {
+  int count = 0;
+  long la = 0, lb = 0, lc = 0;
+  u32 *a = nullptr, *b = nullptr, *c = nullptr, *ws = nullptr;
+  ConvJob* jobs = nullptr;
+  ~BatchBufs() {
+    for (void* q : {(void*)a, (void*)b, (void*)c, (void*)ws, (void*)jobs})
+      if (q) hipFree(q);
+  }
+};
+
+static int batch_count(long lc) {
+  long L = 1;
+  while (L < lc) L <<= 1;
+  const long n = (1l << 24) / L;
+  return (int)(n < 1 ? 1 : (n > 4096 ? 4096 : n));
+}
+
+static pm_status batch_inputs(long lc, u32 p, BatchBufs* T, hipStream_t s) {
+  T->count = batch_count(lc);
+  T->lc = lc;
+  T->la = (lc + 2) / 2;
+  T->lb = lc + 1 - T->la;
+  long L = 1;
+  while (L < lc) L <<= 1;
+  const size_t n = (size_t)T->count;
+  if (hipMalloc(&T->a, n * T->la * 4) || hipMalloc(&T->b, n * T->lb * 4) || hipMalloc(&T->c, n * lc * 4) ||
+      hipMalloc(&T->ws, n * 2 * (size_t)L * 4) || hipMalloc(&T->jobs, n * sizeof(ConvJob)))
+    return PM_ENOMEM;
+  const long na = (long)n * T->la, nb = (long)n * T->lb;
+  k_fill_mod<<<(unsigned)((na + 255) / 256), 256, 0, s>>>(T->a, na, p, 1);
+  k_fill_mod<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(T->b, nb, p, 2);
+  return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
+pm_status launch_class(const Plan& P, bool lazy, int in_type, const JobRef& jr, int njobs, int max_rows,
+                       hipStream_t s);
+pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
+                   long lc, u32* Ta, u32* Tb, ConvJob* J, int ring);
+
+// median time per product in microseconds of `reps` batch runs of plan P
+static pm_status time_plan_batch(DevCtx* c, const Plan& P, int pidx, const BatchBufs& B, int reps, hipStream_t s,
+                                 double* us) {
+  if (P.kind == PLAN_DIRECT) {  // the executor launches these one by one
+    std::vector<float> t;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) || hipEventCreate(&e1)) return PM_EDEVICE;
+    pm_status st = PM_OK;
+    for (int r = 0; r <= reps && st == PM_OK; ++r) {
+      hipEventRecord(e0, s);
+      for (int k = 0; k < B.count && st == PM_OK; ++k)
+        st = run_product(c, P, B.a + (long)k * B.la, B.la, B.b + (long)k * B.lb, B.lb, 0, B.c + (long)k * B.lc, B.lc,
+                         pidx, nullptr, s);
+      hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) st = PM_EDEVICE;
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r) t.push_back(ms);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    std::sort(t.begin(), t.end());
+    *us = 1e3 * t[t.size() / 2] / B.count;
+    return PM_OK;
+  }
+  const long np = plan_nprime(P);
+  std::vector<ConvJob> jobs(B.count);
+  int max_rows = 0;
+  for (int k = 0; k < B.count; ++k) {
+    u32* Ta = P.kind == PLAN_FOURSTEP ? B.ws + (size_t)k * 2 * np : nullptr;
+    u32* Tb = Ta ? Ta + np : nullptr;
+    pm_status st = make_job(c, P, pidx, B.a + (long)k * B.la, B.la, B.b + (long)k * B.lb, B.lb, B.c + (long)k * B.lc,
+                            B.lc, Ta, Tb, &jobs[k], 0);
+    if (st) return st;
+    max_rows = std::max(max_rows, jobs[k].rows);
+  }
+  if (hipMemcpyAsync(B.jobs, jobs.data(), jobs.size() * sizeof(ConvJob), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return PM_EDEVICE;
+  JobRef jr;
+  jr.one = jobs[0];
+  jr.many = B.jobs;
+  const bool lazy = prime_info(pidx).lazy;
+  pm_status st = launch_class(P, lazy, 0, jr, B.count, max_rows, s);
+  if (st) return st;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) || hipEventCreate(&e1)) return PM_EDEVICE;
+  std::vector<float> t;
+  for (int r = 0; r < reps && st == PM_OK; ++r) {
+    hipEventRecord(e0, s);
+    st = launch_class(P, lazy, 0, jr, B.count, max_rows, s);
+    hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) st = PM_EDEVICE;
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    t.push_back(ms);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) return st;
+  std::sort(t.begin(), t.end());
+  *us = 1e3 * (t.size() % 2 ? t[t.size() / 2] : 0.5 * (t[t.size() / 2 - 1] + t[t.size() / 2])) / B.count;
+  return PM_OK;
+}
+
+// Time every candidate of one length in context tctx, record the rows, cache
+// the best.  The caller holds the device lock.
+pm_status tune_one(DevCtx* c, long lc, int pidx, int reps, hipStream_t s, Plan* best_out, int tctx) {
   const u32 p = prime_info(pidx).p;
   TuneBufs B;
-  pm_status st = tune_inputs(lc, p, &B, s);
+  BatchBufs BB;
+  pm_status st = tctx == kCtxBatch ? batch_inputs(lc, p, &BB, s) : tune_inputs(lc, p, &B, s);
   if (st) return st;
   std::vector<Plan> cands = plan_candidates(lc, pidx);
   double best = 1e300;
   Plan bestP = default_plan(lc, pidx);
   for (const Plan& P : cands) {
     double us = 0;
-    st = time_plan(c, P, lc, pidx, B, reps, s, &us);
+    st = tctx == kCtxBatch ? time_plan_batch(c, P, pidx, BB, reps, s, &us) : time_plan(c, P, lc, pidx, B, reps, s, &us);
     if (st) return st;
     {
       std::lock_guard<std::mutex> lk(g_db_mu);
-      g_db.push_back(DbRow{lc, p, P, us});
+      g_db.push_back(DbRow{lc, p, P, us, tctx});
     }
     if (us < best) {
       best = us;
       bestP = P;
     }
   }
-  plan_cache_set(lc, p, bestP);
+  plan_cache_set(lc, p, bestP, tctx);
   if (best_out) *best_out = bestP;
   return PM_OK;
 }
@@ -170,7 +286,7 @@ static std::mutex g_model_mu;
 static Model g_model;
 
 // predicted log(us) of each plan for (lc, pidx); the caller holds no locks
-static pm_status model_predict(long lc, int pidx, const std::vector<Plan>& plans, std::vector<double>* out) {
+static pm_status model_predict(long lc, int pidx, const std::vector<Plan>& plans, int tctx, std::vector<double>* out) {
   Model M;
   {
     std::lock_guard<std::mutex> lk(g_model_mu);
@@ -179,7 +295,7 @@ static pm_status model_predict(long lc, int pidx, const std::vector<Plan>& plans
   }
   const int B = (int)plans.size();
   std::vector<float> X((size_t)B * kMlpF), y(B);
-  for (int i = 0; i < B; ++i) plan_features(lc, pidx, plans[i], &X[(size_t)i * kMlpF]);
+  for (int i = 0; i < B; ++i) plan_features(lc, pidx, plans[i], tctx, &X[(size_t)i * kMlpF]);
   pm_status st = pm_mlp_forward(M.w.data(), X.data(), B, y.data());
   if (st) return st;
   out->resize(B);
@@ -187,16 +303,82 @@ static pm_status model_predict(long lc, int pidx, const std::vector<Plan>& plans
   return PM_OK;
 }
 
-Plan learned_plan(long lc, int pidx, bool* ok) {
+Plan learned_plan(long lc, int pidx, bool* ok, int tctx) {
   *ok = false;
   std::vector<Plan> cands = plan_candidates(lc, pidx);
   std::vector<double> pred;
-  if (cands.empty() || model_predict(lc, pidx, cands, &pred) != PM_OK) return Plan();
+  if (cands.empty() || model_predict(lc, pidx, cands, tctx, &pred) != PM_OK) return Plan();
   size_t bi = 0;
   for (size_t i = 1; i < cands.size(); ++i)
     if (pred[i] < pred[bi]) bi = i;
   *ok = true;
   return cands[bi];
+}
+
+// Plans for the products of one batch, chosen per size class: the items of
+// one transform length L and prime share one plan family (every plan
+// parameter but the kept blocks ma, which follow each item's length), the one
+// whose predicted times, summed over the items, are least.  Chosen item by
+// item, neighbouring lengths scatter over many plan variants, and the
+// executor would launch each variant as a class of its own.
+pm_status learned_batch_plans(const std::vector<long>& lcs, const std::vector<int>& pidx, std::vector<Plan>* out) {
+  Model M;
+  {
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    if (!g_model.ok) return PM_EINVAL;
+    M = g_model;
+  }
+  out->assign(lcs.size(), Plan());
+  std::map<std::pair<int, int>, std::vector<size_t>> groups;  // (log L, prime) -> items
+  for (size_t i = 0; i < lcs.size(); ++i) {
+    if (lcs[i] <= 64) continue;
+    int l = 0;
+    while ((1l << l) < lcs[i]) ++l;
+    groups[std::make_pair(l, pidx[i])].push_back(i);
+  }
+  for (auto& g : groups) {
+    const std::vector<size_t>& items = g.second;
+    const int pid = g.first.second;
+    // families from the candidates of the longest item (its kept blocks are
+    // the most, so every family valid for it is valid for the others)
+    size_t rep = items[0];
+    for (size_t i : items)
+      if (lcs[i] > lcs[rep]) rep = i;
+    std::vector<Plan> fams;
+    for (const Plan& P : plan_candidates(lcs[rep], pid)) {
+      Plan F = P;
+      F.ma = P.ma == (1 << P.logRA) ? 0 : -1;  // 0: all blocks kept, -1: the item's own kept blocks
+      bool dup = false;
+      for (const Plan& Q : fams)
+        dup |= Q.kind == F.kind && Q.logRA == F.logRA && Q.logRB == F.logRB && Q.logC == F.logC && Q.lq == F.lq &&
+               Q.lnt == F.lnt && Q.ma == F.ma;
+      if (!dup) fams.push_back(F);
+    }
+    auto item_plan = [&](const Plan& F, long lc) {
+      Plan P = F;
+      const long gran = 1l << (P.logL - P.logRA);
+      P.ma = F.ma == 0 ? (1 << P.logRA) : (int)((lc + gran - 1) / gran);
+      return P;
+    };
+    const size_t nf = fams.size(), B = items.size() * nf;
+    std::vector<float> X(B * kMlpF), y(B);
+    for (size_t k = 0; k < items.size(); ++k)
+      for (size_t f = 0; f < nf; ++f)
+        plan_features(lcs[items[k]], pid, item_plan(fams[f], lcs[items[k]]), kCtxBatch, &X[(k * nf + f) * kMlpF]);
+    pm_status st = pm_mlp_forward(M.w.data(), X.data(), (int)B, y.data());
+    if (st) return st;
+    std::vector<double> total(nf, 0.0);
+    for (size_t k = 0; k < items.size(); ++k)
+      for (size_t f = 0; f < nf; ++f) {
+        const Plan P = item_plan(fams[f], lcs[items[k]]);
+        total[f] += std::exp((double)y[k * nf + f] * M.std + M.mean) * plan_nprime_d(lcs[items[k]], P);
+      }
+    size_t bf = 0;
+    for (size_t f = 1; f < nf; ++f)
+      if (total[f] < total[bf]) bf = f;
+    for (size_t i : items) (*out)[i] = item_plan(fams[bf], lcs[i]);
+  }
+  return PM_OK;
 }
 
 static pm_plan to_pub(const Plan& P) {
@@ -239,7 +421,11 @@ using namespace pm;
 extern "C" {
 
 pm_status pm_tune(const size_t* lcs, size_t n, uint32_t p, int reps, void* stream) {
-  if (!lcs || reps < 1) return PM_EINVAL;
+  return pm_tune_ctx(lcs, n, p, reps, PM_CTX_SINGLE, stream);
+}
+
+pm_status pm_tune_ctx(const size_t* lcs, size_t n, uint32_t p, int reps, int context, void* stream) {
+  if (!lcs || reps < 1 || (context != PM_CTX_SINGLE && context != PM_CTX_BATCH)) return PM_EINVAL;
   const int pidx = prime_index(p);
   if (pidx < 0) return PM_EUNSUPPORTED;
   for (size_t i = 0; i < n; ++i) {
@@ -253,14 +439,19 @@ pm_status pm_tune(const size_t* lcs, size_t n, uint32_t p, int reps, void* strea
   if (!c) return st;
   std::lock_guard<std::mutex> lk(c->mu);
   for (size_t i = 0; i < n; ++i) {
-    st = tune_one(c, (long)lcs[i], pidx, reps, (hipStream_t)stream, nullptr);
+    st = tune_one(c, (long)lcs[i], pidx, reps, (hipStream_t)stream, nullptr, context);
     if (st) return st;
   }
   return PM_OK;
 }
 
 pm_status pm_time_plan(size_t lc, uint32_t p, const pm_plan* plan, int reps, double* us) {
-  if (!plan || !us || lc == 0 || reps < 1) return PM_EINVAL;
+  return pm_time_plan_ctx(lc, p, plan, reps, PM_CTX_SINGLE, us);
+}
+
+pm_status pm_time_plan_ctx(size_t lc, uint32_t p, const pm_plan* plan, int reps, int context, double* us) {
+  if (!plan || !us || lc == 0 || reps < 1 || (context != PM_CTX_SINGLE && context != PM_CTX_BATCH))
+    return PM_EINVAL;
   const int pidx = prime_index(p);
   if (pidx < 0) return PM_EUNSUPPORTED;
   Plan P = from_pub(*plan);
@@ -269,6 +460,12 @@ pm_status pm_time_plan(size_t lc, uint32_t p, const pm_plan* plan, int reps, dou
   DevCtx* c = ctx_current(&st);
   if (!c) return st;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (context == PM_CTX_BATCH) {
+    BatchBufs BB;
+    st = batch_inputs((long)lc, p, &BB, 0);
+    if (st) return st;
+    return time_plan_batch(c, P, pidx, BB, reps, 0, us);
+  }
   TuneBufs B;
   st = tune_inputs((long)lc, p, &B, 0);
   if (st) return st;
@@ -280,21 +477,22 @@ size_t pm_tune_db_size(void) {
   return g_db.size();
 }
 
-pm_status pm_tune_db_get(size_t i, size_t* lc, uint32_t* p, pm_plan* plan, double* us) {
+pm_status pm_tune_db_get(size_t i, size_t* lc, uint32_t* p, pm_plan* plan, double* us, int* context) {
   std::lock_guard<std::mutex> lk(g_db_mu);
   if (i >= g_db.size()) return PM_EINVAL;
   if (lc) *lc = (size_t)g_db[i].lc;
   if (p) *p = g_db[i].p;
   if (plan) *plan = to_pub(g_db[i].plan);
   if (us) *us = g_db[i].us;
+  if (context) *context = g_db[i].tctx;
   return PM_OK;
 }
 
-pm_status pm_tune_db_add(size_t lc, uint32_t p, const pm_plan* plan, double us) {
-  if (!plan || lc == 0) return PM_EINVAL;
+pm_status pm_tune_db_add(size_t lc, uint32_t p, const pm_plan* plan, double us, int context) {
+  if (!plan || lc == 0 || (context != PM_CTX_SINGLE && context != PM_CTX_BATCH)) return PM_EINVAL;
   if (prime_index(p) < 0) return PM_EUNSUPPORTED;
   std::lock_guard<std::mutex> lk(g_db_mu);
-  g_db.push_back(DbRow{(long)lc, p, from_pub(*plan), us});
+  g_db.push_back(DbRow{(long)lc, p, from_pub(*plan), us, context});
   return PM_OK;
 }
 
@@ -308,10 +506,10 @@ pm_status pm_tune_db_save(const char* path) {
   FILE* f = fopen(path, "w");
   if (!f) return PM_EINVAL;
   std::lock_guard<std::mutex> lk(g_db_mu);
-  fprintf(f, "# lc p kind log_l log_ra log_rb log_c ma lq lnt us\n");
+  fprintf(f, "# lc p kind log_l log_ra log_rb log_c ma lq lnt us context\n");
   for (auto& r : g_db)
-    fprintf(f, "%ld %u %d %d %d %d %d %d %d %d %.4f\n", r.lc, r.p, r.plan.kind, r.plan.logL, r.plan.logRA,
-            r.plan.logRB, r.plan.logC, r.plan.ma, r.plan.lq, r.plan.lnt, r.us);
+    fprintf(f, "%ld %u %d %d %d %d %d %d %d %d %.4f %d\n", r.lc, r.p, r.plan.kind, r.plan.logL, r.plan.logRA,
+            r.plan.logRB, r.plan.logC, r.plan.ma, r.plan.lq, r.plan.lnt, r.us, r.tctx);
   fclose(f);
   return PM_OK;
 }
@@ -325,8 +523,10 @@ pm_status pm_tune_db_load(const char* path) {
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
     DbRow r;
-    if (sscanf(line, "%ld %u %d %d %d %d %d %d %d %d %lf", &r.lc, &r.p, &r.plan.kind, &r.plan.logL, &r.plan.logRA,
-               &r.plan.logRB, &r.plan.logC, &r.plan.ma, &r.plan.lq, &r.plan.lnt, &r.us) != 11) {
+    const int got = sscanf(line, "%ld %u %d %d %d %d %d %d %d %d %lf %d", &r.lc, &r.p, &r.plan.kind, &r.plan.logL,
+                           &r.plan.logRA, &r.plan.logRB, &r.plan.logC, &r.plan.ma, &r.plan.lq, &r.plan.lnt, &r.us,
+                           &r.tctx);
+    if (got < 11 || (got == 12 && r.tctx != kCtxSingle && r.tctx != kCtxBatch)) {  // 11 fields: a single-context row
       fclose(f);
       return PM_EINVAL;
     }
@@ -343,11 +543,11 @@ pm_status pm_tune_db_load(const char* path) {
   return PM_OK;
 }
 
-pm_status pm_model_features(size_t lc, uint32_t p, const pm_plan* plan, float* out) {
-  if (!plan || !out || lc == 0) return PM_EINVAL;
+pm_status pm_model_features(size_t lc, uint32_t p, const pm_plan* plan, int context, float* out) {
+  if (!plan || !out || lc == 0 || (context != PM_CTX_SINGLE && context != PM_CTX_BATCH)) return PM_EINVAL;
   const int pidx = prime_index(p);
   if (pidx < 0) return PM_EUNSUPPORTED;
-  plan_features((long)lc, pidx, from_pub(*plan), out);
+  plan_features((long)lc, pidx, from_pub(*plan), context, out);
   return PM_OK;
 }
 
@@ -365,7 +565,7 @@ pm_status pm_model_train(const float* init, int steps, float lr, float* losses) 
   std::vector<double> raw(B);
   for (int i = 0; i < B; ++i) {
     const int pidx = prime_index(rows[i].p);
-    plan_features(rows[i].lc, pidx, rows[i].plan, &X[(size_t)i * kMlpF]);
+    plan_features(rows[i].lc, pidx, rows[i].plan, rows[i].tctx, &X[(size_t)i * kMlpF]);
     raw[i] = std::log(rows[i].us) - std::log(plan_nprime_d(rows[i].lc, rows[i].plan));
     mean += raw[i];
   }
@@ -415,14 +615,15 @@ pm_status pm_model_set(const float* params, float mean, float sd) {
   return PM_OK;
 }
 
-pm_status pm_model_predict(size_t lc, uint32_t p, const pm_plan* plans, size_t n, double* log_us) {
-  if (!plans || !log_us || lc == 0 || n == 0) return PM_EINVAL;
+pm_status pm_model_predict(size_t lc, uint32_t p, const pm_plan* plans, size_t n, int context, double* log_us) {
+  if (!plans || !log_us || lc == 0 || n == 0 || (context != PM_CTX_SINGLE && context != PM_CTX_BATCH))
+    return PM_EINVAL;
   const int pidx = prime_index(p);
   if (pidx < 0) return PM_EUNSUPPORTED;
   std::vector<Plan> v(n);
   for (size_t i = 0; i < n; ++i) v[i] = from_pub(plans[i]);
   std::vector<double> out;
-  pm_status st = model_predict((long)lc, pidx, v, &out);
+  pm_status st = model_predict((long)lc, pidx, v, context, &out);
   if (st) return st;
   for (size_t i = 0; i < n; ++i) log_us[i] = out[i];
   return PM_OK;
@@ -434,7 +635,7 @@ pm_status pm_model_save(const char* path) {
   if (!g_model.ok) return PM_EINVAL;
   FILE* f = fopen(path, "w");
   if (!f) return PM_EINVAL;
-  fprintf(f, "polymul-cost-model v1 features=%d hidden=%d params=%d\n%.9g %.9g\n", kMlpF, kMlpH, kMlpParams,
+  fprintf(f, "polymul-cost-model v2 features=%d hidden=%d params=%d\n%.9g %.9g\n", kMlpF, kMlpH, kMlpParams,
           g_model.mean, g_model.std);
   for (float x : g_model.w) fprintf(f, "%.9g\n", x);
   fclose(f);
@@ -447,7 +648,7 @@ pm_status pm_model_load(const char* path) {
   if (!f) return PM_EINVAL;
   int nf = 0, nh = 0, np = 0;
   Model M;
-  if (fscanf(f, "polymul-cost-model v1 features=%d hidden=%d params=%d", &nf, &nh, &np) != 3 || nf != kMlpF ||
+  if (fscanf(f, "polymul-cost-model v2 features=%d hidden=%d params=%d", &nf, &nh, &np) != 3 || nf != kMlpF ||
       nh != kMlpH || np != kMlpParams || fscanf(f, "%f %f", &M.mean, &M.std) != 2) {
     fclose(f);
     return PM_EINVAL;

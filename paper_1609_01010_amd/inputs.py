@@ -163,7 +163,7 @@ def split_output_length(lc: int):
 
 # --- cost-model initial weights -------------------------------------------------
 
-MLP_F, MLP_H = 16, 64
+MLP_F, MLP_H = 17, 64
 
 
 def mlp_init(tag=7):

@@ -2,22 +2,28 @@
 
 1. The tuner times every candidate plan of each training length (every power
    of two 2^10..2^20 plus 300 non-power-of-two lengths log-uniform in
-   [2^10, 2^20]) and records the timing database.
-2. The cost model is trained on those rows by the library's own kernels.
+   [2^10, 2^20]), for each of the four primes, in both timing contexts: a
+   product on its own, and the time per product of a batch of about 2^24 / L
+   products of the length (enough to keep the device full).
+2. The cost model is trained on all those rows by the library's own kernels;
+   the context is one of its features.
 3. On the held-out lengths (2^21..2^24 plus 200 non-power-of-two lengths
-   log-uniform in [2^10, 2^24]) the model's pick is compared with the fastest
-   plan found by timing every candidate (exhaustive search), and with the
-   default plan (the library without the model).
+   log-uniform in [2^10, 2^24]), in each context, the model's pick is
+   compared with the fastest plan found by timing every candidate (exhaustive
+   search), and with the default plan (the library without the model).
+4. The 4096-product batch is timed with the default plans, with the model's
+   picks for the batch context (what the batch executor uses), and with the
+   model's picks for products on their own forced onto the batch.
 
 Regret of a length = t(pick) / t(best) - 1.  The exhaustive pass takes the
 median of `reps` runs per candidate; the minimum over many noisy candidates
 is biased low, so the pick, the best and the default plan are then re-timed
 interleaved (three rounds of `reps` runs each, median of the three medians)
-and the regret is computed from those.  Reported: the geometric mean of
-(1 + regret) - 1 over the held-out set, the maximum, the fraction at or below
-5%, and the gain of the learned policy over the default one (geometric mean
-of t(default) / t(pick)).  All products use p = 2013265921 (transforms up to
-2^27 exist for it).
+and the regret is computed from those.  Reported per context: the geometric
+mean of (1 + regret) - 1 over the held-out set, the maximum, the fraction at
+or below 5%, and the gain of the learned policy over the default one
+(geometric mean of t(default) / t(pick)).  The held-out products of step 3
+use p = 2013265921 (transforms up to 2^27 exist for it).
 
     python -m paper_1609_01010_amd.learned_eval --out DIR [--reps 5] [--quick]
 """
@@ -48,7 +54,11 @@ def geomean(xs):
 
 
 def run(out_dir: str, reps: int = 5, steps: int = 3000, lr: float = 3e-3, quick: bool = False):
+    import torch
+
     import paper_1609_01010_amd as pm
+
+    torch.zeros(1, device="cuda")  # torch takes the device before the library does (the batch step uses both)
 
     os.makedirs(out_dir, exist_ok=True)
     pm.lib()
@@ -59,60 +69,129 @@ def run(out_dir: str, reps: int = 5, steps: int = 3000, lr: float = 3e-3, quick:
     train = inputs.tuning_lengths(n_random=n_train_rnd)
     held = inputs.heldout_lengths(n_random=n_held_rnd, exclude=train)
     t0 = time.time()
-    for i in range(0, len(train), 16):
-        pm.tune(train[i:i + 16], P, reps=reps)
-        log(f"tuned {min(i + 16, len(train))}/{len(train)} training lengths ({time.time() - t0:.0f} s)")
+    for ctx, cname in ((pm.CTX_SINGLE, "single"), (pm.CTX_BATCH, "batch")):
+        for q in inputs.PRIME_LIST:
+            for i in range(0, len(train), 32):
+                pm.tune(train[i:i + 32], q, reps=reps, context=ctx)
+            log(f"tuned {len(train)} training lengths mod {q}, {cname} ({time.time() - t0:.0f} s)")
+    pm.plan_cache_clear()
     pm.tune_db_save(os.path.join(out_dir, "tuning_db.txt"))
-    rows = pm.tune_db_rows()
+    n_rows = {c: len(pm.tune_db_rows(c)) for c in (pm.CTX_SINGLE, pm.CTX_BATCH)}
     losses = pm.model_train(inputs.mlp_init(), steps=steps, lr=lr)
-    log(f"trained on {len(rows)} rows: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    log(f"trained on {sum(n_rows.values())} rows: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     pm.model_save(os.path.join(out_dir, "cost_model.txt"))
 
-    recs = []
-    for k, lc in enumerate(held):
-        cands = pm.plan_candidates(lc, P)
-        pred = pm.model_predict(lc, P, cands)
-        pick = cands[int(np.argmin(pred))]
-        default = pm.plan_for(lc, P)  # the default policy (nothing cached for held-out lengths)
-        times = [pm.time_plan(lc, P, Q, reps=reps) for Q in cands]
-        best = int(np.argmin(times))
-        trio = {"pick": pick, "best": cands[best], "default": default}
-        rt = {k: [] for k in trio}
-        for _ in range(3):
-            for name, Q in trio.items():
-                rt[name].append(pm.time_plan(lc, P, Q, reps=reps))
-        t_pick, t_best, t_def = (float(np.median(rt[name])) for name in ("pick", "best", "default"))
-        recs.append({
-            "lc": lc, "candidates": len(cands), "t_best_us": t_best, "t_pick_us": t_pick,
-            "t_default_us": t_def, "regret": max(t_pick / t_best - 1.0, 0.0),
-            "regret_first_pass": times[int(np.argmin(pred))] / times[best] - 1.0,
-            "best": list(cands[best].as_tuple()), "pick": list(pick.as_tuple()),
-            "pred_err_log": float(pred[int(np.argmin(pred))] - math.log(t_pick)),
-        })
-        if k % 10 == 0 or k < 4:
-            log(f"held-out {k + 1}/{len(held)} lc={lc}: regret {recs[-1]['regret']:.3f} "
-                f"best {times[best]:.1f} us pick {t_pick:.1f} us default {t_def:.1f} us")
-    reg = [r["regret"] for r in recs]
+    recs = {}
+    for ctx, cname in ((pm.CTX_SINGLE, "single"), (pm.CTX_BATCH, "batch")):
+        recs[cname] = []
+        for k, lc in enumerate(held):
+            cands = pm.plan_candidates(lc, P)
+            pred = pm.model_predict(lc, P, cands, context=ctx)
+            ipick = int(np.argmin(pred))
+            pick = cands[ipick]
+            default = pm.plan_for(lc, P)  # the default policy (nothing cached for held-out lengths)
+            pm.tune_db_clear()
+            pm.tune([lc], P, reps=reps, context=ctx)
+            timed = {tuple(Q.as_tuple()): us for (_, _, Q, us) in pm.tune_db_rows(ctx)}
+            pm.plan_cache_clear()
+            times = [timed[tuple(Q.as_tuple())] for Q in cands]
+            best = int(np.argmin(times))
+            trio = {"pick": pick, "best": cands[best], "default": default}
+            rt = {name: [] for name in trio}
+            for _ in range(3):
+                for name, Q in trio.items():
+                    rt[name].append(pm.time_plan(lc, P, Q, reps=reps, context=ctx))
+            t_pick, t_best, t_def = (float(np.median(rt[name])) for name in ("pick", "best", "default"))
+            recs[cname].append({
+                "lc": lc, "candidates": len(cands), "t_best_us": t_best, "t_pick_us": t_pick,
+                "t_default_us": t_def, "regret": max(t_pick / t_best - 1.0, 0.0),
+                "regret_first_pass": times[ipick] / times[best] - 1.0,
+                "best": list(cands[best].as_tuple()), "pick": list(pick.as_tuple()),
+                "pred_err_log": float(pred[ipick] - math.log(t_pick)),
+            })
+            if k % 20 == 0 or k < 2:
+                r = recs[cname][-1]
+                log(f"held-out {cname} {k + 1}/{len(held)} lc={lc}: regret {r['regret']:.3f} "
+                    f"best {times[best]:.1f} us pick {t_pick:.1f} us default {t_def:.1f} us")
+    pm.tune_db_clear()
+
+    def ctx_summary(rs):
+        reg = [r["regret"] for r in rs]
+        return {
+            "regret_geomean": geomean([1 + r for r in reg]) - 1,
+            "regret_max": float(max(reg)),
+            "regret_frac_le_5pct": float(np.mean([r <= 0.05 for r in reg])),
+            "gain_vs_default_geomean": geomean([r["t_default_us"] / r["t_pick_us"] for r in rs]),
+            "default_regret_geomean": geomean([max(r["t_default_us"] / r["t_best_us"], 1.0) for r in rs]) - 1,
+            "regret_first_pass_geomean": geomean([1 + max(r["regret_first_pass"], 0.0) for r in rs]) - 1,
+        }
+
+    single = ctx_summary(recs["single"])
     summary = {
         "prime": P,
         "train_lengths": len(train),
-        "train_rows": len(rows),
+        "train_rows": n_rows[pm.CTX_SINGLE],
+        "train_rows_batch": n_rows[pm.CTX_BATCH],
         "heldout_lengths": len(held),
         "loss_first": float(losses[0]),
         "loss_last": float(losses[-1]),
-        "regret_geomean": geomean([1 + r for r in reg]) - 1,
-        "regret_max": float(max(reg)),
-        "regret_frac_le_5pct": float(np.mean([r <= 0.05 for r in reg])),
-        "gain_vs_default_geomean": geomean([r["t_default_us"] / r["t_pick_us"] for r in recs]),
-        "default_regret_geomean": geomean([max(r["t_default_us"] / r["t_best_us"], 1.0) for r in recs]) - 1,
-        "regret_first_pass_geomean": geomean([1 + max(r["regret_first_pass"], 0.0) for r in recs]) - 1,
-        "pow2_heldout": [r for r in recs if r["lc"] & (r["lc"] - 1) == 0],
+        **single,
+        "batch_context": ctx_summary(recs["batch"]),
+        "uneven_batch_4096": batch_policies(pm, reps),
         "wall_s": time.time() - t0,
     }
     with open(os.path.join(out_dir, "learned_eval.json"), "w") as f:
-        json.dump({"summary": summary, "heldout": recs}, f, indent=1)
-    log(json.dumps({k: v for k, v in summary.items() if k != "pow2_heldout"}))
+        json.dump({"summary": summary, "heldout": recs["single"], "heldout_batch": recs["batch"]}, f, indent=1)
+    log(json.dumps(summary))
     return summary
+
+
+def batch_policies(pm, reps: int):
+    """The 4096 uneven products (four primes) as one batch, with three plan
+    choices: the default plans, the model's picks for the batch context (what
+    pm_poly_mul_batch uses under the learned policy), and the model's picks for
+    products on their own forced onto the batch (plan cache)."""
+    import torch
+
+    items = inputs.batch_uneven()
+    dev = torch.device("cuda")
+    probs = [(torch.from_numpy(it.a).to(dev), torch.from_numpy(it.b).to(dev), it.p) for it in items]
+    outs = [torch.empty(it.a.size + it.b.size - 1, dtype=torch.uint32, device=dev) for it in items]
+
+    def timed():
+        pb = pm.PreparedBatch(probs, outs=outs)
+        pb.run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(7, reps)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pb.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    out = {}
+    pm.plan_cache_clear()
+    pm.set_policy(pm.POLICY_DEFAULT)
+    out["default_ms"] = timed()
+    pm.set_policy(pm.POLICY_LEARNED)
+    pm.plan_cache_clear()
+    out["learned_batch_context_ms"] = timed()
+    pm.plan_cache_clear()
+    for it in items:
+        lc = it.a.size + it.b.size - 1
+        if lc > 64:
+            pm.plan_cache_put(lc, it.p, pm.plan_for(lc, it.p))  # the single-context pick
+    out["learned_single_context_ms"] = timed()
+    pm.plan_cache_clear()
+    pm.set_policy(pm.POLICY_DEFAULT)
+    if pm.stream_check() != 0:
+        raise SystemExit("device error in the batch")
+    log(f"4096 uneven products: {json.dumps(out)}")
+    return out
 
 
 def main(argv=None):

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -105,6 +106,41 @@ def test_workspace_queries_on_host(L):
         want += (n.value + 255) // 256 * 256
     assert L.pm_batch_workspace_query(probs, len(lens), ctypes.byref(n)) == 0
     assert n.value == want and want > 0
+
+
+def test_tuning_database_contexts_round_trip(tmp_path):
+    """Rows of both timing contexts survive save and load; a row written
+    without the context column loads as a single-product row."""
+    import paper_1609_01010_amd as pm
+
+    pm.tune_db_clear()
+    P1 = pm.plan_candidates(70001, 998244353)[0]
+    P2 = pm.plan_candidates(3000, 2013265921)[-1]
+    pm.tune_db_add(70001, 998244353, P1, 12.5, pm.CTX_SINGLE)
+    pm.tune_db_add(3000, 2013265921, P2, 3.25, pm.CTX_BATCH)
+    path = str(tmp_path / "db.txt")
+    pm.tune_db_save(path)
+    pm.tune_db_clear()
+    with open(path, "a") as f:
+        f.write("70001 998244353 " + " ".join(str(v) for v in P1.as_tuple()) + " 11.0000\n")
+    pm.tune_db_load(path)
+    single, batch = pm.tune_db_rows(pm.CTX_SINGLE), pm.tune_db_rows(pm.CTX_BATCH)
+    assert [(r[0], r[1], r[2].as_tuple(), r[3]) for r in single] == [(70001, 998244353, P1.as_tuple(), 12.5),
+                                                                     (70001, 998244353, P1.as_tuple(), 11.0)]
+    assert [(r[0], r[1], r[2].as_tuple(), r[3]) for r in batch] == [(3000, 2013265921, P2.as_tuple(), 3.25)]
+    with pytest.raises(pm.PolymulError):
+        pm.tune_db_add(3000, 2013265921, P2, 1.0, 7)  # no such context
+    pm.tune_db_clear()
+
+
+def test_features_carry_the_context():
+    import paper_1609_01010_amd as pm
+
+    P = pm.plan_candidates(70001, 998244353)[0]
+    f0 = pm.model_features(70001, 998244353, P, pm.CTX_SINGLE)
+    f1 = pm.model_features(70001, 998244353, P, pm.CTX_BATCH)
+    assert f0.size == 17 and f0[16] == 0.0 and f1[16] == 1.0
+    assert np.array_equal(f0[:16], f1[:16])
 
 
 def test_granularity(L):

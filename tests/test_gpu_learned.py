@@ -112,6 +112,39 @@ def test_tuner_records_every_candidate_and_caches_the_best(gpu_lib):
     pm.plan_cache_clear()
 
 
+def test_batch_context_tuning_drives_the_batch(gpu_lib):
+    """Tuning in the batch context times each candidate as a batch of
+    products (rows recorded with that context, the best in the batch
+    context's cache); pm_poly_mul_batch then runs those plans, exactly."""
+    import torch
+
+    pm = gpu_lib
+    p = 998244353
+    pm.tune_db_clear()
+    pm.plan_cache_clear()
+    lcs = [3000, 70001]
+    pm.tune(lcs, p, reps=3, context=pm.CTX_BATCH)
+    assert pm.tune_db_rows(pm.CTX_SINGLE) == []
+    rows = pm.tune_db_rows(pm.CTX_BATCH)
+    for lc in lcs:
+        mine = [r for r in rows if r[0] == lc]
+        assert len(mine) == len(pm.plan_candidates(lc, p)) and all(r[3] > 0 for r in mine)
+        best = min(mine, key=lambda r: r[3])[2]
+        # per-product time of the best plan, timed again in the batch context
+        assert pm.time_plan(lc, p, best, reps=3, context=pm.CTX_BATCH) > 0
+    items = []
+    for k in range(6):
+        for lc in lcs:
+            la, lb = inputs.split_output_length(lc)
+            items.append(inputs.poly_pair((112, lc, k), la, lb, p))
+    outs = pm.poly_mul_batch([(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), p) for a, b in items])
+    assert pm.stream_check() == 0
+    for (a, b), c in zip(items, outs):
+        assert np.array_equal(c.cpu().numpy(), op.poly_mul(a, b, p))
+    pm.tune_db_clear()
+    pm.plan_cache_clear()
+
+
 def test_learned_policy_trains_predicts_and_stays_exact(gpu_lib, tmp_path):
     """A small version of the learned-plan experiment: tune a few lengths,
     train the network on the device, pick plans for unseen lengths; the
