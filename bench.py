@@ -90,6 +90,15 @@ def cpu_baseline(a2, b2, a3, b3, target_s=10.0):
     op.poly_mul_ntt(a3, b3, P, G)
     dt_ntt = time.perf_counter() - t0
     lc_step = a2.size + b2.size - 1 + a3.size + b3.size - 1
+    # the oracle's integer product (CPython int, one thread) on the first 2^17
+    # limbs of the two 2^21-limb operands
+    from paper_1609_01010_amd import inputs
+
+    ia, ib = inputs.int_operands()
+    n17 = 1 << 17
+    t0 = time.perf_counter()
+    op.int_mul(ia[:n17], ib[:n17])
+    dt_int = time.perf_counter() - t0
     return {
         "value": cnt / dt,
         "unit": "coeffs/s",
@@ -99,6 +108,8 @@ def cpu_baseline(a2, b2, a3, b3, target_s=10.0):
                   f"product) by the schoolbook sum c_k = sum a_i b_(k-i) mod p, OpenMP over k; {dt:.1f} s",
         "ntt_route": {"value": lc_step / dt_ntt, "unit": "coeffs/s", "cores": threads,
                       "sample": f"one whole step (both products) by the oracle's radix-2 transforms; {dt_ntt:.2f} s"},
+        "int_mul_route": {"value": 2 * n17 / dt_int, "unit": "limbs/s", "cores": 1,
+                          "sample": f"2^17 x 2^17 16-bit limbs by CPython's int multiply; {dt_int:.2f} s"},
     }
 
 

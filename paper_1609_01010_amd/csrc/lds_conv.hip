@@ -115,9 +115,12 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
   }
 }
 
-// threads of the one-work-group convolution of length 2^ln
-inline int lds_conv_threads(int ln) {
-  int nthr = (1 << ln) / 16;
+// threads of the one-work-group convolution of length 2^ln: 16 values per
+// thread in a batch (several work-groups share a compute unit), 4 for a
+// product on its own, which has the compute unit to itself and is bound by
+// the latency of its rounds
+inline int lds_conv_threads(int ln, int njobs) {
+  int nthr = (1 << ln) / (njobs == 1 ? 4 : 16);
   return nthr < 64 ? 64 : (nthr > 1024 ? 1024 : nthr);
 }
 
@@ -127,7 +130,7 @@ static hipError_t lds_conv_inst(const JobRef& jr, int njobs, hipStream_t s) {
   const size_t lds = 2 * (size_t)N * sizeof(u32);
   auto kern = k_lds_conv<LN, LRA, 4, kLazy, TWIST>;
   ensure_lds_attr((const void*)kern, lds);
-  return launch("lds_conv", kern, dim3(1, 1, njobs), lds_conv_threads(LN), lds, s, jr);
+  return launch("lds_conv", kern, dim3(1, 1, njobs), lds_conv_threads(LN, njobs), lds, s, jr);
 }
 
 // the nega-circular products (twisted) use the first radix 16 only
