@@ -145,6 +145,40 @@ def test_batch_context_tuning_drives_the_batch(gpu_lib):
     pm.plan_cache_clear()
 
 
+def test_learned_batch_policy_stays_exact(gpu_lib):
+    """The shipped cost model under the learned policy on a batch of uneven
+    products: the first call plans the batch per size class and compares the
+    whole batch with the default plans; later calls of the same shape (new
+    operand and output buffers) take the repeated-shape path.  Every product
+    of every call is exact, and the batch context's plans are valid plans of
+    the candidate space."""
+    import os
+
+    import torch
+
+    pm = gpu_lib
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pm.model_load(os.path.join(root, "paper_1609_01010_amd", "data", "cost_model.txt"))
+    items = inputs.batch_uneven(count=96, lo=16, hi=40000, tag=(113,))
+    pm.plan_cache_clear()
+    pm.set_policy(pm.POLICY_LEARNED)
+    try:
+        for rnd in range(3):
+            probs = [(torch.from_numpy(it.a).cuda(), torch.from_numpy(it.b).cuda(), it.p) for it in items]
+            say("case: learned batch, call", rnd)
+            outs = pm.poly_mul_batch(probs)
+            assert pm.stream_check() == 0
+            for it, c in zip(items, outs):
+                assert np.array_equal(c.cpu().numpy(), op.poly_mul_ntt(it.a, it.b, it.p, inputs.PRIMES[it.p]))
+        for it in items[:12]:
+            lc = it.a.size + it.b.size - 1
+            P = pm.plan_for(lc, it.p, pm.CTX_BATCH)
+            assert any(P.as_tuple() == Q.as_tuple() for Q in pm.plan_candidates(lc, it.p)), (lc, P)
+    finally:
+        pm.set_policy(pm.POLICY_DEFAULT)
+        pm.plan_cache_clear()
+
+
 def test_learned_policy_trains_predicts_and_stays_exact(gpu_lib, tmp_path):
     """A small version of the learned-plan experiment: tune a few lengths,
     train the network on the device, pick plans for unseen lengths; the
