@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 
 P = 2013265921
 G = 31                                 # a primitive root mod P
+# the autotuner's picks for the two products on MI355X (four-step L = 2^22,
+# RA 16, RB 32, C 2^13; four-step L = 2^20, RA 32 with 31 blocks kept, RB 8, C 2^12)
+TUNED_PLANS = "2,22,4,5,13,16,3,9;2,20,5,3,12,31,3,9"
 CU, LANES, CLOCK = 256, 64, 2.4e9
 ALU_PEAK = CU * LANES * CLOCK          # 32-bit VALU issue slots per second
 HBM_PEAK = 8.0e12                      # bytes per second
@@ -351,9 +354,10 @@ def main():
                     help="buffer sets rotated over the steps (16 sets = 640 MiB, over twice the 256 MB MALL)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
-    ap.add_argument("--plans", default=None,
-                    help="fixed plans for the two products, 'kind,log_l,log_ra,log_rb,log_c,ma,lq,lnt;...' "
-                         "(skips the autotuner, e.g. for profiling runs)")
+    ap.add_argument("--plans", default=TUNED_PLANS,
+                    help="plans for the two products, 'kind,log_l,log_ra,log_rb,log_c,ma,lq,lnt;...' "
+                         "(default: the autotuner's picks on MI355X, the plans of the committed profiles)")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner for the two products instead")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 256 MiB three times (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -391,23 +395,25 @@ def main():
     for _ in range(args.rotate):
         sets.append(tuple(torch.from_numpy(x).to(dev) for x in (a2, b2, a3, b3)) +
                     (torch.empty(lc2, dtype=torch.uint32, device=dev), torch.empty(lc3, dtype=torch.uint32, device=dev)))
-    # plans: the autotuner's picks (exhaustive empirical search, before the
-    # timed region; for the 10^6 product among the relaxed-TFT plans only: the
-    # workload excludes padding to 2^20).  The cost model's picks are listed
-    # beside them.
+    # plans: the autotuner's picks on MI355X (exhaustive empirical search; for
+    # the 10^6 product among the relaxed-TFT plans only: the workload excludes
+    # padding to 2^20), fixed so that the default run is the profiled one;
+    # --tune searches again before the timed region.  The cost model's picks
+    # are listed beside them.
     pm.model_load(os.path.join(ROOT, "paper_1609_01010_amd", "data", "cost_model.txt"))
     lplan2 = learned_pick(pm, lc2, P)
     lplan3 = learned_pick(pm, lc3, P, only_truncated=True)
-    if args.plans:
-        plan2, plan3 = (pm.Plan(*[int(v) for v in s.split(",")]) for s in args.plans.split(";"))
-        plan_source = "given on the command line"
-    else:
+    if args.tune:
         pm.tune_db_clear()
         plan2 = tuned_pick(pm, lc2, P)
         plan3 = tuned_pick(pm, lc3, P, only_truncated=True)
         pm.tune_db_clear()
         pm.plan_cache_clear()
-        plan_source = "autotuner (every candidate timed, fastest kept)"
+        plan_source = "autotuner, this run (every candidate timed, fastest kept)"
+    else:
+        plan2, plan3 = (pm.Plan(*[int(v) for v in s.split(",")]) for s in args.plans.split(";"))
+        plan_source = ("given on the command line" if args.plans != TUNED_PLANS else
+                       "the autotuner's picks on MI355X (fixed; --tune searches again)")
     log("plans:", plan2, plan3, "learned:", lplan2, lplan3)
 
     def step(i):
