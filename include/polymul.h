@@ -144,11 +144,12 @@ pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream)
  * allocates with hipMalloc on first use and grows as needed (growing waits
  * for the stream).  Callers that manage device memory themselves supply it:
  *
- *   pm_workspace_query:        bytes pm_poly_mul(len_a, len_b, p) needs under
- *                              the current policy and plan cache (the largest
- *                              over the candidate plans when the policy is
- *                              exhaustive); 0 for one-work-group and
- *                              defining-sum plans.
+ *   pm_workspace_query:        bytes pm_poly_mul(len_a, len_b, p) needs: under
+ *                              the default policy, for the cached or default
+ *                              plan (0 for one-work-group and defining-sum
+ *                              plans); under the learned and exhaustive
+ *                              policies, whose plan is picked at call time,
+ *                              the most any candidate plan needs.
  *   pm_batch_workspace_query:  bytes pm_poly_mul_batch needs for these
  *                              problems (host array).
  *   pm_int_mul_workspace_query: bytes pm_int_mul(na, nb) needs.

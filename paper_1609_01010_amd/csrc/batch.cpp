@@ -205,11 +205,23 @@ static size_t batch_workspace_bytes(const std::vector<Plan>& plans) {
 
 extern "C" pm_status pm_batch_workspace_query(const pm_problem* probs, size_t count, size_t* bytes) {
   if ((!probs && count) || !bytes || count > 65535) return PM_EINVAL;
-  std::vector<Plan> plans;
-  std::vector<int> pidx;
-  const pm_status st = batch_plans(probs, count, plans, pidx);
-  if (st) return st;
-  *bytes = batch_workspace_bytes(plans);
+  size_t wsb = 0;
+  for (size_t i = 0; i < count; ++i) {
+    const pm_problem& q = probs[i];
+    if (!q.a || !q.b || !q.c || q.len_a == 0 || q.len_b == 0) return PM_EINVAL;
+    if (q.len_a > (1ul << 24) || q.len_b > (1ul << 24)) return PM_ETOOLARGE;
+    const int pi = prime_index(q.p);
+    if (pi < 0) return PM_EUNSUPPORTED;
+    const long lc = (long)(q.len_a + q.len_b - 1);
+    if (!plan_valid(default_plan(lc, pi), lc, pi)) return PM_ETOOLARGE;
+    // the same bound per product as pm_workspace_query, batched the way the executor lays it out
+    Plan P;
+    const size_t w = current_policy() == PM_POLICY_DEFAULT && !plan_cache_get(lc, q.p, &P, kCtxBatch)
+                         ? plan_workspace_bytes(default_plan(lc, pi))
+                         : product_workspace_bound(lc, pi);
+    if (w) wsb += (w + 255) & ~(size_t)255;
+  }
+  *bytes = wsb;
   return PM_OK;
 }
 

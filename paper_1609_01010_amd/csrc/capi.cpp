@@ -447,6 +447,21 @@ static pm_status mixed_product(const uint32_t* a, size_t len_a, const uint32_t* 
   return dev_status(launch_mixed_merge(C, (int)q, M, c, lc, pidx, s));
 }
 
+// Workspace a product of output length lc may need, on the host alone: under
+// the default policy the cached or default plan's; otherwise (the plan is
+// picked by the cost model or by timing at call time, and a batch may fall
+// back to the default plans) the most any candidate plan needs.
+size_t product_workspace_bound(long lc, int pidx) {
+  Plan P;
+  if (g_policy == PM_POLICY_DEFAULT || plan_pinned(lc, prime_info(pidx).p)) {
+    P = choose_plan(lc, pidx);
+    return plan_workspace_bytes(P);
+  }
+  size_t w = plan_workspace_bytes(default_plan(lc, pidx));
+  for (const Plan& Q : plan_candidates(lc, pidx)) w = std::max(w, plan_workspace_bytes(Q));
+  return w;
+}
+
 }  // namespace pm
 
 using namespace pm;
@@ -533,14 +548,7 @@ pm_status pm_workspace_query(size_t len_a, size_t len_b, uint32_t p, size_t* byt
   const uint32_t one = 1;
   pm_status st = check_product_args(&one, len_a, &one, len_b, p, &one, &pidx, &lc);
   if (st) return st;
-  size_t w = 0;
-  if (g_policy == PM_POLICY_EXHAUSTIVE) {
-    // the plan is picked by timing at call time: any candidate may win
-    for (const Plan& P : plan_candidates(lc, pidx)) w = std::max(w, plan_workspace_bytes(P));
-  }
-  const Plan P = choose_plan(lc, pidx);
-  if (!plan_valid(P, lc, pidx)) return PM_ETOOLARGE;
-  *bytes = std::max(w, plan_workspace_bytes(P));
+  *bytes = product_workspace_bound(lc, pidx);
   return PM_OK;
 }
 

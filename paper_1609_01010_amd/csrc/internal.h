@@ -115,6 +115,8 @@ bool plan_cache_get(long lc, u32 p, Plan* P, int tctx = kCtxSingle);
 bool plan_pinned(long lc, u32 p);
 // the library's plan without a model or a search
 Plan default_plan(long lc, int pidx);
+// workspace bytes a product of output length lc may need, found on the host
+size_t product_workspace_bound(long lc, int pidx);
 // the cost model's pick (tune.cpp)
 Plan learned_plan(long lc, int pidx, bool* ok, int tctx);
 // the cost model's picks for the items of one batch, one plan family per

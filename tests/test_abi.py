@@ -108,6 +108,29 @@ def test_workspace_queries_on_host(L):
     assert n.value == want and want > 0
 
 
+def test_workspace_queries_bound_the_policies_without_a_device(L):
+    """Under the learned policy the plan is chosen at call time (by the cost
+    model on the device): the queries return the most any candidate needs,
+    still on the host alone."""
+    import paper_1609_01010_amd as pm
+
+    n = ctypes.c_size_t(0)
+    pm.set_policy(pm.POLICY_LEARNED)
+    try:
+        assert L.pm_workspace_query(1 << 21, 1 << 21, 2013265921, ctypes.byref(n)) == 0
+        assert n.value == 2 * 4 * (1 << 22)
+        assert L.pm_workspace_query(600001, 400000, 2013265921, ctypes.byref(n)) == 0
+        assert n.value == 2 * 4 * (1 << 20)  # a candidate without truncation
+        assert L.pm_workspace_query(1024, 1024, 998244353, ctypes.byref(n)) == 0 and n.value == 0
+        probs = (pm.Problem * 2)()
+        for i, (la, lb) in enumerate(((600001, 400000), (1024, 1024))):
+            probs[i].a, probs[i].len_a, probs[i].b, probs[i].len_b = 4096, la, 4096, lb
+            probs[i].p, probs[i].c = 2013265921, 4096
+        assert L.pm_batch_workspace_query(probs, 2, ctypes.byref(n)) == 0 and n.value == 2 * 4 * (1 << 20)
+    finally:
+        pm.set_policy(pm.POLICY_DEFAULT)
+
+
 def test_tuning_database_contexts_round_trip(tmp_path):
     """Rows of both timing contexts survive save and load; a row written
     without the context column loads as a single-product row."""
