@@ -146,6 +146,43 @@ def test_large_power_of_two_product_sampled(gpu_lib):
     assert np.array_equal(got, op.poly_mul_ntt(a, b, p, 31))
 
 
+def test_maximum_sizes(gpu_lib):
+    """The largest transform lengths the library accepts: L = 2^24 mod
+    2013265921 (the library's limit) and L = 2^23 mod 998244353 (its 2-adic
+    order), the integer product at na + nb - 1 = 2^23, and the transform of
+    2^24 points.  Sampled coefficients against the defining sum, the product
+    at random points, the integer product mod 2^61 - 1, the transform against
+    the evaluation definition and its exact round trip."""
+    pm = gpu_lib
+    rng = random.Random(24)
+    for p, lg in ((2013265921, 23), (998244353, 22)):
+        say("case: maximum product", p, lg)
+        a, b = inputs.poly_pair((104, lg), 1 << lg, 1 << lg, p)
+        got = host(pm.poly_mul(dev(a), dev(b), p))
+        assert pm.stream_check() == 0
+        assert got.size == (1 << (lg + 1)) - 1
+        ks = sorted(set([0, 1, got.size // 2, got.size - 1] + rng.sample(range(got.size), 28)))
+        assert np.array_equal(got[ks], op.poly_mul_sample(a, b, p, ks))
+        for _ in range(4):
+            x = rng.randrange(2, p)
+            assert op.eval_at(got, p, x) == op.eval_at(a, p, x) * op.eval_at(b, p, x) % p
+    say("case: maximum integer product")
+    ia, ib = inputs.int_operands(1 << 22, tag=105)
+    ic = host(pm.int_mul(dev(ia, np.uint16), dev(ib, np.uint16)))
+    assert pm.stream_check() == 0
+    q = (1 << 61) - 1
+    assert op.limbs_to_int(ic) % q == (op.limbs_to_int(ia) % q) * (op.limbs_to_int(ib) % q) % q
+    assert ic.size == 1 << 23
+    say("case: transform of 2^24 points")
+    p, g = 2013265921, inputs.PRIMES[2013265921]
+    x = inputs.uniform_mod(inputs.rng_for(106), 1 << 24, p)
+    X = host(pm.ntt(dev(x), p))
+    ks = [0, 1, 12345, (1 << 24) - 1]
+    assert np.array_equal(X[ks], op.dft_eval(x, p, g, ks=ks))
+    assert np.array_equal(host(pm.ntt(dev(X), p, inverse=True)), x)
+    assert pm.stream_check() == 0
+
+
 def test_large_tft_product(gpu_lib):
     """600001 x 400000 mod 2013265921 -> 10^6 coefficients by a truncated transform."""
     pm = gpu_lib
