@@ -130,10 +130,19 @@ typedef struct {
 
 /*
  * Batch of independent products (each as pm_poly_mul), of uneven lengths and
- * mixed primes.  `probs` is a HOST array of `count` problems.  The batch is
- * grouped by size class and run as one hipGraph launch of persistent
- * kernels; graphs are cached by the batch's shape signature.  On a host-side
- * error no problem is computed.  Output arrays must be pairwise disjoint.
+ * mixed primes.  `probs` is a HOST array of `count` <= 65535 problems.  The
+ * products are grouped into classes of equal plan; each class runs one
+ * launch per pass over all its products, and the classes are captured into
+ * one hipGraph, cached by the batch's class signature.  A call whose problems
+ * have the same lengths and primes, in order, as the previous call on the
+ * stream only patches the pointers into the previous job descriptors and
+ * relaunches.  Under PM_POLICY_LEARNED the plans come from the cost model in
+ * the batch context, one plan family per transform length and prime; the
+ * first call of a batch shape also runs the batch with the default plans,
+ * waits for the device (the call is synchronous, and must not be made while
+ * the stream is being captured), and keeps the faster plans for that shape.
+ * On a host-side error no problem is computed.  Output arrays must be
+ * pairwise disjoint.
  */
 pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream);
 
