@@ -374,7 +374,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library's path runs on a single MI355X and has no "
-              "multi-GPU mode (see DESIGN.md for how it would shard). Run with --gpus 1.", file=sys.stderr)
+              "multi-GPU mode. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -76,7 +76,7 @@ struct BatchState {
   hipEvent_t staged = nullptr;  // the last upload from `staging` has completed
   // learned policy: per batch shape (hash of the lengths and primes), whether
   // the default plans ran the whole batch faster than the model's (1) or not (0)
-  std::map<u64, int> verdict;
+  std::map<u64, int> plan_choice;
 };
 // one state per (device, stream): batches on different streams may overlap
 std::map<std::pair<int, hipStream_t>, BatchState*> g_batch;
@@ -469,13 +469,13 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
   }
   if (!differ) return batch_run(c, B, probs, count, plans, pidx, s);
   const u64 h = shape_hash(probs, count);
-  auto v = B->verdict.find(h);
-  if (v == B->verdict.end()) {
+  auto v = B->plan_choice.find(h);
+  if (v == B->plan_choice.end()) {
     float t_model = 0, t_default = 0;
     st = time_batch(c, B, probs, count, plans, pidx, s, &t_model);
     if (st == PM_OK) st = time_batch(c, B, probs, count, dplans, pidx, s, &t_default);
     if (st) return st;
-    v = B->verdict.emplace(h, t_default < t_model ? 1 : 0).first;
+    v = B->plan_choice.emplace(h, t_default < t_model ? 1 : 0).first;
   }
   return batch_run(c, B, probs, count, v->second ? dplans : plans, pidx, s);
 }
