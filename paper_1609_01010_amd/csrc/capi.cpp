@@ -61,7 +61,8 @@ static int kept_blocks(long lc, int logL, int logRA) {
 }
 
 Plan default_plan(long lc, int pidx) {
-  // measured on MI355X: row length C = L / 256 (at least 2^10, at most 2^14),
+  // measured on MI355X: row length C = L / 256 (at least 2^10, at most 2^13,
+  // and at least L / 1024 so that the columns have at most 32 x 32 points),
   // columns split 16 x R/16, 16 elements per row thread, LDS rounds of radix
   // 8 in the rows; truncation with the finest first radix (32) when the
   // output length is not a power of two
@@ -78,7 +79,8 @@ Plan default_plan(long lc, int pidx) {
     P.logRA = P.logL < 4 ? P.logL : 4;
   } else {
     P.kind = PLAN_FOURSTEP;
-    P.logC = P.logL - 8 < 10 ? 10 : (P.logL - 8 > 14 ? 14 : P.logL - 8);
+    P.logC = P.logL - 8 < 10 ? 10 : (P.logL - 8 > 13 ? 13 : P.logL - 8);
+    if (P.logL - P.logC > 10) P.logC = P.logL - 10;
     const int logR = P.logL - P.logC;
     if (logR <= 4) {
       P.logRA = logR;
