@@ -700,7 +700,9 @@ pm_status pm_stream_check(void* stream) {
 size_t pm_itft_granularity(size_t L) { return L <= 32 ? 1 : L / 32; }
 
 // the hooks' plan for length L: one work-group up to 2^14, else four-step
-// with first radix 32, rows of up to 2^14, and 16 values per row thread
+// with first radix 32, rows of up to 2^13 (two row work-groups per compute
+// unit at 2^22) but at least L / 2^10 (columns of at most 2^10), and 16
+// values per row thread
 static Plan hook_plan(int logL, int ma) {
   Plan P;
   P.logL = logL;
@@ -710,7 +712,8 @@ static Plan hook_plan(int logL, int ma) {
   } else {
     P.kind = PLAN_FOURSTEP;
     P.logRA = 5;
-    P.logC = logL - 5 > 14 ? 14 : logL - 5;
+    P.logC = logL - 5 > 13 ? 13 : logL - 5;
+    if (logL - P.logC > 10) P.logC = logL - 10;
     P.logRB = logL - 5 - P.logC;
     P.lnt = P.logC - 4;
   }

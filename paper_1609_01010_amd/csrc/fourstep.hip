@@ -163,12 +163,14 @@ __global__ void __launch_bounds__(1024) k_col_fwdr(JobRef jr, int logC, int lw) 
 
 // Columns per work-group: 32 (128-byte row segments) unless the tile of R
 // rows would exceed 64 KB, and 16 when the grid would otherwise have fewer
-// work-groups than the chip has compute units.
-inline int col_lw(int logR, int logC, long groups) {
+// than min_wg work-groups: the chip's 256 compute units, or two per unit for
+// the forward pass of a single operand (the transform hooks), whose half
+// as many tiles otherwise leave one work-group per unit.
+inline int col_lw(int logR, int logC, long groups, long min_wg = 256) {
   int lw = 5;
   if (logR + lw > 14) lw = 14 - logR;
   if (lw > logC) lw = logC;
-  while (lw > 4 && (groups << (logC - lw)) < 256) --lw;
+  while (lw > 4 && (groups << (logC - lw)) < min_wg) --lw;
   return lw;
 }
 inline int col_threads(int logR, int lw) {
@@ -178,7 +180,8 @@ inline int col_threads(int logR, int lw) {
 
 template <int LR, typename TIn, bool TWIST>
 static hipError_t col_fwdr_launch(const Plan& P, int nops, const JobRef& jr, int njobs, hipStream_t s) {
-  const int lw = col_lw(LR, P.logC, (long)nops * njobs);
+  const long groups = (long)nops * njobs;
+  const int lw = col_lw(LR, P.logC, groups, groups == 1 ? 512 : 256);
   const long C = 1l << P.logC;
   if (C < (1l << lw) || col_threads(LR, lw) > 1024) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << (lw + LR)) * sizeof(u32);
