@@ -893,10 +893,16 @@ static const u32 kIntPrimes[3] = {469762049u, 998244353u, 167772161u};
 struct IntLayout {
   Plan plans[3];
   bool widen = false;
-  size_t res_b = 0, wid_b = 0, pw = 0, total = 0;
+  bool merged = false;  // one four-step plan for the three primes: each pass runs once over all three
+  size_t res_b = 0, wid_b = 0, pw = 0, jobs_b = 0, total = 0;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool same_plan(const Plan& x, const Plan& y) {
+  return x.kind == y.kind && x.logL == y.logL && x.logRA == y.logRA && x.logRB == y.logRB && x.logC == y.logC &&
+         x.ma == y.ma && x.lq == y.lq && x.lnt == y.lnt && x.twist == y.twist;
+}
 
 static pm_status int_mul_layout(size_t na, size_t nb, IntLayout* L) {
   const long lc = (long)(na + nb - 1);
@@ -909,9 +915,17 @@ static pm_status int_mul_layout(size_t na, size_t nb, IntLayout* L) {
     const size_t w = plan_workspace_bytes(L->plans[i]);
     if (w > L->pw) L->pw = w;
   }
+  // the three primes are below 2^30 (one value range), so equal plans can
+  // share launches; each product then has its own four-step workspace
+  L->merged = L->plans[0].kind == PLAN_FOURSTEP && same_plan(L->plans[0], L->plans[1]) &&
+              same_plan(L->plans[0], L->plans[2]);
+  if (L->merged) {
+    L->pw = 3 * align256(L->pw);
+    L->jobs_b = align256(3 * sizeof(ConvJob));
+  }
   L->res_b = align256((size_t)lc * 4);
   L->wid_b = L->widen ? align256((na + nb) * 4) : 0;
-  L->total = 3 * L->res_b + L->wid_b + align256(L->pw) + align256(crt_workspace_bytes((long)(na + nb)));
+  L->total = 3 * L->res_b + L->wid_b + align256(L->pw) + L->jobs_b + align256(crt_workspace_bytes((long)(na + nb)));
   return PM_OK;
 }
 
@@ -949,12 +963,31 @@ pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb,
   u32* wa = (u32*)(base + 3 * res_b);
   u32* wb = wa + na;
   void* pws = base + 3 * res_b + wid_b;
-  void* cws = (char*)pws + al(pw);
+  ConvJob* djobs = (ConvJob*)((char*)pws + al(pw));
+  void* cws = (char*)djobs + LY.jobs_b;
   hipError_t e = hipSuccess;
   if (widen) {
     e = launch_widen(a, (long)na, wa, s);
     if (e == hipSuccess) e = launch_widen(b, (long)nb, wb, s);
     if (e != hipSuccess) return PM_EDEVICE;
+  }
+  if (LY.merged) {
+    const Plan& P = plans[0];
+    const size_t pw1 = pw / 3;
+    ConvJob J[3];
+    for (int i = 0; i < 3; ++i) {
+      u32* Ta = (u32*)((char*)pws + i * pw1);
+      st = make_job(c, P, prime_index(kIntPrimes[i]), a, (long)na, b, (long)nb, res[i], lc, Ta, Ta + plan_nprime(P),
+                    &J[i], 0);
+      if (st) return st;
+    }
+    if (launch_store_jobs3(J, djobs, s) != hipSuccess) return PM_EDEVICE;
+    JobRef jr;
+    jr.one = J[0];
+    jr.many = djobs;
+    st = launch_class(P, prime_info(prime_index(kIntPrimes[0])).lazy, 1, jr, 3, J[0].rows, s);
+    if (st) return st;
+    return dev_status(launch_crt_carry(res[0], res[1], res[2], lc, nl, cws, out, s));
   }
   for (int i = 0; i < 3; ++i) {
     const int pidx = prime_index(kIntPrimes[i]);

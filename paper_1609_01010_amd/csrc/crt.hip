@@ -221,4 +221,26 @@ hipError_t launch_widen(const uint16_t* in, long n, u32* out, hipStream_t s) {
   return launch("widen", k_widen, (unsigned)((n + 255) / 256), 256, 0, s, in, n, out);
 }
 
+// The descriptors of the three products, written to device memory so that
+// each pass of their common four-step plan runs once over the three primes
+// (blockIdx.z selects the prime).
+struct JobsOf3 {
+  ConvJob j[3];
+};
+
+__global__ void k_store_jobs3(JobsOf3 t, ConvJob* __restrict__ out) {
+  if (threadIdx.x == 0)
+    out[0] = t.j[0];
+  else if (threadIdx.x == 1)
+    out[1] = t.j[1];
+  else if (threadIdx.x == 2)
+    out[2] = t.j[2];
+}
+
+hipError_t launch_store_jobs3(const ConvJob* jobs, ConvJob* out, hipStream_t s) {
+  JobsOf3 t;
+  for (int i = 0; i < 3; ++i) t.j[i] = jobs[i];
+  return launch("store_jobs", k_store_jobs3, 1, 64, 0, s, t, out);
+}
+
 }  // namespace pm
