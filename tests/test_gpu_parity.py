@@ -253,6 +253,34 @@ def test_int_mul(gpu_lib):
         assert np.array_equal(got, op.int_mul(ff, ff))
 
 
+def test_int_mul_plans_differ(gpu_lib):
+    """With one plan for the three primes, each pass runs once over the three
+    products; with plans that differ (one pinned here) the products run one
+    after the other.  Both give the exact product."""
+    pm = gpu_lib
+    rng = np.random.default_rng(19)
+    na, nb = 40000, 39000
+    lc = na + nb - 1
+    a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+    b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+    want = op.int_mul(a, b)
+    primes = (469762049, 998244353, 167772161)
+    base = pm.plan_for(lc, primes[0])
+    assert base.kind == 2 and all(pm.plan_for(lc, p).as_tuple() == base.as_tuple() for p in primes)
+    t = list(base.as_tuple())
+    t[7] = t[7] + 1 if t[4] - t[7] > 3 else t[7] - 1  # twice or half the row threads
+    try:
+        for pinned in (None, pm.Plan(*t)):
+            say("case: int plans", pinned.as_tuple() if pinned else "shared")
+            if pinned:
+                pm.plan_cache_put(lc, primes[1], pinned)
+            got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16)))
+            assert pm.stream_check() == 0
+            assert np.array_equal(got, want)
+    finally:
+        pm.plan_cache_clear()
+
+
 def test_int_mul_full_size(gpu_lib):
     """Two random 2^21-limb integers, bit-exact against CPython's multiply."""
     pm = gpu_lib
