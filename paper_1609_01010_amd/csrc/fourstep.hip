@@ -57,7 +57,10 @@ __global__ void __launch_bounds__(64) k_col_fwd1(JobRef jr, int logC) {
     if constexpr (TWIST) x[s] = A.mul(x[s], cld(J.twf + s));
   }
   if (bad) atomicOr(J.err, 1);
-  dif_reg<RA>(A, x, J.T.pf);
+  if ((C << (LRA - 1)) >= z)  // rows RA/2 and up are zero
+    dif_reg<RA, LAZY, false, true>(A, x, J.T.pf);
+  else
+    dif_reg<RA>(A, x, J.T.pf);
 #pragma unroll
   for (int t = 0; t < RA; ++t)
     if (t < J.ma) gst(out + C * t + j2, x[t]);
@@ -114,7 +117,12 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
           x[s] = sm[(row << lw) + c];
         }
       }
-      dif_reg<Q, LAZY, (LS > 0)>(A, x, T.pf);
+      // the first round spans whole columns (LB = log R): rows R/2 and up
+      // are zero when the operand has at most L/2 values
+      if (FROM_GLOBAL && (C << (LB - 1)) >= z)
+        dif_reg<Q, LAZY, (LS > 0), true>(A, x, T.pf);
+      else
+        dif_reg<Q, LAZY, (LS > 0)>(A, x, T.pf);
       const uint2* tw = T.rf[LQ - 1] + (1 << LB) + j * Q;
 #pragma unroll
       for (int t = 0; t < Q; ++t) {

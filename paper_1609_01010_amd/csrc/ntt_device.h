@@ -76,8 +76,10 @@ __device__ __forceinline__ PrimeTables fresh(const PrimeTables& T) {
 
 // forward DIF: natural in, bit-reversed out.  RAW_TAIL: outputs 1..Q-1 are
 // left in [0, 2K) (for a caller that multiplies each of them next); output 0
-// is always reduced.
-template <int Q, bool LAZY, bool RAW_TAIL = false>
+// is always reduced.  HZ: the caller guarantees x[Q/2..Q) = 0 (an operand
+// shorter than half the transform), so the first level is (a, 0) -> (a, a w)
+// with no sum or difference.
+template <int Q, bool LAZY, bool RAW_TAIL = false, bool HZ = false>
 __device__ __forceinline__ void dif_reg(const Arith<LAZY>& A, u32* x, const uint2* __restrict__ pf) {
 #pragma unroll
   for (int h = Q / 2; h >= 1; h >>= 1) {
@@ -85,7 +87,9 @@ __device__ __forceinline__ void dif_reg(const Arith<LAZY>& A, u32* x, const uint
     for (int blk = 0; blk < Q; blk += 2 * h) {
 #pragma unroll
       for (int i = 0; i < h; ++i) {
-        if (i != 0)
+        if (HZ && h == Q / 2)
+          x[i + h] = i == 0 ? x[i] : A.mul(x[i], cld(pf + 2 * h + i));
+        else if (i != 0)
           bfly_dif(A, x[blk + i], x[blk + i + h], cld(pf + 2 * h + i));
         else if (RAW_TAIL && h == 1 && blk > 0)
           bfly_dif1_raw(A, x[blk], x[blk + 1]);
