@@ -88,6 +88,26 @@ def test_every_candidate_plan_agrees(gpu_lib):
                 assert np.array_equal(got, want), (p, lc, P)
 
 
+def test_operand_half_length_boundary(gpu_lib):
+    """An operand of at most L/2 values leaves the upper half of every forward
+    column zero and takes the shortened first level; one value more does not.
+    Every candidate plan of L = 2^16 on both sides of that boundary, with the
+    extreme value p - 1 at the last position of each operand."""
+    pm = gpu_lib
+    L = 1 << 16
+    for p in (998244353, 2013265921):
+        for la in (L // 2, L // 2 + 1):
+            lb = L - la  # lc = L - 1
+            a, b = inputs.poly_pair((103, la, p % 1000), la, lb, p)
+            a[-1] = p - 1
+            b[-1] = p - 1
+            want = op.poly_mul(a, b, p)
+            for P in pm.plan_candidates(L - 1, p):
+                say("case: half boundary", p, la, P)
+                got = _product(pm, a, b, p, plan=P)
+                assert np.array_equal(got, want), (p, la, P)
+
+
 @pytest.mark.parametrize("p", [998244353, 2013265921])
 def test_truncated_inverse_near_full(gpu_lib, p):
     """Relaxed plans that keep all but d = 0..4 blocks of the first radix
