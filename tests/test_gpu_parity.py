@@ -232,6 +232,26 @@ def test_ntt_hook(gpu_lib, p, g):
         assert pm.stream_check() == 0
 
 
+def test_ntt_hook_large_sampled(gpu_lib):
+    """The hooks' four-step plans at 2^22 and 2^23 (rows of 2^13) and 2^24
+    (rows of 2^14, columns of at most 2^10): natural-order outputs sampled
+    against evaluation at w^k, and the inverse round trip compared whole."""
+    pm = gpu_lib
+    for p, g, logn in ((2013265921, 31, 22), (998244353, 3, 23), (2013265921, 31, 24)):
+        n = 1 << logn
+        say("case: ntt large", p, n)
+        x = inputs.uniform_mod(inputs.rng_for((105, logn)), n, p)
+        X = pm.ntt(dev(x), p)
+        Xh = host(X)
+        w = op.root(p, g, n)
+        for k in (0, 1, n // 2 - 1, n // 2, n - 1):
+            assert int(Xh[k]) == op.eval_at(x, p, pow(w, k, p)), (p, n, k)
+        y = host(pm.ntt(X, p, inverse=True))
+        assert np.array_equal(y, x)
+        assert pm.stream_check() == 0
+        del X
+
+
 @pytest.mark.parametrize("p,g", PRIMES[:2])
 def test_tft_and_itft_hooks(gpu_lib, p, g):
     pm = gpu_lib
