@@ -24,12 +24,12 @@ static int ceil_log2(long x) {
 }
 
 static std::mutex g_plan_mu;
-static pm_policy g_policy = PM_POLICY_DEFAULT;
+static std::atomic<int> g_policy{PM_POLICY_DEFAULT};
 static std::atomic<unsigned long> g_plan_epoch{1};
 
 // changes whenever a plan choice could change (policy, cache, model)
 unsigned long plan_epoch() { return g_plan_epoch.load(); }
-pm_policy current_policy() { return g_policy; }
+pm_policy current_policy() { return (pm_policy)g_policy.load(); }
 void plan_epoch_bump() { g_plan_epoch.fetch_add(1); }
 static std::map<std::tuple<long, u32, int>, Plan> g_plan_cache;
 static std::set<std::pair<long, u32>> g_plan_pinned;  // (lc, p) put by the caller (pm_plan_cache_put)
@@ -635,7 +635,7 @@ pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, s
 
 pm_status pm_set_policy(pm_policy policy) {
   if (policy != PM_POLICY_DEFAULT && policy != PM_POLICY_EXHAUSTIVE && policy != PM_POLICY_LEARNED) return PM_EINVAL;
-  g_policy = policy;
+  g_policy.store(policy);
   plan_epoch_bump();
   return PM_OK;
 }

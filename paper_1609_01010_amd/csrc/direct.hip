@@ -1,22 +1,7 @@
-// Convolution kernels: the defining sum for tiny products, the one-work-group
-// LDS-resident convolution, and the three passes of the four-step convolution.
-//
-// The product is computed by the convolution theorem (Theorem 1, eq. 10):
-// forward transforms of both zero-padded operands (eq. 12; the padding is
-// never read from memory), the pointwise product (the operator P of eq. 11),
-// the inverse transform, and the scaling by the inverse length.  With
-// truncation (eq. 14) only the first n' >= len_a + len_b - 1 bit-reversed
-// transform values are formed, multiplied and inverted.
-//
-// Four-step split used throughout, for L = R * C:
-//   input index  j = C j1 + j2   (j1 < R: column position, j2 < C: column)
-//   output index k = k1 + R k2
-//   X_{k1 + R k2} = sum_{j2} w_C^{j2 k2} w_L^{j2 k1} sum_{j1} x_{C j1 + j2} w_R^{j1 k1}
-// Column pass: length-R transforms of the columns (bit-reversed out).  Row
-// pass: row t holds k1 = rev(t); twiddle by w_L^{j2 k1}, length-C transform,
-// and for the convolution the pointwise product and the inverse, untwiddled.
-// Truncating to rows t < m keeps the first m C bit-reversed outputs: the TFT
-// with granularity C (relaxed, as the paper's library relaxes its breakdown).
+// Products by their defining sums (Def. 2, eq. 2; and the sums of the two
+// quotient rings of eq. 13), for products too small for a transform to pay:
+// one thread per output coefficient, exact 64-bit accumulation, one
+// reduction per output.
 #include "internal.h"
 #include "trace.h"
 

@@ -1,8 +1,9 @@
 // Twiddle-table generation (GPU kernels) and the per-device context.
 //
-// The transforms need the principal roots of unity w_N = g^((p-1)/N) of the
-// ring (section 3: "R contains a principal L-th root of unity") and their
-// powers, each stored with its Shoup companion floor(w * 2^32 / p).
+// The transforms need principal roots of unity of the coefficient ring, the
+// w_N = g^((p-1)/N) that the convolution theorem evaluates at (section 3,
+// eq. 10), and their powers, each stored with its Shoup companion
+// floor(w * 2^32 / p).
 #include <cstdio>
 #include <cstdlib>
 

@@ -84,7 +84,8 @@ def test_mlp_training_follows_oracle_and_learns(gpu_lib):
     ref = omlp.train(inputs.mlp_unflatten(w0), X, t, steps=5, lr=1e-3)
     W = inputs.mlp_unflatten(w)
     for k in omlp.NAMES:
-        assert _rel(W[k], ref[k]) <= 1e-3, k
+        say("trajectory", k, _rel(W[k], ref[k]))
+        assert _rel(W[k], ref[k]) <= TOL, k
     w, losses = pm.mlp_train(w0, X, t, steps=400, lr=3e-3)
     assert losses[-1] < 0.2 * losses[0]
 

@@ -538,6 +538,66 @@ def test_mlp_closed_forms():
     assert np.isclose(p2["b3"][0], 0.5 - 0.01 * np.sign(g["b3"][0]) * abs(g["b3"][0]) / (abs(g["b3"][0]) + 1e-8))
 
 
+def _adam_case():
+    """Parameters and two gradients per element for the Adam pins.  W1 row 0:
+    the same gradient twice; row 1: g then -g; row 2: g then 0.  The other
+    tensors get the same gradient at both steps."""
+    F, H = 3, 4
+    g1 = np.array([[0.5, -2.0, 3e-3], [1.5, -0.25, 7.0], [2.0, -0.75, 0.125], [1.0, 1.0, -1.0]])
+    g2 = g1.copy()
+    g2[1] = -g1[1]
+    g2[2] = 0.0
+    params = {"W1": np.full((H, F), 0.25), "b1": np.zeros(H), "W2": np.eye(H), "b2": np.ones(H),
+              "W3": np.ones((1, H)), "b3": np.array([0.5])}
+    grads1 = {"W1": g1, "b1": np.full(H, -0.5), "W2": np.full((H, H), 2.0), "b2": np.full(H, 4.0),
+              "W3": np.full((1, H), -1.0), "b3": np.array([0.01])}
+    grads2 = dict(grads1, W1=g2)
+    return params, grads1, grads2
+
+
+def check_adam(step_fn, lr=0.01, eps=1e-8):
+    """Adam with bias correction (beta1 0.9, beta2 0.999), pinned by values
+    derived by hand from the moments' closed forms:
+      - a gradient g held for t steps: m_t = (1 - beta1^t) g and
+        v_t = (1 - beta2^t) g^2, so every step moves by lr g / (|g| + eps);
+      - g then -g: m_2 = -(1 - beta1)^2 g, so m_2 / (1 - beta1^2) = -g/19,
+        and v_2 / (1 - beta2^2) = g^2: the second step moves by
+        +lr g / (19 (|g| + eps));
+      - g then 0: the corrected moments are 9/19 g and 999/1999 g^2, so the
+        second step moves by -lr (9/19) g / (sqrt(999/1999) |g| + eps)."""
+    params, grads1, grads2 = _adam_case()
+    p = {k: v.copy() for k, v in params.items()}
+    state = {}
+    step_fn(p, grads1, state, lr=lr)
+    for k in omlp.NAMES:
+        g = grads1[k]
+        assert np.allclose(p[k], params[k] - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-12), ("step 1", k)
+    after1 = {k: np.array(v, dtype=np.float64) for k, v in p.items()}
+    step_fn(p, grads2, state, lr=lr)
+    g = grads1["W1"]
+    want = after1["W1"].copy()
+    want[0] -= lr * g[0] / (np.abs(g[0]) + eps)
+    want[1] += lr * g[1] / (19.0 * (np.abs(g[1]) + eps))
+    want[2] -= lr * (9.0 / 19.0) * g[2] / (math.sqrt(999.0 / 1999.0) * np.abs(g[2]) + eps)
+    want[3] -= lr * g[3] / (np.abs(g[3]) + eps)
+    assert np.allclose(p["W1"], want, rtol=0, atol=1e-12), "step 2, W1"
+    for k in omlp.NAMES[1:]:
+        gk = grads1[k]
+        assert np.allclose(p[k], after1[k] - lr * gk / (np.abs(gk) + eps), rtol=0, atol=1e-12), ("step 2", k)
+    # three more steps of a constant gradient: each moves by lr g / (|g| + eps)
+    p = {k: v.copy() for k, v in params.items()}
+    state = {}
+    for _ in range(5):
+        step_fn(p, grads1, state, lr=lr)
+    for k in omlp.NAMES:
+        g = grads1[k]
+        assert np.allclose(p[k], params[k] - 5 * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-11), ("step 5", k)
+
+
+def test_adam_steps_match_closed_forms():
+    check_adam(omlp.adam_step)
+
+
 def test_mlp_training_reduces_loss():
     params = _mlp_params(F=3, H=16, seed=3)
     rng = np.random.default_rng(2)
@@ -667,3 +727,34 @@ def _backward_transposed(params, X, t):
 def test_mlp_pins_catch_mistakes(mutant):
     with pytest.raises(AssertionError):
         check_mlp_grad(mutant)
+
+
+def _adam_variant(bias_t=None, persist=True, betas=(0.9, 0.999)):
+    """A copy of the oracle's Adam step with one planted change."""
+    def step(params, grads, state, lr=1e-3, eps=1e-8):
+        beta1, beta2 = betas
+        state["t"] = state.get("t", 0) + 1
+        tt = state["t"] if bias_t is None else bias_t
+        if not persist:
+            state["m"], state["v"] = {}, {}
+        for k in omlp.NAMES:
+            g = np.asarray(grads[k], dtype=np.float64)
+            m = state.setdefault("m", {}).setdefault(k, np.zeros_like(g))
+            v = state.setdefault("v", {}).setdefault(k, np.zeros_like(g))
+            m[...] = beta1 * m + (1.0 - beta1) * g
+            v[...] = beta2 * v + (1.0 - beta2) * g * g
+            mhat = m / (1.0 - beta1 ** tt)
+            vhat = v / (1.0 - beta2 ** tt)
+            params[k] = np.asarray(params[k], dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps)
+        return params
+    return step
+
+
+@pytest.mark.parametrize("mutant", [_adam_variant(bias_t=1), _adam_variant(persist=False),
+                                    _adam_variant(betas=(0.999, 0.9))],
+                         ids=["bias_correction_stuck_at_t1", "moments_not_persisted", "betas_swapped"])
+def test_adam_pins_catch_mistakes(mutant):
+    # the unmodified copy passes: the pins see only the planted change
+    check_adam(_adam_variant())
+    with pytest.raises(AssertionError):
+        check_adam(mutant)
