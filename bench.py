@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the NTT/TFT modular polynomial product on one MI355X.
 
-One step = the two plain large products over Z/2013265921Z:
-  (a) 2^21 x 2^21 coefficients through transforms of length 2^22, and
-  (b) 600001 x 400000 coefficients through a relaxed truncated transform
-      (10^6 outputs, no padding to 2^20).
-value = output coefficients per second (inputs resident in HBM when the
-timed region starts; buffers rotate over more than the 256 MB MALL).
+One step = one batch of 4096 independent products of uneven lengths (each
+operand length log-uniform in [64, 65536], primes drawn from the four
+supported ones, coefficients uniform in [0, p)), computed by one
+pm_poly_mul_batch call: one hipGraph launch, plans from the learned cost
+model.  value = output coefficients per second of the batched, learned-plan
+path, with the inputs resident in HBM when the timed region starts.
 
-The JSON line also carries the roofline of the dominant kernel (timed live
-with HIP events on the library's launch stream) and the CPU oracle timed on
-a bounded sample of the same workload.
+Beside it, the same batch "plain": a loop of one pm_poly_mul call per
+product with padded power-of-two plans, and the same graph with padded
+default plans and with the relaxed default plans (the library without the
+cost model).  The JSON line carries the roofline of the batch launch (its
+algorithmic VALU slots and HBM bytes over its duration, from HIP events on
+the launch stream), the dominant kernel family of the batch, and the CPU
+oracle timed on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu-baseline]
 """
 
 from __future__ import annotations
@@ -29,8 +33,9 @@ sys.path.insert(0, ROOT)
 
 P = 2013265921
 G = 31                                 # a primitive root mod P
-# the autotuner's picks for the two products on MI355X (four-step L = 2^22,
-# RA 16, RB 32, C 2^13; four-step L = 2^20, RA 32 with 31 blocks kept, RB 8, C 2^12)
+# the autotuner's picks for the two plain large products on MI355X (four-step
+# L = 2^22, RA 16, RB 32, C 2^13; four-step L = 2^20, RA 32 with 31 blocks
+# kept, RB 8, C 2^12)
 TUNED_PLANS = "2,22,4,5,13,16,3,9;2,20,5,3,12,31,3,9"
 CU, LANES, CLOCK = 256, 64, 2.4e9
 ALU_PEAK = CU * LANES * CLOCK          # 32-bit VALU issue slots per second
@@ -39,10 +44,68 @@ HBM_PEAK = 8.0e12                      # bytes per second
 SLOTS_BUTTERFLY = 10                   # Shoup multiply (5) + add and subtract with range reduction (5)
 SLOTS_MULMOD_CONST = 5                 # Shoup: mul_hi (2) + 2 mul_lo + sub
 SLOTS_MULMOD_VAR = 8                   # Montgomery: 2 mul_hi (4) + 2 mul_lo + add + carry
+MODEL = os.path.join(ROOT, "paper_1609_01010_amd", "data", "cost_model.txt")
+KIND_DIRECT, KIND_LDS, KIND_FOURSTEP = 0, 1, 2
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def nprime(plan):
+    """Relaxed transform length n' = ma L / RA of a plan."""
+    return plan.ma << (plan.log_l - plan.log_ra)
+
+
+def per_element_slots(log_n):
+    """Algorithmic VALU slots per element of n' of a product whose transforms
+    span 2^log_n points: three transforms of (log_n)/2 butterflies per element,
+    three four-step twiddle multiplies and the scale (constants), one
+    pointwise product (variables)."""
+    return 3 * (log_n / 2) * SLOTS_BUTTERFLY + 4 * SLOTS_MULMOD_CONST + SLOTS_MULMOD_VAR
+
+
+def product_units(la, lb, plan):
+    """(algorithmic HBM bytes, algorithmic VALU slots) of one product: operands
+    read once and the result written once; a four-step plan also writes and
+    reads its two n'-word intermediates (8 n' + 8 n' + 4 n' + 4 n'); the
+    defining sum costs one variable product per term."""
+    lc = la + lb - 1
+    byts = 4 * (la + lb + lc)
+    if plan.kind == KIND_DIRECT:
+        return byts, SLOTS_MULMOD_VAR * la * lb
+    n = nprime(plan)
+    if plan.kind == KIND_FOURSTEP:
+        byts += 24 * n
+    return byts, n * per_element_slots(plan.log_l)
+
+
+def family_units(items, plans):
+    """Algorithmic (bytes, slots) per kernel family of a batch: the defining
+    sums, the one-work-group convolution, and the four-step convolution's
+    column forward, row and column inverse passes."""
+    out = {}
+
+    def add(k, b, s):
+        x = out.setdefault(k, [0.0, 0.0])
+        x[0] += b
+        x[1] += s
+
+    for it, pl in zip(items, plans):
+        la, lb = it.a.size, it.b.size
+        lc = la + lb - 1
+        if pl.kind == KIND_DIRECT:
+            add("direct", *product_units(la, lb, pl))
+        elif pl.kind == KIND_LDS:
+            add("lds_conv", *product_units(la, lb, pl))
+        else:
+            n = nprime(pl)
+            log_r = pl.log_l - pl.log_c
+            add("col_fwd", 4 * (la + lb) + 8 * n, 2 * n * (log_r / 2) * SLOTS_BUTTERFLY)
+            add("row_conv", 12 * n, n * (3 * (pl.log_c / 2) * SLOTS_BUTTERFLY + 4 * SLOTS_MULMOD_CONST +
+                                         SLOTS_MULMOD_VAR))
+            add("col_inv", 4 * n + 4 * lc, n * (log_r / 2) * SLOTS_BUTTERFLY)
+    return out
 
 
 def row_conv_units(plan, n_rows_elems):
@@ -64,76 +127,6 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
     ms = time_loop(torch, lambda i: dst.copy_(src), reps)
     del src, dst
     return 2 * nbytes / (ms * 1e-3)
-
-
-def cpu_baseline(a2, b2, a3, b3, target_s=10.0):
-    """The oracle's defining sum timed on a bounded sample of output coefficients."""
-    import numpy as np
-
-    from oracle import poly as op
-
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    rng = np.random.default_rng(7)
-
-    def run(n):
-        k2 = np.sort(rng.choice((1 << 22) - 1, size=n, replace=False))
-        k3 = np.sort(rng.choice(1000000, size=max(1, n // 4), replace=False))
-        t0 = time.perf_counter()
-        op.poly_mul_sample(a2, b2, P, k2)
-        op.poly_mul_sample(a3, b3, P, k3)
-        return time.perf_counter() - t0, n + max(1, n // 4)
-
-    dt, cnt = run(64)
-    n = int(min(200000, max(64, 64 * target_s / max(dt, 1e-3))))
-    dt, cnt = run(n)
-    # the oracle's O(n log n) route (textbook radix-2 transforms, OpenMP over
-    # the blocks of each level) on the whole step, for scale
-    t0 = time.perf_counter()
-    op.poly_mul_ntt(a2, b2, P, G)
-    op.poly_mul_ntt(a3, b3, P, G)
-    dt_ntt = time.perf_counter() - t0
-    lc_step = a2.size + b2.size - 1 + a3.size + b3.size - 1
-    # the oracle's integer product (CPython int, one thread) on the first 2^17
-    # limbs of the two 2^21-limb operands
-    from paper_1609_01010_amd import inputs
-
-    ia, ib = inputs.int_operands()
-    n17 = 1 << 17
-    t0 = time.perf_counter()
-    op.int_mul(ia[:n17], ib[:n17])
-    dt_int = time.perf_counter() - t0
-    return {
-        "value": cnt / dt,
-        "unit": "coeffs/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": f"{cnt} output coefficients ({n} of the 2^21 x 2^21 product, {cnt - n} of the 600001 x 400000 "
-                  f"product) by the schoolbook sum c_k = sum a_i b_(k-i) mod p, OpenMP over k; {dt:.1f} s",
-        "ntt_route": {"value": lc_step / dt_ntt, "unit": "coeffs/s", "cores": threads,
-                      "sample": f"one whole step (both products) by the oracle's radix-2 transforms; {dt_ntt:.2f} s"},
-        "int_mul_route": {"value": 2 * n17 / dt_int, "unit": "limbs/s", "cores": 1,
-                          "sample": f"2^17 x 2^17 16-bit limbs by CPython's int multiply; {dt_int:.2f} s"},
-    }
-
-
-def learned_pick(pm, lc, p, only_truncated=False):
-    """The cost model's pick among the candidate plans (optionally only the
-    relaxed-TFT plans, n' < L)."""
-    cands = pm.plan_candidates(lc, p)
-    if only_truncated:
-        cands = [c for c in cands if c.kind != 0 and (c.ma << (c.log_l - c.log_ra)) < (1 << c.log_l)]
-    pred = pm.model_predict(lc, p, cands)
-    return cands[int(pred.argmin())]
-
-
-def tuned_pick(pm, lc, p, only_truncated=False, reps=7):
-    """The autotuner's pick: every candidate plan timed (median of reps runs),
-    the fastest kept (optionally among the relaxed-TFT plans only)."""
-    pm.tune([lc], p, reps=reps)
-    rows = [r for r in pm.tune_db_rows() if r[0] == lc and r[1] == p]
-    if only_truncated:
-        rows = [r for r in rows if r[2].kind != 0 and (r[2].ma << (r[2].log_l - r[2].log_ra)) < (1 << r[2].log_l)]
-    return min(rows, key=lambda r: r[3])[2]
 
 
 def time_calls(torch, fn, reps):
@@ -165,6 +158,272 @@ def time_loop(torch, fn, n):
     return e0.elapsed_time(e1) / n
 
 
+def source_hash():
+    """Hash of the library sources and the shipped cost model: counter files
+    taken on other sources are not reported."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1609_01010_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    with open(MODEL, "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def counters_from_profiles(name, src_hash):
+    """A committed rocprofv3 counter summary (profiles/<name>.json), if it was
+    taken on the current sources, else None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    return d if d.get("source_sha256") == src_hash else None
+
+
+# ---------------------------------------------------------------------------
+# CPU baselines
+
+def cpu_baseline(items, target_s=10.0):
+    """The oracle timed on a bounded sample of the batch: its schoolbook sum
+    c_k = sum a_i b_(k-i) mod p on output coefficients drawn uniformly over
+    all the batch's outputs, and its textbook radix-2 transforms on every
+    16th product whole."""
+    import numpy as np
+
+    from oracle import poly as op
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(7)
+    lcs = np.array([it.a.size + it.b.size - 1 for it in items], dtype=np.int64)
+    cum = np.cumsum(lcs)
+    total = int(cum[-1])
+
+    def run(n):
+        picks = np.sort(rng.choice(total, size=n, replace=False))
+        prod = np.searchsorted(cum, picks, side="right")
+        t0 = time.perf_counter()
+        for k in np.unique(prod):
+            ks = picks[prod == k] - (cum[k] - lcs[k])
+            it = items[int(k)]
+            op.poly_mul_sample(it.a, it.b, it.p, ks)
+        return time.perf_counter() - t0
+
+    dt = run(512)
+    n = int(min(2_000_000, max(512, 512 * target_s / max(dt, 1e-3))))
+    dt = run(n)
+    sub = items[::16]
+    t0 = time.perf_counter()
+    for it in sub:
+        op.poly_mul_ntt(it.a, it.b, it.p, _root(it.p))
+    dt_ntt = time.perf_counter() - t0
+    lc_sub = sum(it.a.size + it.b.size - 1 for it in sub)
+    return {
+        "value": n / dt,
+        "unit": "coeffs/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{n} output coefficients drawn uniformly over the {len(items)} products' {total} outputs, by "
+                  f"the oracle's schoolbook sum c_k = sum a_i b_(k-i) mod p (OpenMP over k); {dt:.1f} s",
+        "ntt_route": {"value": lc_sub / dt_ntt, "unit": "coeffs/s", "cores": threads,
+                      "sample": f"every 16th product ({len(sub)} of {len(items)}) whole by the oracle's radix-2 "
+                                f"transforms; {dt_ntt:.2f} s"},
+    }
+
+
+def _root(p):
+    from paper_1609_01010_amd import inputs
+
+    return inputs.PRIMES[p]
+
+
+# ---------------------------------------------------------------------------
+# the headline: the 4096-product batch
+
+def padded_plan(pm, lc, p):
+    """The default plan of output length lc without truncation (the padded
+    power-of-two transform); the defining sum for at most 64 outputs."""
+    pl = pm.plan_for(lc, p)
+    if pl.kind != KIND_DIRECT:
+        pl.ma = 1 << pl.log_ra
+    return pl
+
+
+def batch_bench(pm, torch, dev, args):
+    import ctypes
+
+    import numpy as np
+
+    from oracle import poly as op
+    from paper_1609_01010_amd import inputs
+
+    items = inputs.batch_uneven()
+    lcs = [it.a.size + it.b.size - 1 for it in items]
+    ncoef = sum(lcs)
+    # two buffer sets (each about 0.9 GB of operands and outputs), alternated
+    # from step to step: every step reads its inputs from HBM, not from the
+    # 256 MB MALL
+    sets = []
+    for _ in range(2):
+        probs = [(torch.from_numpy(it.a).to(dev), torch.from_numpy(it.b).to(dev), it.p) for it in items]
+        outs = [torch.empty(lc, dtype=torch.uint32, device=dev) for lc in lcs]
+        sets.append((probs, outs))
+    torch.cuda.synchronize()
+    set_bytes = sum(4 * (it.a.size + it.b.size + lc) for it, lc in zip(items, lcs))
+    log(f"batch: {len(items)} products, {ncoef} output coefficients, {set_bytes / 1e9:.2f} GB per buffer set")
+
+    # --- batched + learned plans (the headline)
+    pm.model_load(MODEL)
+    pm.set_policy(pm.POLICY_LEARNED)
+    pm.plan_cache_clear()
+    prepared = [pm.PreparedBatch(pr, outs=o) for pr, o in sets]
+    t0 = time.perf_counter()
+    prepared[0].run()  # plans the shape: the model's picks, checked against the default plans on the whole batch
+    torch.cuda.synchronize()
+    first_call_s = time.perf_counter() - t0
+    plans = pm.batch_plans_used(len(items))
+    for i in range(args.warmup):
+        prepared[i % 2].run()
+    torch.cuda.synchronize()
+    if pm.stream_check() != 0:
+        raise SystemExit("device reported an error during warm-up")
+    # spot check against the oracle's schoolbook sum (the full parity tests live in tests/)
+    rng = np.random.default_rng(5)
+    for k in rng.choice(len(items), 24, replace=False):
+        for si in range(2):
+            it = items[int(k)]
+            ks = rng.integers(0, lcs[int(k)], 4)
+            got = sets[si][1][int(k)].cpu().numpy()[ks]
+            assert np.array_equal(got, op.poly_mul_sample(it.a, it.b, it.p, ks)), "batch output differs from the oracle"
+
+    # timed: K graph launches back to back, HIP events on the launch stream
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    e0.record()
+    for i in range(args.steps):
+        prepared[i % 2].run()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    gpu_ms = e0.elapsed_time(e1)
+    ms_step = gpu_ms / args.steps
+    if pm.stream_check() != 0:
+        raise SystemExit("device reported an error in the timed steps")
+
+    # per-kernel durations: the same batch traced (its classes' launches one
+    # after the other, each bracketed by its own events)
+    pm.trace_reset()
+    pm.trace_enable(True)
+    for i in range(2):
+        prepared[i % 2].run()
+    torch.cuda.synchronize()
+    pm.trace_enable(False)
+    traced = {}
+    for name in pm.trace_names():
+        tot, n = pm.trace_query(name)
+        traced[name] = {"launches": n, "total_us_per_batch": 1e3 * tot / 2, "avg_us": 1e3 * tot / max(n, 1)}
+    pm.trace_reset()
+    traced_ms = sum(v["total_us_per_batch"] for v in traced.values()) / 1e3
+
+    fam = family_units(items, plans)
+    for name, v in traced.items():
+        if name in fam:
+            v["alg_bytes_per_batch"], v["alg_slots_per_batch"] = fam[name]
+            t = v["total_us_per_batch"] * 1e-6
+            v["alu_frac"] = fam[name][1] / t / ALU_PEAK
+            v["hbm_frac"] = fam[name][0] / t / HBM_PEAK
+    dom = max((k for k in traced if k in fam), key=lambda k: traced[k]["total_us_per_batch"])
+    plan_hist = {}
+    for pl in plans:
+        key = ",".join(str(v) for v in pl.as_tuple()[:5]) + "," + ",".join(str(v) for v in pl.as_tuple()[6:])
+        plan_hist[key] = plan_hist.get(key, 0) + 1
+
+    byts, slots = 0.0, 0.0
+    for it, pl in zip(items, plans):
+        b, s_ = product_units(it.a.size, it.b.size, pl)
+        byts += b
+        slots += s_
+    res = {
+        "items": items, "plans": plans, "ncoef": ncoef, "ms_step": ms_step, "gpu_ms": gpu_ms, "wall": wall,
+        "value": ncoef / (ms_step * 1e-3), "alg_bytes": byts, "alg_slots": slots,
+        "traced": traced, "traced_ms": traced_ms, "dom": dom, "plan_hist": plan_hist,
+        "first_call_s": first_call_s, "set_bytes": set_bytes, "plain": None,
+    }
+    if args.headline_only:
+        pm.set_policy(pm.POLICY_DEFAULT)
+        return res
+
+    # --- plain: one call per product, padded power-of-two plans
+    pm.set_policy(pm.POLICY_DEFAULT)
+    pm.plan_cache_clear()
+    pplans = [padded_plan(pm, lc, it.p) for it, lc in zip(items, lcs)]
+    L = pm.lib()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    probs0, outs0 = sets[0]
+    args_loop = [(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(y.data_ptr()), y.numel(), pp,
+                  ctypes.c_void_p(o.data_ptr()), ctypes.byref(pl), sp)
+                 for (x, y, pp), o, pl in zip(probs0, outs0, pplans)]
+
+    def plain_loop():
+        for a_ in args_loop:
+            st = L.pm_poly_mul_plan(*a_)
+            if st:
+                raise SystemExit(f"pm_poly_mul_plan failed: {st}")
+
+    plain_loop()
+    ms_loop = time_calls(torch, plain_loop, 3)
+
+    def graph_time(put_plans):
+        pm.plan_cache_clear()
+        if put_plans is not None:
+            for it, lc, pl in zip(items, lcs, put_plans):
+                if pl.kind != KIND_DIRECT:
+                    pm.plan_cache_put(lc, it.p, pl)
+        pb = [pm.PreparedBatch(pr, outs=o) for pr, o in sets]
+        pb[0].run()
+        torch.cuda.synchronize()
+        ms = time_calls(torch, lambda: (pb[0].run(), pb[1].run()), max(5, args.steps // 4)) / 2
+        return ms
+
+    ms_graph_padded = graph_time(pplans)
+    ms_graph_default = graph_time(None)
+    pm.plan_cache_clear()
+    if pm.stream_check() != 0:
+        raise SystemExit("device error in the plain legs")
+    # the last leg (relaxed default plans) left its products in set 0: check some
+    for k in rng.choice(len(items), 8, replace=False):
+        it = items[int(k)]
+        ks = rng.integers(0, lcs[int(k)], 4)
+        assert np.array_equal(sets[0][1][int(k)].cpu().numpy()[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
+    pad_bytes, pad_slots = 0.0, 0.0
+    for it, pl in zip(items, pplans):
+        b, s = product_units(it.a.size, it.b.size, pl)
+        pad_bytes += b
+        pad_slots += s
+
+    res["plain"] = {
+        "loop_of_single_calls_padded_ms": ms_loop,
+        "graph_padded_default_plans_ms": ms_graph_padded,
+        "graph_relaxed_default_plans_ms": ms_graph_default,
+        "batched_learned_ms": ms_step,
+        "speedup_vs_loop_padded": ms_loop / ms_step,
+        "speedup_vs_graph_padded": ms_graph_padded / ms_step,
+        "speedup_vs_graph_default": ms_graph_default / ms_step,
+        "padded_alg_slots": pad_slots, "padded_alg_bytes": pad_bytes,
+        "note": "loop: one pm_poly_mul_plan call per product (host-call bound); graph legs: the same "
+                "pm_poly_mul_batch graph with padded power-of-two default plans, and with the relaxed "
+                "default plans (the library without the cost model)",
+    }
+    del sets, prepared
+    return res
+
+
+# ---------------------------------------------------------------------------
+# the other workloads
+
 def standalone_transform(pm, torch, dev, copy_bw, n_calls=40):
     """Forward transform of 2^22 points in bit-reversed order (the TFT hook with
     n = L): two passes over HBM, 16 N algorithmic bytes; 8 rotating buffer
@@ -186,6 +445,17 @@ def standalone_transform(pm, torch, dev, copy_bw, n_calls=40):
         for i in range(8):
             fwd(i)
         ms = time_loop(torch, fwd, n_calls)
+        pm.trace_reset()
+        pm.trace_enable(True)
+        for i in range(8):
+            fwd(i)
+        torch.cuda.synchronize()
+        pm.trace_enable(False)
+        kern = {}
+        for name in pm.trace_names():
+            tot, n = pm.trace_query(name)
+            kern[name] = 1e3 * tot / max(n, 1)
+        pm.trace_reset()
         x0, y0 = xs[0].cpu().numpy(), ys[0].cpu().numpy()
         w = op.root(pp, g, N)
         ok = all(int(y0[i]) == op.eval_at(x0, pp, pow(w, op.bitrev(i, 22), pp)) for i in (0, 1, 12345, N - 1))
@@ -193,82 +463,136 @@ def standalone_transform(pm, torch, dev, copy_bw, n_calls=40):
                                   "hbm_alg_GBps": 16 * N / (ms * 1e-3) / 1e9,
                                   "hbm_frac": 16 * N / (ms * 1e-3) / HBM_PEAK,
                                   "hbm_frac_vs_copy": 16 * N / (ms * 1e-3) / copy_bw,
+                                  "kernels_avg_us": kern,
                                   "bit_exact_sampled": bool(ok)}
         del xs, ys
     return out
 
 
-def extra_configs(pm, torch, dev, copy_bw, reps=5):
-    """The other workloads, each timed on its own: the 1024 x 1024 product,
-    the three-primes integer product of two 2^21-limb integers, and the batch
-    of 4096 uneven products, plain (a loop of single products with the
-    default plans) against batched (one graph launch, learned plans)."""
+def large_products(pm, torch, dev, args):
+    """The two plain large products over Z/2013265921Z (2^21 x 2^21 through
+    L = 2^22, and 600001 x 400000 through the relaxed TFT of 10^6 outputs),
+    with the autotuner's plans; per-kernel durations from a traced pass and
+    the row pass's roofline."""
+    import numpy as np
+
+    from oracle import poly as op
+    from paper_1609_01010_amd import inputs
+
+    a2, b2, _ = inputs.large_pow2_product()
+    a3, b3, _ = inputs.large_tft_product()
+    lc2, lc3 = a2.size + b2.size - 1, a3.size + b3.size - 1
+    sets = []
+    for _ in range(16):
+        sets.append(tuple(torch.from_numpy(x).to(dev) for x in (a2, b2, a3, b3)) +
+                    (torch.empty(lc2, dtype=torch.uint32, device=dev), torch.empty(lc3, dtype=torch.uint32, device=dev)))
+    plan2, plan3 = (pm.Plan(*[int(v) for v in s.split(",")]) for s in args.plans.split(";"))
+
+    def step(i):
+        ta2, tb2, ta3, tb3, c2, c3 = sets[i % len(sets)]
+        pm.poly_mul(ta2, tb2, P, out=c2, plan=plan2)
+        pm.poly_mul(ta3, tb3, P, out=c3, plan=plan3)
+
+    for i in range(3):
+        step(i)
+    torch.cuda.synchronize()
+    ks = np.array([0, 1, 12345, lc2 // 2, lc2 - 1])
+    assert np.array_equal(sets[0][4].cpu().numpy()[ks], op.poly_mul_sample(a2, b2, P, ks))
+    ks = np.array([0, 1, 12345, lc3 // 2, lc3 - 1])
+    assert np.array_equal(sets[0][5].cpu().numpy()[ks], op.poly_mul_sample(a3, b3, P, ks))
+    n = 30
+    ms = time_loop(torch, step, n)
+    pm.trace_reset()
+    pm.trace_enable(True)
+    for i in range(n):
+        step(i)
+    torch.cuda.synchronize()
+    pm.trace_enable(False)
+    kernels = {}
+    for name in pm.trace_names():
+        tot, k = pm.trace_query(name)
+        kernels[name] = {"launches": k, "avg_us": 1e3 * tot / max(k, 1)}
+    pm.trace_reset()
+    row = kernels["row_conv"]
+    slots2, bytes2 = row_conv_units(plan2, (plan2.ma << plan2.log_rb) << plan2.log_c)
+    slots3, bytes3 = row_conv_units(plan3, (plan3.ma << plan3.log_rb) << plan3.log_c)
+    achieved = (slots2 + slots3) / 2 / (row["avg_us"] * 1e-6)
+    del sets
+    return {
+        "workload": "2^21 x 2^21 (transform 2^22) + 600001 x 400000 (relaxed TFT, 10^6 outputs) mod 2013265921",
+        "plans": [list(plan2.as_tuple()), list(plan3.as_tuple())],
+        "us_per_step": ms * 1e3, "coeffs_per_s": (lc2 + lc3) / (ms * 1e-3),
+        "kernels": kernels,
+        "row_conv_alu_frac": achieved / ALU_PEAK,
+        "row_conv_hbm_frac": (bytes2 + bytes3) / 2 / (row["avg_us"] * 1e-6) / HBM_PEAK,
+    }
+
+
+def extra_configs(pm, torch, dev, copy_bw, args, reps=5):
+    """The other workloads, each timed on its own: the 1024 x 1024 product
+    (latency, beside its kernel time), the two plain large products, the
+    three-primes integer product, the 2^22-point transform, a bivariate
+    product, the products of the two factor rings of eq. 13 and the general
+    radix."""
     import numpy as np
 
     from oracle import poly as op
     from paper_1609_01010_amd import inputs
 
     out = {}
+    pm.set_policy(pm.POLICY_DEFAULT)
+    pm.plan_cache_clear()
     a, b, p = inputs.single_product_1024()
     ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
     c = torch.empty(2047, dtype=torch.uint32, device=dev)
     pm.poly_mul(ta, tb, p, out=c)
     ms = time_calls(torch, lambda: pm.poly_mul(ta, tb, p, out=c), 50)
+    ms_loop = time_loop(torch, lambda i: pm.poly_mul(ta, tb, p, out=c), 200)
+    pm.trace_reset()
+    pm.trace_enable(True)
+    for _ in range(20):
+        pm.poly_mul(ta, tb, p, out=c)
+    torch.cuda.synchronize()
+    pm.trace_enable(False)
+    ktot = 0.0
+    for name in pm.trace_names():
+        tot, n = pm.trace_query(name)
+        ktot += 1e3 * tot / 20
+    pm.trace_reset()
+    t0 = time.perf_counter()
+    for _ in range(200):
+        pm.poly_mul(ta, tb, p, out=c)
+    host_us = (time.perf_counter() - t0) / 200 * 1e6
+    torch.cuda.synchronize()
     assert np.array_equal(c.cpu().numpy(), op.poly_mul(a, b, p))
-    out["single_1024x1024_p998244353"] = {"us": ms * 1e3, "coeffs_per_s": 2047 / (ms * 1e-3), "bit_exact": True}
+    out["single_1024x1024_p998244353"] = {
+        "us_one_call": ms * 1e3, "us_per_call_back_to_back": ms_loop * 1e3, "kernel_us": ktot,
+        "host_us_per_call": host_us, "coeffs_per_s": 2047 / (ms * 1e-3), "bit_exact": True}
+
+    out["plain_large_products"] = large_products(pm, torch, dev, args)
 
     ia, ib = inputs.int_operands()
     tia, tib = torch.from_numpy(ia).to(dev), torch.from_numpy(ib).to(dev)
     ic = torch.empty(ia.size + ib.size, dtype=torch.uint16, device=dev)
     pm.int_mul(tia, tib, out=ic)
     ms = time_calls(torch, lambda: pm.int_mul(tia, tib, out=ic), reps)
+    pm.trace_reset()
+    pm.trace_enable(True)
+    pm.int_mul(tia, tib, out=ic)
+    torch.cuda.synchronize()
+    pm.trace_enable(False)
+    ik = {}
+    for name in pm.trace_names():
+        tot, n = pm.trace_query(name)
+        ik[name] = 1e3 * tot
+    pm.trace_reset()
     got = ic.cpu().numpy()
     q = (1 << 61) - 1
     ok = op.limbs_to_int(got) % q == (op.limbs_to_int(ia) % q) * (op.limbs_to_int(ib) % q) % q
-    out["int_mul_2^21x2^21_limbs"] = {"ms": ms, "limbs_per_s": got.size / (ms * 1e-3),
+    out["int_mul_2^21x2^21_limbs"] = {"ms": ms, "limbs_per_s": got.size / (ms * 1e-3), "kernels_us": ik,
                                       "check": "product mod 2^61-1 matches" if ok else "MISMATCH"}
+    del tia, tib, ic
 
-    items = inputs.batch_uneven()
-    probs = [(torch.from_numpy(it.a).to(dev), torch.from_numpy(it.b).to(dev), it.p) for it in items]
-    outs = [torch.empty(it.a.size + it.b.size - 1, dtype=torch.uint32, device=dev) for it in items]
-    ncoef = sum(o.numel() for o in outs)
-
-    # arguments marshalled once for both: the plain loop makes one C call per
-    # product on the current stream, the batch one C call in all
-    import ctypes
-
-    L = pm.lib()
-    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    args = [(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(y.data_ptr()), y.numel(), pp,
-             ctypes.c_void_p(o.data_ptr()), sp) for (x, y, pp), o in zip(probs, outs)]
-
-    def plain():
-        for a_ in args:
-            L.pm_poly_mul(*a_)
-
-    pm.set_policy(pm.POLICY_DEFAULT)
-    pm.plan_cache_clear()
-    plain()
-    ms_plain = time_calls(torch, plain, 3)
-    prepared = pm.PreparedBatch(probs, outs=outs)
-    prepared.run()
-    torch.cuda.synchronize()
-    ms_batch_default = time_calls(torch, prepared.run, max(reps, 7))
-    pm.set_policy(pm.POLICY_LEARNED)
-    pm.plan_cache_clear()
-    prepared = pm.PreparedBatch(probs, outs=outs)
-    prepared.run()
-    torch.cuda.synchronize()
-    ms_batch = time_calls(torch, prepared.run, max(reps, 7))
-    pm.set_policy(pm.POLICY_DEFAULT)
-    pm.plan_cache_clear()
-    if pm.stream_check() != 0:
-        raise SystemExit("device error in the batch")
-    rng = np.random.default_rng(5)
-    for k in rng.choice(len(items), 16, replace=False):
-        it = items[int(k)]
-        ks = rng.integers(0, outs[int(k)].numel(), 4)
-        assert np.array_equal(outs[int(k)].cpu().numpy()[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
     out.update(standalone_transform(pm, torch, dev, copy_bw))
 
     # a bivariate product by Kronecker substitution: 1024 x 1024 coefficients
@@ -282,9 +606,7 @@ def extra_configs(pm, torch, dev, copy_bw, reps=5):
     out["bivariate_1024^2_x_1024^2_p2013265921"] = {"us": ms * 1e3, "coeffs_per_s": 2047 * 2047 / (ms * 1e-3)}
     del ma, mb, mc
 
-    # products in the two factors of eq. 13 at n = 2^21: the operands of the
-    # headline's 2^21 x 2^21 product, reduced mod x^n - 1 / x^n + 1 (length-n
-    # transforms, no padding)
+    # products in the two factors of eq. 13 at n = 2^21 (length-n transforms, no padding)
     a2, b2, pp = inputs.large_pow2_product()
     n21 = a2.size
     ra, rb = torch.from_numpy(a2).to(dev), torch.from_numpy(b2).to(dev)
@@ -298,9 +620,10 @@ def extra_configs(pm, torch, dev, copy_bw, reps=5):
         want = (lin[:4] + sign * lin[4:]) % pp
         ok = np.array_equal(rc.cpu().numpy()[ks], want.astype(np.uint32))
         out[f"{name}_2^21_p{pp}"] = {"us": ms * 1e3, "coeffs_per_s": n21 / (ms * 1e-3), "bit_exact_sampled": bool(ok)}
+    del ra, rb, rc
     # general radix: products of length q 2^k - 1 through the length-q 2^k
-    # circular convolution (prime-factor split, q rows of 2^k), beside the
-    # same product by the autotuned power-of-two plans (relaxed TFT)
+    # circular convolution (prime-factor split), beside the default
+    # power-of-two plan (relaxed TFT) of the same product
     for q, k in ((3, 20), (5, 18), (15, 16)):
         la = (q << k) // 2
         lb = (q << k) - la
@@ -312,52 +635,28 @@ def extra_configs(pm, torch, dev, copy_bw, reps=5):
         ms_mixed = time_loop(torch, lambda i: pm.poly_mul_mixed(xa, xb, pp, q, out=xc), 20)
         ks = np.array([0, 1, lcm // 3, lcm - 1])
         ok = np.array_equal(xc.cpu().numpy()[ks], op.poly_mul_sample(ma_, mb_, pp, ks))
-        plan = tuned_pick(pm, lcm, pp)
-        pm.tune_db_clear()
-        pm.poly_mul(xa, xb, pp, out=xc, plan=plan)
-        ms_pow2 = time_loop(torch, lambda i: pm.poly_mul(xa, xb, pp, out=xc, plan=plan), 20)
+        pm.poly_mul(xa, xb, pp, out=xc)
+        ms_pow2 = time_loop(torch, lambda i: pm.poly_mul(xa, xb, pp, out=xc), 20)
         out[f"mixed_radix_{q}x2^{k}_p{pp}"] = {
             "lc": lcm, "us": ms_mixed * 1e3, "coeffs_per_s": lcm / (ms_mixed * 1e-3),
-            "pow2_tuned_us": ms_pow2 * 1e3, "pow2_plan": list(plan.as_tuple()), "bit_exact_sampled": bool(ok)}
+            "pow2_default_us": ms_pow2 * 1e3, "bit_exact_sampled": bool(ok)}
         del xa, xb, xc
-    out["batch_4096_uneven"] = {
-        "output_coeffs": ncoef,
-        "plain_ms": ms_plain, "plain_coeffs_per_s": ncoef / (ms_plain * 1e-3),
-        "batched_learned_ms": ms_batch, "batched_learned_coeffs_per_s": ncoef / (ms_batch * 1e-3),
-        "batched_default_plans_ms": ms_batch_default,
-        "speedup": ms_plain / ms_batch,
-    }
     return out
-
-
-def counters_from_profiles(kernel_src_hash):
-    """HBM bytes per launch and VALU utilisation of the dominant kernel from the
-    committed rocprofv3 counter runs, if they were taken on the current kernel
-    source (else None, None)."""
-    path = os.path.join(ROOT, "profiles", "row_conv_counters.json")
-    try:
-        with open(path) as f:
-            d = json.load(f)
-    except OSError:
-        return None, None
-    if d.get("source_sha256") != kernel_src_hash:
-        return None, None
-    return d.get("hbm_bytes_per_launch"), d.get("valu")
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--rotate", type=int, default=16,
-                    help="buffer sets rotated over the steps (16 sets = 640 MiB, over twice the 256 MB MALL)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the batched, learned-plan steps (no plain legs, other workloads or CPU baseline): "
+                         "the command the profiles of the batch are taken with")
     ap.add_argument("--plans", default=TUNED_PLANS,
-                    help="plans for the two products, 'kind,log_l,log_ra,log_rb,log_c,ma,lq,lnt;...' "
-                         "(default: the autotuner's picks on MI355X, the plans of the committed profiles)")
-    ap.add_argument("--tune", action="store_true", help="run the autotuner for the two products instead")
+                    help="plans of the two plain large products among the other workloads, "
+                         "'kind,log_l,log_ra,log_rb,log_c,ma,lq,lnt;...' (default: the autotuner's picks on MI355X)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 256 MiB three times (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -377,154 +676,87 @@ def main():
               "multi-GPU mode. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1609_01010_amd as pm
-    from paper_1609_01010_amd import inputs
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     pm.lib()
     dev = torch.device("cuda:0")
-    a2, b2, _ = inputs.large_pow2_product()
-    a3, b3, _ = inputs.large_tft_product()
-    lc2, lc3 = a2.size + b2.size - 1, a3.size + b3.size - 1
-    sets = []
-    for _ in range(args.rotate):
-        sets.append(tuple(torch.from_numpy(x).to(dev) for x in (a2, b2, a3, b3)) +
-                    (torch.empty(lc2, dtype=torch.uint32, device=dev), torch.empty(lc3, dtype=torch.uint32, device=dev)))
-    # plans: the autotuner's picks on MI355X (exhaustive empirical search; for
-    # the 10^6 product among the relaxed-TFT plans only: the workload excludes
-    # padding to 2^20), fixed so that the default run is the profiled one;
-    # --tune searches again before the timed region.  The cost model's picks
-    # are listed beside them.
-    pm.model_load(os.path.join(ROOT, "paper_1609_01010_amd", "data", "cost_model.txt"))
-    lplan2 = learned_pick(pm, lc2, P)
-    lplan3 = learned_pick(pm, lc3, P, only_truncated=True)
-    if args.tune:
-        pm.tune_db_clear()
-        plan2 = tuned_pick(pm, lc2, P)
-        plan3 = tuned_pick(pm, lc3, P, only_truncated=True)
-        pm.tune_db_clear()
-        pm.plan_cache_clear()
-        plan_source = "autotuner, this run (every candidate timed, fastest kept)"
-    else:
-        plan2, plan3 = (pm.Plan(*[int(v) for v in s.split(",")]) for s in args.plans.split(";"))
-        plan_source = ("given on the command line" if args.plans != TUNED_PLANS else
-                       "the autotuner's picks on MI355X (fixed; --tune searches again)")
-    log("plans:", plan2, plan3, "learned:", lplan2, lplan3)
-
-    def step(i):
-        ta2, tb2, ta3, tb3, c2, c3 = sets[i % len(sets)]
-        pm.poly_mul(ta2, tb2, P, out=c2, plan=plan2)
-        pm.poly_mul(ta3, tb3, P, out=c3, plan=plan3)
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    if pm.stream_check() != 0:
-        raise SystemExit("device reported an error during warm-up")
-    # correctness spot check of the timed configuration (the full parity
-    # tests live in tests/)
-    from oracle import poly as op
-
-    ks = np.array([0, 1, 12345, lc2 // 2, lc2 - 1])
-    assert np.array_equal(sets[0][4].cpu().numpy()[ks], op.poly_mul_sample(a2, b2, P, ks))
-
-    # the timed steps run untraced; a second, traced pass of the same steps
-    # gives the per-kernel durations (events around every launch)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    for i in range(args.steps):
-        step(i)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = e0.elapsed_time(e1)
-    ms_per_step = gpu_ms / args.steps
-    coeffs = (lc2 + lc3) * args.steps
-    value = coeffs / (gpu_ms * 1e-3)
-
-    pm.trace_reset()
-    pm.trace_enable(True)
-    for i in range(args.steps):
-        step(i)
-    torch.cuda.synchronize()
-    pm.trace_enable(False)
-    kernels = {}
-    for name in pm.trace_names():
-        tot, n = pm.trace_query(name)
-        kernels[name] = {"launches": n, "avg_us": 1e3 * tot / max(n, 1), "share": tot / gpu_ms}
-    pm.trace_reset()
-    dom = max(kernels, key=lambda k: kernels[k]["share"])
+    torch.zeros(1, device=dev)
     copy_bw = copy_bandwidth(torch, dev)
-    row = kernels.get("row_conv")
-    rows2 = plan2.ma << plan2.log_rb
-    rows3 = plan3.ma << plan3.log_rb
-    slots2, bytes2 = row_conv_units(plan2, rows2 << plan2.log_c)
-    slots3, bytes3 = row_conv_units(plan3, rows3 << plan3.log_c)
-    per_launch_slots = (slots2 + slots3) / 2
-    per_launch_bytes = (bytes2 + bytes3) / 2
-    src = open(os.path.join(ROOT, "paper_1609_01010_amd", "csrc", "fourstep.hip"), "rb").read()
-    src += open(os.path.join(ROOT, "paper_1609_01010_amd", "csrc", "ntt_device.h"), "rb").read()
-    src += open(os.path.join(ROOT, "paper_1609_01010_amd", "csrc", "arith.h"), "rb").read()
-    src_hash = hashlib.sha256(src).hexdigest()
-    achieved = per_launch_slots / (row["avg_us"] * 1e-6)
-    traffic, valu = counters_from_profiles(src_hash)
+
+    if args.headline_only:
+        args.no_cpu_baseline = args.no_extra = True
+    r = batch_bench(pm, torch, dev, args)
+    t = r["ms_step"] * 1e-3
+    src_hash = source_hash()
+    counters = counters_from_profiles("batch_counters.json", src_hash)
+    traffic = counters.get("hbm_bytes_per_batch") if counters else None
+    dom = r["dom"]
+    dk = r["traced"][dom]
     roofline = {
-        "kernel": "row_conv",
+        "kernel": "one pm_poly_mul_batch graph launch: every kernel of the 4096 products",
         "bound": "alu",
-        "achieved": achieved / 1e12,
+        "achieved": r["alg_slots"] / t / 1e12,
         "peak": ALU_PEAK / 1e12,
         "unit": "Tslot/s",
-        "frac": achieved / ALU_PEAK,
+        "frac": r["alg_slots"] / t / ALU_PEAK,
         "traffic": traffic,
-        "valu_counters": valu,
-        "algorithmic_slots_per_launch": per_launch_slots,
-        "hbm_achieved_GBps": per_launch_bytes / (row["avg_us"] * 1e-6) / 1e9,
-        "hbm_frac": per_launch_bytes / (row["avg_us"] * 1e-6) / HBM_PEAK,
-        "hbm_frac_vs_copy": per_launch_bytes / (row["avg_us"] * 1e-6) / copy_bw,
+        "algorithmic_slots_per_launch": r["alg_slots"],
+        "algorithmic_bytes_per_launch": r["alg_bytes"],
+        "launch_us": r["ms_step"] * 1e3,
+        "hbm_achieved_GBps": r["alg_bytes"] / t / 1e9,
+        "hbm_frac": r["alg_bytes"] / t / HBM_PEAK,
+        "hbm_frac_vs_copy": r["alg_bytes"] / t / copy_bw,
         "copy_GBps": copy_bw / 1e9,
+        "dominant_kernel": {
+            "family": dom, "launches_per_batch": dk["launches"] / 2, "total_us_per_batch": dk["total_us_per_batch"],
+            "bound": "alu", "achieved": dk["alg_slots_per_batch"] / (dk["total_us_per_batch"] * 1e-6) / 1e12,
+            "peak": ALU_PEAK / 1e12, "unit": "Tslot/s", "frac": dk["alu_frac"], "hbm_frac": dk["hbm_frac"],
+            "timing": "the batch's class launches run one after the other, each between its own HIP events",
+        },
+        "slot_model": f"{SLOTS_BUTTERFLY} slots per radix-2 butterfly, {SLOTS_MULMOD_CONST} per multiply by a "
+                      f"constant, {SLOTS_MULMOD_VAR} per product of two variables; (15 log2 L + 28) n' per product",
     }
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(a2, b2, a3, b3)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(r["items"])
     extra = None
     if not args.no_extra:
-        del sets
         torch.cuda.empty_cache()
-        extra = extra_configs(pm, torch, dev, copy_bw)
+        extra = extra_configs(pm, torch, dev, copy_bw, args)
     out = {
         "metric": "conv coefficients/s",
-        "value": value,
+        "value": r["value"],
         "unit": "coeffs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": "plain large products mod 2013265921: 2^21 x 2^21 (transform 2^22) + "
-                        "600001 x 400000 (relaxed TFT, 10^6 outputs)",
-            "coeffs_per_step": lc2 + lc3,
-            "plans": [list(plan2.as_tuple()), list(plan3.as_tuple())],
-            "plan_source": plan_source,
-            "learned_plans": [list(lplan2.as_tuple()), list(lplan3.as_tuple())],
-            "dominant_kernel": dom,
-            "wall_s": wall,
+            "workload": "batched + learned plans: 4096 independent products, operand lengths log-uniform in "
+                        "[64, 65536], primes uniform over 998244353, 2013265921, 469762049, 167772161, "
+                        "one pm_poly_mul_batch call (one hipGraph launch)",
+            "coeffs_per_step": r["ncoef"],
+            "buffer_sets": 2,
+            "bytes_per_buffer_set": r["set_bytes"],
+            "plans_used": r["plan_hist"],
+            "plan_source": "the shipped cost model (data/cost_model.txt) in the batch context, one plan family per "
+                           "transform length and prime, kept for the shape only if the whole batch ran faster "
+                           "with them than with the default plans on its first call",
+            "first_call_s": r["first_call_s"],
+            "wall_s": r["wall"],
         },
         "roofline": roofline,
+        "plain": r["plain"],
         "cpu_baseline": cpu,
-        "kernels": kernels,
+        "kernels": r["traced"],
         "other_configs": extra,
     }
     print(json.dumps(out), flush=True)

@@ -131,9 +131,10 @@ typedef struct {
 /*
  * Batch of independent products (each as pm_poly_mul), of uneven lengths and
  * mixed primes.  `probs` is a HOST array of `count` <= 65535 problems.  The
- * products are grouped into classes of equal plan; each class runs one
- * launch per pass over all its products, and the classes are captured into
- * one hipGraph, cached by the batch's class signature.  A call whose problems
+ * products are grouped into classes of equal plan (those of at most 64
+ * outputs, computed by their defining sums, form one class); each class runs
+ * one launch per pass over all its products, and the classes are captured
+ * into one hipGraph, cached by the batch's class signature.  A call whose problems
  * have the same lengths and primes, in order, as the previous call on the
  * stream only patches the pointers into the previous job descriptors and
  * relaunches.  Under PM_POLICY_LEARNED the plans come from the cost model in
@@ -269,6 +270,14 @@ pm_status pm_set_policy(pm_policy policy);
 pm_status pm_plan_for(size_t lc, uint32_t p, pm_plan* plan);
 pm_status pm_plan_for_ctx(size_t lc, uint32_t p, int context, pm_plan* plan);
 
+/*
+ * The plans the last pm_poly_mul_batch call on `stream` (current device)
+ * used, problem by problem (kind 0 for the defining sums), into the HOST
+ * array out of `count` entries; PM_EINVAL if no batch ran on the stream or
+ * its size was not `count`.
+ */
+pm_status pm_batch_plans_used(void* stream, pm_plan* out, size_t count);
+
 /* Product with an explicit plan (validated; PM_EINVAL if it does not fit). */
 pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
                            uint32_t* c, const pm_plan* plan, void* stream);
@@ -348,7 +357,10 @@ pm_status pm_mlp_train(float* params, const float* X, const float* t, int B, int
  * events recorded on its own stream, so kernel durations can be measured in
  * a live run.  Kernel names: "direct", "lds_conv", "col_fwd", "row_conv",
  * "col_inv", "row_xform", "lds_xform", "permute", "crt_sums", "carry_scan",
- * "carry_apply", "widen". */
+ * "carry_apply", "widen", "patch_jobs"; a batch's graph launch is recorded as
+ * "batch_graph".  While tracing is on, pm_poly_mul_batch runs its classes'
+ * launches one after the other on the caller's stream instead of launching
+ * its graph, so that every recorded duration is that kernel's alone. */
 void pm_trace_enable(int on);
 /* Forget all records (waits for the recorded events). */
 void pm_trace_reset(void);

@@ -80,6 +80,7 @@ SIGNATURES = {
     "pm_init": (_int, []),
     "pm_poly_mul": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, _vp]),
     "pm_poly_mul_batch": (_int, [ctypes.POINTER(Problem), _sz, _vp]),
+    "pm_batch_plans_used": (_int, [_vp, ctypes.POINTER(Plan), _sz]),
     "pm_cyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
     "pm_poly_mul_mixed": (_int, [_vp, _sz, _vp, _sz, _u32, _u32, _vp, _vp]),
     "pm_workspace_query": (_int, [_sz, _sz, _u32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -205,6 +206,11 @@ def poly_mul(a, b, p: int, out=None, plan: Plan | None = None, stream=None):
     return out
 
 
+def init():
+    """Build the twiddle tables of the four primes on the current device."""
+    _check(lib().pm_init(), "pm_init")
+
+
 def poly_mul_multi(a, b, p: int, out=None, stream=None):
     """Dense multivariate product by Kronecker substitution.  a, b: uint32 device
     tensors with one dimension per variable (1 + the degree in it); returns the
@@ -316,6 +322,13 @@ class PreparedBatch:
     def run(self, stream=None):
         _check(lib().pm_poly_mul_batch(self.arr, self.n, _stream(stream)), "pm_poly_mul_batch")
         return self.outs
+
+
+def batch_plans_used(count: int, stream=None):
+    """The plans the last batch of `count` problems on the stream used, in problem order."""
+    arr = (Plan * max(count, 1))()
+    _check(lib().pm_batch_plans_used(_stream(stream), arr, count), "pm_batch_plans_used")
+    return [arr[i] for i in range(count)]
 
 
 def poly_mul_batch(problems, outs=None, stream=None):

@@ -1,12 +1,15 @@
 // Batched products (pm_poly_mul_batch): thousands of independent products of
 // uneven lengths and mixed primes in one hipGraph launch.
 //
-// Products are grouped into classes of equal plan and prime range; each
-// class runs as one launch per pass over all its products (blockIdx.z picks
-// the product's job descriptor).  The class launches are captured once per
-// batch shape into a graph whose classes hang off a fork, so independent
-// classes may run concurrently; later batches of the same shape reuse the
-// graph and only upload their job descriptors.
+// Products are grouped into classes of equal plan and prime range (the
+// products of at most 64 outputs, computed by their defining sums, form one
+// class); each class runs as one launch per pass over all its products
+// (blockIdx.z picks the product's job descriptor).  The class launches are
+// captured once per batch shape into a graph whose classes hang off a fork,
+// so independent classes may run concurrently; later batches of the same
+// shape reuse the graph and only upload their job descriptors.  While
+// kernel tracing is on, the classes run one after the other on the caller's
+// stream instead, so that each launch's recorded time is its own.
 #include <algorithm>
 #include <cstring>
 #include <tuple>
@@ -17,8 +20,6 @@
 namespace pm {
 bool plan_valid(const Plan& P, long lc, int pidx);
 size_t plan_workspace_bytes(const Plan& P);
-pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
-                   long lc, u32* Ta, u32* Tb, ConvJob* J, int ring);
 pm_status launch_class(const Plan& P, bool lazy, int in_type, const JobRef& jr, int njobs, int max_rows,
                        hipStream_t s);
 void trace_suppress(bool on);
@@ -41,11 +42,18 @@ struct ClassRun {
   int count;
   int max_rows;
   double work = 0;  // sum over the products of n' (3 log2 L + 10): the butterflies and multiplies
+  long wgs = 0;     // work-groups of the class's widest launch
 };
+
+// A class whose launches have fewer work-groups than the device has compute
+// units cannot fill it: its time is the latency of its rounds, and it runs
+// beside the large classes rather than after them.
+constexpr long kSmallClassWgs = 256;
 
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
-  ConvJob* djobs = nullptr;  // device job array baked into the graph
+  ConvJob* djobs = nullptr;      // device job array baked into the graph
+  const void** dptrs = nullptr;  // (a, b, c) per job: the graph's first kernel patches them into djobs
   size_t njobs = 0;
 };
 
@@ -61,8 +69,8 @@ struct LastShape {
   void* ws = nullptr;       // workspace the jobs point into
   std::vector<ConvJob> jobs;
   std::vector<int> order;   // job index -> problem index
-  std::vector<size_t> direct;
-  std::vector<int> direct_pidx;
+  std::vector<ClassRun> runs;
+  std::vector<Plan> plans;  // per problem
   GraphEntry* graph = nullptr;
 };
 
@@ -73,7 +81,9 @@ struct BatchState {
   std::vector<hipStream_t> branches;                        // fork streams
   ConvJob* staging = nullptr;                               // pinned host copy of the jobs
   size_t staging_cap = 0;
-  hipEvent_t staged = nullptr;  // the last upload from `staging` has completed
+  const void** pstaging = nullptr;                          // pinned host copy of the pointers
+  size_t pstaging_cap = 0;
+  hipEvent_t staged = nullptr;  // the last upload from the staging buffers has completed
   // learned policy: per batch shape (hash of the lengths and primes), whether
   // the default plans ran the whole batch faster than the model's (1) or not (0)
   std::map<u64, int> plan_choice;
@@ -100,24 +110,37 @@ pm_status batch_state(DevCtx* c, hipStream_t s, BatchState** out) {
   return PM_OK;
 }
 
-pm_status capture_graph(BatchState* B, const std::vector<ClassRun>& runs, ConvJob* djobs, hipGraphExec_t* exec) {
+pm_status capture_graph(BatchState* B, const std::vector<ClassRun>& runs, const GraphEntry& G,
+                        hipGraphExec_t* exec) {
   hipStream_t cs = B->cap;
+  ConvJob* djobs = G.djobs;
   trace_suppress(true);
   pm_status st = PM_OK;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     trace_suppress(false);
     return PM_EDEVICE;
   }
+  // this launch's operand and output pointers into the descriptors, before any class
+  if (launch_patch_jobs(djobs, G.dptrs, (int)G.njobs, cs) != hipSuccess) st = PM_EDEVICE;
   std::vector<hipEvent_t> evs;
   hipEvent_t fork;
   hipEventCreateWithFlags(&fork, hipEventDisableTiming);
   hipEventRecord(fork, cs);
-  // classes in decreasing work, each on the branch with the least work so far
+  // The small classes first, all on branch 0, so that they start with the
+  // large ones instead of trailing them; then the large classes in
+  // decreasing work, each on the branch with the least work so far.
   std::vector<bool> used(B->branches.size(), false);
   std::vector<double> load(B->branches.size(), 0.0);
-  for (size_t k = 0; k < runs.size() && st == PM_OK; ++k) {
+  std::vector<size_t> order;
+  for (int pass = 0; pass < 2; ++pass)
+    for (size_t k = 0; k < runs.size(); ++k)
+      if ((runs[k].wgs < kSmallClassWgs) == (pass == 0)) order.push_back(k);
+  for (size_t k : order) {
+    if (st != PM_OK) break;
     const ClassRun& r = runs[k];
-    const size_t bi = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    const size_t bi = r.wgs < kSmallClassWgs
+                          ? 0
+                          : (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
     load[bi] += r.work;
     hipStream_t bs = B->branches[bi];
     if (!used[bi]) {
@@ -225,10 +248,56 @@ extern "C" pm_status pm_batch_workspace_query(const pm_problem* probs, size_t co
   return PM_OK;
 }
 
+// The batch's classes: one graph launch, or (kernel tracing on) the class
+// launches one after the other on s
+static pm_status launch_batch(GraphEntry* G, const std::vector<ClassRun>& runs, hipStream_t s) {
+  if (trace_on()) {
+    if (launch_patch_jobs(G->djobs, G->dptrs, (int)G->njobs, s) != hipSuccess) return PM_EDEVICE;
+    for (const ClassRun& r : runs) {
+      JobRef jr;
+      memset(&jr.one, 0, sizeof(jr.one));
+      jr.many = G->djobs + r.first;
+      const pm_status st = launch_class(r.plan, r.lazy, 0, jr, r.count, r.max_rows, s);
+      if (st) return st;
+    }
+    return PM_OK;
+  }
+  TraceScope ts(s, "batch_graph");
+  return hipGraphLaunch(G->exec, s) == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
+// pinned staging of at least n entries
+template <typename T>
+static pm_status staging_room(T** buf, size_t* cap, size_t n) {
+  if (*cap >= n) return PM_OK;
+  if (*buf) hipHostFree((void*)*buf);
+  *buf = nullptr;
+  *cap = 0;
+  if (hipHostMalloc((void**)buf, n * sizeof(T), hipHostMallocDefault) != hipSuccess) return PM_ENOMEM;
+  *cap = n;
+  return PM_OK;
+}
+
+// upload the (a, b, c) pointers of every job, in job order, to G->dptrs
+static pm_status upload_ptrs(BatchState* B, GraphEntry* G, const pm_problem* probs, const std::vector<int>& order,
+                             hipStream_t s) {
+  const size_t n = order.size();
+  for (size_t k = 0; k < n; ++k) {
+    const pm_problem& q = probs[order[k]];
+    B->pstaging[3 * k] = q.a;
+    B->pstaging[3 * k + 1] = q.b;
+    B->pstaging[3 * k + 2] = q.c;
+  }
+  if (hipMemcpyAsync(G->dptrs, B->pstaging, 3 * n * sizeof(void*), hipMemcpyHostToDevice, s) != hipSuccess)
+    return PM_EDEVICE;
+  return PM_OK;
+}
+
 // Fast path: the same shape (lengths and primes, in order) as the previous
-// batch on this stream, under the same plans and workspace: patch the
-// operand and output pointers into the previous jobs, upload them, relaunch
-// the graph.  Returns false, launching nothing, when the shape differs.
+// batch on this stream, under the same plans and workspace: upload the new
+// operand and output pointers (the graph's first kernel patches them into
+// the descriptors) and relaunch the graph.  Returns false, launching
+// nothing, when the shape differs.
 static bool batch_fast(DevCtx* c, BatchState* B, const pm_problem* probs, size_t count, hipStream_t s,
                        pm_status* st) {
   LastShape& L = B->last;
@@ -242,29 +311,12 @@ static bool batch_fast(DevCtx* c, BatchState* B, const pm_problem* probs, size_t
       return true;
     }
   *st = PM_EDEVICE;
-  for (size_t k = 0; k < L.direct.size(); ++k) {
-    const pm_problem& q = probs[L.direct[k]];
-    if (launch_direct(q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, L.direct_pidx[k], c->errflag, s) != hipSuccess)
-      return true;
-  }
-  if (L.jobs.empty()) {
-    *st = PM_OK;
-    return true;
-  }
   if (hipEventSynchronize(B->staged) != hipSuccess) return true;
-  for (size_t k = 0; k < L.jobs.size(); ++k) {
-    const pm_problem& q = probs[L.order[k]];
-    ConvJob& J = B->staging[k];
-    J = L.jobs[k];
-    J.a = q.a;
-    J.b = q.b;
-    J.c = q.c;
-  }
-  const size_t bytes = L.jobs.size() * sizeof(ConvJob);
-  if (hipMemcpyAsync(L.graph->djobs, B->staging, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return true;
+  *st = upload_ptrs(B, L.graph, probs, L.order, s);
+  if (*st) return true;
+  *st = PM_EDEVICE;
   if (hipEventRecord(B->staged, s) != hipSuccess) return true;
-  TraceScope ts(s, "batch_graph");
-  *st = hipGraphLaunch(L.graph->exec, s) == hipSuccess ? PM_OK : PM_EDEVICE;
+  *st = launch_batch(L.graph, L.runs, s);
   return true;
 }
 
@@ -276,16 +328,12 @@ static pm_status batch_run(DevCtx* c, BatchState* B, const pm_problem* probs, si
   pm_status st = PM_OK;
   if (batch_fast(c, B, probs, count, s, &st)) return st;
 
-  // classes, largest transforms first
+  // classes, largest transforms first (the defining sums form one class)
   std::map<ClassKey, std::vector<size_t>> groups;
-  std::vector<size_t> direct;
   const size_t wsb = batch_workspace_bytes(plans);
   for (size_t i = 0; i < count; ++i) {
-    if (plans[i].kind == PLAN_DIRECT) {
-      direct.push_back(i);
-      continue;
-    }
-    groups[class_key(plans[i], prime_info(pidx[i]).lazy)].push_back(i);
+    const bool lazy = plans[i].kind != PLAN_DIRECT && prime_info(pidx[i]).lazy;
+    groups[class_key(plans[i], lazy)].push_back(i);
   }
   void* wsp = nullptr;
   if (wsb) {
@@ -319,20 +367,16 @@ static pm_status batch_run(DevCtx* c, BatchState* B, const pm_problem* probs, si
       st = make_job(c, plans[i], pidx[i], q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, lc, Ta, Tb, &J, 0);
       if (st) return st;
       r.max_rows = std::max(r.max_rows, J.rows);
-      r.work += (double)plan_nprime(plans[i]) * (3.0 * plans[i].logL + 10.0);
+      r.work += plans[i].kind == PLAN_DIRECT ? (double)q.len_a * q.len_b
+                                              : (double)plan_nprime(plans[i]) * (3.0 * plans[i].logL + 10.0);
       jobs.push_back(J);
       order.push_back((int)i);
     }
+    r.wgs = r.plan.kind == PLAN_FOURSTEP ? (long)r.count * r.max_rows : (long)r.count;
     runs.push_back(r);
   }
   std::stable_sort(runs.begin(), runs.end(), [](const ClassRun& x, const ClassRun& y) { return x.work > y.work; });
 
-  for (size_t i : direct) {
-    const pm_problem& q = probs[i];
-    if (launch_direct(q.a, (long)q.len_a, q.b, (long)q.len_b, q.c, pidx[i], c->errflag, s) != hipSuccess)
-      return PM_EDEVICE;
-  }
-  if (jobs.empty()) return PM_OK;
 
   Signature sig;
   for (auto& r : runs) sig.emplace_back(r.key, r.count, r.max_rows);
@@ -343,26 +387,26 @@ static pm_status batch_run(DevCtx* c, BatchState* B, const pm_problem* probs, si
     GraphEntry ge;
     ge.njobs = jobs.size();
     if (hipMalloc(&ge.djobs, jobs.size() * sizeof(ConvJob)) != hipSuccess) return PM_ENOMEM;
-    st = capture_graph(B, runs, ge.djobs, &ge.exec);
+    if (hipMalloc((void**)&ge.dptrs, 3 * jobs.size() * sizeof(void*)) != hipSuccess) {
+      hipFree(ge.djobs);
+      return PM_ENOMEM;
+    }
+    st = capture_graph(B, runs, ge, &ge.exec);
     if (st) {
       hipFree(ge.djobs);
+      hipFree((void*)ge.dptrs);
       return st;
     }
     G = &(B->graphs[gkey] = ge);
   } else {
     G = &git->second;
   }
-  // upload the job descriptors (the graph reads them from G->djobs)
+  // upload the job descriptors (the graph reads them from G->djobs) and
+  // their pointers (which its first kernel writes into them again)
   if (hipEventSynchronize(B->staged) != hipSuccess) return PM_EDEVICE;
-  if (B->staging_cap < jobs.size()) {
-    if (B->staging) hipHostFree(B->staging);
-    B->staging = nullptr;
-    if (hipHostMalloc((void**)&B->staging, jobs.size() * sizeof(ConvJob), hipHostMallocDefault) != hipSuccess) {
-      B->staging_cap = 0;
-      return PM_ENOMEM;
-    }
-    B->staging_cap = jobs.size();
-  }
+  st = staging_room(&B->staging, &B->staging_cap, jobs.size());
+  if (st == PM_OK) st = staging_room(&B->pstaging, &B->pstaging_cap, 3 * jobs.size());
+  if (st) return st;
   // the device array keeps the class-by-class layout the graph was captured with
   memcpy(B->staging, jobs.data(), jobs.size() * sizeof(ConvJob));
   {
@@ -377,17 +421,16 @@ static pm_status batch_run(DevCtx* c, BatchState* B, const pm_problem* probs, si
     L.ws = wsp;
     L.jobs = jobs;
     L.order = order;
-    L.direct = direct;
-    L.direct_pidx.clear();
-    for (size_t i : direct) L.direct_pidx.push_back(pidx[i]);
+    L.runs = runs;
+    L.plans = plans;
     L.graph = G;
   }
   if (hipMemcpyAsync(G->djobs, B->staging, jobs.size() * sizeof(ConvJob), hipMemcpyHostToDevice, s) != hipSuccess)
     return PM_EDEVICE;
+  st = upload_ptrs(B, G, probs, order, s);
+  if (st) return st;
   if (hipEventRecord(B->staged, s) != hipSuccess) return PM_EDEVICE;
-  TraceScope ts(s, "batch_graph");
-  if (hipGraphLaunch(G->exec, s) != hipSuccess) return PM_EDEVICE;
-  return PM_OK;
+  return launch_batch(G, runs, s);
 }
 
 // FNV-1a over the (len_a, len_b, p) of every problem
@@ -478,4 +521,26 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
     v = B->plan_choice.emplace(h, t_default < t_model ? 1 : 0).first;
   }
   return batch_run(c, B, probs, count, v->second ? dplans : plans, pidx, s);
+}
+
+extern "C" pm_status pm_batch_plans_used(void* stream, pm_plan* out, size_t count) {
+  if (!out) return PM_EINVAL;
+  pm_status st;
+  DevCtx* c = ctx_current(&st);
+  if (!c) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = g_batch.find({c->dev, (hipStream_t)stream});
+  if (it == g_batch.end() || it->second->last.plans.size() != count) return PM_EINVAL;
+  const std::vector<Plan>& v = it->second->last.plans;
+  for (size_t i = 0; i < count; ++i) {
+    out[i].kind = v[i].kind;
+    out[i].log_l = v[i].logL;
+    out[i].log_ra = v[i].logRA;
+    out[i].log_rb = v[i].logRB;
+    out[i].log_c = v[i].logC;
+    out[i].ma = v[i].ma;
+    out[i].lq = v[i].lq;
+    out[i].lnt = v[i].lnt;
+  }
+  return PM_OK;
 }

@@ -240,12 +240,10 @@ size_t plan_workspace_bytes(const Plan& P) {
   return 2 * (size_t)plan_nprime(P) * sizeof(u32);
 }
 
-// Fill the job of one product with plan P (tables are built on first use).
-// Ta/Tb: the four-step workspace (n' words each) or null for other plans.
-// ring: 0 the product in Z/pZ[x] (or, with lc = L, the circular one), 2 the
-// nega-circular product (inputs twisted by psi^j, outputs untwisted).
+// Fill the job of one product with plan P (tables are built on first use,
+// unless the row tables are given).
 pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
-                   long lc, u32* Ta, u32* Tb, ConvJob* J, int ring) {
+                   long lc, u32* Ta, u32* Tb, ConvJob* J, int ring, const RowTables* rows) {
   pm_status st = ensure_prime_tables(c, pidx);
   if (st) return st;
   const PrimeInfo& PI = prime_info(pidx);
@@ -269,7 +267,13 @@ pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, c
     st = get_twist_tables(c, pidx, P.logL, P.kind == PLAN_FOURSTEP ? P.logC : 0, &J->twf, &J->twi);
     if (st) return st;
   }
-  if (P.kind == PLAN_FOURSTEP) return get_row_tables(c, pidx, P.logL, P.logC, plan_row_lnt(P), J->sc.x, ring == 2, &J->W);
+  if (P.kind == PLAN_FOURSTEP) {
+    if (rows) {
+      J->W = *rows;
+      return PM_OK;
+    }
+    return get_row_tables(c, pidx, P.logL, P.logC, plan_row_lnt(P), J->sc.x, ring == 2, &J->W);
+  }
   return PM_OK;
 }
 
@@ -278,7 +282,10 @@ pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, c
 pm_status launch_class(const Plan& P, bool lazy, int in_type, const JobRef& jr, int njobs, int max_rows,
                        hipStream_t s) {
   hipError_t e;
-  if (P.kind == PLAN_LDS) {
+  if (P.kind == PLAN_DIRECT) {
+    if (in_type != 0) return PM_EINVAL;
+    e = launch_direct_jobs(jr, njobs, s);
+  } else if (P.kind == PLAN_LDS) {
     e = launch_lds_conv(P, lazy, jr, njobs, s);
   } else {
     e = launch_col_fwd(P, lazy, in_type, 2, jr, njobs, s);
@@ -505,6 +512,7 @@ pm_status pm_init(void) {
   return PM_OK;
 }
 
+
 static pm_status check_product_args(const void* a, size_t la, const void* b, size_t lb, uint32_t p, const void* c,
                                     int* pidx, long* lc) {
   if (!a || !b || !c || la == 0 || lb == 0) return PM_EINVAL;
@@ -542,6 +550,7 @@ pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t
                       void* stream) {
   return product_with(a, len_a, b, len_b, p, c, nullptr, stream);
 }
+
 
 pm_status pm_workspace_query(size_t len_a, size_t len_b, uint32_t p, size_t* bytes) {
   if (!bytes) return PM_EINVAL;

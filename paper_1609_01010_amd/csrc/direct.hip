@@ -28,6 +28,42 @@ __global__ void __launch_bounds__(64) k_direct(const u32* __restrict__ a, int la
   c[k] = (u32)(acc % mp.p);
 }
 
+// the same over the jobs of a batch: work-group z computes job z's product
+// (one thread per output coefficient, at most 64)
+__global__ void __launch_bounds__(64) k_direct_jobs(JobRef jr) {
+  const ConvJob J = load_job(jr);
+  const int k = threadIdx.x;
+  const int la = (int)J.la, lb = (int)J.lb;
+  if (k >= (int)J.lc) return;
+  const u32* __restrict__ a = (const u32*)J.a;
+  const u32* __restrict__ b = (const u32*)J.b;
+  const u32 p = J.mp.p;
+  u64 acc = 0;  // < 64 terms each below 2^31
+  const int i0 = k - (lb - 1) > 0 ? k - (lb - 1) : 0;
+  const int i1 = k < la - 1 ? k : la - 1;
+  bool bad = false;
+  for (int i = i0; i <= i1; ++i) {
+    const u32 x = gld(a + i), y = gld(b + k - i);
+    bad |= x >= p || y >= p;
+    acc += (u64)x * y % p;
+  }
+  if (bad) atomicOr(J.err, 1);
+  gst(J.c + k, (u32)(acc % p));
+}
+
+// a batch launch's operand and output pointers into its job descriptors:
+// job i takes ptrs[3 i], ptrs[3 i + 1], ptrs[3 i + 2] as a, b, c
+__global__ void __launch_bounds__(256) k_patch_jobs(ConvJob* jobs, const void* const* ptrs, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  typedef const void* VP;
+  PM_GMEM ConvJob* J = (PM_GMEM ConvJob*)(jobs + i);
+  const PM_GMEM VP* q = (const PM_GMEM VP*)(ptrs + 3 * (size_t)i);
+  J->a = q[0];
+  J->b = q[1];
+  J->c = (u32*)q[2];
+}
+
 // products in Z/pZ[x]/(x^n - 1) (NEG = false, the circular convolution of
 // eq. 5) and Z/pZ[x]/(x^n + 1) (NEG = true) by their defining sums, n <= 64:
 // c_i = sum_{j+k = i} a_j b_k +- sum_{j+k = i+n} a_j b_k
@@ -58,6 +94,14 @@ hipError_t launch_direct_ring(const u32* a, long la, const u32* b, long lb, long
   const ModP mp = modp_of(prime_info(pidx));
   if (negacyclic) return launch("direct", k_direct_ring<true>, 1, 64, 0, s, a, (int)la, b, (int)lb, (int)n, c, mp, err);
   return launch("direct", k_direct_ring<false>, 1, 64, 0, s, a, (int)la, b, (int)lb, (int)n, c, mp, err);
+}
+
+hipError_t launch_patch_jobs(ConvJob* jobs, const void* const* ptrs, int n, hipStream_t s) {
+  return launch("patch_jobs", k_patch_jobs, dim3((unsigned)((n + 255) / 256)), 256, 0, s, jobs, ptrs, n);
+}
+
+hipError_t launch_direct_jobs(const JobRef& jr, int njobs, hipStream_t s) {
+  return launch("direct", k_direct_jobs, dim3(1, 1, njobs), 64, 0, s, jr);
 }
 
 hipError_t launch_direct(const u32* a, long la, const u32* b, long lb, u32* c, int pidx, int* err, hipStream_t s) {

@@ -58,8 +58,26 @@ struct RowKey {
   }
 };
 
+// Device buffers of the cost model's inference, allocated once with the
+// device context: plan choice under the learned policy then allocates
+// nothing and waits only for its own stream.
+constexpr int kMlpInferRows = 8192;  // feature rows per inference launch
+struct MlpInfer {
+  std::mutex mu;
+  hipStream_t s = nullptr;  // the library's inference stream (default priority)
+  hipEvent_t ev = nullptr;
+  float *dP = nullptr, *dX = nullptr, *dY = nullptr;  // weights, features, outputs (device)
+  float *hP = nullptr, *hX = nullptr, *hY = nullptr;  // pinned host staging
+  unsigned long ver = 0;                              // model version held in dP (0: none)
+};
+pm_status mlp_infer_init(MlpInfer* I);
+// y[i] = network(X[i]) for B rows of host features, with the weights w of
+// model version `ver` (uploaded when it differs from the last one used)
+pm_status mlp_infer(MlpInfer* I, const float* w, unsigned long ver, const float* X, int B, float* y);
+
 struct DevCtx {
   int dev = -1;
+  MlpInfer infer;
   uint2* prime_mem[kNumPrimes] = {nullptr, nullptr, nullptr, nullptr};
   PrimeTables tabs[kNumPrimes];
   std::map<RowKey, std::pair<uint2*, RowTables>> rowtw;
@@ -73,6 +91,8 @@ struct DevCtx {
 };
 
 DevCtx* ctx_current(pm_status* st);
+// the current device's context if it exists (creates nothing)
+DevCtx* ctx_lookup();
 pm_status ensure_prime_tables(DevCtx* c, int pidx);
 // the workspace of stream s, grown to at least `bytes`; a caller-owned one
 // (pm_set_workspace) is never grown: PM_ENOMEM if it is smaller
@@ -81,6 +101,11 @@ pm_status stream_workspace(DevCtx* c, hipStream_t s, size_t bytes, void** out);
 void* stream_workspace_current(DevCtx* c, hipStream_t s);
 // scale: the value multiplied into the inverse factors (1 for none)
 pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, int twist, RowTables* out);
+// the same tables written into caller memory `mem` (row_tables_bytes) by
+// kernels on stream s, without allocating or waiting
+size_t row_tables_bytes(int logL, int logC, int lnt);
+pm_status fill_row_tables(int pidx, int logL, int logC, int lnt, u32 scale, int twist, uint2* mem, hipStream_t s,
+                          RowTables* out);
 // powers psi^(i s) and psi^(-i s), i < L / s, of a primitive 2L-th root of
 // unity psi, stride s = 2^log_stride (the nega-circular product's twist)
 pm_status get_twist_tables(DevCtx* c, int pidx, int logL, int log_stride, const uint2** fwd, const uint2** inv);
@@ -136,8 +161,19 @@ inline int plan_row_lnt(const Plan& P) {
 // relaxed transform length n' = ma * L / RA
 inline long plan_nprime(const Plan& P) { return (long)P.ma << (P.logL - P.logRA); }
 
+// Fill the job of one product with plan P (capi.cpp).  Ta/Tb: the four-step
+// workspace (n' words each) or null; ring 0 the product (or with lc = L the
+// circular one), 2 the nega-circular one; rows: the four-step row tables to
+// use (null: the context's cached ones, built on first use).
+pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
+                   long lc, u32* Ta, u32* Tb, ConvJob* J, int ring, const RowTables* rows = nullptr);
+
 // ---- launchers (return hipSuccess or the launch error) --------------------
 hipError_t launch_direct(const u32* a, long la, const u32* b, long lb, u32* c, int pidx, int* err, hipStream_t s);
+// the defining sums of njobs products of at most 64 outputs (jobs in jr)
+hipError_t launch_direct_jobs(const JobRef& jr, int njobs, hipStream_t s);
+// jobs[i].a, .b, .c = ptrs[3 i], ptrs[3 i + 1], ptrs[3 i + 2] for i < n (device arrays)
+hipError_t launch_patch_jobs(ConvJob* jobs, const void* const* ptrs, int n, hipStream_t s);
 constexpr int kKronMaxVars = 8;
 hipError_t launch_kron_pack(const u32* a, int nv, const long* da, const long* dc, long n_out, u32* out,
                             hipStream_t s);

@@ -14,7 +14,8 @@
 
 namespace pm {
 
-// forward: one 64-thread block per sample; keeps h1, h2, y for the backward
+// forward: one 64-thread block per sample; keeps h1, h2 for the backward
+// (H1, H2 null: inference, only y)
 __global__ void __launch_bounds__(kMlpH) k_mlp_forward(const float* __restrict__ P, const float* __restrict__ X, int B,
                                                        float* __restrict__ H1, float* __restrict__ H2,
                                                        float* __restrict__ Y) {
@@ -36,12 +37,12 @@ __global__ void __launch_bounds__(kMlpH) k_mlp_forward(const float* __restrict__
   for (int f = 0; f < kMlpF; ++f) z = fmaf(W1[j * kMlpF + f], x[f], z);
   const float a1 = tanhf(z);
   h1[j] = a1;
-  H1[(size_t)b * kMlpH + j] = a1;
+  if (H1) H1[(size_t)b * kMlpH + j] = a1;
   __syncthreads();
   float z2 = b2[j];
   for (int k = 0; k < kMlpH; ++k) z2 = fmaf(W2[j * kMlpH + k], h1[k], z2);
   const float a2 = tanhf(z2);
-  H2[(size_t)b * kMlpH + j] = a2;
+  if (H2) H2[(size_t)b * kMlpH + j] = a2;
   part[j] = W3[j] * a2;
   __syncthreads();
   if (j == 0) {
@@ -191,6 +192,47 @@ hipError_t MlpDev::adam(int step, float lr, hipStream_t s) {
   const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
   k_mlp_adam<<<(kMlpParams + 255) / 256, 256, 0, s>>>(P, G, M, V, kMlpParams, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
+}
+
+pm_status mlp_infer_init(MlpInfer* I) {
+  const size_t rows = kMlpInferRows;
+  if (hipStreamCreateWithFlags(&I->s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&I->ev, hipEventDisableTiming) != hipSuccess)
+    return PM_EDEVICE;
+  if (hipMalloc(&I->dP, kMlpParams * 4) || hipMalloc(&I->dX, rows * kMlpF * 4) || hipMalloc(&I->dY, rows * 4) ||
+      hipHostMalloc((void**)&I->hP, kMlpParams * 4, hipHostMallocDefault) ||
+      hipHostMalloc((void**)&I->hX, rows * kMlpF * 4, hipHostMallocDefault) ||
+      hipHostMalloc((void**)&I->hY, rows * 4, hipHostMallocDefault))
+    return PM_ENOMEM;
+  return PM_OK;
+}
+
+// Rows go through in chunks of kMlpInferRows: staged in pinned memory,
+// copied and evaluated on the inference stream, and read back after its
+// event (no device-wide synchronisation, no allocation).
+pm_status mlp_infer(MlpInfer* I, const float* w, unsigned long ver, const float* X, int B, float* y) {
+  std::lock_guard<std::mutex> lk(I->mu);
+  if (I->ver != ver) {
+    // the previous upload (if any) has completed: every call below waits for its event
+    memcpy(I->hP, w, kMlpParams * 4);
+    if (hipMemcpyAsync(I->dP, I->hP, kMlpParams * 4, hipMemcpyHostToDevice, I->s) != hipSuccess) return PM_EDEVICE;
+    I->ver = ver;
+  }
+  for (int o = 0; o < B; o += kMlpInferRows) {
+    const int n = B - o < kMlpInferRows ? B - o : kMlpInferRows;
+    memcpy(I->hX, X + (size_t)o * kMlpF, (size_t)n * kMlpF * 4);
+    if (hipMemcpyAsync(I->dX, I->hX, (size_t)n * kMlpF * 4, hipMemcpyHostToDevice, I->s) != hipSuccess)
+      return PM_EDEVICE;
+    k_mlp_forward<<<n, kMlpH, 0, I->s>>>(I->dP, I->dX, n, nullptr, nullptr, I->dY);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(I->hY, I->dY, (size_t)n * 4, hipMemcpyDeviceToHost, I->s) != hipSuccess ||
+        hipEventRecord(I->ev, I->s) != hipSuccess || hipEventSynchronize(I->ev) != hipSuccess) {
+      I->ver = 0;
+      return PM_EDEVICE;
+    }
+    memcpy(y + o, I->hY, (size_t)n * 4);
+  }
+  return PM_OK;
 }
 
 }  // namespace pm

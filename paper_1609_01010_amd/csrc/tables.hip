@@ -153,6 +153,14 @@ __global__ void k_pows(uint2* out, int n, u32 p, u32 base) {
 static std::mutex g_ctx_mu;
 static std::map<int, DevCtx*> g_ctx;
 
+DevCtx* ctx_lookup() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  auto it = g_ctx.find(dev);
+  return it == g_ctx.end() ? nullptr : it->second;
+}
+
 DevCtx* ctx_current(pm_status* st) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
@@ -176,6 +184,8 @@ DevCtx* ctx_current(pm_status* st) {
     *st = PM_EDEVICE;
     return nullptr;
   }
+  *st = mlp_infer_init(&c->infer);
+  if (*st) return nullptr;
   g_ctx[dev] = c;
   *st = PM_OK;
   return c;
@@ -268,6 +278,39 @@ pm_status ensure_prime_tables(DevCtx* c, int pidx) {
   return PM_OK;
 }
 
+size_t row_tables_bytes(int logL, int logC, int lnt) {
+  const size_t R = (size_t)1 << (logL - logC), nt = (size_t)1 << lnt, ept = (size_t)1 << (logC - lnt);
+  return 2 * (R * nt + R * ept) * sizeof(uint2);
+}
+
+pm_status fill_row_tables(int pidx, int logL, int logC, int lnt, u32 scale, int twist, uint2* mem, hipStream_t s,
+                          RowTables* out) {
+  const PrimeInfo& P = prime_info(pidx);
+  const int R = 1 << (logL - logC), nt = 1 << lnt, ept = 1 << (logC - lnt);
+  const int ng = R * nt, nf = R * ept;
+  if (twist && logL + 1 > P.two_adic) return PM_ETOOLARGE;
+  // cyclic: w_L^(j2 k1); twisted: psi^(j2 (2 k1 + 1)) with psi^2 = w_L
+  const int lord = twist ? logL + 1 : logL;
+  const u32 w = h_powmod(P.g, (P.p - 1) >> lord, P.p);
+  const u32 wi = h_inv(w, P.p);
+  const u32 mask = (u32)((1ull << lord) - 1);
+  const u32 kmul = twist ? 2 : 1, kadd = twist ? 1 : 0;
+  uint2* gf = mem;
+  uint2* gi = gf + ng;
+  uint2* ff = gi + ng;
+  uint2* fi = ff + nf;
+  k_row_pows<<<(ng + 255) / 256, 256, 0, s>>>(gf, R, nt, mask, P.p, w, kmul, kadd);
+  k_row_pows<<<(ng + 255) / 256, 256, 0, s>>>(gi, R, nt, mask, P.p, wi, kmul, kadd);
+  k_row_factors<<<(nf + 255) / 256, 256, 0, s>>>(ff, R, ept, nt, mask, P.p, w, 1, kmul, kadd);
+  k_row_factors<<<(nf + 255) / 256, 256, 0, s>>>(fi, R, ept, nt, mask, P.p, wi, scale, kmul, kadd);
+  if (hipGetLastError() != hipSuccess) return PM_EDEVICE;
+  out->gf = gf;
+  out->gi = gi;
+  out->ff = ff;
+  out->fi = fi;
+  return PM_OK;
+}
+
 pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 scale, int twist, RowTables* out) {
   const RowKey key{pidx, logL, logC, lnt, scale, twist};
   auto it = c->rowtw.find(key);
@@ -275,35 +318,16 @@ pm_status get_row_tables(DevCtx* c, int pidx, int logL, int logC, int lnt, u32 s
     *out = it->second.second;
     return PM_OK;
   }
-  const PrimeInfo& P = prime_info(pidx);
-  const int R = 1 << (logL - logC), nt = 1 << lnt, ept = 1 << (logC - lnt);
-  const int ng = R * nt, nf = R * ept;
-  if (twist && logL + 1 > P.two_adic) return PM_ETOOLARGE;
+  if (twist && logL + 1 > prime_info(pidx).two_adic) return PM_ETOOLARGE;
   uint2* mem = nullptr;
-  if (hipMalloc(&mem, 2 * (size_t)(ng + nf) * sizeof(uint2)) != hipSuccess) return PM_ENOMEM;
-  // cyclic: w_L^(j2 k1); twisted: psi^(j2 (2 k1 + 1)) with psi^2 = w_L
-  const int lord = twist ? logL + 1 : logL;
-  const u32 w = h_powmod(P.g, (P.p - 1) >> lord, P.p);
-  const u32 wi = h_inv(w, P.p);
-  const u32 mask = (u32)((1ull << lord) - 1);
-  const u32 kmul = twist ? 2 : 1, kadd = twist ? 1 : 0;
+  if (hipMalloc(&mem, row_tables_bytes(logL, logC, lnt)) != hipSuccess) return PM_ENOMEM;
   RowTables W;
-  uint2* gf = mem;
-  uint2* gi = gf + ng;
-  uint2* ff = gi + ng;
-  uint2* fi = ff + nf;
-  k_row_pows<<<(ng + 255) / 256, 256>>>(gf, R, nt, mask, P.p, w, kmul, kadd);
-  k_row_pows<<<(ng + 255) / 256, 256>>>(gi, R, nt, mask, P.p, wi, kmul, kadd);
-  k_row_factors<<<(nf + 255) / 256, 256>>>(ff, R, ept, nt, mask, P.p, w, 1, kmul, kadd);
-  k_row_factors<<<(nf + 255) / 256, 256>>>(fi, R, ept, nt, mask, P.p, wi, scale, kmul, kadd);
-  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+  pm_status st = fill_row_tables(pidx, logL, logC, lnt, scale, twist, mem, 0, &W);
+  if (st == PM_OK && hipDeviceSynchronize() != hipSuccess) st = PM_EDEVICE;
+  if (st) {
     hipFree(mem);
-    return PM_EDEVICE;
+    return st;
   }
-  W.gf = gf;
-  W.gi = gi;
-  W.ff = ff;
-  W.fi = fi;
   c->rowtw[key] = std::make_pair(mem, W);
   *out = W;
   return PM_OK;

@@ -176,8 +176,6 @@ static pm_status batch_inputs(long lc, u32 p, BatchBufs* T, hipStream_t s) {
 
 pm_status launch_class(const Plan& P, bool lazy, int in_type, const JobRef& jr, int njobs, int max_rows,
                        hipStream_t s);
-pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, const void* b, long lb, u32* out,
-                   long lc, u32* Ta, u32* Tb, ConvJob* J, int ring);
 
 // median time per product in microseconds of `reps` batch runs of plan P
 static pm_status time_plan_batch(DevCtx* c, const Plan& P, int pidx, const BatchBufs& B, int reps, hipStream_t s,
@@ -281,9 +279,19 @@ struct Model {
   bool ok = false;
   std::vector<float> w;
   float mean = 0.f, std = 1.f;
+  unsigned long ver = 0;  // changes with every new set of weights
 };
 static std::mutex g_model_mu;
 static Model g_model;
+static unsigned long g_model_ver = 0;  // guarded by g_model_mu
+
+// the network on the current device's preallocated inference buffers
+static pm_status infer_rows(const Model& M, const float* X, int B, float* y) {
+  pm_status st;
+  DevCtx* c = ctx_current(&st);
+  if (!c) return st;
+  return mlp_infer(&c->infer, M.w.data(), M.ver, X, B, y);
+}
 
 // predicted log(us) of each plan for (lc, pidx); the caller holds no locks
 static pm_status model_predict(long lc, int pidx, const std::vector<Plan>& plans, int tctx, std::vector<double>* out) {
@@ -296,7 +304,7 @@ static pm_status model_predict(long lc, int pidx, const std::vector<Plan>& plans
   const int B = (int)plans.size();
   std::vector<float> X((size_t)B * kMlpF), y(B);
   for (int i = 0; i < B; ++i) plan_features(lc, pidx, plans[i], tctx, &X[(size_t)i * kMlpF]);
-  pm_status st = pm_mlp_forward(M.w.data(), X.data(), B, y.data());
+  pm_status st = infer_rows(M, X.data(), B, y.data());
   if (st) return st;
   out->resize(B);
   for (int i = 0; i < B; ++i) (*out)[i] = (double)y[i] * M.std + M.mean + std::log(plan_nprime_d(lc, plans[i]));
@@ -365,7 +373,7 @@ pm_status learned_batch_plans(const std::vector<long>& lcs, const std::vector<in
     for (size_t k = 0; k < items.size(); ++k)
       for (size_t f = 0; f < nf; ++f)
         plan_features(lcs[items[k]], pid, item_plan(fams[f], lcs[items[k]]), kCtxBatch, &X[(k * nf + f) * kMlpF]);
-    pm_status st = pm_mlp_forward(M.w.data(), X.data(), (int)B, y.data());
+    pm_status st = infer_rows(M, X.data(), (int)B, y.data());
     if (st) return st;
     std::vector<double> total(nf, 0.0);
     for (size_t k = 0; k < items.size(); ++k)
@@ -591,6 +599,7 @@ pm_status pm_model_train(const float* init, int steps, float lr, float* losses) 
   g_model.mean = (float)mean;
   g_model.std = (float)sd;
   g_model.ok = true;
+  g_model.ver = ++g_model_ver;
   plan_epoch_bump();
   return PM_OK;
 }
@@ -611,6 +620,7 @@ pm_status pm_model_set(const float* params, float mean, float sd) {
   g_model.mean = mean;
   g_model.std = sd;
   g_model.ok = true;
+  g_model.ver = ++g_model_ver;
   plan_epoch_bump();
   return PM_OK;
 }
@@ -663,6 +673,7 @@ pm_status pm_model_load(const char* path) {
   M.ok = true;
   std::lock_guard<std::mutex> lk(g_model_mu);
   g_model = M;
+  g_model.ver = ++g_model_ver;
   plan_epoch_bump();
   return PM_OK;
 }
