@@ -183,6 +183,53 @@ def counters_from_profiles(name, src_hash):
 
 
 # ---------------------------------------------------------------------------
+# spot checks of the GPU results (the parity tests live in tests/): a
+# polynomial identity at random points, evaluated here with numpy
+
+def eval_mod(c, p, x):
+    """sum_i c_i x^i mod p for coefficients c < 2^32, in blocks of 4096 powers."""
+    import numpy as np
+
+    c = np.asarray(c, dtype=np.uint64)
+    B = 4096
+    pw = np.empty(B, dtype=np.uint64)
+    v = 1
+    for i in range(B):
+        pw[i] = v
+        v = v * x % p
+    acc, sk = 0, 1
+    for k in range(0, c.size, B):
+        blk = c[k:k + B]
+        acc = (acc + int(((blk * pw[:blk.size]) % np.uint64(p)).sum()) % p * sk) % p
+        sk = sk * v % p
+    return acc
+
+
+def check_product(a, b, c, p, rng, points=2, n=None, sign=0):
+    """c(x) = a(x) b(x) mod p at random points x (false accept <= len(c)/p
+    each); with n: the product mod x^n - sign, checked where x^n = sign."""
+    for _ in range(points):
+        if n is None:
+            x = int(rng.integers(2, p - 1))
+        else:
+            root = pow(_root(p), (p - 1) // (2 * n), p)  # a primitive 2n-th root: root^n = -1
+            x = pow(root, 2 * int(rng.integers(0, n)) + (0 if sign == 1 else 1), p)
+        if eval_mod(c, p, x) != eval_mod(a, p, x) * eval_mod(b, p, x) % p:
+            return False
+    return True
+
+
+def bitrev(i, bits):
+    return int(format(i, f"0{bits}b")[::-1], 2)
+
+
+def limbs_value(limbs):
+    import numpy as np
+
+    return int.from_bytes(np.asarray(limbs, dtype="<u2").tobytes(), "little")
+
+
+# ---------------------------------------------------------------------------
 # CPU baselines
 
 def cpu_baseline(items, target_s=10.0):
@@ -255,7 +302,6 @@ def batch_bench(pm, torch, dev, args):
 
     import numpy as np
 
-    from oracle import poly as op
     from paper_1609_01010_amd import inputs
 
     items = inputs.batch_uneven()
@@ -288,14 +334,12 @@ def batch_bench(pm, torch, dev, args):
     torch.cuda.synchronize()
     if pm.stream_check() != 0:
         raise SystemExit("device reported an error during warm-up")
-    # spot check against the oracle's schoolbook sum (the full parity tests live in tests/)
+    # spot check: 24 products of each buffer set at two random points
     rng = np.random.default_rng(5)
     for k in rng.choice(len(items), 24, replace=False):
         for si in range(2):
             it = items[int(k)]
-            ks = rng.integers(0, lcs[int(k)], 4)
-            got = sets[si][1][int(k)].cpu().numpy()[ks]
-            assert np.array_equal(got, op.poly_mul_sample(it.a, it.b, it.p, ks)), "batch output differs from the oracle"
+            assert check_product(it.a, it.b, sets[si][1][int(k)].cpu().numpy(), it.p, rng), "wrong batch product"
 
     # timed: K graph launches back to back, HIP events on the launch stream
     torch.cuda.synchronize()
@@ -396,8 +440,7 @@ def batch_bench(pm, torch, dev, args):
     # the last leg (relaxed default plans) left its products in set 0: check some
     for k in rng.choice(len(items), 8, replace=False):
         it = items[int(k)]
-        ks = rng.integers(0, lcs[int(k)], 4)
-        assert np.array_equal(sets[0][1][int(k)].cpu().numpy()[ks], op.poly_mul_sample(it.a, it.b, it.p, ks))
+        assert check_product(it.a, it.b, sets[0][1][int(k)].cpu().numpy(), it.p, rng), "wrong batch product"
     pad_bytes, pad_slots = 0.0, 0.0
     for it, pl in zip(items, pplans):
         b, s = product_units(it.a.size, it.b.size, pl)
@@ -428,7 +471,6 @@ def standalone_transform(pm, torch, dev, copy_bw, n_calls=40):
     """Forward transform of 2^22 points in bit-reversed order (the TFT hook with
     n = L): two passes over HBM, 16 N algorithmic bytes; 8 rotating buffer
     pairs (256 MiB); four outputs checked against direct evaluation."""
-    from oracle import poly as op
     from paper_1609_01010_amd import inputs
 
     N = 1 << 22
@@ -457,14 +499,14 @@ def standalone_transform(pm, torch, dev, copy_bw, n_calls=40):
             kern[name] = 1e3 * tot / max(n, 1)
         pm.trace_reset()
         x0, y0 = xs[0].cpu().numpy(), ys[0].cpu().numpy()
-        w = op.root(pp, g, N)
-        ok = all(int(y0[i]) == op.eval_at(x0, pp, pow(w, op.bitrev(i, 22), pp)) for i in (0, 1, 12345, N - 1))
+        w = pow(g, (pp - 1) // N, pp)
+        ok = all(int(y0[i]) == eval_mod(x0, pp, pow(w, bitrev(i, 22), pp)) for i in (0, 1, 12345, N - 1))
         out[f"ntt_2^22_p{pp}"] = {"us": ms * 1e3, "points_per_s": N / (ms * 1e-3),
                                   "hbm_alg_GBps": 16 * N / (ms * 1e-3) / 1e9,
                                   "hbm_frac": 16 * N / (ms * 1e-3) / HBM_PEAK,
                                   "hbm_frac_vs_copy": 16 * N / (ms * 1e-3) / copy_bw,
                                   "kernels_avg_us": kern,
-                                  "bit_exact_sampled": bool(ok)}
+                                  "checked_at_random_points": bool(ok)}
         del xs, ys
     return out
 
@@ -476,7 +518,6 @@ def large_products(pm, torch, dev, args):
     the row pass's roofline."""
     import numpy as np
 
-    from oracle import poly as op
     from paper_1609_01010_amd import inputs
 
     a2, b2, _ = inputs.large_pow2_product()
@@ -496,10 +537,9 @@ def large_products(pm, torch, dev, args):
     for i in range(3):
         step(i)
     torch.cuda.synchronize()
-    ks = np.array([0, 1, 12345, lc2 // 2, lc2 - 1])
-    assert np.array_equal(sets[0][4].cpu().numpy()[ks], op.poly_mul_sample(a2, b2, P, ks))
-    ks = np.array([0, 1, 12345, lc3 // 2, lc3 - 1])
-    assert np.array_equal(sets[0][5].cpu().numpy()[ks], op.poly_mul_sample(a3, b3, P, ks))
+    rng = np.random.default_rng(6)
+    assert check_product(a2, b2, sets[0][4].cpu().numpy(), P, rng)
+    assert check_product(a3, b3, sets[0][5].cpu().numpy(), P, rng)
     n = 30
     ms = time_loop(torch, step, n)
     pm.trace_reset()
@@ -536,10 +576,10 @@ def extra_configs(pm, torch, dev, copy_bw, args, reps=5):
     radix."""
     import numpy as np
 
-    from oracle import poly as op
     from paper_1609_01010_amd import inputs
 
     out = {}
+    rng = np.random.default_rng(8)
     pm.set_policy(pm.POLICY_DEFAULT)
     pm.plan_cache_clear()
     a, b, p = inputs.single_product_1024()
@@ -564,10 +604,10 @@ def extra_configs(pm, torch, dev, copy_bw, args, reps=5):
         pm.poly_mul(ta, tb, p, out=c)
     host_us = (time.perf_counter() - t0) / 200 * 1e6
     torch.cuda.synchronize()
-    assert np.array_equal(c.cpu().numpy(), op.poly_mul(a, b, p))
+    assert check_product(a, b, c.cpu().numpy(), p, rng, points=3)
     out["single_1024x1024_p998244353"] = {
         "us_one_call": ms * 1e3, "us_per_call_back_to_back": ms_loop * 1e3, "kernel_us": ktot,
-        "host_us_per_call": host_us, "coeffs_per_s": 2047 / (ms * 1e-3), "bit_exact": True}
+        "host_us_per_call": host_us, "coeffs_per_s": 2047 / (ms * 1e-3), "checked_at_random_points": True}
 
     out["plain_large_products"] = large_products(pm, torch, dev, args)
 
@@ -588,7 +628,7 @@ def extra_configs(pm, torch, dev, copy_bw, args, reps=5):
     pm.trace_reset()
     got = ic.cpu().numpy()
     q = (1 << 61) - 1
-    ok = op.limbs_to_int(got) % q == (op.limbs_to_int(ia) % q) * (op.limbs_to_int(ib) % q) % q
+    ok = limbs_value(got) % q == (limbs_value(ia) % q) * (limbs_value(ib) % q) % q
     out["int_mul_2^21x2^21_limbs"] = {"ms": ms, "limbs_per_s": got.size / (ms * 1e-3), "kernels_us": ik,
                                       "check": "product mod 2^61-1 matches" if ok else "MISMATCH"}
     del tia, tib, ic
@@ -614,12 +654,8 @@ def extra_configs(pm, torch, dev, copy_bw, args, reps=5):
     for name, fn in (("cyclic", pm.cyclic_mul), ("negacyclic", pm.negacyclic_mul)):
         fn(ra, rb, n21, pp, out=rc)
         ms = time_loop(torch, lambda i: fn(ra, rb, n21, pp, out=rc), 20)
-        ks = np.array([0, 1, n21 // 2, n21 - 2])
-        lin = op.poly_mul_sample(a2, b2, pp, np.concatenate([ks, ks + n21])).astype(np.int64)
-        sign = 1 if name == "cyclic" else -1
-        want = (lin[:4] + sign * lin[4:]) % pp
-        ok = np.array_equal(rc.cpu().numpy()[ks], want.astype(np.uint32))
-        out[f"{name}_2^21_p{pp}"] = {"us": ms * 1e3, "coeffs_per_s": n21 / (ms * 1e-3), "bit_exact_sampled": bool(ok)}
+        ok = check_product(a2, b2, rc.cpu().numpy(), pp, rng, n=n21, sign=1 if name == "cyclic" else -1)
+        out[f"{name}_2^21_p{pp}"] = {"us": ms * 1e3, "coeffs_per_s": n21 / (ms * 1e-3), "checked_at_random_points": bool(ok)}
     del ra, rb, rc
     # general radix: products of length q 2^k - 1 through the length-q 2^k
     # circular convolution (prime-factor split), beside the default
@@ -633,13 +669,12 @@ def extra_configs(pm, torch, dev, copy_bw, args, reps=5):
         xc = torch.empty(lcm, dtype=torch.uint32, device=dev)
         pm.poly_mul_mixed(xa, xb, pp, q, out=xc)
         ms_mixed = time_loop(torch, lambda i: pm.poly_mul_mixed(xa, xb, pp, q, out=xc), 20)
-        ks = np.array([0, 1, lcm // 3, lcm - 1])
-        ok = np.array_equal(xc.cpu().numpy()[ks], op.poly_mul_sample(ma_, mb_, pp, ks))
+        ok = check_product(ma_, mb_, xc.cpu().numpy(), pp, rng)
         pm.poly_mul(xa, xb, pp, out=xc)
         ms_pow2 = time_loop(torch, lambda i: pm.poly_mul(xa, xb, pp, out=xc), 20)
         out[f"mixed_radix_{q}x2^{k}_p{pp}"] = {
             "lc": lcm, "us": ms_mixed * 1e3, "coeffs_per_s": lcm / (ms_mixed * 1e-3),
-            "pow2_default_us": ms_pow2 * 1e3, "bit_exact_sampled": bool(ok)}
+            "pow2_default_us": ms_pow2 * 1e3, "checked_at_random_points": bool(ok)}
         del xa, xb, xc
     return out
 
@@ -657,6 +692,9 @@ def main():
     ap.add_argument("--plans", default=TUNED_PLANS,
                     help="plans of the two plain large products among the other workloads, "
                          "'kind,log_l,log_ra,log_rb,log_c,ma,lq,lnt;...' (default: the autotuner's picks on MI355X)")
+    ap.add_argument("--transform-only", action="store_true",
+                    help="only the forward transforms of 2^22 points (the command their counters are taken with); "
+                         "prints their timings, not the headline line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 256 MiB three times (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -687,6 +725,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.zeros(1, device=dev)
     copy_bw = copy_bandwidth(torch, dev)
+    if args.transform_only:
+        print(json.dumps(standalone_transform(pm, torch, dev, copy_bw)), flush=True)
+        return
 
     if args.headline_only:
         args.no_cpu_baseline = args.no_extra = True
