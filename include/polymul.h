@@ -70,6 +70,30 @@ pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t
                       void* stream);
 
 /*
+ * pm_poly_mul for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * same product as pm_poly_mul, computed by the same kernels, but every
+ * intermediate (the four-step workspace and the row-pass factor tables of the
+ * plan) lives in a static device array of 22 MiB that each device holds from
+ * the library's load until the process ends; the call allocates nothing and
+ * never waits for the device.
+ *  - pm_init() must have run on the current device first (it finds the
+ *    array's address there); otherwise PM_EINVAL.
+ *  - The plan is the cached plan of the length (pm_plan_cache_put), else the
+ *    default plan; the cost model and the tuner are not consulted.
+ *  - Products whose plan needs more than the array (a relaxed transform
+ *    length n' above 2^21, i.e. len_a + len_b - 1 > 2^21 for the default
+ *    plans) give PM_ETOOLARGE and launch nothing.
+ *  - Every call on a device shares that device's array, which keeps the last
+ *    call's contents (nothing in it needs to start at zero): calls on
+ *    different streams of one device that overlap in time race on it, so
+ *    order them (one stream, or events).
+ * Other arguments and errors as pm_poly_mul.
+ */
+pm_status pm_poly_mul_noalloc(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
+                              uint32_t* c, void* stream);
+
+/*
  * Products in the quotient rings of the factorisation of eq. 13:
  *   pm_cyclic_mul:     c = a b mod (x^n - 1), the circular convolution
  *                      (Def. 4, eq. 5): c_i = sum_{j+k = i mod n} a_j b_k;

@@ -79,6 +79,7 @@ SIGNATURES = {
     "pm_status_str": (ctypes.c_char_p, [_int]),
     "pm_init": (_int, []),
     "pm_poly_mul": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, _vp]),
+    "pm_poly_mul_noalloc": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, _vp]),
     "pm_poly_mul_batch": (_int, [ctypes.POINTER(Problem), _sz, _vp]),
     "pm_batch_plans_used": (_int, [_vp, ctypes.POINTER(Plan), _sz]),
     "pm_cyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
@@ -207,8 +208,19 @@ def poly_mul(a, b, p: int, out=None, plan: Plan | None = None, stream=None):
 
 
 def init():
-    """Build the twiddle tables of the four primes on the current device."""
+    """Build the twiddle tables of the four primes on the current device and
+    find the allocation-free product's scratch array there."""
     _check(lib().pm_init(), "pm_init")
+
+
+def poly_mul_noalloc(a, b, p: int, out, stream=None):
+    """pm_poly_mul with every intermediate in the library's static scratch
+    array (nothing allocated; init() first; out is required)."""
+    torch = _torch()
+    la, lb = a.numel(), b.numel()
+    _check(lib().pm_poly_mul_noalloc(_dev_ptr(a, torch.uint32, "a"), la, _dev_ptr(b, torch.uint32, "b"), lb, p,
+                                     _dev_ptr(out, torch.uint32, "out"), _stream(stream)), "pm_poly_mul_noalloc")
+    return out
 
 
 def poly_mul_multi(a, b, p: int, out=None, stream=None):

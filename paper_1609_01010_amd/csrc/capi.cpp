@@ -15,6 +15,17 @@ size_t crt_workspace_bytes(long nl);
 hipError_t launch_widen(const uint16_t* in, long n, u32* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// the allocation-free product's scratch: the four-step workspace (two arrays
+// of at most kNoAllocMaxN words) and the row-pass factor tables of its plan.
+// One static device array; each device holds its own copy at its own
+// address, found by pm_init (hipGetSymbolAddress) and kept in the context.
+constexpr long kNoAllocMaxN = 1l << 21;
+constexpr size_t kNoAllocWsWords = 2 * (size_t)kNoAllocMaxN;
+constexpr size_t kNoAllocRowWords = (size_t)3 << 19;  // 6 MiB: the row tables of any plan with L <= 2^21
+constexpr size_t kScratchWords = kNoAllocWsWords + kNoAllocRowWords;
+static __device__ __align__(256) u32 scratch[kScratchWords];
+
+// ---------------------------------------------------------------------------
 // plans
 
 static int ceil_log2(long x) {
@@ -509,6 +520,13 @@ pm_status pm_init(void) {
     st = ensure_prime_tables(c, i);
     if (st) return st;
   }
+  if (!c->scratch) {
+    // this device's copy of the static scratch array (the host-side name is
+    // only a stand-in: kernels receive this address)
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PM_EDEVICE;
+    c->scratch = (u32*)ptr;
+  }
   return PM_OK;
 }
 
@@ -551,6 +569,43 @@ pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t
   return product_with(a, len_a, b, len_b, p, c, nullptr, stream);
 }
 
+pm_status pm_poly_mul_noalloc(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
+                              uint32_t* c, void* stream) {
+  int pidx;
+  long lc;
+  pm_status st = check_product_args(a, len_a, b, len_b, p, c, &pidx, &lc);
+  if (st) return st;
+  DevCtx* ctx = ctx_lookup();
+  if (!ctx || !ctx->scratch) return PM_EINVAL;  // pm_init has not run on this device
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!ctx->prime_mem[pidx]) return PM_EINVAL;
+  // the cached plan of the length, else the default one: neither the cost
+  // model nor the tuner is consulted
+  Plan P;
+  if (!plan_cache_get(lc, p, &P, kCtxSingle)) P = default_plan(lc, pidx);
+  if (!plan_valid(P, lc, pidx)) return PM_ETOOLARGE;
+  hipStream_t s = (hipStream_t)stream;
+  if (P.kind == PLAN_DIRECT) return dev_status(launch_direct(a, (long)len_a, b, (long)len_b, c, pidx, ctx->errflag, s));
+  JobRef jr;
+  jr.many = nullptr;
+  if (P.kind == PLAN_LDS) {
+    st = make_job(ctx, P, pidx, a, (long)len_a, b, (long)len_b, c, lc, nullptr, nullptr, &jr.one, 0, nullptr);
+    if (st) return st;
+    return launch_class(P, prime_info(pidx).lazy, 0, jr, 1, jr.one.rows, s);
+  }
+  const long n = plan_nprime(P);
+  const int lnt = plan_row_lnt(P);
+  if (n > kNoAllocMaxN || row_tables_bytes(P.logL, P.logC, lnt) > kNoAllocRowWords * sizeof(u32)) return PM_ETOOLARGE;
+  u32* Ta = ctx->scratch;
+  u32* Tb = Ta + n;
+  uint2* rmem = (uint2*)(ctx->scratch + kNoAllocWsWords);
+  RowTables W;
+  st = fill_row_tables(pidx, P.logL, P.logC, lnt, conv_scale(P, pidx).x, 0, rmem, s, &W);
+  if (st) return st;
+  st = make_job(ctx, P, pidx, a, (long)len_a, b, (long)len_b, c, lc, Ta, Tb, &jr.one, 0, &W);
+  if (st) return st;
+  return launch_class(P, prime_info(pidx).lazy, 0, jr, 1, jr.one.rows, s);
+}
 
 pm_status pm_workspace_query(size_t len_a, size_t len_b, uint32_t p, size_t* bytes) {
   if (!bytes) return PM_EINVAL;

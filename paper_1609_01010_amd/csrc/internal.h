@@ -88,6 +88,9 @@ struct DevCtx {
   // caller-owned workspace per stream (pm_set_workspace): used instead of ws
   std::map<hipStream_t, std::pair<void*, size_t>> user_ws;
   std::mutex mu;
+  // the allocation-free product's scratch (a static device array): its
+  // address on this device, found once at initialisation (null before)
+  u32* scratch = nullptr;
 };
 
 DevCtx* ctx_current(pm_status* st);
