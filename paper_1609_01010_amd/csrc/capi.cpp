@@ -9,9 +9,12 @@
 #include "internal.h"
 
 namespace pm {
-hipError_t launch_crt_carry(const u32* r1, const u32* r2, const u32* r3, long lc, long nl, void* ws, uint16_t* out,
-                            hipStream_t s);
-size_t crt_workspace_bytes(long nl);
+bool int3_fused_ok(const Plan& P);
+hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* jobs, hipStream_t s);
+hipError_t launch_col_inv_crt3(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s);
+hipError_t launch_crt_x(const u32* r1, const u32* r2, const u32* r3, long lc, u64* X, hipStream_t s);
+hipError_t launch_carry(const u64* X, long lc, long nl, void* ws, uint16_t* out, hipStream_t s);
+size_t carry_workspace_bytes(long nl);
 hipError_t launch_widen(const uint16_t* in, long n, u32* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
@@ -951,14 +954,19 @@ pm_status pm_itft(const uint32_t* v, size_t L, size_t n, uint32_t p, uint32_t* o
 
 static const u32 kIntPrimes[3] = {469762049u, 998244353u, 167772161u};
 
-// The integer product's plans and workspace: three residue arrays, the
-// widened operands when a plan needs 32-bit input, the largest plan
-// workspace, the carry state.
+// The integer product's plans and workspace.  When the three primes share
+// one four-step plan whose column passes have a fused three-prime form, the
+// passes run once over the three primes (the forward columns read the limbs
+// once; the inverse columns combine the residues in registers and write the
+// coefficients x_k as 64-bit words): the workspace holds each prime's Ta/Tb,
+// their descriptors, x and the carry state.  Otherwise each prime's product
+// writes a residue array (widened 32-bit operands for plans that need them),
+// a kernel combines the residues into x, and the carries follow.
 struct IntLayout {
   Plan plans[3];
   bool widen = false;
-  bool merged = false;  // one four-step plan for the three primes: each pass runs once over all three
-  size_t res_b = 0, wid_b = 0, pw = 0, jobs_b = 0, total = 0;
+  bool fused = false;
+  size_t res_b = 0, wid_b = 0, pw = 0, jobs_b = 0, x_b = 0, total = 0;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -968,6 +976,18 @@ static bool same_plan(const Plan& x, const Plan& y) {
          x.ma == y.ma && x.lq == y.lq && x.lnt == y.lnt && x.twist == y.twist;
 }
 
+static void int_layout_sizes(size_t na, size_t nb, IntLayout* L) {
+  const long lc = (long)(na + nb - 1);
+  L->x_b = align256((size_t)lc * 8);
+  L->res_b = L->fused ? 0 : align256((size_t)lc * 4);
+  L->wid_b = L->widen ? align256((na + nb) * 4) : 0;
+  const size_t pw = L->fused ? 3 * align256(L->pw) : align256(L->pw);
+  L->jobs_b = L->fused ? align256(3 * sizeof(ConvJob)) : 0;
+  L->total = 3 * L->res_b + L->wid_b + pw + L->jobs_b + L->x_b + align256(carry_workspace_bytes((long)(na + nb)));
+}
+
+// the plans the policy picks (plan choice may consult the cost model, so
+// this runs at call time)
 static pm_status int_mul_layout(size_t na, size_t nb, IntLayout* L) {
   const long lc = (long)(na + nb - 1);
   if (ceil_log2(lc) > 23) return PM_ETOOLARGE;
@@ -976,29 +996,46 @@ static pm_status int_mul_layout(size_t na, size_t nb, IntLayout* L) {
     L->plans[i] = choose_plan(lc, pidx);
     if (!plan_valid(L->plans[i], lc, pidx)) return PM_ETOOLARGE;
     if (L->plans[i].kind != PLAN_FOURSTEP) L->widen = true;
-    const size_t w = plan_workspace_bytes(L->plans[i]);
-    if (w > L->pw) L->pw = w;
+    L->pw = std::max(L->pw, plan_workspace_bytes(L->plans[i]));
   }
-  // the three primes are below 2^30 (one value range), so equal plans can
-  // share launches; each product then has its own four-step workspace
-  L->merged = L->plans[0].kind == PLAN_FOURSTEP && same_plan(L->plans[0], L->plans[1]) &&
-              same_plan(L->plans[0], L->plans[2]);
-  if (L->merged) {
-    L->pw = 3 * align256(L->pw);
-    L->jobs_b = align256(3 * sizeof(ConvJob));
-  }
-  L->res_b = align256((size_t)lc * 4);
-  L->wid_b = L->widen ? align256((na + nb) * 4) : 0;
-  L->total = 3 * L->res_b + L->wid_b + align256(L->pw) + L->jobs_b + align256(crt_workspace_bytes((long)(na + nb)));
+  // the three primes are below 2^30 (one value range), so equal plans can share launches
+  L->fused = int3_fused_ok(L->plans[0]) && same_plan(L->plans[0], L->plans[1]) && same_plan(L->plans[0], L->plans[2]);
+  int_layout_sizes(na, nb, L);
   return PM_OK;
 }
 
 pm_status pm_int_mul_workspace_query(size_t na, size_t nb, size_t* bytes) {
   if (!bytes || na == 0 || nb == 0) return PM_EINVAL;
+  const long lc = (long)(na + nb - 1);
+  if (ceil_log2(lc) > 23) return PM_ETOOLARGE;
+  // on the host alone: under the default policy (or with every prime's plan
+  // put by the caller) the plans the call will use; otherwise (the cost model
+  // picks at call time) the most any candidate plan could need, in the
+  // layout that needs more
+  bool known = current_policy() == PM_POLICY_DEFAULT;
+  if (!known) {
+    known = true;
+    for (int i = 0; i < 3; ++i) known = known && plan_pinned(lc, kIntPrimes[i]);
+  }
   IntLayout L;
-  const pm_status st = int_mul_layout(na, nb, &L);
-  if (st) return st;
-  *bytes = L.total;
+  if (known) {
+    const pm_status st = int_mul_layout(na, nb, &L);
+    if (st) return st;
+    *bytes = L.total;
+    return PM_OK;
+  }
+  size_t pw = 0;
+  for (int i = 0; i < 3; ++i) pw = std::max(pw, product_workspace_bound(lc, prime_index(kIntPrimes[i])));
+  size_t worst = 0;
+  for (int fused = 0; fused < 2; ++fused) {
+    IntLayout W;
+    W.pw = pw;
+    W.widen = !fused;
+    W.fused = fused != 0;
+    int_layout_sizes(na, nb, &W);
+    worst = std::max(worst, W.total);
+  }
+  *bytes = worst;
   return PM_OK;
 }
 
@@ -1015,53 +1052,54 @@ pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb,
   IntLayout LY;
   st = int_mul_layout(na, nb, &LY);
   if (st) return st;
-  const Plan* plans = LY.plans;
-  const bool widen = LY.widen;
-  const size_t res_b = LY.res_b, wid_b = LY.wid_b, pw = LY.pw, total = LY.total;
-  auto al = align256;
   void* wsp = nullptr;
-  st = stream_workspace(c, s, total, &wsp);
+  st = stream_workspace(c, s, LY.total, &wsp);
   if (st) return st;
   char* base = (char*)wsp;
-  u32* res[3] = {(u32*)base, (u32*)(base + res_b), (u32*)(base + 2 * res_b)};
-  u32* wa = (u32*)(base + 3 * res_b);
+  u32* res[3] = {(u32*)base, (u32*)(base + LY.res_b), (u32*)(base + 2 * LY.res_b)};
+  u32* wa = (u32*)(base + 3 * LY.res_b);
   u32* wb = wa + na;
-  void* pws = base + 3 * res_b + wid_b;
-  ConvJob* djobs = (ConvJob*)((char*)pws + al(pw));
-  void* cws = (char*)djobs + LY.jobs_b;
-  hipError_t e = hipSuccess;
-  if (widen) {
-    e = launch_widen(a, (long)na, wa, s);
-    if (e == hipSuccess) e = launch_widen(b, (long)nb, wb, s);
-    if (e != hipSuccess) return PM_EDEVICE;
-  }
-  if (LY.merged) {
-    const Plan& P = plans[0];
-    const size_t pw1 = pw / 3;
+  char* pws = base + 3 * LY.res_b + LY.wid_b;
+  const size_t pw1 = align256(LY.pw);
+  ConvJob* djobs = (ConvJob*)(pws + (LY.fused ? 3 * pw1 : pw1));
+  u64* X = (u64*)((char*)djobs + LY.jobs_b);
+  void* cws = (char*)X + LY.x_b;
+  if (LY.fused) {
+    // each pass once over the three primes; the residues never leave the inverse column pass
+    const Plan& P = LY.plans[0];
     ConvJob J[3];
     for (int i = 0; i < 3; ++i) {
-      u32* Ta = (u32*)((char*)pws + i * pw1);
-      st = make_job(c, P, prime_index(kIntPrimes[i]), a, (long)na, b, (long)nb, res[i], lc, Ta, Ta + plan_nprime(P),
+      u32* Ta = (u32*)(pws + i * pw1);
+      st = make_job(c, P, prime_index(kIntPrimes[i]), a, (long)na, b, (long)nb, nullptr, lc, Ta, Ta + plan_nprime(P),
                     &J[i], 0);
       if (st) return st;
     }
-    if (launch_store_jobs3(J, djobs, s) != hipSuccess) return PM_EDEVICE;
     JobRef jr;
     jr.one = J[0];
     jr.many = djobs;
-    st = launch_class(P, prime_info(prime_index(kIntPrimes[0])).lazy, 1, jr, 3, J[0].rows, s);
-    if (st) return st;
-    return dev_status(launch_crt_carry(res[0], res[1], res[2], lc, nl, cws, out, s));
+    hipError_t e = launch_store_jobs3(J, djobs, s);
+    if (e == hipSuccess) e = launch_col_fwd_int3(P, djobs, s);
+    if (e == hipSuccess) e = launch_row_conv(P, true, J[0].rows, jr, 3, s);
+    if (e == hipSuccess) e = launch_col_inv_crt3(P, djobs, X, s);
+    if (e == hipSuccess) e = launch_carry(X, lc, nl, cws, out, s);
+    return dev_status(e);
+  }
+  if (LY.widen) {
+    hipError_t e = launch_widen(a, (long)na, wa, s);
+    if (e == hipSuccess) e = launch_widen(b, (long)nb, wb, s);
+    if (e != hipSuccess) return PM_EDEVICE;
   }
   for (int i = 0; i < 3; ++i) {
     const int pidx = prime_index(kIntPrimes[i]);
-    if (plans[i].kind == PLAN_FOURSTEP)
-      st = run_product(c, plans[i], a, (long)na, b, (long)nb, 1, res[i], lc, pidx, pws, s);
+    if (LY.plans[i].kind == PLAN_FOURSTEP)
+      st = run_product(c, LY.plans[i], a, (long)na, b, (long)nb, 1, res[i], lc, pidx, pws, s);
     else
-      st = run_product(c, plans[i], wa, (long)na, wb, (long)nb, 0, res[i], lc, pidx, pws, s);
+      st = run_product(c, LY.plans[i], wa, (long)na, wb, (long)nb, 0, res[i], lc, pidx, pws, s);
     if (st) return st;
   }
-  return dev_status(launch_crt_carry(res[0], res[1], res[2], lc, nl, cws, out, s));
+  hipError_t e = launch_crt_x(res[0], res[1], res[2], lc, X, s);
+  if (e == hipSuccess) e = launch_carry(X, lc, nl, cws, out, s);
+  return dev_status(e);
 }
 
 }  // extern "C"

@@ -1,0 +1,162 @@
+// Column passes of the four-step transforms: rounds of radix at most 16 over
+// an [R][W] LDS tile of W adjacent columns (lanes along the columns, so every
+// global access is a run of W consecutive words), used by the convolutions'
+// column kernels and by the integer product's three-prime kernels.
+//
+// Split used throughout, for L = R * C: input index j = C j1 + j2 (j1 < R the
+// row, j2 < C the column); the column transforms are length-R DIF networks
+// (natural in, bit-reversed out), and the rows t < mr are the ones kept.
+#pragma once
+#include "internal.h"
+
+namespace pm {
+
+// radix (log2) of round k (outermost first) of a length-2^LR column transform
+template <int LR, int K>
+constexpr int col_round_lq() {
+  constexpr int seq[11][3] = {{0, 0, 0}, {1, 0, 0}, {2, 0, 0}, {3, 0, 0}, {4, 0, 0}, {2, 3, 0},
+                              {3, 3, 0}, {3, 4, 0}, {4, 4, 0}, {3, 3, 3}, {4, 3, 3}};
+  return seq[LR][K];
+}
+
+// DIF round of radix 2^LQ over the blocks of 2^LB rows that start below mr;
+// FROM_GLOBAL: the input is the operand in global memory (rows beyond its
+// length are zero), else LDS; TO_GLOBAL: output rows below mr go to `out`,
+// else back to LDS
+template <int LB, int LQ, bool FROM_GLOBAL, bool TO_GLOBAL, bool LAZY, typename TIn, bool TWIST>
+__device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
+                                              int tid, int nthr, const TIn* __restrict__ in, long z, long C, long col0,
+                                              u32* __restrict__ out, const uint2* twf, bool& bad) {
+  constexpr int Q = 1 << LQ;
+  constexpr int LS = LB - LQ;
+  constexpr int K = 16 / Q;
+  const int ntask = (((mr + (1 << LB) - 1) >> LB) << LS) << lw;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int task = tid + k * nthr;
+    if (task < ntask) {
+      const int c = task & ((1 << lw) - 1);
+      const int g = task >> lw;
+      const int j = g & ((1 << LS) - 1);
+      const int base = ((g >> LS) << LB) + j;
+      u32 x[Q];
+#pragma unroll
+      for (int s = 0; s < Q; ++s) {
+        const int row = base + (s << LS);
+        if constexpr (FROM_GLOBAL) {
+          const long pos = C * row + col0 + c;
+          x[s] = pos < z ? (u32)gld(in + pos) : 0u;
+          bad |= x[s] >= A.p;
+          if constexpr (TWIST) x[s] = A.mul(x[s], cld(twf + row));
+        } else {
+          x[s] = sm[(row << lw) + c];
+        }
+      }
+      // the first round spans whole columns (LB = log R): rows R/2 and up
+      // are zero when the operand has at most L/2 values
+      if (FROM_GLOBAL && (C << (LB - 1)) >= z)
+        dif_reg<Q, LAZY, (LS > 0), true>(A, x, T.pf);
+      else
+        dif_reg<Q, LAZY, (LS > 0)>(A, x, T.pf);
+      const uint2* tw = T.rf[LQ - 1] + (1 << LB) + j * Q;
+#pragma unroll
+      for (int t = 0; t < Q; ++t) {
+        const int row = base + (t << LS);
+        u32 v = x[t];
+        if (LS > 0 && t > 0) v = A.mul(v, cld(tw + t));
+        if constexpr (TO_GLOBAL) {
+          if (row < mr) gst(out + C * row + col0 + c, v);
+        } else {
+          sm[(row << lw) + c] = v;
+        }
+      }
+    }
+  }
+}
+
+// rounds K.. of the forward column transform on blocks of 2^LB rows; a
+// barrier separates consecutive rounds
+template <int LR, int K, int LB, bool LAZY, typename TIn, bool TWIST>
+__device__ __forceinline__ void col_dif_rounds(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
+                                               int tid, int nthr, const TIn* in, long z, long C, long col0, u32* out,
+                                               const uint2* twf, bool& bad) {
+  constexpr int LQ = col_round_lq<LR, K>();
+  constexpr bool first = K == 0;
+  constexpr bool last = LB == LQ;
+  col_dif_round<LB, LQ, first, last, LAZY, TIn, TWIST>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, twf, bad);
+  if constexpr (!last) {
+    __syncthreads();
+    col_dif_rounds<LR, K + 1, LB - LQ, LAZY, TIn, TWIST>(A, sm, lw, mr, T, tid, nthr, in, z, C, col0, out, twf, bad);
+  }
+}
+
+// Columns per work-group: 32 (128-byte row segments) unless the tile of R
+// rows would exceed 64 KB, and 16 when the grid would otherwise have fewer
+// than min_wg work-groups: the chip's 256 compute units, or two per unit for
+// the forward pass of a single operand (the transform hooks), whose half
+// as many tiles otherwise leave one work-group per unit.
+inline int col_lw(int logR, int logC, long groups, long min_wg = 256) {
+  int lw = 5;
+  if (logR + lw > 14) lw = 14 - logR;
+  if (lw > logC) lw = logC;
+  while (lw > 4 && (groups << (logC - lw)) < min_wg) --lw;
+  return lw;
+}
+inline int col_threads(int logR, int lw) {
+  const int n = 1 << (lw + logR - 4);
+  return n < 64 ? 64 : n;
+}
+
+// DIT round of radix 2^LQ over the blocks of 2^LB rows below mr (all whole);
+// FROM_GLOBAL: the input rows come from `in` (the innermost round), else LDS
+template <int LB, int LQ, bool FROM_GLOBAL, bool LAZY>
+__device__ __forceinline__ void col_dit_round(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
+                                              int tid, int nthr, const u32* __restrict__ in, long C, long col0) {
+  constexpr int Q = 1 << LQ;
+  constexpr int LS = LB - LQ;
+  constexpr int K = 16 / Q;
+  const int ntask = ((mr >> LB) << LS) << lw;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int task = tid + k * nthr;
+    if (task < ntask) {
+      const int c = task & ((1 << lw) - 1);
+      const int g = task >> lw;
+      const int j = g & ((1 << LS) - 1);
+      const int base = ((g >> LS) << LB) + j;
+      const uint2* tw = T.ri[LQ - 1] + (1 << LB) + j * Q;
+      u32 x[Q];
+#pragma unroll
+      for (int t = 0; t < Q; ++t) {
+        const int row = base + (t << LS);
+        u32 v = FROM_GLOBAL ? gld(in + C * row + col0 + c) : sm[(row << lw) + c];
+        if (LS > 0 && t > 0) v = A.mul(v, cld(tw + t));
+        x[t] = v;
+      }
+      dit_reg<Q>(A, x, T.pi);
+#pragma unroll
+      for (int s = 0; s < Q; ++s) sm[((base + (s << LS)) << lw) + c] = x[s];
+    }
+  }
+}
+
+// inverse rounds of the length-RB blocks: the mirror of the forward split of
+// LRB (rounds K, K-1, .., 0, innermost first); each ends with a barrier
+template <int LRB, int K, int LB, bool LAZY>
+__device__ __forceinline__ void col_dit_rounds(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
+                                               int tid, int nthr, const u32* in, long C, long col0) {
+  constexpr int LQ = col_round_lq<LRB, K>();
+  if constexpr (LQ > 0) {
+    constexpr bool first = LB == 0;
+    col_dit_round<LB + LQ, LQ, first, LAZY>(A, sm, lw, mr, T, tid, nthr, in, C, col0);
+    __syncthreads();
+    if constexpr (K > 0) col_dit_rounds<LRB, K - 1, LB + LQ, LAZY>(A, sm, lw, mr, T, tid, nthr, in, C, col0);
+  }
+}
+
+template <int LR>
+constexpr int col_last_round() {
+  return col_round_lq<LR, 2>() ? 2 : (col_round_lq<LR, 1>() ? 1 : 0);
+}
+
+}  // namespace pm

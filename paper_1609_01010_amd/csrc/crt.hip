@@ -1,57 +1,32 @@
-// Three-primes integer product, final steps (section 1): the residues of each
-// coefficient modulo p1 = 469762049, p2 = 998244353, p3 = 167772161 give the
-// exact coefficient x_k < p1 p2 p3 (Chinese remainder theorem, Garner's
-// mixed-radix form); then sum_k x_k 2^{16 k} is written in 16-bit limbs.
+// Three-primes integer product (section 1): the limb sequences are
+// convolved modulo p1 = 469762049, p2 = 998244353, p3 = 167772161, the three
+// residues of every coefficient give the exact coefficient x_k < p1 p2 p3
+// (Chinese remainder theorem, Garner's mixed-radix form), and sum_k x_k
+// 2^{16 k} is written in 16-bit limbs.
 //
-// Carry propagation: x_k < 2^96 is split into six 16-bit digits and digit d
-// is added to limb k + d, so every limb sum s_m = sum_d digit_d(x_{m-d}) is
-// below 6 * 2^16.  Limb m is (s_m + carry_m) mod 2^16 and the carry into
-// limb m + 1 is (s_m + carry_m) >> 16 <= 6.  A run of limbs maps its carry-in
-// c in [0, 7) to a carry-out in [0, 7); these maps are composed with a
-// parallel scan (function composition is associative), so the carries of
-// all limbs are found in three passes over memory.
+// When the three primes share one four-step plan, the column passes run once
+// for all three: the forward pass reads each tile of limbs once and
+// transforms it modulo each prime in turn, and the inverse pass inverts each
+// prime's tile in turn, keeps the residues in registers and combines them, so
+// only the coefficients x_k reach memory (never the residues).  For the
+// supported sizes (na + nb - 1 <= 2^23, so min(na, nb) <= 2^22) every
+// x_k < 2^22 (2^16 - 1)^2 < 2^54 fits one 64-bit word.
+//
+// Carries: x_k < 2^54 is four 16-bit digits; digit d goes to limb k + d, so
+// the limb sum s_m = sum_{d<4} digit_d(x_{m-d}) < 2^18.  Splitting s_m into
+// its low 16 bits and its high part h_m <= 3, the value t_m = lo(s_m) +
+// h_{m-1} <= 2^16 + 2 leaves carries of 0 or 1 only: limb m is (t_m + c_m)
+// mod 2^16 and c_{m+1} = (t_m + c_m) >> 16.  A run of limbs maps its
+// carry-in c in {0, 1} to a carry-out; the maps (two bits) compose
+// associatively, so the carries are found by a scan in three passes.
+#include "colpass.h"
 #include "internal.h"
 #include "trace.h"
 
 namespace pm {
 
-constexpr int kCrtThreads = 256;
-constexpr int kCrtPer = 8;                          // limbs per thread
-constexpr int kCrtBlock = kCrtThreads * kCrtPer;    // limbs per work-group
-constexpr int kCarryStates = 7;                     // carries 0..6
-
-// carry maps packed 3 bits per state: f(c) = (F >> 3c) & 7
-__device__ __forceinline__ u32 cm_apply(u32 F, u32 c) { return (F >> (3 * c)) & 7u; }
-__device__ __forceinline__ u32 cm_compose(u32 G, u32 F) {  // G after F
-  u32 H = 0;
-#pragma unroll
-  for (u32 c = 0; c < kCarryStates; ++c) H |= cm_apply(G, cm_apply(F, c)) << (3 * c);
-  return H;
-}
-__device__ __forceinline__ u32 cm_identity() {
-  u32 H = 0;
-#pragma unroll
-  for (u32 c = 0; c < kCarryStates; ++c) H |= c << (3 * c);
-  return H;
-}
-// inclusive scan over the work-group: on return maps[t] = F_t o ... o F_0
-template <int NT>
-__device__ __forceinline__ void cm_block_scan(u32* maps, int tid) {
-  for (int off = 1; off < NT; off <<= 1) {
-    u32 G = maps[tid];
-    if (tid >= off) G = cm_compose(G, maps[tid - off]);
-    __syncthreads();
-    maps[tid] = G;
-    __syncthreads();
-  }
-}
-// map of one limb with sum s
-__device__ __forceinline__ u32 cm_limb(u32 s) {
-  u32 H = 0;
-#pragma unroll
-  for (u32 c = 0; c < kCarryStates; ++c) H |= ((s + c) >> 16) << (3 * c);
-  return H;
-}
+// ---------------------------------------------------------------------------
+// Garner's reconstruction
 
 struct CrtConsts {
   u32 p1, p2, p3;
@@ -66,8 +41,9 @@ __device__ __forceinline__ u32 shoup_canon(u32 x, uint2 w, u32 p) {
   return min(r, r - p);
 }
 
-// x_k as three 32-bit words (x0 least significant)
-__device__ __forceinline__ void crt_value(const CrtConsts& K, u32 r1, u32 r2, u32 r3, u32& x0, u32& x1, u32& x2) {
+// x = v1 + p1 v2 + p1 p2 v3 from canonical residues r1, r2, r3; the caller
+// guarantees x < 2^64 (the sizes the integer product supports)
+__device__ __forceinline__ u64 crt_value(const CrtConsts& K, u32 r1, u32 r2, u32 r3) {
   const u32 v1 = r1;
   const u32 v2 = shoup_canon(r2 + K.p2 - v1, K.inv_p1_mod_p2, K.p2);  // v1 < p1 < p2
   u32 v1m3 = v1;
@@ -78,118 +54,10 @@ __device__ __forceinline__ void crt_value(const CrtConsts& K, u32 r1, u32 r2, u3
   u32 u = v1m3 + t;
   u = min(u, u - K.p3);
   const u32 v3 = shoup_canon(r3 + K.p3 - u, K.inv_p1p2_mod_p3, K.p3);
-  // x = v1 + p1 v2 + p1 p2 v3 < 2^87
-  const u64 s = (u64)v1 + (u64)K.p1 * v2;  // < 2^60
-  const u64 lo = K.p1p2 * (u64)v3;
-  const u64 hi = __umul64hi(K.p1p2, (u64)v3);
-  const u64 lo2 = lo + s;
-  const u64 hi2 = hi + (lo2 < lo ? 1ull : 0ull);
-  x0 = (u32)lo2;
-  x1 = (u32)(lo2 >> 32);
-  x2 = (u32)hi2;
+  return (u64)v1 + (u64)K.p1 * v2 + K.p1p2 * (u64)v3;
 }
 
-__device__ __forceinline__ u32 digit(u32 x0, u32 x1, u32 x2, int d) {
-  const u32 w = d < 2 ? x0 : (d < 4 ? x1 : x2);
-  return (d & 1) ? (w >> 16) : (w & 0xFFFFu);
-}
-
-// Pass 1: limb sums s_m for m < nl and the carry map of each work-group's run.
-__global__ void __launch_bounds__(kCrtThreads) k_crt_sums(const u32* __restrict__ r1, const u32* __restrict__ r2,
-                                                          const u32* __restrict__ r3, long lc, long nl, CrtConsts K,
-                                                          u32* __restrict__ sums, u32* __restrict__ bmap) {
-  __shared__ u32 xs[3][kCrtBlock + 8];
-  __shared__ u32 maps[kCrtThreads];
-  const long m0 = (long)blockIdx.x * kCrtBlock;
-  const int tid = threadIdx.x;
-  // coefficients k in [m0 - 5, m0 + kCrtBlock)
-  for (int i = tid; i < kCrtBlock + 5; i += kCrtThreads) {
-    const long k = m0 - 5 + i;
-    u32 x0 = 0, x1 = 0, x2 = 0;
-    if (k >= 0 && k < lc) crt_value(K, r1[k], r2[k], r3[k], x0, x1, x2);
-    xs[0][i] = x0;
-    xs[1][i] = x1;
-    xs[2][i] = x2;
-  }
-  __syncthreads();
-  u32 F = cm_identity();
-  for (int q = 0; q < kCrtPer; ++q) {
-    const int i = tid * kCrtPer + q;  // limb m0 + i
-    const long m = m0 + i;
-    u32 s = 0;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      const int k = i + 5 - d;  // index of x_{m-d} in xs
-      s += digit(xs[0][k], xs[1][k], xs[2][k], d);
-    }
-    if (m < nl) {
-      sums[m] = s;
-      F = cm_compose(cm_limb(s), F);
-    }
-  }
-  maps[tid] = F;
-  __syncthreads();
-  cm_block_scan<kCrtThreads>(maps, tid);
-  if (tid == kCrtThreads - 1) bmap[blockIdx.x] = maps[tid];
-}
-
-// Pass 2 (one work-group): carry into every run, from the composed maps.
-__global__ void __launch_bounds__(1024) k_carry_scan(const u32* __restrict__ bmap, int nblk, u32* __restrict__ cin) {
-  __shared__ u32 sc[1024];
-  const int tid = threadIdx.x;
-  const int per = (nblk + 1023) / 1024;
-  const int b0 = tid * per;
-  u32 F = cm_identity();
-  for (int q = 0; q < per; ++q)
-    if (b0 + q < nblk) F = cm_compose(bmap[b0 + q], F);
-  sc[tid] = F;
-  __syncthreads();
-  cm_block_scan<1024>(sc, tid);
-  u32 c = tid > 0 ? cm_apply(sc[tid - 1], 0) : 0u;
-  for (int q = 0; q < per; ++q) {
-    if (b0 + q < nblk) {
-      cin[b0 + q] = c;
-      c = cm_apply(bmap[b0 + q], c);
-    }
-  }
-}
-
-// Pass 3: limbs from the sums and the carries.
-__global__ void __launch_bounds__(kCrtThreads) k_carry_apply(const u32* __restrict__ sums, long nl,
-                                                             const u32* __restrict__ cin, uint16_t* __restrict__ out) {
-  __shared__ u32 maps[kCrtThreads];
-  const long m0 = (long)blockIdx.x * kCrtBlock;
-  const int tid = threadIdx.x;
-  u32 s[kCrtPer];
-  u32 F = cm_identity();
-#pragma unroll
-  for (int q = 0; q < kCrtPer; ++q) {
-    const long m = m0 + tid * kCrtPer + q;
-    s[q] = m < nl ? sums[m] : 0u;
-    F = cm_compose(cm_limb(s[q]), F);
-  }
-  maps[tid] = F;
-  __syncthreads();
-  cm_block_scan<kCrtThreads>(maps, tid);
-  // carry into this thread's run: the runs of the threads before it
-  u32 c = cin[blockIdx.x];
-  if (tid > 0) c = cm_apply(maps[tid - 1], c);
-#pragma unroll
-  for (int q = 0; q < kCrtPer; ++q) {
-    const long m = m0 + tid * kCrtPer + q;
-    const u32 v = s[q] + c;
-    if (m < nl) out[m] = (uint16_t)(v & 0xFFFFu);
-    c = v >> 16;
-  }
-}
-
-size_t crt_workspace_bytes(long nl) {
-  const long nblk = (nl + kCrtBlock - 1) / kCrtBlock;
-  return (size_t)nl * 4 + (size_t)nblk * 8 + 256;
-}
-
-hipError_t launch_crt_carry(const u32* r1, const u32* r2, const u32* r3, long lc, long nl, void* ws, uint16_t* out,
-                            hipStream_t s) {
+static CrtConsts crt_consts() {
   const PrimeInfo& P1 = prime_info(prime_index(469762049u));
   const PrimeInfo& P2 = prime_info(prime_index(998244353u));
   const PrimeInfo& P3 = prime_info(prime_index(167772161u));
@@ -201,13 +69,345 @@ hipError_t launch_crt_carry(const u32* r1, const u32* r2, const u32* r3, long lc
   K.p1_mod_p3 = h_shoup(P1.p % P3.p, P3.p);
   K.inv_p1p2_mod_p3 = h_shoup(h_inv(h_mulmod(P1.p % P3.p, P2.p % P3.p, P3.p), P3.p), P3.p);
   K.p1p2 = (u64)P1.p * P2.p;
-  const long nblk = (nl + kCrtBlock - 1) / kCrtBlock;
-  u32* sums = (u32*)ws;
-  u32* bmap = sums + nl;
+  return K;
+}
+
+// the coefficients from three residue arrays (plans that differ per prime)
+__global__ void __launch_bounds__(256) k_crt_x(const u32* __restrict__ r1, const u32* __restrict__ r2,
+                                               const u32* __restrict__ r3, long lc, CrtConsts K, u64* __restrict__ X) {
+  const long k = (long)blockIdx.x * 256 + threadIdx.x;
+  if (k < lc) X[k] = crt_value(K, r1[k], r2[k], r3[k]);
+}
+
+// ---------------------------------------------------------------------------
+// the three primes' column passes (four-step plan shared by the primes; all
+// three are below 2^30, so the LAZY value range)
+
+__device__ __forceinline__ ConvJob job_at(const ConvJob* many, int k) {
+  ConvJob J;
+  const PM_CMEM uint32_t* s = (const PM_CMEM uint32_t*)(many + k);
+  uint32_t* d = reinterpret_cast<uint32_t*>(&J);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(ConvJob) / 4); ++i) d[i] = s[i];
+  return J;
+}
+
+// Forward columns of one operand (blockIdx.y) modulo the three primes
+// (jobs[0..2]), one after the other on the same tile of limbs: the first
+// prime's round reads the tile from memory, the others find it in the L2
+// cache (each limb is read from HBM once), and the stores of one prime drain
+// while the next one computes.
+template <int LR>
+__global__ void __launch_bounds__(1024) k_col_fwd_int3(const ConvJob* jobs, int logC, int lw) {
+  extern __shared__ u32 sm[];  // [R][W]
+  const int nthr = blockDim.x;
+  const long C = 1l << logC;
+  const long col0 = (long)blockIdx.x << lw;
+  bool bad = false;
+#pragma unroll 1
+  for (int pr = 0; pr < 3; ++pr) {
+    // the thread index passes through an empty asm each prime, so the
+    // compiler cannot hoist every round's addresses out of the loop and
+    // hold them in registers across it
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const ConvJob J = job_at(jobs, pr);
+    const Arith<true> A(J.mp);
+    const uint16_t* in = (const uint16_t*)(blockIdx.y ? J.b : J.a);
+    const long z = blockIdx.y ? J.lb : J.la;
+    u32* out = blockIdx.y ? J.Tb : J.Ta;
+    col_dif_rounds<LR, 0, LR, true, uint16_t, false>(A, sm, lw, J.rows, fresh(J.T), tid, nthr, in, z, C, col0, out,
+                                                     nullptr, bad);
+    __syncthreads();  // the next prime reuses the tile
+  }
+}
+
+// Inverse columns modulo the three primes and Garner's reconstruction: each
+// prime's length-RB inverses of the tile (the innermost round from its row
+// pass output), then per (column, j1b) task the inverse of radix RA with ma
+// known values, into registers; the three residues of every output give x_k,
+// written as one 64-bit word.  RA <= 16: a thread owns 16 / RA tasks and keeps
+// 48 residues, so work-groups are at most 512 threads (16-column tiles at R =
+// 512), which leaves each thread up to 256 registers.
+// one prime's inverse columns of the tile (jobs[pr]), residues canonical
+template <int LRA, int LRB, int TPT>
+__device__ __forceinline__ void inv_tile_prime(const ConvJob* jobs, int pr, u32* sm, long C, int lw, long c0, int nthr,
+                                               u32 (&res)[TPT][1 << LRA]) {
+  constexpr int RA = 1 << LRA, RB = 1 << LRB, R = RA * RB;
+  int tid = threadIdx.x;  // through an empty asm per prime: no addresses hoisted across primes
+  asm volatile("" : "+v"(tid));
+  const ConvJob J = job_at(jobs, pr);
+  const Arith<true> A(J.mp);
+  const PrimeTables T = fresh(J.T);
+  const int ma = J.ma;
+  const int W = 1 << lw;
+  col_dit_rounds<LRB, col_last_round<LRB>(), 0, true>(A, sm, lw, ma << LRB, T, tid, nthr, J.Ta, C, c0);
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int task = tid + q * nthr;  // < W RB: the grid has exactly W R / 16 threads
+    const int cc = task & (W - 1);
+    const int j1b = task >> lw;
+    const uint2* tw = T.ri[LRA - 1] + R + j1b * RA;
+    u32 x[RA];
+#pragma unroll
+    for (int ta = 0; ta < RA; ++ta) {
+      u32 v = 0;
+      if (ta < ma) {
+        v = sm[((ta * RB + j1b) << lw) + cc];
+        if (ta > 0) v = A.mul(v, cld(tw + ta));
+      }
+      x[ta] = v;
+    }
+    inv_column<RA, true>(A, x, ma, T);
+#pragma unroll
+    for (int e = 0; e < RA; ++e) res[q][e] = A.canon(x[e]);
+  }
+  __syncthreads();  // the next prime reuses the tile
+}
+
+template <int LRA, int LRB>
+__global__ void __launch_bounds__(512) k_col_inv_crt3(const ConvJob* jobs, int logC, int lw, CrtConsts K,
+                                                      u64* __restrict__ X) {
+  constexpr int RA = 1 << LRA, RB = 1 << LRB;
+  constexpr int TPT = 16 / RA;
+  static_assert(LRA <= 4, "at most one task of 16 values per thread");
+  extern __shared__ u32 sm[];  // [R][W]
+  const long C = 1l << logC;
+  const int W = 1 << lw;
+  const long c0 = (long)blockIdx.x << lw;
+  const int nthr = blockDim.x;
+  u32 r1[TPT][RA], r2[TPT][RA], r3[TPT][RA];
+  inv_tile_prime<LRA, LRB, TPT>(jobs, 0, sm, C, lw, c0, nthr, r1);
+  inv_tile_prime<LRA, LRB, TPT>(jobs, 1, sm, C, lw, c0, nthr, r2);
+  inv_tile_prime<LRA, LRB, TPT>(jobs, 2, sm, C, lw, c0, nthr, r3);
+  const ConvJob J0 = job_at(jobs, 0);
+  const int ma = J0.ma;
+  const long lc = J0.lc;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int task = tid + q * nthr;
+    const int cc = task & (W - 1);
+    const int j1b = task >> lw;
+#pragma unroll
+    for (int e = 0; e < RA; ++e) {
+      const long pos = C * (j1b + RB * e) + c0 + cc;
+      if (e < ma && pos < lc) gst(X + pos, crt_value(K, r1[q][e], r2[q][e], r3[q][e]));
+    }
+  }
+}
+
+// the fused passes: four-step plans with the first radix 16 (a thread then
+// owns one inverse task of 16 values per prime) and 2^6 .. 2^9 column rows
+bool int3_fused_ok(const Plan& P) {
+  return P.kind == PLAN_FOURSTEP && P.logRA == 4 && P.logRB >= 2 && P.logRB <= 5;
+}
+
+template <int LR>
+static hipError_t fwd_int3_lr(const Plan& P, const ConvJob* jobs, hipStream_t s) {
+  const int lw = col_lw(LR, P.logC, 2);
+  const long C = 1l << P.logC;
+  if (C < (1l << lw) || col_threads(LR, lw) > 1024) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)1 << (lw + LR)) * sizeof(u32);
+  auto kern = k_col_fwd_int3<LR>;
+  ensure_lds_attr((const void*)kern, lds);
+  return launch("col_fwd", kern, dim3((unsigned)(C >> lw), 2, 1), col_threads(LR, lw), lds, s, jobs, P.logC, lw);
+}
+
+hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* jobs, hipStream_t s) {
+  if (!int3_fused_ok(P)) return hipErrorInvalidValue;
+  switch (P.logRA + P.logRB) {
+    case 6: return fwd_int3_lr<6>(P, jobs, s);
+    case 7: return fwd_int3_lr<7>(P, jobs, s);
+    case 8: return fwd_int3_lr<8>(P, jobs, s);
+    case 9: return fwd_int3_lr<9>(P, jobs, s);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int LRA, int LRB>
+static hipError_t inv_crt3_inst(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s) {
+  int lw = col_lw(LRA + LRB, P.logC, 1);
+  while (lw > 0 && col_threads(LRA + LRB, lw) > 512) --lw;
+  const long C = 1l << P.logC;
+  // the kernel gives every thread exactly 16 / RA tasks: W R / 16 threads
+  if (C < (1l << lw) || col_threads(LRA + LRB, lw) > 512 || 16 * col_threads(LRA + LRB, lw) != (1 << (lw + LRA + LRB)))
+    return hipErrorInvalidValue;
+  const size_t lds = ((size_t)1 << (lw + LRA + LRB)) * sizeof(u32);
+  auto kern = k_col_inv_crt3<LRA, LRB>;
+  ensure_lds_attr((const void*)kern, lds);
+  return launch("col_inv", kern, dim3((unsigned)(C >> lw), 1, 1), col_threads(LRA + LRB, lw), lds, s, jobs, P.logC,
+                lw, crt_consts(), X);
+}
+
+hipError_t launch_col_inv_crt3(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s) {
+  if (!int3_fused_ok(P)) return hipErrorInvalidValue;
+  switch (P.logRB) {
+    case 2: return inv_crt3_inst<4, 2>(P, jobs, X, s);
+    case 3: return inv_crt3_inst<4, 3>(P, jobs, X, s);
+    case 4: return inv_crt3_inst<4, 4>(P, jobs, X, s);
+    case 5: return inv_crt3_inst<4, 5>(P, jobs, X, s);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_crt_x(const u32* r1, const u32* r2, const u32* r3, long lc, u64* X, hipStream_t s) {
+  return launch("crt", k_crt_x, (unsigned)((lc + 255) / 256), 256, 0, s, r1, r2, r3, lc, crt_consts(), X);
+}
+
+// ---------------------------------------------------------------------------
+// carries
+
+constexpr int kCarryThreads = 256;
+constexpr int kCarryPer = 8;                              // consecutive limbs per thread
+constexpr int kCarryBlock = kCarryThreads * kCarryPer;    // limbs per work-group
+
+// the carry map of a run of limbs: bit c = carry-out for carry-in c
+__device__ __forceinline__ u32 cmap_limb(u32 t) { return (t >> 16) | (((t + 1u) >> 16) << 1); }
+__device__ __forceinline__ u32 cmap_apply(u32 f, u32 c) { return (f >> c) & 1u; }
+__device__ __forceinline__ u32 cmap_compose(u32 g, u32 f) {  // g after f
+  return cmap_apply(g, f & 1u) | (cmap_apply(g, (f >> 1) & 1u) << 1);
+}
+constexpr u32 kCmapIdentity = 2u;
+
+__device__ __forceinline__ u32 digit16(u64 x, int d) { return (u32)(x >> (16 * d)) & 0xFFFFu; }
+
+// Pass 1: t_m = lo(s_m) + hi(s_{m-1}) for the work-group's limbs, and the
+// carry map of its run.
+__global__ void __launch_bounds__(kCarryThreads) k_carry_t(const u64* __restrict__ X, long lc, long nl,
+                                                           u32* __restrict__ tout, u32* __restrict__ bmap) {
+  __shared__ u64 xs[kCarryBlock + 4];  // x_k, k in [m0 - 4, m0 + kCarryBlock)
+  __shared__ u32 ss[kCarryBlock + 1];  // s_m, m in [m0 - 1, m0 + kCarryBlock)
+  __shared__ u32 maps[kCarryThreads];
+  const long m0 = (long)blockIdx.x * kCarryBlock;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kCarryBlock + 4; i += kCarryThreads) {
+    const long k = m0 - 4 + i;
+    xs[i] = (k >= 0 && k < lc) ? gld(X + k) : 0ull;
+  }
+  __syncthreads();
+  for (int i = tid; i < kCarryBlock + 1; i += kCarryThreads) {
+    // s_{m0 - 1 + i} = sum_d digit_d(x_{m0 - 1 + i - d}); x index in xs: i + 3 - d
+    u32 s = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) s += digit16(xs[i + 3 - d], d);
+    ss[i] = s;
+  }
+  __syncthreads();
+  u32* tl = reinterpret_cast<u32*>(xs);  // the x values are no longer needed after this barrier
+  u32 tv[kCarryPer];
+#pragma unroll
+  for (int q = 0; q < kCarryPer; ++q) {
+    const int i = q * kCarryThreads + tid;
+    tv[q] = (ss[i + 1] & 0xFFFFu) + (ss[i] >> 16);
+    if (m0 + i < nl) gst(tout + m0 + i, tv[q]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kCarryPer; ++q) tl[q * kCarryThreads + tid] = tv[q];
+  __syncthreads();
+  u32 F = kCmapIdentity;
+#pragma unroll
+  for (int q = 0; q < kCarryPer; ++q) {
+    const int i = tid * kCarryPer + q;
+    if (m0 + i < nl) F = cmap_compose(cmap_limb(tl[i]), F);
+  }
+  maps[tid] = F;
+  __syncthreads();
+  // in-order reduction: maps[i] = maps[i + off] after maps[i]
+  for (int off = 1; off < kCarryThreads; off <<= 1) {
+    if ((tid & (2 * off - 1)) == 0) maps[tid] = cmap_compose(maps[tid + off], maps[tid]);
+    __syncthreads();
+  }
+  if (tid == 0) bmap[blockIdx.x] = maps[0];
+}
+
+// inclusive in-order scan over the work-group: maps[t] = F_t o ... o F_0
+template <int NT>
+__device__ __forceinline__ void cmap_scan(u32* maps, int tid) {
+  for (int off = 1; off < NT; off <<= 1) {
+    u32 G = maps[tid];
+    if (tid >= off) G = cmap_compose(G, maps[tid - off]);
+    __syncthreads();
+    maps[tid] = G;
+    __syncthreads();
+  }
+}
+
+// Pass 2 (one work-group): the carry into every run.
+__global__ void __launch_bounds__(1024) k_carry_scan(const u32* __restrict__ bmap, int nblk, u32* __restrict__ cin) {
+  __shared__ u32 sc[1024];
+  const int tid = threadIdx.x;
+  const int per = (nblk + 1023) / 1024;
+  const int b0 = tid * per;
+  u32 F = kCmapIdentity;
+  for (int q = 0; q < per; ++q)
+    if (b0 + q < nblk) F = cmap_compose(bmap[b0 + q], F);
+  sc[tid] = F;
+  __syncthreads();
+  cmap_scan<1024>(sc, tid);
+  u32 c = tid > 0 ? cmap_apply(sc[tid - 1], 0) : 0u;
+  for (int q = 0; q < per; ++q) {
+    if (b0 + q < nblk) {
+      cin[b0 + q] = c;
+      c = cmap_apply(bmap[b0 + q], c);
+    }
+  }
+}
+
+// Pass 3: the limbs (t_m + c_m) mod 2^16.
+__global__ void __launch_bounds__(kCarryThreads) k_carry_apply(const u32* __restrict__ tin, long nl,
+                                                               const u32* __restrict__ cin,
+                                                               uint16_t* __restrict__ out) {
+  __shared__ u32 tl[kCarryBlock];
+  __shared__ u32 maps[kCarryThreads];
+  const long m0 = (long)blockIdx.x * kCarryBlock;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kCarryPer; ++q) {
+    const int i = q * kCarryThreads + tid;
+    tl[i] = m0 + i < nl ? gld(tin + m0 + i) : 0u;
+  }
+  __syncthreads();
+  u32 F = kCmapIdentity;
+#pragma unroll
+  for (int q = 0; q < kCarryPer; ++q) F = cmap_compose(cmap_limb(tl[tid * kCarryPer + q]), F);
+  maps[tid] = F;
+  __syncthreads();
+  cmap_scan<kCarryThreads>(maps, tid);
+  u32 c = cin[blockIdx.x];
+  if (tid > 0) c = cmap_apply(maps[tid - 1], c);
+  // limbs into tl in place: each thread rewrites only its own run
+#pragma unroll
+  for (int q = 0; q < kCarryPer; ++q) {
+    const int i = tid * kCarryPer + q;
+    const u32 v = tl[i] + c;
+    tl[i] = v & 0xFFFFu;
+    c = v >> 16;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kCarryPer; ++q) {
+    const int i = q * kCarryThreads + tid;
+    if (m0 + i < nl) gst(out + m0 + i, (uint16_t)tl[i]);
+  }
+}
+
+size_t carry_workspace_bytes(long nl) {
+  const long nblk = (nl + kCarryBlock - 1) / kCarryBlock;
+  return (size_t)nl * 4 + (size_t)nblk * 8 + 256;
+}
+
+hipError_t launch_carry(const u64* X, long lc, long nl, void* ws, uint16_t* out, hipStream_t s) {
+  const long nblk = (nl + kCarryBlock - 1) / kCarryBlock;
+  u32* t = (u32*)ws;
+  u32* bmap = t + nl;
   u32* cin = bmap + nblk;
-  hipError_t e = launch("crt_sums", k_crt_sums, (unsigned)nblk, kCrtThreads, 0, s, r1, r2, r3, lc, nl, K, sums, bmap);
+  hipError_t e = launch("carry_t", k_carry_t, (unsigned)nblk, kCarryThreads, 0, s, X, lc, nl, t, bmap);
   if (e == hipSuccess) e = launch("carry_scan", k_carry_scan, 1, 1024, 0, s, bmap, (int)nblk, cin);
-  if (e == hipSuccess) e = launch("carry_apply", k_carry_apply, (unsigned)nblk, kCrtThreads, 0, s, sums, nl, cin, out);
+  if (e == hipSuccess) e = launch("carry_apply", k_carry_apply, (unsigned)nblk, kCarryThreads, 0, s, t, nl, cin, out);
   return e;
 }
 
@@ -222,8 +422,7 @@ hipError_t launch_widen(const uint16_t* in, long n, u32* out, hipStream_t s) {
 }
 
 // The descriptors of the three products, written to device memory so that
-// each pass of their common four-step plan runs once over the three primes
-// (blockIdx.z selects the prime).
+// each pass of their common four-step plan runs once over the three primes.
 struct JobsOf3 {
   ConvJob j[3];
 };

@@ -321,6 +321,40 @@ def test_int_mul_plans_differ(gpu_lib):
         pm.plan_cache_clear()
 
 
+def test_int_mul_three_prime_column_passes(gpu_lib):
+    """The fused three-prime column passes (first radix 16, 2^2 .. 2^5 second
+    radix, pinned for all three primes so the passes are shared): exact
+    against CPython, including all-0xFFFF operands (the longest carry chains)
+    and lengths that end mid-tile."""
+    pm = gpu_lib
+    rng = np.random.default_rng(29)
+    primes = (469762049, 998244353, 167772161)
+    try:
+        for log_rb, log_c, (na, nb) in ((2, 10, (40000, 25537)), (3, 10, (70001, 60000)), (4, 10, (131072, 100000)),
+                                        (5, 10, (200000, 262144))):
+            lc = na + nb - 1
+            log_l = (lc - 1).bit_length()
+            assert log_l == 4 + log_rb + log_c
+            gran = 1 << (log_l - 4)
+            plan = pm.Plan(2, log_l, 4, log_rb, log_c, (lc + gran - 1) // gran, 3, log_c - 4)
+            pm.plan_cache_clear()
+            for p in primes:
+                pm.plan_cache_put(lc, p, plan)
+            for ff in (False, True):
+                say("case: int fused", plan.as_tuple(), na, nb, "ffff" if ff else "random")
+                if ff:
+                    a = np.full(na, 0xFFFF, dtype=np.uint16)
+                    b = np.full(nb, 0xFFFF, dtype=np.uint16)
+                else:
+                    a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+                    b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+                got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16)))
+                assert pm.stream_check() == 0
+                assert np.array_equal(got, op.int_mul(a, b)), (plan.as_tuple(), ff)
+    finally:
+        pm.plan_cache_clear()
+
+
 def test_int_mul_full_size(gpu_lib):
     """Two random 2^21-limb integers, bit-exact against CPython's multiply."""
     pm = gpu_lib
