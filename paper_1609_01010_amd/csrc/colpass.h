@@ -11,6 +11,19 @@
 
 namespace pm {
 
+// The column tile of an inverse column pass.  Work-groups go to the chip's
+// 8 XCDs in turn (linear work-group index mod 8), each XCD with its own L2,
+// and a tile of 16 columns reads half of each 128-byte line.  With
+// gridDim.x a multiple of 16, work-groups x and x + 8 (one XCD) take tiles
+// 2i and 2i + 1 of the same run of 16, so the two halves of a line are read
+// through one L2.  Measured: 0.2-2.5 us faster for the inverse passes of the
+// 10^6 and integer products; slower (by 2-3 us) for the forward pass of the
+// 2^22-point transform, which keeps the plain order.
+__device__ __forceinline__ long col_tile_paired() {
+  const unsigned x = blockIdx.x, g = gridDim.x;
+  return (g & 15u) ? (long)x : (long)(((x >> 4) << 4) | ((x & 7u) << 1) | ((x >> 3) & 1u));
+}
+
 // radix (log2) of round k (outermost first) of a length-2^LR column transform
 template <int LR, int K>
 constexpr int col_round_lq() {

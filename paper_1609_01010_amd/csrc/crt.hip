@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(512) k_col_inv_crt3(const ConvJob* jobs, int l
   extern __shared__ u32 sm[];  // [R][W]
   const long C = 1l << logC;
   const int W = 1 << lw;
-  const long c0 = (long)blockIdx.x << lw;
+  const long c0 = col_tile_paired() << lw;
   const int nthr = blockDim.x;
   u32 r1[TPT][RA], r2[TPT][RA], r3[TPT][RA];
   inv_tile_prime<LRA, LRB, TPT>(jobs, 0, sm, C, lw, c0, nthr, r1);
