@@ -80,7 +80,8 @@ pm_status pm_poly_mul(const uint32_t* a, size_t len_a, const uint32_t* b, size_t
  *  - pm_init() must have run on the current device first (it finds the
  *    array's address there); otherwise PM_EINVAL.
  *  - The plan is the cached plan of the length (pm_plan_cache_put), else the
- *    default plan; the cost model and the tuner are not consulted.
+ *    default plan (also in place of a cached general-radix plan, kind 3);
+ *    the cost model and the tuner are not consulted.
  *  - Products whose plan needs more than the array (a relaxed transform
  *    length n' above 2^21, i.e. len_a + len_b - 1 > 2^21 for the default
  *    plans) give PM_ETOOLARGE and launch nothing.
@@ -264,7 +265,9 @@ typedef enum { PM_POLICY_DEFAULT = 0, PM_POLICY_EXHAUSTIVE = 1, PM_POLICY_LEARNE
 
 /* Plan description (see pm_plan_for / pm_poly_mul_plan). */
 typedef struct {
-  int32_t kind;  /* 0: defining sum, 1: one work-group in LDS, 2: four-step */
+  int32_t kind;  /* 0: defining sum, 1: one work-group in LDS, 2: four-step,
+                    3: general radix (as pm_poly_mul_mixed: q circular row
+                    products of length 2^log_l; the other fields unused) */
   int32_t log_l; /* transform length L = 2^log_l */
   int32_t log_ra; /* first radix (the truncated one) */
   int32_t log_rb; /* second column radix of the four-step (0: none) */
@@ -272,6 +275,7 @@ typedef struct {
   int32_t ma;     /* kept blocks of the first radix, 1 .. 2^log_ra */
   int32_t lq;     /* log radix of the LDS rounds */
   int32_t lnt;    /* log2 threads per row work-group of the four-step (0: default) */
+  int32_t q;      /* kind 3: the odd factor (3 or 5) */
 } pm_plan;
 
 /* Select the policy used by pm_poly_mul / pm_poly_mul_batch to pick plans. */
@@ -306,11 +310,17 @@ pm_status pm_batch_plans_used(void* stream, pm_plan* out, size_t count);
 pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
                            uint32_t* c, const pm_plan* plan, void* stream);
 
-/* Number of candidate plans for (lc, p) and the i-th one (the tuner's space). */
+/* Number of candidate plans for (lc, p) and the i-th one (the tuner's space):
+ * the power-of-two plans (kinds 0-2), then the general-radix plans (kind 3:
+ * for each supported odd q dividing p - 1, the shortest q 2^k >= lc, where
+ * it is shorter than the power of two).  Kind 3 runs for products alone:
+ * the batch executor, the tuner's PM_CTX_BATCH and the cost model take the
+ * power-of-two plans only. */
 size_t pm_plan_candidates(size_t lc, uint32_t p, pm_plan* out, size_t max_out);
 
 /* Record the plan to use for (lc, p) in the plan cache, for both contexts
- * (used by all policies before they choose). */
+ * (used by all policies before they choose); a general-radix plan (kind 3)
+ * for products alone only. */
 pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan);
 void pm_plan_cache_clear(void);
 
@@ -324,12 +334,14 @@ void pm_plan_cache_clear(void);
  * plan is timed on one product; in PM_CTX_BATCH on about 2^24 / L products
  * of the length at once (at most 4096: enough to fill the device whatever the
  * plan) (each pass one launch over all of them, as the batch
- * executor runs a class), and the time per product is recorded.
+ * executor runs a class), and the time per product is recorded.  Products
+ * alone also time the general-radix plans (kind 3).
  * Synchronous: returns after timing.  pm_tune is pm_tune_ctx(.., PM_CTX_SINGLE). */
 pm_status pm_tune(const size_t* lcs, size_t n, uint32_t p, int reps, void* stream);
 pm_status pm_tune_ctx(const size_t* lcs, size_t n, uint32_t p, int reps, int context, void* stream);
 /* Median running time of one plan for output length lc (synchronous); in
- * PM_CTX_BATCH the time per product of a batch, as the tuner measures it.
+ * PM_CTX_BATCH the time per product of a batch, as the tuner measures it
+ * (kind 3 there: PM_EINVAL).
  * pm_time_plan is pm_time_plan_ctx(.., PM_CTX_SINGLE, ..). */
 pm_status pm_time_plan(size_t lc, uint32_t p, const pm_plan* plan, int reps, double* us);
 pm_status pm_time_plan_ctx(size_t lc, uint32_t p, const pm_plan* plan, int reps, int context, double* us);
@@ -339,8 +351,9 @@ pm_status pm_tune_db_get(size_t i, size_t* lc, uint32_t* p, pm_plan* plan, doubl
 pm_status pm_tune_db_add(size_t lc, uint32_t p, const pm_plan* plan, double us, int context);
 void pm_tune_db_clear(void);
 /* Text file, one row per line: lc p kind log_l log_ra log_rb log_c ma lq lnt us
- * context (a line without the context is a PM_CTX_SINGLE row).  Load appends
- * (tuning resumes from the rows already measured). */
+ * context q (a line without the context is a PM_CTX_SINGLE row; q, the odd
+ * factor, is required for kind 3 only).  Load appends (tuning resumes from
+ * the rows already measured). */
 pm_status pm_tune_db_save(const char* path);
 pm_status pm_tune_db_load(const char* path);
 
@@ -349,7 +362,10 @@ pm_status pm_tune_db_load(const char* path);
  * predicts the log running time per relaxed coefficient of a (length, plan,
  * context); under PM_POLICY_LEARNED the plan with the least predicted time in
  * the caller's context is used (and cached).  Trained on the timing database
- * (both contexts) by the library's own forward, backward and Adam kernels. */
+ * (both contexts) by the library's own forward, backward and Adam kernels.
+ * The model covers the power-of-two plans (kinds 0-2): training skips the
+ * database's kind-3 rows, and features or predictions of kind 3 give
+ * PM_EINVAL. */
 /* Feature vector (17 floats) of a (length, prime, plan, context). */
 pm_status pm_model_features(size_t lc, uint32_t p, const pm_plan* plan, int context, float* out);
 /* Train on the database for `steps` full-batch Adam steps at rate lr from

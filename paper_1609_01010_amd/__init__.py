@@ -24,6 +24,8 @@ PRIMES = (998244353, 2013265921, 469762049, 167772161)
 PM_OK, PM_EINVAL, PM_EUNSUPPORTED, PM_ETOOLARGE, PM_ENOTREDUCED, PM_ENOMEM, PM_EDEVICE = range(7)
 CTX_SINGLE, CTX_BATCH = 0, 1  # tuning contexts: a product alone, one of a batch
 POLICY_DEFAULT, POLICY_EXHAUSTIVE, POLICY_LEARNED = range(3)
+# plan kinds: defining sum, one work-group in LDS, four-step, general radix (q 2^k)
+PLAN_DIRECT, PLAN_LDS, PLAN_FOURSTEP, PLAN_MIXED = range(4)
 
 
 class PolymulError(RuntimeError):
@@ -45,6 +47,7 @@ class Plan(ctypes.Structure):
         ("ma", ctypes.c_int32),
         ("lq", ctypes.c_int32),
         ("lnt", ctypes.c_int32),
+        ("q", ctypes.c_int32),
     ]
 
     def as_tuple(self):
@@ -415,11 +418,14 @@ def plan_for(lc: int, p: int, context: int = 0) -> Plan:
     return P
 
 
-def plan_candidates(lc: int, p: int):
+def plan_candidates(lc: int, p: int, general_radix: bool = True):
+    """The tuner's plans for (lc, p); general_radix=False keeps the
+    power-of-two plans (kinds 0-2), the ones the batch executor and the cost
+    model take."""
     n = lib().pm_plan_candidates(lc, p, None, 0)
     arr = (Plan * max(n, 1))()
     lib().pm_plan_candidates(lc, p, arr, n)
-    return [arr[i] for i in range(n)]
+    return [arr[i] for i in range(n) if general_radix or arr[i].kind != PLAN_MIXED]
 
 
 def plan_cache_put(lc: int, p: int, plan: Plan):

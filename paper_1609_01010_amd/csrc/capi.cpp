@@ -52,6 +52,9 @@ bool plan_valid(const Plan& P, long lc, int pidx) {
   const PrimeInfo& PI = prime_info(pidx);
   if (P.lq != 3 && P.lq != 4) return false;
   if (P.kind == PLAN_DIRECT) return lc >= 1 && lc <= 64;
+  if (P.kind == PLAN_MIXED)
+    return mixed_q_supported(P.q) && (PI.p - 1) % (u32)P.q == 0 && P.logL >= 7 && P.logL <= PI.two_adic &&
+           P.logL <= 24 && lc > 64 && plan_nprime(P) >= lc && P.twist == 0;
   if (P.logL < 1 || P.logL > PI.two_adic || P.logL > 24) return false;
   if (P.logRA < 1 || P.logRA > 5 || P.ma < 1 || P.ma > (1 << P.logRA)) return false;
   if (plan_nprime(P) < lc) return false;
@@ -113,8 +116,11 @@ Plan default_plan(long lc, int pidx) {
 }
 
 // candidate plans for the tuner: every valid (kind, C, RA, RB, lq) with and
-// without truncation
-std::vector<Plan> plan_candidates(long lc, int pidx) {
+// without truncation; with_mixed: also the products through the shortest
+// circular convolution of length q 2^k >= lc of each odd factor q the
+// general-radix product supports (q dividing p - 1), where it is shorter
+// than the power-of-two length
+std::vector<Plan> plan_candidates(long lc, int pidx, bool with_mixed) {
   std::vector<Plan> out;
   if (lc <= 64) {
     Plan P;
@@ -161,6 +167,16 @@ std::vector<Plan> plan_candidates(long lc, int pidx) {
       }
     }
   }
+  if (with_mixed) {
+    for (int q : {3, 5, 7, 15, 17}) {
+      Plan P;
+      P.kind = PLAN_MIXED;
+      P.q = q;
+      P.logL = 0;
+      while (((long)q << P.logL) < lc) ++P.logL;
+      if (((long)q << P.logL) < (1l << logL) && plan_valid(P, lc, pidx)) out.push_back(P);
+    }
+  }
   return out;
 }
 
@@ -205,7 +221,7 @@ Plan choose_plan(long lc, int pidx, DevCtx* c, hipStream_t s, int tctx) {
   return default_plan(lc, pidx);
 }
 
-static pm_plan to_pub(const Plan& P) {
+pm_plan plan_to_pub(const Plan& P) {
   pm_plan q;
   q.kind = P.kind;
   q.log_l = P.logL;
@@ -215,9 +231,10 @@ static pm_plan to_pub(const Plan& P) {
   q.ma = P.ma;
   q.lq = P.lq;
   q.lnt = P.lnt;
+  q.q = P.q;
   return q;
 }
-static Plan from_pub(const pm_plan& q) {
+Plan plan_from_pub(const pm_plan& q) {
   Plan P;
   P.kind = q.kind;
   P.logL = q.log_l;
@@ -227,6 +244,7 @@ static Plan from_pub(const pm_plan& q) {
   P.ma = q.ma;
   P.lq = q.lq;
   P.lnt = q.lnt;
+  P.q = q.kind == PLAN_MIXED ? q.q : 0;
   return P;
 }
 
@@ -249,7 +267,40 @@ static uint2 conv_scale(const Plan& P, int pidx) {
   return h_shoup(h_mulmod(inv, h_powmod(2, 32, PI.p), PI.p), PI.p);
 }
 
+// the plan of the q row products of a general-radix product: the length-M
+// circular product's default plan (n' = M); the q rows run side by side, but
+// a one-work-group plan would still give each row a single compute unit, so
+// from 2^12 on, four-step rows of 2^10
+static Plan mixed_row_plan(long M, int pidx) {
+  Plan P = default_plan(M, pidx);
+  const int logM = ceil_log2(M);
+  if (P.kind == PLAN_LDS && logM >= 12) {
+    Plan F;
+    F.kind = PLAN_FOURSTEP;
+    F.logL = logM;
+    F.logC = 10;
+    F.logRA = logM - 10;
+    F.logRB = 0;
+    F.ma = 1 << F.logRA;
+    F.lq = 3;
+    F.lnt = 6;
+    if (plan_valid(F, M, pidx)) P = F;
+  }
+  return P;
+}
+
+// the general-radix product's workspace: the rows' job descriptors, then A,
+// B, C (q rows of M each), then the four-step workspace of every row
+static size_t mixed_workspace_bytes(int q, long M, int pidx) {
+  const size_t rows_words = (size_t)q * M;
+  const size_t job_bytes = (q * sizeof(ConvJob) + 255) / 256 * 256;
+  const bool fourstep = M > 64 && mixed_row_plan(M, pidx).kind == PLAN_FOURSTEP;
+  return job_bytes + (fourstep ? 5 : 3) * rows_words * sizeof(u32);
+}
+
 size_t plan_workspace_bytes(const Plan& P) {
+  // (the row plans of a general-radix product do not depend on the prime)
+  if (P.kind == PLAN_MIXED) return mixed_workspace_bytes(P.q, 1l << P.logL, 0);
   if (P.kind != PLAN_FOURSTEP) return 0;
   return 2 * (size_t)plan_nprime(P) * sizeof(u32);
 }
@@ -309,9 +360,16 @@ pm_status launch_class(const Plan& P, bool lazy, int in_type, const JobRef& jr, 
   return dev_status(e);
 }
 
+static pm_status run_mixed(DevCtx* ctx, int pidx, int q, long M, const u32* a, long la, const u32* b, long lb, u32* c,
+                           long lc, void* ws, hipStream_t s);
+
 // run one product with plan P; `ws` has plan_workspace_bytes(P) bytes
 pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const void* b, long lb, int in_type, u32* out,
                       long lc, int pidx, void* ws, hipStream_t s) {
+  if (P.kind == PLAN_MIXED) {
+    if (in_type != 0) return PM_EINVAL;
+    return run_mixed(c, pidx, P.q, 1l << P.logL, (const u32*)a, la, (const u32*)b, lb, out, lc, ws, s);
+  }
   if (P.kind == PLAN_DIRECT) {
     if (in_type != 0) return PM_EINVAL;
     return dev_status(launch_direct((const u32*)a, la, (const u32*)b, lb, out, pidx, c->errflag, s));
@@ -356,6 +414,7 @@ static pm_status cyclic_rows(DevCtx* ctx, int pidx, const Plan& P, const u32* A,
 // nega-circular variant
 static pm_status ring_plan(long n, int pidx, DevCtx* ctx, hipStream_t s, int twist, Plan* out) {
   Plan P = choose_plan(n, pidx, ctx, s);
+  if (P.kind == PLAN_MIXED) P = default_plan(n, pidx);  // a plan of the linear product only
   if (twist) {
     P.twist = 1;
     if (P.kind == PLAN_LDS) {  // the twisted one-work-group kernels exist for the first radix 16
@@ -410,6 +469,27 @@ static pm_status ring_product(int ring, const uint32_t* a, size_t len_a, const u
 // into q rows (length-q transform over j mod q), q circular products of
 // length M, and the merge (inverse length-q transform, factor q^-1) into the
 // lc = la + lb - 1 outputs; N >= lc makes the circular product the product.
+// ws: mixed_workspace_bytes(q, M) bytes.
+static pm_status run_mixed(DevCtx* ctx, int pidx, int q, long M, const u32* a, long la, const u32* b, long lb, u32* c,
+                           long lc, void* ws, hipStream_t s) {
+  pm_status st = ensure_prime_tables(ctx, pidx);
+  if (st) return st;
+  const Plan P = mixed_row_plan(M, pidx);
+  const size_t rows_words = (size_t)q * M;
+  const size_t job_bytes = (q * sizeof(ConvJob) + 255) / 256 * 256;
+  const bool fourstep = M > 64 && P.kind == PLAN_FOURSTEP;
+  ConvJob* jobs = (ConvJob*)ws;
+  u32* A = (u32*)((char*)ws + job_bytes);
+  u32* B = A + rows_words;
+  u32* C = B + rows_words;
+  u32* Ta = fourstep ? C + rows_words : nullptr;
+  u32* Tb = fourstep ? Ta + rows_words : nullptr;
+  if (launch_mixed_split(a, la, A, b, lb, B, q, M, pidx, ctx->errflag, s) != hipSuccess) return PM_EDEVICE;
+  st = cyclic_rows(ctx, pidx, P, A, B, C, q, M, jobs, Ta, Tb, s);
+  if (st) return st;
+  return dev_status(launch_mixed_merge(C, q, M, c, lc, pidx, s));
+}
+
 static pm_status mixed_product(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
                                uint32_t q, uint32_t* c, void* stream) {
   if (!a || !b || !c || len_a == 0 || len_b == 0) return PM_EINVAL;
@@ -427,47 +507,10 @@ static pm_status mixed_product(const uint32_t* a, size_t len_a, const uint32_t* 
   if (!ctx) return st;
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipStream_t s = (hipStream_t)stream;
-  st = ensure_prime_tables(ctx, pidx);
-  if (st) return st;
-  Plan P;
-  if (M > 64) {
-    st = ring_plan(M, pidx, ctx, s, 0, &P);
-    if (st) return st;
-    // the q rows run side by side, but a one-work-group plan would still give
-    // each row a single compute unit: from 2^12 on, rows of 2^10 instead
-    if (P.kind == PLAN_LDS && logM >= 12) {
-      Plan F;
-      F.kind = PLAN_FOURSTEP;
-      F.logL = logM;
-      F.logC = 10;
-      F.logRA = logM - 10;
-      F.logRB = 0;
-      F.ma = 1 << F.logRA;
-      F.lq = 3;
-      F.lnt = 6;
-      if (plan_valid(F, M, pidx)) P = F;
-    }
-  }
-  // workspace: the rows' job descriptors, then A, B, C (q rows of M each),
-  // then the four-step workspace of every row
-  const size_t rows_words = (size_t)q * M;
-  const size_t job_bytes = (q * sizeof(ConvJob) + 255) / 256 * 256;
-  const bool fourstep = M > 64 && P.kind == PLAN_FOURSTEP;
-  const size_t wsb = job_bytes + (fourstep ? 5 : 3) * rows_words * sizeof(u32);
   void* ws = nullptr;
-  st = stream_workspace(ctx, s, wsb, &ws);
+  st = stream_workspace(ctx, s, mixed_workspace_bytes((int)q, M, pidx), &ws);
   if (st) return st;
-  ConvJob* jobs = (ConvJob*)ws;
-  u32* A = (u32*)((char*)ws + job_bytes);
-  u32* B = A + rows_words;
-  u32* C = B + rows_words;
-  u32* Ta = fourstep ? C + rows_words : nullptr;
-  u32* Tb = fourstep ? Ta + rows_words : nullptr;
-  if (launch_mixed_split(a, (long)len_a, A, b, (long)len_b, B, (int)q, M, pidx, ctx->errflag, s) != hipSuccess)
-    return PM_EDEVICE;
-  st = cyclic_rows(ctx, pidx, P, A, B, C, (int)q, M, jobs, Ta, Tb, s);
-  if (st) return st;
-  return dev_status(launch_mixed_merge(C, (int)q, M, c, lc, pidx, s));
+  return run_mixed(ctx, pidx, (int)q, M, a, (long)len_a, b, (long)len_b, c, lc, ws, s);
 }
 
 // Workspace a product of output length lc may need, on the host alone: under
@@ -481,7 +524,7 @@ size_t product_workspace_bound(long lc, int pidx) {
     return plan_workspace_bytes(P);
   }
   size_t w = plan_workspace_bytes(default_plan(lc, pidx));
-  for (const Plan& Q : plan_candidates(lc, pidx)) w = std::max(w, plan_workspace_bytes(Q));
+  for (const Plan& Q : plan_candidates(lc, pidx, true)) w = std::max(w, plan_workspace_bytes(Q));
   return w;
 }
 
@@ -585,7 +628,7 @@ pm_status pm_poly_mul_noalloc(const uint32_t* a, size_t len_a, const uint32_t* b
   // the cached plan of the length, else the default one: neither the cost
   // model nor the tuner is consulted
   Plan P;
-  if (!plan_cache_get(lc, p, &P, kCtxSingle)) P = default_plan(lc, pidx);
+  if (!plan_cache_get(lc, p, &P, kCtxSingle) || P.kind == PLAN_MIXED) P = default_plan(lc, pidx);
   if (!plan_valid(P, lc, pidx)) return PM_ETOOLARGE;
   hipStream_t s = (hipStream_t)stream;
   if (P.kind == PLAN_DIRECT) return dev_status(launch_direct(a, (long)len_a, b, (long)len_b, c, pidx, ctx->errflag, s));
@@ -696,7 +739,7 @@ pm_status pm_poly_mul_mixed(const uint32_t* a, size_t len_a, const uint32_t* b, 
 pm_status pm_poly_mul_plan(const uint32_t* a, size_t len_a, const uint32_t* b, size_t len_b, uint32_t p,
                            uint32_t* c, const pm_plan* plan, void* stream) {
   if (!plan) return PM_EINVAL;
-  Plan P = from_pub(*plan);
+  Plan P = plan_from_pub(*plan);
   return product_with(a, len_a, b, len_b, p, c, &P, stream);
 }
 
@@ -715,15 +758,15 @@ pm_status pm_plan_for_ctx(size_t lc, uint32_t p, int context, pm_plan* plan) {
   if (pidx < 0) return PM_EUNSUPPORTED;
   const int logL = ceil_log2((long)lc);
   if (lc > 64 && (logL > prime_info(pidx).two_adic || logL > 24)) return PM_ETOOLARGE;
-  *plan = to_pub(choose_plan((long)lc, pidx, nullptr, 0, context));
+  *plan = plan_to_pub(choose_plan((long)lc, pidx, nullptr, 0, context));
   return PM_OK;
 }
 
 size_t pm_plan_candidates(size_t lc, uint32_t p, pm_plan* out, size_t max_out) {
   const int pidx = prime_index(p);
   if (pidx < 0 || lc == 0) return 0;
-  std::vector<Plan> v = plan_candidates((long)lc, pidx);
-  for (size_t i = 0; i < v.size() && i < max_out && out; ++i) out[i] = to_pub(v[i]);
+  std::vector<Plan> v = plan_candidates((long)lc, pidx, true);
+  for (size_t i = 0; i < v.size() && i < max_out && out; ++i) out[i] = plan_to_pub(v[i]);
   return v.size();
 }
 
@@ -731,11 +774,11 @@ pm_status pm_plan_cache_put(size_t lc, uint32_t p, const pm_plan* plan) {
   const int pidx = prime_index(p);
   if (pidx < 0) return PM_EUNSUPPORTED;
   if (!plan || lc == 0) return PM_EINVAL;
-  Plan P = from_pub(*plan);
+  Plan P = plan_from_pub(*plan);
   if (!plan_valid(P, (long)lc, pidx)) return PM_EINVAL;
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plan_cache[std::make_tuple((long)lc, p, kCtxSingle)] = P;  // for products alone and in batches
-  g_plan_cache[std::make_tuple((long)lc, p, kCtxBatch)] = P;
+  if (P.kind != PLAN_MIXED) g_plan_cache[std::make_tuple((long)lc, p, kCtxBatch)] = P;
   g_plan_pinned.insert(std::make_pair((long)lc, p));
   plan_epoch_bump();
   return PM_OK;

@@ -116,7 +116,7 @@ pm_status get_twist_tables(DevCtx* c, int pidx, int logL, int log_stride, const 
 inline ModP modp_of(const PrimeInfo& P) { return ModP{P.p, 2u * P.p, P.ninv}; }
 
 // ---- plans --------------------------------------------------------------
-enum PlanKind { PLAN_DIRECT = 0, PLAN_LDS = 1, PLAN_FOURSTEP = 2 };
+enum PlanKind { PLAN_DIRECT = 0, PLAN_LDS = 1, PLAN_FOURSTEP = 2, PLAN_MIXED = 3 };
 
 struct Plan {
   int kind = PLAN_DIRECT;
@@ -128,6 +128,7 @@ struct Plan {
   int lq = 4;     // log radix of the LDS rounds
   int lnt = 0;    // log2 threads of the row pass (0: the default for logC)
   int twist = 0;  // nega-circular product: the passes twist the operands and untwist the result
+  int q = 0;      // PLAN_MIXED: the odd factor of the length-q 2^logL circular convolution
 };
 
 // Timing contexts of the tuner and the cost model: a product on its own
@@ -143,6 +144,12 @@ bool plan_cache_get(long lc, u32 p, Plan* P, int tctx = kCtxSingle);
 bool plan_pinned(long lc, u32 p);
 // the library's plan without a model or a search
 Plan default_plan(long lc, int pidx);
+// the tuner's plan space for (lc, prime); with_mixed adds the general-radix
+// plans (products on their own only: the batch executor and the cost model
+// do not run them)
+std::vector<Plan> plan_candidates(long lc, int pidx, bool with_mixed = false);
+pm_plan plan_to_pub(const Plan& P);
+Plan plan_from_pub(const pm_plan& q);
 // workspace bytes a product of output length lc may need, found on the host
 size_t product_workspace_bound(long lc, int pidx);
 // the cost model's pick (tune.cpp)
@@ -161,8 +168,10 @@ inline int plan_row_lnt(const Plan& P) {
   return P.logC - 5 < 6 ? 6 : (P.logC - 5 > 9 ? 9 : P.logC - 5);  // 32 elements per thread
 }
 
-// relaxed transform length n' = ma * L / RA
-inline long plan_nprime(const Plan& P) { return (long)P.ma << (P.logL - P.logRA); }
+// relaxed transform length n' = ma * L / RA (q 2^logL for the general radix)
+inline long plan_nprime(const Plan& P) {
+  return P.kind == PLAN_MIXED ? (long)P.q << P.logL : (long)P.ma << (P.logL - P.logRA);
+}
 
 // Fill the job of one product with plan P (capi.cpp).  Ta/Tb: the four-step
 // workspace (n' words each) or null; ring 0 the product (or with lc = L the

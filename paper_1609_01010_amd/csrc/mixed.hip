@@ -32,7 +32,9 @@
 //
 // With r = j2 mod q and m = M mod q, j = j2 + M t has j mod q = (r + m t) mod
 // q, so the length-q sum over t has the wave-uniform root w_q^{m k1} and a
-// per-lane factor w_q^{r k1}, taken from a table in LDS.
+// per-lane factor w_q^{r k1}, taken from a table in LDS.  The length-q sums
+// pair the terms t and q - t (half the products of the plain sum), and q = 15
+// runs as 3 x 5 (prime-factor algorithm).
 #include "internal.h"
 #include "trace.h"
 
@@ -41,23 +43,72 @@ namespace pm {
 constexpr int kMixedMaxQ = 17;
 
 struct MixedRoots {
-  uint2 u[kMixedMaxQ];  // (w_q^{+-m})^e, e < q: the wave-uniform length-q root powers
+  uint2 c[kMixedMaxQ];  // (U^e + U^-e) / 2, e < q, U = w_q^{+-m}: the wave-uniform root
+  uint2 d[kMixedMaxQ];  // (U^e - U^-e) / 2
   uint2 v[kMixedMaxQ];  // s * w_q^{+-e}, e < q: the per-lane factors (times the scale s)
 };
 
-// The length-q transform y_k = sum_t x_t U^{t k} (U = u[1]) of registers,
-// exponents reduced mod Q at compile time; canonical in and out.
+// The length-N transform y_k = sum_t x_t V^{t k} of registers, N odd, with
+// V = U^D of order N (U of order Q).  The inputs t and N - t meet V^{tk} and
+// V^{-tk}, so with their sum s_t and difference d_t,
+//   x_t V^{tk} + x_{N-t} V^{-tk} = s_t (V^{tk} + V^{-tk}) / 2 + d_t (V^{tk} - V^{-tk}) / 2,
+// and the output N - k takes the same products with the d terms negated:
+// (N - 1)^2 / 2 products in place of (N - 1)^2.  Exponents are reduced at
+// compile time; canonical in and out.
+template <int Q, int N, int D>
+__device__ __forceinline__ void dft_pairs(const Arith<false>& A, const u32 (&x)[N], u32 (&y)[N], const MixedRoots& R) {
+  constexpr int H = (N - 1) / 2;
+  u32 sm[H + 1], df[H + 1];
+  u32 y0 = x[0];
+#pragma unroll
+  for (int t = 1; t <= H; ++t) {
+    sm[t] = A.add(x[t], x[N - t]);
+    df[t] = A.subraw(x[t], x[N - t]);  // only multiplied: (0, 2p) is a Shoup input
+    y0 = A.add(y0, sm[t]);
+  }
+  y[0] = y0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    u32 ev = x[0], od = 0;
+#pragma unroll
+    for (int t = 1; t <= H; ++t) {
+      const int e = (D * ((t * k) % N)) % Q;
+      ev = A.add(ev, A.mul(sm[t], R.c[e]));
+      od = A.add(od, A.mul(df[t], R.d[e]));
+    }
+    y[k] = A.add(ev, od);
+    y[N - k] = A.sub(ev, od);
+  }
+}
+
+// The length-q transform y_k = sum_t x_t U^{t k} (U of order q).  q = 15 by
+// the prime-factor algorithm over 3 x 5 (Good-Thomas): the input t sits at
+// (t mod 3, t mod 5), that is t = (10 t1 + 6 t2) mod 15, and the output k at
+// k = (5 k1 + 3 k2) mod 15; then t k = 5 t1 k1 + 3 t2 k2 (mod 15), so the
+// 15-point transform is five 3-point transforms with root U^5 and three
+// 5-point ones with root U^3, no twiddles.
 template <int Q>
 __device__ __forceinline__ void dft_q(const Arith<false>& A, const u32 (&x)[Q], u32 (&y)[Q], const MixedRoots& R) {
+  if constexpr (Q == 15) {
+    u32 z[5][3];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    u32 acc = x[0];
+    for (int t2 = 0; t2 < 5; ++t2) {
+      u32 in[3];
 #pragma unroll
-    for (int t = 1; t < Q; ++t) {
-      const int e = (t * k) % Q;
-      acc = A.add(acc, e == 0 ? x[t] : A.mul(x[t], R.u[e]));
+      for (int t1 = 0; t1 < 3; ++t1) in[t1] = x[(10 * t1 + 6 * t2) % 15];
+      dft_pairs<15, 3, 5>(A, in, z[t2], R);
     }
-    y[k] = acc;
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      u32 in[5], out[5];
+#pragma unroll
+      for (int t2 = 0; t2 < 5; ++t2) in[t2] = z[t2][k1];
+      dft_pairs<15, 5, 3>(A, in, out, R);
+#pragma unroll
+      for (int k2 = 0; k2 < 5; ++k2) y[(5 * k1 + 3 * k2) % 15] = out[k2];
+    }
+  } else {
+    dft_pairs<Q, Q, 1>(A, x, y, R);
   }
 }
 
@@ -174,12 +225,19 @@ static MixedRoots mixed_roots(const PrimeInfo& P, int q, long M, int dir, u32 sc
   u32 w = h_powmod(P.g, (P.p - 1) / (u32)q, P.p);
   if (dir) w = h_inv(w, P.p);
   const u32 wm = h_powmod(w, (u64)(M % q), P.p);
+  const u32 half = (P.p + 1) / 2;  // 2^-1 mod p
+  u32 up[kMixedMaxQ];
   u32 a = 1, b = scale % P.p;
   for (int e = 0; e < q; ++e) {
-    R.u[e] = h_shoup(a, P.p);
+    up[e] = a;
     R.v[e] = h_shoup(b, P.p);
     a = h_mulmod(a, wm, P.p);
     b = h_mulmod(b, w, P.p);
+  }
+  for (int e = 0; e < q; ++e) {
+    const u32 x = up[e], y = up[(q - e) % q];  // U^e, U^-e
+    R.c[e] = h_shoup(h_mulmod((x + y) % P.p, half, P.p), P.p);
+    R.d[e] = h_shoup(h_mulmod((x + P.p - y) % P.p, half, P.p), P.p);
   }
   return R;
 }

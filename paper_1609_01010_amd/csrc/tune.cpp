@@ -20,7 +20,6 @@
 
 namespace pm {
 bool plan_valid(const Plan& P, long lc, int pidx);
-std::vector<Plan> plan_candidates(long lc, int pidx);
 size_t plan_workspace_bytes(const Plan& P);
 pm_status run_product(DevCtx* c, const Plan& P, const void* a, long la, const void* b, long lb, int in_type, u32* out,
                       long lc, int pidx, void* ws, hipStream_t s);
@@ -251,7 +250,8 @@ pm_status tune_one(DevCtx* c, long lc, int pidx, int reps, hipStream_t s, Plan* 
   BatchBufs BB;
   pm_status st = tctx == kCtxBatch ? batch_inputs(lc, p, &BB, s) : tune_inputs(lc, p, &B, s);
   if (st) return st;
-  std::vector<Plan> cands = plan_candidates(lc, pidx);
+  // the general-radix plans for products alone (the batch executor does not run them)
+  std::vector<Plan> cands = plan_candidates(lc, pidx, tctx == kCtxSingle);
   double best = 1e300;
   Plan bestP = default_plan(lc, pidx);
   for (const Plan& P : cands) {
@@ -389,31 +389,6 @@ pm_status learned_batch_plans(const std::vector<long>& lcs, const std::vector<in
   return PM_OK;
 }
 
-static pm_plan to_pub(const Plan& P) {
-  pm_plan q;
-  q.kind = P.kind;
-  q.log_l = P.logL;
-  q.log_ra = P.logRA;
-  q.log_rb = P.logRB;
-  q.log_c = P.logC;
-  q.ma = P.ma;
-  q.lq = P.lq;
-  q.lnt = P.lnt;
-  return q;
-}
-static Plan from_pub(const pm_plan& q) {
-  Plan P;
-  P.kind = q.kind;
-  P.logL = q.log_l;
-  P.logRA = q.log_ra;
-  P.logRB = q.log_rb;
-  P.logC = q.log_c;
-  P.ma = q.ma;
-  P.lq = q.lq;
-  P.lnt = q.lnt;
-  return P;
-}
-
 // SplitMix64 (Steele, Lea, Flood 2014): the initial weights when none are given
 static u64 splitmix64(u64& s) {
   u64 z = (s += 0x9E3779B97F4A7C15ull);
@@ -462,8 +437,8 @@ pm_status pm_time_plan_ctx(size_t lc, uint32_t p, const pm_plan* plan, int reps,
     return PM_EINVAL;
   const int pidx = prime_index(p);
   if (pidx < 0) return PM_EUNSUPPORTED;
-  Plan P = from_pub(*plan);
-  if (!plan_valid(P, (long)lc, pidx)) return PM_EINVAL;
+  Plan P = plan_from_pub(*plan);
+  if (!plan_valid(P, (long)lc, pidx) || (P.kind == PLAN_MIXED && context == PM_CTX_BATCH)) return PM_EINVAL;
   pm_status st;
   DevCtx* c = ctx_current(&st);
   if (!c) return st;
@@ -490,7 +465,7 @@ pm_status pm_tune_db_get(size_t i, size_t* lc, uint32_t* p, pm_plan* plan, doubl
   if (i >= g_db.size()) return PM_EINVAL;
   if (lc) *lc = (size_t)g_db[i].lc;
   if (p) *p = g_db[i].p;
-  if (plan) *plan = to_pub(g_db[i].plan);
+  if (plan) *plan = plan_to_pub(g_db[i].plan);
   if (us) *us = g_db[i].us;
   if (context) *context = g_db[i].tctx;
   return PM_OK;
@@ -499,8 +474,10 @@ pm_status pm_tune_db_get(size_t i, size_t* lc, uint32_t* p, pm_plan* plan, doubl
 pm_status pm_tune_db_add(size_t lc, uint32_t p, const pm_plan* plan, double us, int context) {
   if (!plan || lc == 0 || (context != PM_CTX_SINGLE && context != PM_CTX_BATCH)) return PM_EINVAL;
   if (prime_index(p) < 0) return PM_EUNSUPPORTED;
+  const Plan P = plan_from_pub(*plan);
+  if (P.kind == PLAN_MIXED && context != PM_CTX_SINGLE) return PM_EINVAL;
   std::lock_guard<std::mutex> lk(g_db_mu);
-  g_db.push_back(DbRow{(long)lc, p, from_pub(*plan), us, context});
+  g_db.push_back(DbRow{(long)lc, p, P, us, context});
   return PM_OK;
 }
 
@@ -514,10 +491,10 @@ pm_status pm_tune_db_save(const char* path) {
   FILE* f = fopen(path, "w");
   if (!f) return PM_EINVAL;
   std::lock_guard<std::mutex> lk(g_db_mu);
-  fprintf(f, "# lc p kind log_l log_ra log_rb log_c ma lq lnt us context\n");
+  fprintf(f, "# lc p kind log_l log_ra log_rb log_c ma lq lnt us context q\n");
   for (auto& r : g_db)
-    fprintf(f, "%ld %u %d %d %d %d %d %d %d %d %.4f %d\n", r.lc, r.p, r.plan.kind, r.plan.logL, r.plan.logRA,
-            r.plan.logRB, r.plan.logC, r.plan.ma, r.plan.lq, r.plan.lnt, r.us, r.tctx);
+    fprintf(f, "%ld %u %d %d %d %d %d %d %d %d %.4f %d %d\n", r.lc, r.p, r.plan.kind, r.plan.logL, r.plan.logRA,
+            r.plan.logRB, r.plan.logC, r.plan.ma, r.plan.lq, r.plan.lnt, r.us, r.tctx, r.plan.q);
   fclose(f);
   return PM_OK;
 }
@@ -531,10 +508,12 @@ pm_status pm_tune_db_load(const char* path) {
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
     DbRow r;
-    const int got = sscanf(line, "%ld %u %d %d %d %d %d %d %d %d %lf %d", &r.lc, &r.p, &r.plan.kind, &r.plan.logL,
+    // 11 fields: a single-context row; 13: the odd factor of a general-radix plan last
+    const int got = sscanf(line, "%ld %u %d %d %d %d %d %d %d %d %lf %d %d", &r.lc, &r.p, &r.plan.kind, &r.plan.logL,
                            &r.plan.logRA, &r.plan.logRB, &r.plan.logC, &r.plan.ma, &r.plan.lq, &r.plan.lnt, &r.us,
-                           &r.tctx);
-    if (got < 11 || (got == 12 && r.tctx != kCtxSingle && r.tctx != kCtxBatch)) {  // 11 fields: a single-context row
+                           &r.tctx, &r.plan.q);
+    if (got < 11 || (got >= 12 && r.tctx != kCtxSingle && r.tctx != kCtxBatch) ||
+        (r.plan.kind == PLAN_MIXED && (got < 13 || r.tctx != kCtxSingle))) {
       fclose(f);
       return PM_EINVAL;
     }
@@ -555,7 +534,9 @@ pm_status pm_model_features(size_t lc, uint32_t p, const pm_plan* plan, int cont
   if (!plan || !out || lc == 0 || (context != PM_CTX_SINGLE && context != PM_CTX_BATCH)) return PM_EINVAL;
   const int pidx = prime_index(p);
   if (pidx < 0) return PM_EUNSUPPORTED;
-  plan_features((long)lc, pidx, from_pub(*plan), context, out);
+  const Plan P = plan_from_pub(*plan);
+  if (P.kind == PLAN_MIXED) return PM_EINVAL;  // the cost model covers the power-of-two plans
+  plan_features((long)lc, pidx, P, context, out);
   return PM_OK;
 }
 
@@ -564,7 +545,8 @@ pm_status pm_model_train(const float* init, int steps, float lr, float* losses) 
   std::vector<DbRow> rows;
   {
     std::lock_guard<std::mutex> lk(g_db_mu);
-    rows = g_db;
+    for (const DbRow& r : g_db)
+      if (r.plan.kind != PLAN_MIXED) rows.push_back(r);  // the cost model covers the power-of-two plans
   }
   if (rows.empty() || steps < 1) return PM_EINVAL;
   const int B = (int)rows.size();
@@ -631,7 +613,10 @@ pm_status pm_model_predict(size_t lc, uint32_t p, const pm_plan* plans, size_t n
   const int pidx = prime_index(p);
   if (pidx < 0) return PM_EUNSUPPORTED;
   std::vector<Plan> v(n);
-  for (size_t i = 0; i < n; ++i) v[i] = from_pub(plans[i]);
+  for (size_t i = 0; i < n; ++i) {
+    v[i] = plan_from_pub(plans[i]);
+    if (v[i].kind == PLAN_MIXED) return PM_EINVAL;  // the cost model covers the power-of-two plans
+  }
   std::vector<double> out;
   pm_status st = model_predict((long)lc, pidx, v, context, &out);
   if (st) return st;

@@ -26,6 +26,12 @@ or below 5%, and the gain of the learned policy over the default one
 use p = 2013265921 (transforms up to 2^27 exist for it).
 
     python -m paper_1609_01010_amd.learned_eval --out DIR [--reps 5] [--quick]
+
+With --model PATH, steps 1 and 2 are skipped and the given cost model (for
+instance the shipped data/cost_model.txt) is evaluated.  With --budget S the
+held-out loop stops after about S seconds and keeps what it measured in
+DIR/heldout_partial.json; run the same command again to resume (exit status
+3 while incomplete).
 """
 
 from __future__ import annotations
@@ -53,7 +59,8 @@ def geomean(xs):
     return float(np.exp(np.mean(np.log(xs))))
 
 
-def run(out_dir: str, reps: int = 5, steps: int = 3000, lr: float = 3e-3, quick: bool = False):
+def run(out_dir: str, reps: int = 5, steps: int = 3000, lr: float = 3e-3, quick: bool = False,
+        model: str | None = None, budget: float | None = None):
     import torch
 
     import paper_1609_01010_amd as pm
@@ -69,23 +76,40 @@ def run(out_dir: str, reps: int = 5, steps: int = 3000, lr: float = 3e-3, quick:
     train = inputs.tuning_lengths(n_random=n_train_rnd)
     held = inputs.heldout_lengths(n_random=n_held_rnd, exclude=train)
     t0 = time.time()
-    for ctx, cname in ((pm.CTX_SINGLE, "single"), (pm.CTX_BATCH, "batch")):
-        for q in inputs.PRIME_LIST:
-            for i in range(0, len(train), 32):
-                pm.tune(train[i:i + 32], q, reps=reps, context=ctx)
-            log(f"tuned {len(train)} training lengths mod {q}, {cname} ({time.time() - t0:.0f} s)")
-    pm.plan_cache_clear()
-    pm.tune_db_save(os.path.join(out_dir, "tuning_db.txt"))
-    n_rows = {c: len(pm.tune_db_rows(c)) for c in (pm.CTX_SINGLE, pm.CTX_BATCH)}
-    losses = pm.model_train(inputs.mlp_init(), steps=steps, lr=lr)
-    log(f"trained on {sum(n_rows.values())} rows: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
-    pm.model_save(os.path.join(out_dir, "cost_model.txt"))
+    if model:
+        pm.model_load(model)
+        n_rows = {pm.CTX_SINGLE: None, pm.CTX_BATCH: None}
+        losses = [float("nan")]
+    else:
+        for ctx, cname in ((pm.CTX_SINGLE, "single"), (pm.CTX_BATCH, "batch")):
+            for q in inputs.PRIME_LIST:
+                for i in range(0, len(train), 32):
+                    pm.tune(train[i:i + 32], q, reps=reps, context=ctx)
+                log(f"tuned {len(train)} training lengths mod {q}, {cname} ({time.time() - t0:.0f} s)")
+        pm.plan_cache_clear()
+        pm.tune_db_save(os.path.join(out_dir, "tuning_db.txt"))
+        n_rows = {c: len(pm.tune_db_rows(c)) for c in (pm.CTX_SINGLE, pm.CTX_BATCH)}
+        losses = pm.model_train(inputs.mlp_init(), steps=steps, lr=lr)
+        log(f"trained on {sum(n_rows.values())} rows: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+        pm.model_save(os.path.join(out_dir, "cost_model.txt"))
 
-    recs = {}
+    partial = os.path.join(out_dir, "heldout_partial.json")
+    recs = {"single": [], "batch": []}
+    if model and os.path.exists(partial):
+        with open(partial) as f:
+            recs = json.load(f)
+        log(f"resuming: {len(recs['single'])} + {len(recs['batch'])} held-out records")
     for ctx, cname in ((pm.CTX_SINGLE, "single"), (pm.CTX_BATCH, "batch")):
-        recs[cname] = []
+        done = {r["lc"] for r in recs[cname]}
         for k, lc in enumerate(held):
-            cands = pm.plan_candidates(lc, P)
+            if lc in done:
+                continue
+            if budget is not None and time.time() - t0 > budget:
+                with open(partial, "w") as f:
+                    json.dump(recs, f)
+                log(f"budget spent: {len(recs['single'])} + {len(recs['batch'])} of {2 * len(held)} held-out records")
+                return None
+            cands = pm.plan_candidates(lc, P, general_radix=False)
             pred = pm.model_predict(lc, P, cands, context=ctx)
             ipick = int(np.argmin(pred))
             pick = cands[ipick]
@@ -109,6 +133,9 @@ def run(out_dir: str, reps: int = 5, steps: int = 3000, lr: float = 3e-3, quick:
                 "best": list(cands[best].as_tuple()), "pick": list(pick.as_tuple()),
                 "pred_err_log": float(pred[ipick] - math.log(t_pick)),
             })
+            if budget is not None:
+                with open(partial, "w") as f:
+                    json.dump(recs, f)
             if k % 20 == 0 or k < 2:
                 r = recs[cname][-1]
                 log(f"held-out {cname} {k + 1}/{len(held)} lc={lc}: regret {r['regret']:.3f} "
@@ -200,8 +227,12 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--quick", action="store_true", help="30 + 20 random lengths instead of 300 + 200")
+    ap.add_argument("--model", help="evaluate this cost model (no tuning of the training lengths, no training)")
+    ap.add_argument("--budget", type=float, help="seconds for the held-out loop; resume by running again")
     a = ap.parse_args(argv)
-    run(a.out, reps=a.reps, steps=a.steps, quick=a.quick)
+    if run(a.out, reps=a.reps, steps=a.steps, quick=a.quick, model=a.model, budget=a.budget) is None:
+        return 3
+    return 0
 
 
 if __name__ == "__main__":

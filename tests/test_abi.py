@@ -138,17 +138,24 @@ def test_tuning_database_contexts_round_trip(tmp_path):
 
     pm.tune_db_clear()
     P1 = pm.plan_candidates(70001, 998244353)[0]
-    P2 = pm.plan_candidates(3000, 2013265921)[-1]
+    P2 = pm.plan_candidates(3000, 2013265921, general_radix=False)[-1]
     pm.tune_db_add(70001, 998244353, P1, 12.5, pm.CTX_SINGLE)
     pm.tune_db_add(3000, 2013265921, P2, 3.25, pm.CTX_BATCH)
+    P3 = [P for P in pm.plan_candidates(70001, 998244353) if P.kind == pm.PLAN_MIXED][0]
+    assert P3.q == 7
+    pm.tune_db_add(70001, 998244353, P3, 9.75, pm.CTX_SINGLE)
+    with pytest.raises(pm.PolymulError):
+        pm.tune_db_add(70001, 998244353, P3, 9.75, pm.CTX_BATCH)  # products alone only
     path = str(tmp_path / "db.txt")
     pm.tune_db_save(path)
     pm.tune_db_clear()
     with open(path, "a") as f:
-        f.write("70001 998244353 " + " ".join(str(v) for v in P1.as_tuple()) + " 11.0000\n")
+        # the 11-field line: no context (a single-product row), no odd factor
+        f.write("70001 998244353 " + " ".join(str(v) for v in P1.as_tuple()[:8]) + " 11.0000\n")
     pm.tune_db_load(path)
     single, batch = pm.tune_db_rows(pm.CTX_SINGLE), pm.tune_db_rows(pm.CTX_BATCH)
     assert [(r[0], r[1], r[2].as_tuple(), r[3]) for r in single] == [(70001, 998244353, P1.as_tuple(), 12.5),
+                                                                     (70001, 998244353, P3.as_tuple(), 9.75),
                                                                      (70001, 998244353, P1.as_tuple(), 11.0)]
     assert [(r[0], r[1], r[2].as_tuple(), r[3]) for r in batch] == [(3000, 2013265921, P2.as_tuple(), 3.25)]
     with pytest.raises(pm.PolymulError):
@@ -179,15 +186,26 @@ def test_plan_space_on_host():
         for p in pm.PRIMES:
             cands = pm.plan_candidates(lc, p)
             assert cands, (lc, p)
+            pow2 = 1 << max(lc - 1, 1).bit_length()
             for P in cands:
                 if P.kind == 0:
                     assert lc <= 64
+                    continue
+                if P.kind == 3:  # the shortest q 2^k >= lc, shorter than the power of two
+                    assert (p - 1) % P.q == 0 and P.q in (3, 5, 7, 15, 17)
+                    assert (P.q << (P.log_l - 1)) < lc <= (P.q << P.log_l) < pow2
                     continue
                 nprime = P.ma << (P.log_l - P.log_ra)
                 assert nprime >= lc
                 assert 1 <= P.ma <= (1 << P.log_ra)
                 if P.kind == 2:
                     assert P.log_l == P.log_ra + P.log_rb + P.log_c
+    # the general-radix plans, last, for the odd factors of p - 1
+    mixed = [(P.q, P.log_l) for P in pm.plan_candidates(40000, 2013265921) if P.kind == 3]
+    assert mixed == [(3, 14), (5, 13), (15, 12)]  # 49152, 40960, 61440 < 65536
+    assert [P.q for P in pm.plan_candidates(40000, 998244353) if P.kind == 3] == [7]  # 57344 (17: 69632)
+    assert all(P.kind != 3 for P in pm.plan_candidates(40000, 998244353, general_radix=False))
+    assert not [P for P in pm.plan_candidates(1 << 15, 2013265921) if P.kind == 3]
     # truncation: a length just past a power of two is not padded to 2L
     P = pm.plan_for(1000000, 2013265921)
     assert (P.ma << (P.log_l - P.log_ra)) < (1 << 20)

@@ -129,7 +129,7 @@ def test_batch_context_tuning_drives_the_batch(gpu_lib):
     rows = pm.tune_db_rows(pm.CTX_BATCH)
     for lc in lcs:
         mine = [r for r in rows if r[0] == lc]
-        assert len(mine) == len(pm.plan_candidates(lc, p)) and all(r[3] > 0 for r in mine)
+        assert len(mine) == len(pm.plan_candidates(lc, p, general_radix=False)) and all(r[3] > 0 for r in mine)
         best = min(mine, key=lambda r: r[3])[2]
         # per-product time of the best plan, timed again in the batch context
         assert pm.time_plan(lc, p, best, reps=3, context=pm.CTX_BATCH) > 0
@@ -207,7 +207,7 @@ def test_learned_policy_trains_predicts_and_stays_exact(gpu_lib, tmp_path):
     try:
         for lc in (5000, 40000, 150001):
             P = pm.plan_for(lc, p)
-            cands = pm.plan_candidates(lc, p)
+            cands = pm.plan_candidates(lc, p, general_radix=False)
             pred = pm.model_predict(lc, p, cands)
             assert P.as_tuple() == cands[int(np.argmin(pred))].as_tuple()
             la, lb = inputs.split_output_length(lc)
@@ -246,12 +246,13 @@ def test_shipped_model_regret_and_gain_on_heldout_lengths(gpu_lib):
     try:
         for lc in lengths:
             pm.plan_cache_clear()
-            cands = pm.plan_candidates(lc, p)
+            cands = pm.plan_candidates(lc, p, general_radix=False)
             pick = cands[int(np.argmin(pm.model_predict(lc, p, cands)))]
             default = pm.plan_for(lc, p)
             pm.tune_db_clear()
             pm.tune([lc], p, reps=5)
-            rows = [r for r in pm.tune_db_rows() if r[0] == lc and r[1] == p]
+            # the best of the model's space (the power-of-two plans)
+            rows = [r for r in pm.tune_db_rows() if r[0] == lc and r[1] == p and r[2].kind != pm.PLAN_MIXED]
             assert len(rows) == len(cands)
             best = min(rows, key=lambda r: r[3])[2]
             t = {"pick": [], "best": [], "default": []}
