@@ -17,8 +17,10 @@
 // its low 16 bits and its high part h_m <= 3, the value t_m = lo(s_m) +
 // h_{m-1} <= 2^16 + 2 leaves carries of 0 or 1 only: limb m is (t_m + c_m)
 // mod 2^16 and c_{m+1} = (t_m + c_m) >> 16.  A run of limbs maps its
-// carry-in c in {0, 1} to a carry-out; the maps (two bits) compose
-// associatively, so the carries are found by a scan in three passes.
+// carry-in c in {0, 1} to a carry-out; the maps compose associatively, so
+// the carries are a scan, done in two passes over the x_k: the map of every
+// work-group's run, then each work-group takes its carry-in from the maps
+// before it and writes its limbs.
 #include "colpass.h"
 #include "internal.h"
 #include "trace.h"
@@ -261,153 +263,153 @@ hipError_t launch_crt_x(const u32* r1, const u32* r2, const u32* r3, long lc, u6
 // carries
 
 constexpr int kCarryThreads = 256;
-constexpr int kCarryPer = 8;                              // consecutive limbs per thread
+constexpr int kCarryPer = 16;                             // consecutive limbs per thread
 constexpr int kCarryBlock = kCarryThreads * kCarryPer;    // limbs per work-group
 
-// the carry map of a run of limbs: bit c = carry-out for carry-in c
-__device__ __forceinline__ u32 cmap_limb(u32 t) { return (t >> 16) | (((t + 1u) >> 16) << 1); }
-__device__ __forceinline__ u32 cmap_apply(u32 f, u32 c) { return (f >> c) & 1u; }
-__device__ __forceinline__ u32 cmap_compose(u32 g, u32 f) {  // g after f
-  return cmap_apply(g, f & 1u) | (cmap_apply(g, (f >> 1) & 1u) << 1);
-}
+// The carry map of a run of limbs, bit c = carry-out for carry-in c.  With
+// t_m <= 2^16 + 2 every run's map is one of three: kill (0: no carry out),
+// propagate (2: the carry in goes out; the identity) or generate (3: a carry
+// out whatever comes in), so a composition is the last map of the sequence
+// that is not "propagate".
 constexpr u32 kCmapIdentity = 2u;
+__device__ __forceinline__ u32 cmap_limb(u32 t) { return (t >> 16) | (((t + 1u) >> 16) << 1); }
+__device__ __forceinline__ u32 cmap_compose(u32 g, u32 f) { return g == kCmapIdentity ? f : g; }  // g after f
+__device__ __forceinline__ u32 cmap_apply(u32 f, u32 c) { return (f >> c) & 1u; }
 
 __device__ __forceinline__ u32 digit16(u64 x, int d) { return (u32)(x >> (16 * d)) & 0xFFFFu; }
 
-// Pass 1: t_m = lo(s_m) + hi(s_{m-1}) for the work-group's limbs, and the
-// carry map of its run.
-__global__ void __launch_bounds__(kCarryThreads) k_carry_t(const u64* __restrict__ X, long lc, long nl,
-                                                           u32* __restrict__ tout, u32* __restrict__ bmap) {
-  __shared__ u64 xs[kCarryBlock + 4];  // x_k, k in [m0 - 4, m0 + kCarryBlock)
-  __shared__ u32 ss[kCarryBlock + 1];  // s_m, m in [m0 - 1, m0 + kCarryBlock)
-  __shared__ u32 maps[kCarryThreads];
-  const long m0 = (long)blockIdx.x * kCarryBlock;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kCarryBlock + 4; i += kCarryThreads) {
-    const long k = m0 - 4 + i;
-    xs[i] = (k >= 0 && k < lc) ? gld(X + k) : 0ull;
-  }
-  __syncthreads();
-  for (int i = tid; i < kCarryBlock + 1; i += kCarryThreads) {
-    // s_{m0 - 1 + i} = sum_d digit_d(x_{m0 - 1 + i - d}); x index in xs: i + 3 - d
-    u32 s = 0;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) s += digit16(xs[i + 3 - d], d);
-    ss[i] = s;
-  }
-  __syncthreads();
-  u32* tl = reinterpret_cast<u32*>(xs);  // the x values are no longer needed after this barrier
-  u32 tv[kCarryPer];
-#pragma unroll
-  for (int q = 0; q < kCarryPer; ++q) {
-    const int i = q * kCarryThreads + tid;
-    tv[q] = (ss[i + 1] & 0xFFFFu) + (ss[i] >> 16);
-    if (m0 + i < nl) gst(tout + m0 + i, tv[q]);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kCarryPer; ++q) tl[q * kCarryThreads + tid] = tv[q];
-  __syncthreads();
-  u32 F = kCmapIdentity;
-#pragma unroll
-  for (int q = 0; q < kCarryPer; ++q) {
-    const int i = tid * kCarryPer + q;
-    if (m0 + i < nl) F = cmap_compose(cmap_limb(tl[i]), F);
-  }
-  maps[tid] = F;
-  __syncthreads();
-  // in-order reduction: maps[i] = maps[i + off] after maps[i]
-  for (int off = 1; off < kCarryThreads; off <<= 1) {
-    if ((tid & (2 * off - 1)) == 0) maps[tid] = cmap_compose(maps[tid + off], maps[tid]);
-    __syncthreads();
-  }
-  if (tid == 0) bmap[blockIdx.x] = maps[0];
-}
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 
-// inclusive in-order scan over the work-group: maps[t] = F_t o ... o F_0
-template <int NT>
-__device__ __forceinline__ void cmap_scan(u32* maps, int tid) {
-  for (int off = 1; off < NT; off <<= 1) {
-    u32 G = maps[tid];
-    if (tid >= off) G = cmap_compose(G, maps[tid - off]);
-    __syncthreads();
-    maps[tid] = G;
-    __syncthreads();
-  }
-}
-
-// Pass 2 (one work-group): the carry into every run.
-__global__ void __launch_bounds__(1024) k_carry_scan(const u32* __restrict__ bmap, int nblk, u32* __restrict__ cin) {
-  __shared__ u32 sc[1024];
-  const int tid = threadIdx.x;
-  const int per = (nblk + 1023) / 1024;
-  const int b0 = tid * per;
-  u32 F = kCmapIdentity;
-  for (int q = 0; q < per; ++q)
-    if (b0 + q < nblk) F = cmap_compose(bmap[b0 + q], F);
-  sc[tid] = F;
-  __syncthreads();
-  cmap_scan<1024>(sc, tid);
-  u32 c = tid > 0 ? cmap_apply(sc[tid - 1], 0) : 0u;
-  for (int q = 0; q < per; ++q) {
-    if (b0 + q < nblk) {
-      cin[b0 + q] = c;
-      c = cmap_apply(bmap[b0 + q], c);
+// The thread's limbs m = m1 + i, i < kCarryPer: t_m = lo16(s_m) + hi(s_{m-1})
+// with s_m = sum_{d<4} digit_d(x_{m-d}) < 2^18 (x_k = 0 outside [0, lc)), so
+// that sum_m t_m 2^{16m} = sum_k x_k 2^{16k}.
+__device__ __forceinline__ void carry_front(const u64* __restrict__ X, long lc, long m1, u32 (&t)[kCarryPer]) {
+  u64 x[kCarryPer + 4];  // x_{m1 - 4 + i}
+  if (m1 >= 4 && m1 + kCarryPer <= lc) {
+    // m1 is a multiple of 16 and X 256-byte aligned: 16-byte loads
+    const PM_GMEM u64x2* p = (const PM_GMEM u64x2*)(X + m1 - 4);
+#pragma unroll
+    for (int i = 0; i < (kCarryPer + 4) / 2; ++i) {
+      const u64x2 v = p[i];
+      x[2 * i] = v.x;
+      x[2 * i + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kCarryPer + 4; ++i) {
+      const long k = m1 - 4 + i;
+      x[i] = (k >= 0 && k < lc) ? gld(X + k) : 0ull;
     }
   }
+  u32 sprev = digit16(x[3], 0) + digit16(x[2], 1) + digit16(x[1], 2) + digit16(x[0], 3);  // s_{m1 - 1}
+#pragma unroll
+  for (int i = 0; i < kCarryPer; ++i) {
+    const u32 sv = digit16(x[i + 4], 0) + digit16(x[i + 3], 1) + digit16(x[i + 2], 2) + digit16(x[i + 1], 3);
+    t[i] = (sv & 0xFFFFu) + (sprev >> 16);
+    sprev = sv;
+  }
 }
 
-// Pass 3: the limbs (t_m + c_m) mod 2^16.
-__global__ void __launch_bounds__(kCarryThreads) k_carry_apply(const u32* __restrict__ tin, long nl,
-                                                               const u32* __restrict__ cin,
-                                                               uint16_t* __restrict__ out) {
-  __shared__ u32 tl[kCarryBlock];
-  __shared__ u32 maps[kCarryThreads];
-  const long m0 = (long)blockIdx.x * kCarryBlock;
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < kCarryPer; ++q) {
-    const int i = q * kCarryThreads + tid;
-    tl[i] = m0 + i < nl ? gld(tin + m0 + i) : 0u;
-  }
-  __syncthreads();
+// the map of the thread's run
+__device__ __forceinline__ u32 run_map(const u32 (&t)[kCarryPer]) {
   u32 F = kCmapIdentity;
 #pragma unroll
-  for (int q = 0; q < kCarryPer; ++q) F = cmap_compose(cmap_limb(tl[tid * kCarryPer + q]), F);
-  maps[tid] = F;
+  for (int i = 0; i < kCarryPer; ++i) F = cmap_compose(cmap_limb(t[i]), F);
+  return F;
+}
+
+// The in-order composition of the maps of the lanes below `below` (a lane
+// mask) in the wave: the map of the highest such lane that is not the
+// identity, else the identity.
+__device__ __forceinline__ u32 wave_prefix_map(u32 F, u64 below) {
+  const u64 nz = __ballot(F != kCmapIdentity) & below;
+  const int src = nz ? 63 - __clzll((long long)nz) : 0;
+  const u32 G = __shfl(F, src);
+  return nz ? G : kCmapIdentity;
+}
+
+// Pass 1: the carry map of each work-group's run of kCarryBlock limbs.
+__global__ void __launch_bounds__(kCarryThreads) k_carry_maps(const u64* __restrict__ X, long lc,
+                                                              u32* __restrict__ bmap) {
+  __shared__ u32 wmap[kCarryThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  u32 t[kCarryPer];
+  carry_front(X, lc, (long)blockIdx.x * kCarryBlock + (long)tid * kCarryPer, t);
+  const u32 W = wave_prefix_map(run_map(t), ~0ull);
+  if (lane == 0) wmap[w] = W;
   __syncthreads();
-  cmap_scan<kCarryThreads>(maps, tid);
-  u32 c = cin[blockIdx.x];
-  if (tid > 0) c = cmap_apply(maps[tid - 1], c);
-  // limbs into tl in place: each thread rewrites only its own run
+  if (tid == 0) {
+    u32 B = kCmapIdentity;
 #pragma unroll
-  for (int q = 0; q < kCarryPer; ++q) {
-    const int i = tid * kCarryPer + q;
-    const u32 v = tl[i] + c;
-    tl[i] = v & 0xFFFFu;
-    c = v >> 16;
+    for (int i = 0; i < kCarryThreads / 64; ++i) B = cmap_compose(wmap[i], B);
+    gst(bmap + blockIdx.x, B);
+  }
+}
+
+// Pass 2: the carry into the work-group (the last map before it that is not
+// the identity, applied to carry 0), then the carry into each thread's run,
+// and the limbs (t_m + c_m) mod 2^16.  out16: the output is 16-byte aligned.
+__global__ void __launch_bounds__(kCarryThreads) k_carry_limbs(const u64* __restrict__ X, long lc, long nl,
+                                                               const u32* __restrict__ bmap,
+                                                               uint16_t* __restrict__ out, int out16) {
+  __shared__ int wlast[kCarryThreads / 64];
+  __shared__ u32 wmap[kCarryThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int blk = (int)blockIdx.x;
+  // the highest work-group j < blk whose map is not the identity
+  int last = -1;
+  for (int j = tid; j < blk; j += kCarryThreads)
+    if (gld(bmap + j) != kCmapIdentity) last = j;
+  for (int off = 32; off > 0; off >>= 1) last = max(last, __shfl_xor(last, off));
+  const long m1 = (long)blockIdx.x * kCarryBlock + (long)tid * kCarryPer;
+  u32 t[kCarryPer];
+  carry_front(X, lc, m1, t);
+  const u32 F = run_map(t);
+  const u32 below = wave_prefix_map(F, (1ull << lane) - 1);  // lanes before this one
+  const u32 W = wave_prefix_map(F, ~0ull);                      // the whole wave
+  if (lane == 0) {
+    wlast[w] = last;
+    wmap[w] = W;
   }
   __syncthreads();
+  last = wlast[0];
 #pragma unroll
-  for (int q = 0; q < kCarryPer; ++q) {
-    const int i = q * kCarryThreads + tid;
-    if (m0 + i < nl) gst(out + m0 + i, (uint16_t)tl[i]);
+  for (int i = 1; i < kCarryThreads / 64; ++i) last = max(last, wlast[i]);
+  u32 c = last >= 0 ? cmap_apply(gld(bmap + last), 0) : 0u;
+  for (int i = 0; i < w; ++i) c = cmap_apply(wmap[i], c);
+  c = cmap_apply(below, c);
+  u32 limb[kCarryPer];
+#pragma unroll
+  for (int i = 0; i < kCarryPer; ++i) {
+    const u32 v = t[i] + c;
+    limb[i] = v & 0xFFFFu;
+    c = v >> 16;
+  }
+  if (out16 && m1 + kCarryPer <= nl) {
+    PM_GMEM u32x4* o = (PM_GMEM u32x4*)(out + m1);
+    o[0] = u32x4{limb[0] | limb[1] << 16, limb[2] | limb[3] << 16, limb[4] | limb[5] << 16, limb[6] | limb[7] << 16};
+    o[1] = u32x4{limb[8] | limb[9] << 16, limb[10] | limb[11] << 16, limb[12] | limb[13] << 16,
+                 limb[14] | limb[15] << 16};
+  } else {
+#pragma unroll
+    for (int i = 0; i < kCarryPer; ++i)
+      if (m1 + i < nl) gst(out + m1 + i, (uint16_t)limb[i]);
   }
 }
 
 size_t carry_workspace_bytes(long nl) {
   const long nblk = (nl + kCarryBlock - 1) / kCarryBlock;
-  return (size_t)nl * 4 + (size_t)nblk * 8 + 256;
+  return (size_t)nblk * 4 + 256;
 }
 
 hipError_t launch_carry(const u64* X, long lc, long nl, void* ws, uint16_t* out, hipStream_t s) {
   const long nblk = (nl + kCarryBlock - 1) / kCarryBlock;
-  u32* t = (u32*)ws;
-  u32* bmap = t + nl;
-  u32* cin = bmap + nblk;
-  hipError_t e = launch("carry_t", k_carry_t, (unsigned)nblk, kCarryThreads, 0, s, X, lc, nl, t, bmap);
-  if (e == hipSuccess) e = launch("carry_scan", k_carry_scan, 1, 1024, 0, s, bmap, (int)nblk, cin);
-  if (e == hipSuccess) e = launch("carry_apply", k_carry_apply, (unsigned)nblk, kCarryThreads, 0, s, t, nl, cin, out);
+  u32* bmap = (u32*)ws;
+  const int out16 = ((uintptr_t)out & 15u) == 0;
+  hipError_t e = launch("carry_maps", k_carry_maps, (unsigned)nblk, kCarryThreads, 0, s, X, lc, bmap);
+  if (e == hipSuccess)
+    e = launch("carry_limbs", k_carry_limbs, (unsigned)nblk, kCarryThreads, 0, s, X, lc, nl, bmap, out, out16);
   return e;
 }
 
