@@ -213,6 +213,15 @@ pm_status pm_set_workspace(void* stream, void* ptr, size_t bytes);
  * combined by the Chinese remainder theorem into the exact (< 2^87) sum, and
  * carries are propagated.  c receives exactly na + nb limbs of A*B (the top
  * limb may be 0).  Requires na + nb - 1 <= 2^23.
+ * Plans: for each prime, the plan of the output length na + nb - 1 in the
+ * product-alone context: the cached one (pm_plan_cache_put, or the tuner's
+ * pick after pm_tune), else under PM_POLICY_LEARNED the cost model's pick,
+ * else the default plan.  The call never times candidates itself: under
+ * PM_POLICY_EXHAUSTIVE an untuned length takes the default plan (tune it
+ * for the three primes first).  When the three plans are one four-step plan
+ * of first radix 16, each pass runs once for the three primes and the CRT is
+ * taken inside the inverse pass; otherwise each prime's product runs on its
+ * own and the CRT reads the three residue arrays.
  */
 pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint16_t* c, void* stream);
 

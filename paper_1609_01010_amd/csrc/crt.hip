@@ -18,9 +18,10 @@
 // h_{m-1} <= 2^16 + 2 leaves carries of 0 or 1 only: limb m is (t_m + c_m)
 // mod 2^16 and c_{m+1} = (t_m + c_m) >> 16.  A run of limbs maps its
 // carry-in c in {0, 1} to a carry-out; the maps compose associatively, so
-// the carries are a scan, done in two passes over the x_k: the map of every
-// work-group's run, then each work-group takes its carry-in from the maps
-// before it and writes its limbs.
+// the carries are a scan, done in two passes: the map of every work-group's
+// run (the map of its last limb that does not propagate, so the pass reads
+// little more than one chunk of 64 limbs per run), then each work-group takes
+// its carry-in from the maps before it and writes its limbs.
 #include "colpass.h"
 #include "internal.h"
 #include "trace.h"
@@ -329,22 +330,40 @@ __device__ __forceinline__ u32 wave_prefix_map(u32 F, u64 below) {
   return nz ? G : kCmapIdentity;
 }
 
-// Pass 1: the carry map of each work-group's run of kCarryBlock limbs.
-__global__ void __launch_bounds__(kCarryThreads) k_carry_maps(const u64* __restrict__ X, long lc,
-                                                              u32* __restrict__ bmap) {
-  __shared__ u32 wmap[kCarryThreads / 64];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  u32 t[kCarryPer];
-  carry_front(X, lc, (long)blockIdx.x * kCarryBlock + (long)tid * kCarryPer, t);
-  const u32 W = wave_prefix_map(run_map(t), ~0ull);
-  if (lane == 0) wmap[w] = W;
-  __syncthreads();
-  if (tid == 0) {
-    u32 B = kCmapIdentity;
+// t_m of one limb (as carry_front, for a single m)
+__device__ __forceinline__ u32 carry_t_one(const u64* __restrict__ X, long lc, long m) {
+  u64 x[5];  // x_{m-4+i}
 #pragma unroll
-    for (int i = 0; i < kCarryThreads / 64; ++i) B = cmap_compose(wmap[i], B);
-    gst(bmap + blockIdx.x, B);
+  for (int i = 0; i < 5; ++i) {
+    const long k = m - 4 + i;
+    x[i] = (k >= 0 && k < lc) ? gld(X + k) : 0ull;
   }
+  const u32 sv = digit16(x[4], 0) + digit16(x[3], 1) + digit16(x[2], 2) + digit16(x[1], 3);
+  const u32 sp = digit16(x[3], 0) + digit16(x[2], 1) + digit16(x[1], 2) + digit16(x[0], 3);
+  return (sv & 0xFFFFu) + (sp >> 16);
+}
+
+// Pass 1: the carry map of each work-group's run of kCarryBlock limbs, which
+// is the map of its last limb that does not propagate.  One wave per run
+// looks at 64 limbs at a time from the run's end backwards and stops at the
+// first chunk holding such a limb: for most data the last chunk, at worst
+// the whole run.
+__global__ void __launch_bounds__(64) k_carry_maps(const u64* __restrict__ X, long lc, long nl,
+                                                   u32* __restrict__ bmap) {
+  const int lane = threadIdx.x;
+  const long m0 = (long)blockIdx.x * kCarryBlock;
+  const long mend = min(m0 + (long)kCarryBlock, nl);
+  u32 B = kCmapIdentity;
+  for (long top = mend; top > m0; top -= 64) {
+    const long m = top - 64 + lane;
+    const u32 F = m >= m0 ? cmap_limb(carry_t_one(X, lc, m)) : kCmapIdentity;
+    const u64 nz = __ballot(F != kCmapIdentity);
+    if (nz) {
+      B = __shfl(F, 63 - __clzll((long long)nz));
+      break;
+    }
+  }
+  if (lane == 0) gst(bmap + blockIdx.x, B);
 }
 
 // Pass 2: the carry into the work-group (the last map before it that is not
@@ -407,7 +426,7 @@ hipError_t launch_carry(const u64* X, long lc, long nl, void* ws, uint16_t* out,
   const long nblk = (nl + kCarryBlock - 1) / kCarryBlock;
   u32* bmap = (u32*)ws;
   const int out16 = ((uintptr_t)out & 15u) == 0;
-  hipError_t e = launch("carry_maps", k_carry_maps, (unsigned)nblk, kCarryThreads, 0, s, X, lc, bmap);
+  hipError_t e = launch("carry_maps", k_carry_maps, (unsigned)nblk, 64, 0, s, X, lc, nl, bmap);
   if (e == hipSuccess)
     e = launch("carry_limbs", k_carry_limbs, (unsigned)nblk, kCarryThreads, 0, s, X, lc, nl, bmap, out, out16);
   return e;

@@ -173,6 +173,21 @@ def test_features_carry_the_context():
     assert np.array_equal(f0[:16], f1[:16])
 
 
+def test_general_radix_plans_stay_out_of_the_batch_and_the_model():
+    """Kind-3 plans are for products alone: timing one in the batch context,
+    its features and the model's prediction are refused before any device
+    work."""
+    import paper_1609_01010_amd as pm
+
+    P = [Q for Q in pm.plan_candidates(40000, 2013265921) if Q.kind == pm.PLAN_MIXED][0]
+    for call in (lambda: pm.time_plan(40000, 2013265921, P, reps=1, context=pm.CTX_BATCH),
+                 lambda: pm.model_features(40000, 2013265921, P),
+                 lambda: pm.model_predict(40000, 2013265921, [P])):
+        with pytest.raises(pm.PolymulError) as e:
+            call()
+        assert e.value.status == pm.PM_EINVAL
+
+
 def test_granularity(L):
     assert L.pm_itft_granularity(16) == 1
     assert L.pm_itft_granularity(32) == 1

@@ -511,6 +511,44 @@ def test_mixed_radix_errors(gpu_lib):
     assert pm.stream_check() == 0
 
 
+def test_general_radix_plan_pinned(gpu_lib):
+    """A pinned general-radix plan (kind 3: the product through length
+    5 * 2^13 = 40960 for 40000 outputs) drives products alone, while a batch
+    and the allocation-free entry point, which run power-of-two plans only,
+    take their own plans; every result against the schoolbook oracle."""
+    import torch
+
+    pm = gpu_lib
+    p = 2013265921
+    la, lb = 25001, 15000
+    lc = la + lb - 1
+    P = [Q for Q in pm.plan_candidates(lc, p) if Q.kind == pm.PLAN_MIXED and Q.q == 5][0]
+    assert P.log_l == 13
+    a, b = inputs.poly_pair((170, lc), la, lb, p)
+    want = op.poly_mul(a, b, p)
+    pm.plan_cache_clear()
+    try:
+        pm.plan_cache_put(lc, p, P)
+        assert pm.plan_for(lc, p).as_tuple() == P.as_tuple()
+        assert pm.plan_for(lc, p, context=pm.CTX_BATCH).kind != pm.PLAN_MIXED
+        say("case: pinned general radix alone", P)
+        assert np.array_equal(_product(pm, a, b, p), want)
+        say("case: pinned general radix in a batch")
+        outs = pm.poly_mul_batch([(dev(a), dev(b), p), (dev(b), dev(a), p)])
+        assert pm.stream_check() == 0
+        assert all(u.kind != pm.PLAN_MIXED for u in pm.batch_plans_used(2))
+        for o in outs:
+            assert np.array_equal(host(o), want)
+        say("case: pinned general radix, allocation-free entry point")
+        pm.init()
+        out = torch.empty(lc, dtype=torch.uint32, device="cuda")
+        pm.poly_mul_noalloc(dev(a), dev(b), p, out)
+        assert pm.stream_check() == 0
+        assert np.array_equal(host(out), want)
+    finally:
+        pm.plan_cache_clear()
+
+
 def _eval2(c, p, x, y):
     """c(x, y) mod p for a 2-D coefficient array, vectorised with exact int64 steps."""
     c = np.asarray(c, dtype=np.int64)
