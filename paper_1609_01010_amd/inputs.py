@@ -118,9 +118,12 @@ def batch_uneven(count: int = 4096, lo: int = 64, hi: int = 65536, tag=4):
     return items
 
 
-def tuning_lengths(tag=5, n_random: int = 300, lo_log: int = 10, hi_log: int = 20):
+def tuning_lengths(tag=5, n_random: int = 300, lo_log: int = 10, hi_log: int = 20, n_large: int = 60,
+                   large_hi_log: int = 23):
     """Output lengths the tuner measures: every power of two 2^lo..2^hi, plus
-    n_random non-power-of-two lengths log-uniform in [2^lo, 2^hi]."""
+    n_random non-power-of-two lengths log-uniform in [2^lo, 2^hi], plus
+    n_large non-power-of-two lengths log-uniform in [2^hi, 2^large_hi] (no
+    powers of two there: 2^21.. stay held out)."""
     rng = rng_for(tag)
     pow2 = [1 << k for k in range(lo_log, hi_log + 1)]
     rnd = log_uniform_len(rng, 1 << lo_log, 1 << hi_log, n_random * 2)
@@ -133,6 +136,16 @@ def tuning_lengths(tag=5, n_random: int = 300, lo_log: int = 10, hi_log: int = 2
             out.append(x)
         if len(out) >= len(pow2) + n_random:
             break
+    want = len(out) + n_large
+    big = rng_for((tag, 1))
+    while len(out) < want:
+        for x in log_uniform_len(big, 1 << hi_log, 1 << large_hi_log, 64):
+            x = int(x)
+            if x & (x - 1) and x not in seen:
+                seen.add(x)
+                out.append(x)
+                if len(out) >= want:
+                    break
     return out
 
 

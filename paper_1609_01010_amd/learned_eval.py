@@ -1,8 +1,9 @@
 """Learned plan selection, end to end on one GPU.
 
 1. The tuner times every candidate plan of each training length (every power
-   of two 2^10..2^20 plus 300 non-power-of-two lengths log-uniform in
-   [2^10, 2^20]), for each of the four primes, in both timing contexts: a
+   of two 2^10..2^20, 300 non-power-of-two lengths log-uniform in
+   [2^10, 2^20] and 60 in [2^20, 2^23]), for each of the four primes, in
+   both timing contexts: a
    product on its own, and the time per product of a batch of about 2^24 / L
    products of the length (enough to keep the device full).
 2. The cost model is trained on all those rows by the library's own kernels;
@@ -73,7 +74,7 @@ def run(out_dir: str, reps: int = 5, steps: int = 3000, lr: float = 3e-3, quick:
     pm.plan_cache_clear()
     pm.set_policy(pm.POLICY_DEFAULT)
     n_train_rnd, n_held_rnd = (30, 20) if quick else (300, 200)
-    train = inputs.tuning_lengths(n_random=n_train_rnd)
+    train = inputs.tuning_lengths(n_random=n_train_rnd, n_large=6 if quick else 60)
     held = inputs.heldout_lengths(n_random=n_held_rnd, exclude=train)
     t0 = time.time()
     if model:

@@ -224,8 +224,9 @@ def _geomean(xs):
 
 
 def test_shipped_model_regret_and_gain_on_heldout_lengths(gpu_lib):
-    """The shipped cost model (trained on the autotuner's timings of output
-    lengths 2^10..2^20) on 16 held-out lengths: 2^21, 2^22 and 14
+    """The shipped cost model (trained on the autotuner's timings of the
+    powers of two 2^10..2^20 and of non-powers of two up to 2^23, none of
+    them held out) on 16 held-out lengths: 2^21, 2^22 and 14
     non-powers of two log-uniform in [2^10, 2^24], mod 2013265921, products
     on their own.  Per length every candidate plan is timed (the exhaustive
     search); the model's pick, that best plan and the default plan (the
