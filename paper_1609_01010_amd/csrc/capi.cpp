@@ -78,11 +78,16 @@ static int kept_blocks(long lc, int logL, int logRA) {
 }
 
 Plan default_plan(long lc, int pidx) {
-  // measured on MI355X: row length C = L / 256 (at least 2^10, at most 2^13,
-  // and at least L / 1024 so that the columns have at most 32 x 32 points),
-  // columns split 16 x R/16, 16 elements per row thread, LDS rounds of radix
-  // 8 in the rows; truncation with the finest first radix (32) when the
-  // output length is not a power of two
+  // measured on MI355X (the tuner's fastest plans for products alone and in
+  // batches): up to L = 2^11 one work-group with the first radix 8; for
+  // L = 2^12 .. 2^14 the four-step with rows of 2^10 (128 threads) and a
+  // single column radix, which spreads a product over L / 2^10 work-groups
+  // where one work-group would leave it on a single compute unit; beyond,
+  // row length C = L / 256 (at least 2^10, at most 2^13, and at least
+  // L / 1024 so that the columns have at most 32 x 32 points), columns split
+  // 16 x R/16, 16 elements per row thread, LDS rounds of radix 8 in the
+  // rows; truncation with the finest first radix (32) when the output length
+  // is not a power of two
   Plan P;
   if (lc <= 64) {
     P.kind = PLAN_DIRECT;
@@ -91,9 +96,16 @@ Plan default_plan(long lc, int pidx) {
   P.logL = ceil_log2(lc);
   const bool pow2 = (lc & (lc - 1)) == 0;
   (void)pidx;
-  if (P.logL <= 14) {
+  if (P.logL <= 11) {
     P.kind = PLAN_LDS;
-    P.logRA = P.logL < 4 ? P.logL : 4;
+    P.logRA = 3;
+  } else if (P.logL <= 14) {
+    P.kind = PLAN_FOURSTEP;
+    P.logC = 10;
+    P.logRA = P.logL - 10;
+    P.logRB = 0;
+    P.lnt = 7;
+    P.lq = 3;
   } else {
     P.kind = PLAN_FOURSTEP;
     P.logC = P.logL - 8 < 10 ? 10 : (P.logL - 8 > 13 ? 13 : P.logL - 8);
@@ -268,26 +280,9 @@ static uint2 conv_scale(const Plan& P, int pidx) {
 }
 
 // the plan of the q row products of a general-radix product: the length-M
-// circular product's default plan (n' = M); the q rows run side by side, but
-// a one-work-group plan would still give each row a single compute unit, so
-// from 2^12 on, four-step rows of 2^10
-static Plan mixed_row_plan(long M, int pidx) {
-  Plan P = default_plan(M, pidx);
-  const int logM = ceil_log2(M);
-  if (P.kind == PLAN_LDS && logM >= 12) {
-    Plan F;
-    F.kind = PLAN_FOURSTEP;
-    F.logL = logM;
-    F.logC = 10;
-    F.logRA = logM - 10;
-    F.logRB = 0;
-    F.ma = 1 << F.logRA;
-    F.lq = 3;
-    F.lnt = 6;
-    if (plan_valid(F, M, pidx)) P = F;
-  }
-  return P;
-}
+// circular product's default plan (n' = M; from 2^12 on the four-step, so
+// that each row spreads over several compute units)
+static Plan mixed_row_plan(long M, int pidx) { return default_plan(M, pidx); }
 
 // the general-radix product's workspace: the rows' job descriptors, then A,
 // B, C (q rows of M each), then the four-step workspace of every row

@@ -53,13 +53,18 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   bool bad = false;
 
-  // operands one after the other: the twiddles of a column are read again
-  // (from cache) rather than held in registers across both
-  for (int op = 0; op < 2; ++op) {
-    const u32* in = op ? b : a;
-    const int len = op ? lb : la;
-    u32* out = op ? sb : sa;
-    for (int j = tid; j < S; j += nthr) {
+  // The columns of both operands: side by side when there are threads for
+  // all 2S of them (a product on its own, bound by latency), else one
+  // operand after the other (the twiddles of a column are then read again,
+  // from cache, rather than held in registers across both).
+  const bool side = nthr >= 2 * S;
+  for (int pass = 0; pass < (side ? 1 : 2); ++pass) {
+    for (int w = tid; w < (side ? 2 * S : S); w += nthr) {
+      const int op = side ? w / S : pass;
+      const int j = side ? w % S : w;
+      const u32* in = op ? b : a;
+      const int len = op ? lb : la;
+      u32* out = op ? sb : sa;
       const uint2* tw = T.rf[LRA - 1] + N + j * RA;
       u32 x[RA];
 #pragma unroll
