@@ -219,9 +219,11 @@ pm_status pm_set_workspace(void* stream, void* ptr, size_t bytes);
  * else the default plan.  The call never times candidates itself: under
  * PM_POLICY_EXHAUSTIVE an untuned length takes the default plan (tune it
  * for the three primes first).  When the three plans are one four-step plan
- * of first radix 16, each pass runs once for the three primes and the CRT is
- * taken inside the inverse pass; otherwise each prime's product runs on its
- * own and the CRT reads the three residue arrays.
+ * of first radix 16, or 32 with at least 29 of its blocks kept, each pass
+ * runs once for the three primes and the CRT is taken inside the inverse
+ * pass (a plan of first radix 32 with fewer kept blocks runs as its twin of
+ * first radix 16 for this); otherwise each prime's product runs on its own
+ * and the CRT reads the three residue arrays.
  */
 pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint16_t* c, void* stream);
 

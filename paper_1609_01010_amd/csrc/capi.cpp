@@ -1026,12 +1026,30 @@ static void int_layout_sizes(size_t na, size_t nb, IntLayout* L) {
 
 // the plans the policy picks (plan choice may consult the cost model, so
 // this runs at call time)
+// The fused passes take the first radix 16, or 32 with at least 29 blocks
+// kept; a plan of first radix 32 with fewer kept blocks runs as its twin of
+// first radix 16 (the second column radix doubled, or the rows doubled when
+// it is 32 already), so that the three primes still share their passes.
+static Plan int3_twin(const Plan& P, long lc, int pidx) {
+  if (P.kind != PLAN_FOURSTEP || P.logRA != 5 || int3_fused_ok(P)) return P;
+  Plan T = P;
+  T.logRA = 4;
+  T.logRB = P.logRB + 1;
+  if (T.logRB > 5) {
+    T.logRB = 5;
+    T.logC = P.logC + 1;
+    T.lnt = std::min(10, plan_row_lnt(P) + 1);
+  }
+  T.ma = kept_blocks(lc, T.logL, 4);
+  return plan_valid(T, lc, pidx) && int3_fused_ok(T) ? T : P;
+}
+
 static pm_status int_mul_layout(size_t na, size_t nb, IntLayout* L) {
   const long lc = (long)(na + nb - 1);
   if (ceil_log2(lc) > 23) return PM_ETOOLARGE;
   for (int i = 0; i < 3; ++i) {
     const int pidx = prime_index(kIntPrimes[i]);
-    L->plans[i] = choose_plan(lc, pidx);
+    L->plans[i] = int3_twin(choose_plan(lc, pidx), lc, pidx);
     if (!plan_valid(L->plans[i], lc, pidx)) return PM_ETOOLARGE;
     if (L->plans[i].kind != PLAN_FOURSTEP) L->widen = true;
     L->pw = std::max(L->pw, plan_workspace_bytes(L->plans[i]));

@@ -200,10 +200,81 @@ __global__ void __launch_bounds__(512) k_col_inv_crt3(const ConvJob* jobs, int l
   }
 }
 
+// The first radix 32 (at least 29 of its blocks kept): each task of 32
+// values per prime runs on a pair of lanes, 16 values each (inv32_pair), so
+// a thread again keeps 48 residues; work-groups of 2 W RB <= 512 threads.
+template <int LRB>
+__device__ __forceinline__ void inv_tile_prime32(const ConvJob* jobs, int pr, u32* sm, long C, int lw, long c0,
+                                                 int nthr, u32 (&res)[16]) {
+  constexpr int RA = 32, RB = 1 << LRB, R = RA * RB;
+  int tid = threadIdx.x;  // through an empty asm per prime: no addresses hoisted across primes
+  asm volatile("" : "+v"(tid));
+  const ConvJob J = job_at(jobs, pr);
+  const Arith<true> A(J.mp);
+  const PrimeTables T = fresh(J.T);
+  const int ma = J.ma;
+  const int W = 1 << lw;
+  col_dit_rounds<LRB, col_last_round<LRB>(), 0, true>(A, sm, lw, ma << LRB, T, tid, nthr, J.Ta, C, c0);
+  const int task = tid >> 1, half = tid & 1;
+  const int cc = task & (W - 1);
+  const int j1b = task >> lw;
+  const uint2* tw = T.ri[4] + R + j1b * RA + 16 * half;
+  u32 x[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int ta = 16 * half + i;
+    u32 v = 0;
+    if (ta < ma) {
+      v = sm[((ta * RB + j1b) << lw) + cc];
+      if (ta > 0) v = A.mul(v, cld(tw + i));
+    }
+    x[i] = v;
+  }
+  switch (ma) {
+    case 29: inv32_pair<29, true>(A, x, half, T); break;
+    case 30: inv32_pair<30, true>(A, x, half, T); break;
+    case 31: inv32_pair<31, true>(A, x, half, T); break;
+    default: inv32_pair<32, true>(A, x, half, T); break;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) res[i] = A.canon(x[i]);
+  __syncthreads();  // the next prime reuses the tile
+}
+
+template <int LRB>
+__global__ void __launch_bounds__(512) k_col_inv_crt3_32(const ConvJob* jobs, int logC, int lw, CrtConsts K,
+                                                         u64* __restrict__ X) {
+  constexpr int RB = 1 << LRB;
+  extern __shared__ u32 sm[];  // [R][W]
+  const long C = 1l << logC;
+  const int W = 1 << lw;
+  const long c0 = col_tile_paired() << lw;
+  const int nthr = blockDim.x;
+  u32 r1[16], r2[16], r3[16];
+  inv_tile_prime32<LRB>(jobs, 0, sm, C, lw, c0, nthr, r1);
+  inv_tile_prime32<LRB>(jobs, 1, sm, C, lw, c0, nthr, r2);
+  inv_tile_prime32<LRB>(jobs, 2, sm, C, lw, c0, nthr, r3);
+  const ConvJob J0 = job_at(jobs, 0);
+  const int ma = J0.ma;
+  const long lc = J0.lc;
+  const int tid = threadIdx.x, task = tid >> 1, half = tid & 1;
+  const int cc = task & (W - 1);
+  const int j1b = task >> lw;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = 16 * half + i;
+    const long pos = C * (j1b + RB * e) + c0 + cc;
+    if (e < ma && pos < lc) gst(X + pos, crt_value(K, r1[i], r2[i], r3[i]));
+  }
+}
+
 // the fused passes: four-step plans with the first radix 16 (a thread then
-// owns one inverse task of 16 values per prime) and 2^6 .. 2^9 column rows
+// owns one inverse task of 16 values per prime) and 2^6 .. 2^9 column rows,
+// or the first radix 32 with at least 29 blocks kept (a lane pair per task)
+// and 2^7 .. 2^10 column rows
 bool int3_fused_ok(const Plan& P) {
-  return P.kind == PLAN_FOURSTEP && P.logRA == 4 && P.logRB >= 2 && P.logRB <= 5;
+  if (P.kind != PLAN_FOURSTEP || P.logRB < 2 || P.logRB > 5) return false;
+  return P.logRA == 4 || (P.logRA == 5 && P.ma >= 32 - kFillMax);
 }
 
 template <int LR>
@@ -224,6 +295,7 @@ hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* jobs, hipStream_t s
     case 7: return fwd_int3_lr<7>(P, jobs, s);
     case 8: return fwd_int3_lr<8>(P, jobs, s);
     case 9: return fwd_int3_lr<9>(P, jobs, s);
+    case 10: return fwd_int3_lr<10>(P, jobs, s);
     default: break;
   }
   return hipErrorInvalidValue;
@@ -244,8 +316,31 @@ static hipError_t inv_crt3_inst(const Plan& P, const ConvJob* jobs, u64* X, hipS
                 lw, crt_consts(), X);
 }
 
+template <int LRB>
+static hipError_t inv_crt3_32_inst(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s) {
+  int lw = col_lw(5 + LRB, P.logC, 1);
+  while (lw > 0 && col_threads(5 + LRB, lw) > 512) --lw;
+  const long C = 1l << P.logC;
+  // a lane pair per task: 2 W RB threads, which is W R / 16
+  const int nthr = col_threads(5 + LRB, lw);
+  if (C < (1l << lw) || nthr > 512 || nthr != 2 * ((1 << lw) << LRB)) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)1 << (lw + 5 + LRB)) * sizeof(u32);
+  auto kern = k_col_inv_crt3_32<LRB>;
+  ensure_lds_attr((const void*)kern, lds);
+  return launch("col_inv", kern, dim3((unsigned)(C >> lw), 1, 1), nthr, lds, s, jobs, P.logC, lw, crt_consts(), X);
+}
+
 hipError_t launch_col_inv_crt3(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s) {
   if (!int3_fused_ok(P)) return hipErrorInvalidValue;
+  if (P.logRA == 5) {
+    switch (P.logRB) {
+      case 2: return inv_crt3_32_inst<2>(P, jobs, X, s);
+      case 3: return inv_crt3_32_inst<3>(P, jobs, X, s);
+      case 4: return inv_crt3_32_inst<4>(P, jobs, X, s);
+      case 5: return inv_crt3_32_inst<5>(P, jobs, X, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (P.logRB) {
     case 2: return inv_crt3_inst<4, 2>(P, jobs, X, s);
     case 3: return inv_crt3_inst<4, 3>(P, jobs, X, s);

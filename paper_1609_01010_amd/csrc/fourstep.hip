@@ -315,45 +315,6 @@ __global__ void __launch_bounds__(64) k_col_inv1(JobRef jr, int logC) {
   }
 }
 
-// The inverse of radix 32 with M >= 29 known values (inv_column's contract:
-// M = 32 unscaled, else scale 1), split over the two lanes of a pair: lane
-// `half` holds slots 16 half .. 16 half + 15 (bit-reversed order).  The
-// missing values come from the completion matrix, each lane summing over its
-// own known values and the partial sums exchanged; the first four levels of
-// the network stay within each lane's 16 slots; the last level pairs slot i
-// with slot i + 16 across the two lanes.
-template <int M, bool LAZY>
-__device__ __forceinline__ void inv32_pair(const Arith<LAZY>& A, u32 (&x)[16], int half, const PrimeTables& T) {
-  constexpr int D = 32 - M;
-  if constexpr (D > 0) {
-    const uint2* K = T.kx + fill_offset(5, D);
-#pragma unroll
-    for (int r = 0; r < D; ++r) {
-      u32 acc = 0;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int k = 16 * half + i;
-        if (k < M) acc = A.add(acc, A.mul(x[i], cld(K + r * M + k)));
-      }
-      acc = A.add(acc, (u32)__shfl_xor((int)acc, 1));
-      if (half) x[M - 16 + r] = acc;
-    }
-  }
-  dit_reg<16>(A, x, T.pi);
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    // lane 1 forms t = x[i + 16] w_32^-i; lane 0 keeps a = x[i]
-    const u32 t = half ? A.mul(x[i], cld(T.pi + 32 + i)) : 0u;
-    const u32 recv = (u32)__shfl_xor((int)(half ? t : x[i]), 1);
-    x[i] = half ? A.sub(recv, t) : A.add(x[i], recv);
-  }
-  if constexpr (D > 0) {
-    const uint2 qi = cld(T.iv + 5);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = A.mul(x[i], qi);
-  }
-}
-
 // Inverse column pass: the length-RB inverses of the blocks below mr (the
 // innermost round straight from global memory), then per column and j1b
 // the truncated inverse of radix RA with ma known values, written to the

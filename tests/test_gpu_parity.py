@@ -355,6 +355,42 @@ def test_int_mul_three_prime_column_passes(gpu_lib):
         pm.plan_cache_clear()
 
 
+def test_int_mul_first_radix_32(gpu_lib):
+    """The fused three-prime passes with the first radix 32 (a lane pair per
+    inverse task) for 29 .. 32 kept blocks and second radices 2^2 .. 2^5, and
+    a plan of first radix 32 with 20 kept blocks, which the integer product
+    runs as its radix-16 twin: exact against CPython."""
+    pm = gpu_lib
+    rng = np.random.default_rng(31)
+    primes = (469762049, 998244353, 167772161)
+    cases = ((2, 10, 29, (60000, 57000), True), (3, 10, 30, (130000, 110000), False),
+             (4, 10, 31, (260000, 240000), False), (5, 10, 32, (524288, 500000), True),
+             (5, 11, 20, (700000, 600000), False))
+    try:
+        for log_rb, log_c, ma, (na, nb), ff in cases:
+            lc = na + nb - 1
+            log_l = 5 + log_rb + log_c
+            gran = 1 << (log_l - 5)
+            assert (lc - 1).bit_length() == log_l and (lc + gran - 1) // gran == ma
+            plan = pm.Plan(2, log_l, 5, log_rb, log_c, ma, 3, log_c - 4)
+            pm.plan_cache_clear()
+            for p in primes:
+                pm.plan_cache_put(lc, p, plan)
+            for f in ((False, True) if ff else (False,)):
+                say("case: int fused radix 32", plan.as_tuple(), na, nb, "ffff" if f else "random")
+                if f:
+                    a = np.full(na, 0xFFFF, dtype=np.uint16)
+                    b = np.full(nb, 0xFFFF, dtype=np.uint16)
+                else:
+                    a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+                    b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+                got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16)))
+                assert pm.stream_check() == 0
+                assert np.array_equal(got, op.int_mul(a, b)), (plan.as_tuple(), f)
+    finally:
+        pm.plan_cache_clear()
+
+
 def test_int_mul_full_size(gpu_lib):
     """Two random 2^21-limb integers, bit-exact against CPython's multiply."""
     pm = gpu_lib
