@@ -335,10 +335,11 @@ def batch_bench(pm, torch, dev, args):
     torch.cuda.synchronize()
     if pm.stream_check() != 0:
         raise SystemExit("device reported an error during warm-up")
-    # spot check: 24 products of each buffer set at two random points
+    # spot check: 24 products of each buffer set run so far at two random points
     rng = np.random.default_rng(5)
+    sets_run = sorted({0} | {i % 2 for i in range(args.warmup)})
     for k in rng.choice(len(items), 24, replace=False):
-        for si in range(2):
+        for si in sets_run:
             it = items[int(k)]
             assert check_product(it.a, it.b, sets[si][1][int(k)].cpu().numpy(), it.p, rng), "wrong batch product"
 
@@ -693,6 +694,9 @@ def main():
     ap.add_argument("--plans", default=TUNED_PLANS,
                     help="plans of the two plain large products among the other workloads, "
                          "'kind,log_l,log_ra,log_rb,log_c,ma,lq,lnt;...' (default: the autotuner's picks on MI355X)")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only the two plain large products with --plans (the command their profiles are taken "
+                         "with); prints their timings, not the headline line")
     ap.add_argument("--transform-only", action="store_true",
                     help="only the forward transforms of 2^22 points (the command their counters are taken with); "
                          "prints their timings, not the headline line")
@@ -728,6 +732,9 @@ def main():
     copy_bw = copy_bandwidth(torch, dev)
     if args.transform_only:
         print(json.dumps(standalone_transform(pm, torch, dev, copy_bw)), flush=True)
+        return
+    if args.large_only:
+        print(json.dumps(large_products(pm, torch, dev, args)), flush=True)
         return
 
     if args.headline_only:
