@@ -10,7 +10,7 @@
 
 namespace pm {
 bool int3_fused_ok(const Plan& P);
-hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* jobs, hipStream_t s);
+hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* J, ConvJob* jobs, hipStream_t s);
 hipError_t launch_col_inv_crt3(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s);
 hipError_t launch_crt_x(const u32* r1, const u32* r2, const u32* r3, long lc, u64* X, hipStream_t s);
 hipError_t launch_carry(const u64* X, long lc, long nl, void* ws, uint16_t* out, hipStream_t s);
@@ -1133,8 +1133,7 @@ pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb,
     JobRef jr;
     jr.one = J[0];
     jr.many = djobs;
-    hipError_t e = launch_store_jobs3(J, djobs, s);
-    if (e == hipSuccess) e = launch_col_fwd_int3(P, djobs, s);
+    hipError_t e = launch_col_fwd_int3(P, J, djobs, s);
     if (e == hipSuccess) e = launch_row_conv(P, true, J[0].rows, jr, 3, s);
     if (e == hipSuccess) e = launch_col_inv_crt3(P, djobs, X, s);
     if (e == hipSuccess) e = launch_carry(X, lc, nl, cws, out, s);

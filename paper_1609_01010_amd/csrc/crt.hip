@@ -95,13 +95,26 @@ __device__ __forceinline__ ConvJob job_at(const ConvJob* many, int k) {
   return J;
 }
 
+// The descriptors of the three products, passed by value to the forward
+// column pass, which also writes them to device memory for the row and
+// inverse passes (so that each pass of their common plan runs once over the
+// three primes, with no launch of its own to store them).
+struct JobsOf3 {
+  ConvJob j[3];
+};
+
 // Forward columns of one operand (blockIdx.y) modulo the three primes
-// (jobs[0..2]), one after the other on the same tile of limbs: the first
+// (t.j[0..2]), one after the other on the same tile of limbs: the first
 // prime's round reads the tile from memory, the others find it in the L2
 // cache (each limb is read from HBM once), and the stores of one prime drain
 // while the next one computes.
 template <int LR>
-__global__ void __launch_bounds__(1024) k_col_fwd_int3(const ConvJob* jobs, int logC, int lw) {
+__global__ void __launch_bounds__(1024) k_col_fwd_int3(JobsOf3 t, ConvJob* __restrict__ jobs_out, int logC, int lw) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    jobs_out[0] = t.j[0];
+    jobs_out[1] = t.j[1];
+    jobs_out[2] = t.j[2];
+  }
   extern __shared__ u32 sm[];  // [R][W]
   const int nthr = blockDim.x;
   const long C = 1l << logC;
@@ -114,7 +127,7 @@ __global__ void __launch_bounds__(1024) k_col_fwd_int3(const ConvJob* jobs, int 
     // hold them in registers across it
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const ConvJob J = job_at(jobs, pr);
+    const ConvJob J = t.j[pr];
     const Arith<true> A(J.mp);
     const uint16_t* in = (const uint16_t*)(blockIdx.y ? J.b : J.a);
     const long z = blockIdx.y ? J.lb : J.la;
@@ -278,24 +291,27 @@ bool int3_fused_ok(const Plan& P) {
 }
 
 template <int LR>
-static hipError_t fwd_int3_lr(const Plan& P, const ConvJob* jobs, hipStream_t s) {
+static hipError_t fwd_int3_lr(const Plan& P, const JobsOf3& t, ConvJob* jobs, hipStream_t s) {
   const int lw = col_lw(LR, P.logC, 2);
   const long C = 1l << P.logC;
   if (C < (1l << lw) || col_threads(LR, lw) > 1024) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << (lw + LR)) * sizeof(u32);
   auto kern = k_col_fwd_int3<LR>;
   ensure_lds_attr((const void*)kern, lds);
-  return launch("col_fwd", kern, dim3((unsigned)(C >> lw), 2, 1), col_threads(LR, lw), lds, s, jobs, P.logC, lw);
+  return launch("col_fwd", kern, dim3((unsigned)(C >> lw), 2, 1), col_threads(LR, lw), lds, s, t, jobs, P.logC, lw);
 }
 
-hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* jobs, hipStream_t s) {
+// host: J, the three descriptors; jobs, their device copy the pass writes
+hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* J, ConvJob* jobs, hipStream_t s) {
   if (!int3_fused_ok(P)) return hipErrorInvalidValue;
+  JobsOf3 t;
+  for (int i = 0; i < 3; ++i) t.j[i] = J[i];
   switch (P.logRA + P.logRB) {
-    case 6: return fwd_int3_lr<6>(P, jobs, s);
-    case 7: return fwd_int3_lr<7>(P, jobs, s);
-    case 8: return fwd_int3_lr<8>(P, jobs, s);
-    case 9: return fwd_int3_lr<9>(P, jobs, s);
-    case 10: return fwd_int3_lr<10>(P, jobs, s);
+    case 6: return fwd_int3_lr<6>(P, t, jobs, s);
+    case 7: return fwd_int3_lr<7>(P, t, jobs, s);
+    case 8: return fwd_int3_lr<8>(P, t, jobs, s);
+    case 9: return fwd_int3_lr<9>(P, t, jobs, s);
+    case 10: return fwd_int3_lr<10>(P, t, jobs, s);
     default: break;
   }
   return hipErrorInvalidValue;
@@ -535,27 +551,6 @@ __global__ void k_widen(const uint16_t* __restrict__ in, long n, u32* __restrict
 
 hipError_t launch_widen(const uint16_t* in, long n, u32* out, hipStream_t s) {
   return launch("widen", k_widen, (unsigned)((n + 255) / 256), 256, 0, s, in, n, out);
-}
-
-// The descriptors of the three products, written to device memory so that
-// each pass of their common four-step plan runs once over the three primes.
-struct JobsOf3 {
-  ConvJob j[3];
-};
-
-__global__ void k_store_jobs3(JobsOf3 t, ConvJob* __restrict__ out) {
-  if (threadIdx.x == 0)
-    out[0] = t.j[0];
-  else if (threadIdx.x == 1)
-    out[1] = t.j[1];
-  else if (threadIdx.x == 2)
-    out[2] = t.j[2];
-}
-
-hipError_t launch_store_jobs3(const ConvJob* jobs, ConvJob* out, hipStream_t s) {
-  JobsOf3 t;
-  for (int i = 0; i < 3; ++i) t.j[i] = jobs[i];
-  return launch("store_jobs", k_store_jobs3, 1, 64, 0, s, t, out);
 }
 
 }  // namespace pm

@@ -202,7 +202,6 @@ hipError_t launch_mixed_merge(const u32* rows, int q, long M, u32* y, long ly, i
 // q <= 64 job descriptors: base advanced by r * stride (a, b, c) and r * tstride (Ta, Tb)
 hipError_t launch_row_jobs(const ConvJob& base, long stride, long tstride, int q, ConvJob* out, hipStream_t s);
 // the three jobs (host array) to device memory
-hipError_t launch_store_jobs3(const ConvJob* jobs, ConvJob* out, hipStream_t s);
 // rows[k1][k2] <-> flat[(M k1 + q k2) mod N]
 hipError_t launch_mixed_perm(const u32* in, int q, long M, u32* out, int to_flat, hipStream_t s);
 // Convolution launches over njobs jobs of one plan class (jobs in jr: the
