@@ -291,6 +291,21 @@ def test_int_mul(gpu_lib):
         ff = np.full(n, 0xFFFF, dtype=np.uint16)
         got = host(pm.int_mul(dev(ff, np.uint16), dev(ff, np.uint16)))
         assert np.array_equal(got, op.int_mul(ff, ff))
+    # a product of 0xFFFF..FF by 1 is one propagate chain across every run of
+    # limbs (carry maps of the identity), and an output that is not 16-byte
+    # aligned takes the limb-by-limb stores
+    import torch
+
+    for n in (1, 4095, 4096, 4097, 20000):
+        say("case: int chain and unaligned output", n)
+        ff = np.full(n, 0xFFFF, dtype=np.uint16)
+        one = np.ones(1, dtype=np.uint16)
+        buf = torch.full((n + 2,), 0x5A5A, dtype=torch.int32).to(torch.uint16).cuda()
+        out = buf[1:n + 2]  # n + 1 limbs at an offset of 2 bytes
+        pm.int_mul(dev(ff, np.uint16), dev(one, np.uint16), out=out)
+        assert pm.stream_check() == 0
+        h = host(buf)
+        assert np.array_equal(h[1:], op.int_mul(ff, one)) and h[0] == 0x5A5A, n
 
 
 def test_int_mul_plans_differ(gpu_lib):
