@@ -407,8 +407,9 @@ pm_status pm_mlp_train(float* params, const float* X, const float* t, int B, int
  * When enabled, every kernel the library launches is bracketed by two HIP
  * events recorded on its own stream, so kernel durations can be measured in
  * a live run.  Kernel names: "direct", "lds_conv", "col_fwd", "row_conv",
- * "col_inv", "row_xform", "lds_xform", "permute", "crt_sums", "carry_scan",
- * "carry_apply", "widen", "patch_jobs"; a batch's graph launch is recorded as
+ * "col_inv", "row_xform", "lds_xform", "permute", "crt", "carry_maps",
+ * "carry_limbs", "widen", "patch_jobs", "mixed_split", "mixed_merge",
+ * "mixed_perm", "row_jobs", "kron_pack"; a batch's graph launch is recorded as
  * "batch_graph".  While tracing is on, pm_poly_mul_batch runs its classes'
  * launches one after the other on the caller's stream instead of launching
  * its graph, so that every recorded duration is that kernel's alone. */
