@@ -141,6 +141,9 @@ SIGNATURES = {
 def lib():
     """Load libpolymul.so (raises if it has not been built)."""
     global _lib
+    L = _lib
+    if L is not None:  # loaded: no lock on the per-call path
+        return L
     with _lock:
         if _lib is None:
             if not os.path.exists(LIB_PATH):
