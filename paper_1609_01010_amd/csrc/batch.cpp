@@ -294,10 +294,11 @@ static pm_status upload_ptrs(BatchState* B, GraphEntry* G, const pm_problem* pro
 }
 
 // Fast path: the same shape (lengths and primes, in order) as the previous
-// batch on this stream, under the same plans and workspace: upload the new
-// operand and output pointers (the graph's first kernel patches them into
-// the descriptors) and relaunch the graph.  Returns false, launching
-// nothing, when the shape differs.
+// batch on this stream, under the same plan epoch and workspace: upload the
+// new operand and output pointers (the graph's first kernel patches them
+// into the descriptors) and relaunch the graph.  Returns false, launching
+// nothing, when the shape differs.  A caller that holds plans of its own
+// checks first that the last graph was built from them (same_plans).
 static bool batch_fast(DevCtx* c, BatchState* B, const pm_problem* probs, size_t count, hipStream_t s,
                        pm_status* st) {
   LastShape& L = B->last;
@@ -320,13 +321,20 @@ static bool batch_fast(DevCtx* c, BatchState* B, const pm_problem* probs, size_t
   return true;
 }
 
-// Run one batch with the given plans: the fast path when the shape repeats,
-// else classes, jobs and (cached per class signature) the graph.  The caller
-// holds the device lock.
+static bool same_plans(const std::vector<Plan>& x, const std::vector<Plan>& y) {
+  if (x.size() != y.size()) return false;
+  for (size_t i = 0; i < x.size(); ++i)
+    if (!same_plan(x[i], y[i])) return false;
+  return true;
+}
+
+// Run one batch with the given plans: the fast path when the shape repeats
+// under the same plans, else classes, jobs and (cached per class signature)
+// the graph.  The caller holds the device lock.
 static pm_status batch_run(DevCtx* c, BatchState* B, const pm_problem* probs, size_t count,
                            const std::vector<Plan>& plans, const std::vector<int>& pidx, hipStream_t s) {
   pm_status st = PM_OK;
-  if (batch_fast(c, B, probs, count, s, &st)) return st;
+  if (same_plans(B->last.plans, plans) && batch_fast(c, B, probs, count, s, &st)) return st;
 
   // classes, largest transforms first (the defining sums form one class)
   std::map<ClassKey, std::vector<size_t>> groups;
@@ -451,9 +459,11 @@ static u64 shape_hash(const pm_problem* probs, size_t count) {
   return h;
 }
 
-// median milliseconds of three runs of the batch with these plans (after one)
+// three timed runs of the batch with these plans (after one that builds its
+// jobs and graph), appended to *ms
 static pm_status time_batch(DevCtx* c, BatchState* B, const pm_problem* probs, size_t count,
-                            const std::vector<Plan>& plans, const std::vector<int>& pidx, hipStream_t s, float* ms) {
+                            const std::vector<Plan>& plans, const std::vector<int>& pidx, hipStream_t s,
+                            std::vector<float>* ms) {
   pm_status st = batch_run(c, B, probs, count, plans, pidx, s);
   hipEvent_t e0, e1;
   if (st || hipEventCreate(&e0) || hipEventCreate(&e1)) return st ? st : PM_EDEVICE;
@@ -470,9 +480,13 @@ static pm_status time_batch(DevCtx* c, BatchState* B, const pm_problem* probs, s
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st) return st;
-  std::sort(t.begin(), t.end());
-  *ms = t[1];
+  ms->insert(ms->end(), t.begin(), t.end());
   return PM_OK;
+}
+
+static float median_of(std::vector<float> v) {
+  std::sort(v.begin(), v.end());
+  return v[v.size() / 2];
 }
 
 extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream) {
@@ -497,8 +511,8 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
   // Learned policy: the model's plans are chosen per transform length, but
   // the classes of a batch share the device, and how well they overlap
   // decides its time.  The first call of a batch shape therefore runs it
-  // with the model's plans and with the default plans, waits, and keeps the
-  // faster for that shape.
+  // with the model's plans and with the default plans, twice each in turn,
+  // waits, and keeps the plans with the lower median time for that shape.
   std::vector<Plan> dplans(count);
   bool differ = false;
   for (size_t i = 0; i < count; ++i) {
@@ -514,11 +528,13 @@ extern "C" pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, vo
   const u64 h = shape_hash(probs, count);
   auto v = B->plan_choice.find(h);
   if (v == B->plan_choice.end()) {
-    float t_model = 0, t_default = 0;
-    st = time_batch(c, B, probs, count, plans, pidx, s, &t_model);
-    if (st == PM_OK) st = time_batch(c, B, probs, count, dplans, pidx, s, &t_default);
+    std::vector<float> t_model, t_default;
+    for (int r = 0; r < 2 && st == PM_OK; ++r) {
+      st = time_batch(c, B, probs, count, plans, pidx, s, &t_model);
+      if (st == PM_OK) st = time_batch(c, B, probs, count, dplans, pidx, s, &t_default);
+    }
     if (st) return st;
-    v = B->plan_choice.emplace(h, t_default < t_model ? 1 : 0).first;
+    v = B->plan_choice.emplace(h, median_of(t_default) < median_of(t_model) ? 1 : 0).first;
   }
   return batch_run(c, B, probs, count, v->second ? dplans : plans, pidx, s);
 }

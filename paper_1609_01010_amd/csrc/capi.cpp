@@ -1009,11 +1009,6 @@ struct IntLayout {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static bool same_plan(const Plan& x, const Plan& y) {
-  return x.kind == y.kind && x.logL == y.logL && x.logRA == y.logRA && x.logRB == y.logRB && x.logC == y.logC &&
-         x.ma == y.ma && x.lq == y.lq && x.lnt == y.lnt && x.twist == y.twist;
-}
-
 static void int_layout_sizes(size_t na, size_t nb, IntLayout* L) {
   const long lc = (long)(na + nb - 1);
   L->x_b = align256((size_t)lc * 8);

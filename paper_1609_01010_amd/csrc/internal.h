@@ -131,6 +131,11 @@ struct Plan {
   int q = 0;      // PLAN_MIXED: the odd factor of the length-q 2^logL circular convolution
 };
 
+inline bool same_plan(const Plan& x, const Plan& y) {
+  return x.kind == y.kind && x.logL == y.logL && x.logRA == y.logRA && x.logRB == y.logRB && x.logC == y.logC &&
+         x.ma == y.ma && x.lq == y.lq && x.lnt == y.lnt && x.twist == y.twist && x.q == y.q;
+}
+
 // Timing contexts of the tuner and the cost model: a product on its own
 // (latency) or one of many in a batch (throughput, time per product).
 constexpr int kCtxSingle = 0;

@@ -348,19 +348,24 @@ pm_status learned_batch_plans(const std::vector<long>& lcs, const std::vector<in
     const std::vector<size_t>& items = g.second;
     const int pid = g.first.second;
     // families from the candidates of the longest item (its kept blocks are
-    // the most, so every family valid for it is valid for the others)
+    // the most, so every family valid for it is valid for the others); each
+    // shape both untruncated and truncated to each item's own kept blocks,
+    // also where the longest item keeps every block and so has no truncated
+    // candidate of its own
     size_t rep = items[0];
     for (size_t i : items)
       if (lcs[i] > lcs[rep]) rep = i;
     std::vector<Plan> fams;
     for (const Plan& P : plan_candidates(lcs[rep], pid)) {
-      Plan F = P;
-      F.ma = P.ma == (1 << P.logRA) ? 0 : -1;  // 0: all blocks kept, -1: the item's own kept blocks
-      bool dup = false;
-      for (const Plan& Q : fams)
-        dup |= Q.kind == F.kind && Q.logRA == F.logRA && Q.logRB == F.logRB && Q.logC == F.logC && Q.lq == F.lq &&
-               Q.lnt == F.lnt && Q.ma == F.ma;
-      if (!dup) fams.push_back(F);
+      for (int fm = 0; fm >= -1; --fm) {
+        Plan F = P;
+        F.ma = fm;  // 0: all blocks kept, -1: the item's own kept blocks
+        bool dup = false;
+        for (const Plan& Q : fams)
+          dup |= Q.kind == F.kind && Q.logRA == F.logRA && Q.logRB == F.logRB && Q.logC == F.logC &&
+                 Q.lq == F.lq && Q.lnt == F.lnt && Q.ma == F.ma;
+        if (!dup) fams.push_back(F);
+      }
     }
     auto item_plan = [&](const Plan& F, long lc) {
       Plan P = F;

@@ -219,6 +219,49 @@ def test_learned_policy_trains_predicts_and_stays_exact(gpu_lib, tmp_path):
         pm.plan_cache_clear()
 
 
+def test_learned_batch_policy_keeps_the_faster_plans(gpu_lib):
+    """The first call of a batch shape under the learned policy runs the
+    batch with the model's plans and with the default plans and keeps the
+    faster.  A model whose output is negated picks, per size class, the plan
+    family it predicts slowest, so the default plans must be kept, also by
+    the later calls of the shape (the repeated-shape path); every product of
+    every call is exact."""
+    import os
+
+    import torch
+
+    pm = gpu_lib
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pm.model_load(os.path.join(root, "paper_1609_01010_amd", "data", "cost_model.txt"))
+    w, mean, sd = pm.model_get()
+    w[-(inputs.MLP_H + 1):] *= -1.0  # the output layer: predictions negated
+    items = inputs.batch_uneven(count=128, lo=64, hi=20000, tag=(114,))
+    lcs = [it.a.size + it.b.size - 1 for it in items]
+    pm.set_policy(pm.POLICY_DEFAULT)
+    pm.plan_cache_clear()
+    default = [pm.plan_for(lc, it.p, pm.CTX_BATCH).as_tuple() for lc, it in zip(lcs, items)]
+    pm.model_set(w, mean, sd)
+    pm.set_policy(pm.POLICY_LEARNED)
+    try:
+        for rnd in range(2):
+            probs = [(torch.from_numpy(it.a).cuda(), torch.from_numpy(it.b).cuda(), it.p) for it in items]
+            say("case: learned batch with a negated model, call", rnd)
+            outs = pm.poly_mul_batch(probs)
+            assert pm.stream_check() == 0
+            used = [P.as_tuple() for P in pm.batch_plans_used(len(items))]
+            assert used == default, rnd
+            for it, c in zip(items, outs):
+                assert np.array_equal(c.cpu().numpy(), op.poly_mul_ntt(it.a, it.b, it.p, inputs.PRIMES[it.p]))
+        # the comparison was real: the negated model's plans (now in the batch
+        # context's plan cache) differ from the default ones
+        model = [pm.plan_for(lc, it.p, pm.CTX_BATCH).as_tuple() for lc, it in zip(lcs, items)]
+        assert sum(m != d for m, d in zip(model, default)) >= len(items) // 4
+    finally:
+        pm.set_policy(pm.POLICY_DEFAULT)
+        pm.plan_cache_clear()
+        pm.model_load(os.path.join(root, "paper_1609_01010_amd", "data", "cost_model.txt"))
+
+
 def _geomean(xs):
     return float(np.exp(np.mean(np.log(np.asarray(xs, dtype=np.float64)))))
 
