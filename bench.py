@@ -258,9 +258,13 @@ def cpu_baseline(items, target_s=10.0):
             op.poly_mul_sample(it.a, it.b, it.p, ks)
         return time.perf_counter() - t0
 
-    dt = run(512)
-    n = int(min(2_000_000, max(512, 512 * target_s / max(dt, 1e-3))))
+    run(256)  # loads the oracle's C library and starts its threads
+    # grow the sample until it takes about target_s (at most 8 M coefficients)
+    n, cap = 4096, 8_000_000
     dt = run(n)
+    while dt < 0.5 * target_s and n < cap:
+        n = int(min(cap, n * min(target_s / max(dt, 1e-3), 50.0)))
+        dt = run(n)
     sub = items[::16]
     t0 = time.perf_counter()
     for it in sub:
