@@ -617,26 +617,33 @@ def extra_configs(pm, torch, dev, copy_bw, args, reps=5):
 
     out["plain_large_products"] = large_products(pm, torch, dev, args)
 
+    # the three-primes product of two 2^21-limb integers: pm_int_mul's own
+    # choice (32-bit digits, 2^21-point transforms), and the 16-bit limbs as
+    # digits (2^22-point transforms)
     ia, ib = inputs.int_operands()
     tia, tib = torch.from_numpy(ia).to(dev), torch.from_numpy(ib).to(dev)
     ic = torch.empty(ia.size + ib.size, dtype=torch.uint16, device=dev)
-    pm.int_mul(tia, tib, out=ic)
-    ms = time_calls(torch, lambda: pm.int_mul(tia, tib, out=ic), reps)
-    pm.trace_reset()
-    pm.trace_enable(True)
-    pm.int_mul(tia, tib, out=ic)
-    torch.cuda.synchronize()
-    pm.trace_enable(False)
-    ik = {}
-    for name in pm.trace_names():
-        tot, n = pm.trace_query(name)
-        ik[name] = 1e3 * tot
-    pm.trace_reset()
-    got = ic.cpu().numpy()
     q = (1 << 61) - 1
-    ok = limbs_value(got) % q == (limbs_value(ia) % q) * (limbs_value(ib) % q) % q
-    out["int_mul_2^21x2^21_limbs"] = {"ms": ms, "limbs_per_s": got.size / (ms * 1e-3), "kernels_us": ik,
-                                      "check": "product mod 2^61-1 matches" if ok else "MISMATCH"}
+    want = (limbs_value(ia) % q) * (limbs_value(ib) % q) % q
+    for key, digits in (("int_mul_2^21x2^21_limbs", None), ("int_mul_2^21x2^21_limbs_digits16", 16)):
+        pm.int_mul(tia, tib, out=ic, digits=digits)
+        ms = time_calls(torch, lambda: pm.int_mul(tia, tib, out=ic, digits=digits), reps)
+        pm.trace_reset()
+        pm.trace_enable(True)
+        pm.int_mul(tia, tib, out=ic, digits=digits)
+        torch.cuda.synchronize()
+        pm.trace_enable(False)
+        ik = {}
+        for name in pm.trace_names():
+            tot, n = pm.trace_query(name)
+            ik[name] = 1e3 * tot
+        pm.trace_reset()
+        got = ic.cpu().numpy()
+        ok = limbs_value(got) % q == want
+        out[key] = {"digits": "32-bit (pairs of limbs), 2^21-point transforms" if digits is None
+                    else "16-bit limbs, 2^22-point transforms",
+                    "ms": ms, "limbs_per_s": got.size / (ms * 1e-3), "kernels_us": ik,
+                    "check": "product mod 2^61-1 matches" if ok else "MISMATCH"}
     del tia, tib, ic
 
     out.update(standalone_transform(pm, torch, dev, copy_bw))

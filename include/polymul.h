@@ -187,7 +187,9 @@ pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream)
  *                              the most any candidate plan needs.
  *   pm_batch_workspace_query:  bytes pm_poly_mul_batch needs for these
  *                              problems (host array).
- *   pm_int_mul_workspace_query: bytes pm_int_mul(na, nb) needs.
+ *   pm_int_mul_workspace_query: bytes pm_int_mul(na, nb) needs;
+ *                              pm_int_mul_digits_workspace_query: bytes
+ *                              pm_int_mul_digits(na, nb, digit_bits) needs.
  *   pm_set_workspace:          use the caller's device memory [ptr, ptr +
  *                              bytes) as the workspace of `stream` on the
  *                              current device from now on; a call that needs
@@ -203,18 +205,28 @@ pm_status pm_poly_mul_batch(const pm_problem* probs, size_t count, void* stream)
 pm_status pm_workspace_query(size_t len_a, size_t len_b, uint32_t p, size_t* bytes);
 pm_status pm_batch_workspace_query(const pm_problem* probs, size_t count, size_t* bytes);
 pm_status pm_int_mul_workspace_query(size_t na, size_t nb, size_t* bytes);
+pm_status pm_int_mul_digits_workspace_query(size_t na, size_t nb, int digit_bits, size_t* bytes);
 pm_status pm_set_workspace(void* stream, void* ptr, size_t bytes);
 
 /*
  * Integer product by the three-primes algorithm (section 1): A and B are
  * little-endian integers of na and nb 16-bit limbs (A = sum a_i 2^{16 i}).
- * The limb sequences are multiplied as polynomials modulo 469762049,
+ * Their digit sequences are multiplied as polynomials modulo 469762049,
  * 998244353 and 167772161, the three residues of every coefficient are
- * combined by the Chinese remainder theorem into the exact (< 2^87) sum, and
+ * combined by the Chinese remainder theorem into the exact sum (< 2^54 for
+ * 16-bit digits, < 2^85 for 32-bit ones; p1 p2 p3 is about 2^86.02), and
  * carries are propagated.  c receives exactly na + nb limbs of A*B (the top
  * limb may be 0).  Requires na + nb - 1 <= 2^23.
- * Plans: for each prime, the plan of the output length na + nb - 1 in the
- * product-alone context: the cached one (pm_plan_cache_put, or the tuner's
+ * Digits: pm_int_mul takes 32-bit digits (digit j = a_{2j} + 2^16 a_{2j+1},
+ * so the transforms have ceil(na/2) + ceil(nb/2) - 1 points, half as many)
+ * when the three primes' plans at that length are one plan with the fused
+ * passes described below, else the 16-bit limbs themselves.
+ * pm_int_mul_digits chooses with digit_bits = 0 in the same way, and forces
+ * 16 or 32 (32 returns PM_EUNSUPPORTED where the plans do not allow it);
+ * another value is PM_EINVAL.  The digits change the cost, never the result.
+ * Plans: for each prime, the plan of the transform's output length (na +
+ * nb - 1, or the digit product's length above) in the product-alone
+ * context: the cached one (pm_plan_cache_put, or the tuner's
  * pick after pm_tune), else under PM_POLICY_LEARNED the cost model's pick,
  * else the default plan.  The call never times candidates itself: under
  * PM_POLICY_EXHAUSTIVE an untuned length takes the default plan (tune it
@@ -226,6 +238,8 @@ pm_status pm_set_workspace(void* stream, void* ptr, size_t bytes);
  * and the CRT reads the three residue arrays.
  */
 pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint16_t* c, void* stream);
+pm_status pm_int_mul_digits(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, int digit_bits, uint16_t* c,
+                            void* stream);
 
 /*
  * Length-n modular DFT (section 3: evaluation at w^0 .. w^{n-1}, with

@@ -94,6 +94,8 @@ SIGNATURES = {
     "pm_poly_mul_multi": (_int, [_vp, ctypes.POINTER(_sz), _vp, ctypes.POINTER(_sz), _int, _u32, _vp, _vp]),
     "pm_negacyclic_mul": (_int, [_vp, _sz, _vp, _sz, _sz, _u32, _vp, _vp]),
     "pm_int_mul": (_int, [_vp, _sz, _vp, _sz, _vp, _vp]),
+    "pm_int_mul_digits": (_int, [_vp, _sz, _vp, _sz, ctypes.c_int, _vp, _vp]),
+    "pm_int_mul_digits_workspace_query": (_int, [_sz, _sz, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "pm_ntt": (_int, [_vp, _vp, _sz, _u32, _int, _vp]),
     "pm_tft": (_int, [_vp, _sz, _sz, _sz, _u32, _vp, _vp]),
     "pm_itft": (_int, [_vp, _sz, _sz, _u32, _vp, _vp]),
@@ -286,9 +288,13 @@ def workspace_query(len_a: int, len_b: int, p: int) -> int:
     return n.value
 
 
-def int_mul_workspace_query(na: int, nb: int) -> int:
+def int_mul_workspace_query(na: int, nb: int, digits=None) -> int:
     n = ctypes.c_size_t(0)
-    _check(lib().pm_int_mul_workspace_query(na, nb, ctypes.byref(n)), "pm_int_mul_workspace_query")
+    if digits is None:
+        _check(lib().pm_int_mul_workspace_query(na, nb, ctypes.byref(n)), "pm_int_mul_workspace_query")
+    else:
+        _check(lib().pm_int_mul_digits_workspace_query(na, nb, int(digits), ctypes.byref(n)),
+               "pm_int_mul_digits_workspace_query")
     return n.value
 
 
@@ -354,17 +360,20 @@ def poly_mul_batch(problems, outs=None, stream=None):
     return PreparedBatch(problems, outs).run(stream)
 
 
-def int_mul(a, b, out=None, stream=None):
-    """Product of two little-endian 16-bit-limb integers (uint16 tensors): na + nb limbs."""
+def int_mul(a, b, out=None, stream=None, digits=None):
+    """Product of two little-endian 16-bit-limb integers (uint16 tensors): na + nb limbs.
+
+    digits: None (pm_int_mul: 32-bit digits where the plans allow, else the
+    limbs), or 0, 16 or 32 (pm_int_mul_digits)."""
     torch = _torch()
     na, nb = a.numel(), b.numel()
     if out is None:
         out = torch.empty(na + nb, dtype=torch.uint16, device=a.device)
-    _check(
-        lib().pm_int_mul(_dev_ptr(a, torch.uint16, "a"), na, _dev_ptr(b, torch.uint16, "b"), nb,
-                         _dev_ptr(out, torch.uint16, "out"), _stream(stream)),
-        "pm_int_mul",
-    )
+    pa, pb, po = _dev_ptr(a, torch.uint16, "a"), _dev_ptr(b, torch.uint16, "b"), _dev_ptr(out, torch.uint16, "out")
+    if digits is None:
+        _check(lib().pm_int_mul(pa, na, pb, nb, po, _stream(stream)), "pm_int_mul")
+    else:
+        _check(lib().pm_int_mul_digits(pa, na, pb, nb, int(digits), po, _stream(stream)), "pm_int_mul_digits")
     return out
 
 

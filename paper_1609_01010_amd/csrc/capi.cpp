@@ -10,8 +10,9 @@
 
 namespace pm {
 bool int3_fused_ok(const Plan& P);
-hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* J, ConvJob* jobs, hipStream_t s);
-hipError_t launch_col_inv_crt3(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s);
+hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* J, ConvJob* jobs, bool digits32, hipStream_t s);
+hipError_t launch_col_inv_crt3(const Plan& P, const ConvJob* jobs, void* X, bool digits32, hipStream_t s);
+hipError_t launch_carry32(const void* X, long dc, long nl, void* ws, uint16_t* out, hipStream_t s);
 hipError_t launch_crt_x(const u32* r1, const u32* r2, const u32* r3, long lc, u64* X, hipStream_t s);
 hipError_t launch_carry(const u64* X, long lc, long nl, void* ws, uint16_t* out, hipStream_t s);
 size_t carry_workspace_bytes(long nl);
@@ -1000,23 +1001,32 @@ static const u32 kIntPrimes[3] = {469762049u, 998244353u, 167772161u};
 // their descriptors, x and the carry state.  Otherwise each prime's product
 // writes a residue array (widened 32-bit operands for plans that need them),
 // a kernel combines the residues into x, and the carries follow.
+// With 32-bit digits (pairs of limbs; only in the fused form) the
+// transforms have da + db - 1 elements (da = ceil(na / 2)), x_k takes 16
+// bytes and the carries run over 32-bit words.
 struct IntLayout {
   Plan plans[3];
   bool widen = false;
   bool fused = false;
+  bool d32 = false;
+  long lc = 0;  // coefficients: na + nb - 1, or da + db - 1 with 32-bit digits
   size_t res_b = 0, wid_b = 0, pw = 0, jobs_b = 0, x_b = 0, total = 0;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+static long int_digits32_lc(size_t na, size_t nb) { return (long)((na + 1) / 2 + (nb + 1) / 2 - 1); }
+
 static void int_layout_sizes(size_t na, size_t nb, IntLayout* L) {
-  const long lc = (long)(na + nb - 1);
-  L->x_b = align256((size_t)lc * 8);
-  L->res_b = L->fused ? 0 : align256((size_t)lc * 4);
+  L->lc = L->d32 ? int_digits32_lc(na, nb) : (long)(na + nb - 1);
+  L->x_b = align256((size_t)L->lc * (L->d32 ? 16 : 8));
+  L->res_b = L->fused ? 0 : align256((size_t)L->lc * 4);
   L->wid_b = L->widen ? align256((na + nb) * 4) : 0;
   const size_t pw = L->fused ? 3 * align256(L->pw) : align256(L->pw);
   L->jobs_b = L->fused ? align256(3 * sizeof(ConvJob)) : 0;
-  L->total = 3 * L->res_b + L->wid_b + pw + L->jobs_b + L->x_b + align256(carry_workspace_bytes((long)(na + nb)));
+  // the carries' state: one word per run of limbs (or of 32-bit words)
+  const long units = L->d32 ? (long)((na + nb + 1) / 2) : (long)(na + nb);
+  L->total = 3 * L->res_b + L->wid_b + pw + L->jobs_b + L->x_b + align256(carry_workspace_bytes(units));
 }
 
 // the plans the policy picks (plan choice may consult the cost model, so
@@ -1039,9 +1049,39 @@ static Plan int3_twin(const Plan& P, long lc, int pidx) {
   return plan_valid(T, lc, pidx) && int3_fused_ok(T) ? T : P;
 }
 
-static pm_status int_mul_layout(size_t na, size_t nb, IntLayout* L) {
+// 32-bit digits: the three primes' plans at the digit product's length,
+// usable when they are one plan with the fused three-prime passes
+static bool int_layout_d32(size_t na, size_t nb, IntLayout* L) {
+  const long dc = int_digits32_lc(na, nb);
+  if (dc < 2) return false;
+  for (int i = 0; i < 3; ++i) {
+    const int pidx = prime_index(kIntPrimes[i]);
+    L->plans[i] = int3_twin(choose_plan(dc, pidx), dc, pidx);
+    if (!plan_valid(L->plans[i], dc, pidx)) return false;
+  }
+  if (!int3_fused_ok(L->plans[0]) || !same_plan(L->plans[0], L->plans[1]) || !same_plan(L->plans[0], L->plans[2]))
+    return false;
+  L->fused = true;
+  L->d32 = true;
+  L->widen = false;
+  L->pw = plan_workspace_bytes(L->plans[0]);
+  int_layout_sizes(na, nb, L);
+  return true;
+}
+
+// digits: 0 (32-bit digits where their plans allow, else 16), 16 or 32
+static pm_status int_mul_layout(size_t na, size_t nb, int digits, IntLayout* L) {
   const long lc = (long)(na + nb - 1);
   if (ceil_log2(lc) > 23) return PM_ETOOLARGE;
+  if (digits != 0 && digits != 16 && digits != 32) return PM_EINVAL;
+  if (digits != 16) {
+    IntLayout D;
+    if (int_layout_d32(na, nb, &D)) {
+      *L = D;
+      return PM_OK;
+    }
+    if (digits == 32) return PM_EUNSUPPORTED;
+  }
   for (int i = 0; i < 3; ++i) {
     const int pidx = prime_index(kIntPrimes[i]);
     L->plans[i] = int3_twin(choose_plan(lc, pidx), lc, pidx);
@@ -1055,8 +1095,9 @@ static pm_status int_mul_layout(size_t na, size_t nb, IntLayout* L) {
   return PM_OK;
 }
 
-pm_status pm_int_mul_workspace_query(size_t na, size_t nb, size_t* bytes) {
+pm_status pm_int_mul_digits_workspace_query(size_t na, size_t nb, int digit_bits, size_t* bytes) {
   if (!bytes || na == 0 || nb == 0) return PM_EINVAL;
+  if (digit_bits != 0 && digit_bits != 16 && digit_bits != 32) return PM_EINVAL;
   const long lc = (long)(na + nb - 1);
   if (ceil_log2(lc) > 23) return PM_ETOOLARGE;
   // on the host alone: under the default policy (or with every prime's plan
@@ -1068,32 +1109,55 @@ pm_status pm_int_mul_workspace_query(size_t na, size_t nb, size_t* bytes) {
     known = true;
     for (int i = 0; i < 3; ++i) known = known && plan_pinned(lc, kIntPrimes[i]);
   }
+  if (known && digit_bits != 16) {
+    const long dc = int_digits32_lc(na, nb);
+    for (int i = 0; i < 3; ++i) known = known && (current_policy() == PM_POLICY_DEFAULT || plan_pinned(dc, kIntPrimes[i]));
+  }
   IntLayout L;
   if (known) {
-    const pm_status st = int_mul_layout(na, nb, &L);
+    const pm_status st = int_mul_layout(na, nb, digit_bits, &L);
     if (st) return st;
     *bytes = L.total;
     return PM_OK;
   }
-  size_t pw = 0;
-  for (int i = 0; i < 3; ++i) pw = std::max(pw, product_workspace_bound(lc, prime_index(kIntPrimes[i])));
   size_t worst = 0;
-  for (int fused = 0; fused < 2; ++fused) {
-    IntLayout W;
-    W.pw = pw;
-    W.widen = !fused;
-    W.fused = fused != 0;
-    int_layout_sizes(na, nb, &W);
-    worst = std::max(worst, W.total);
+  if (digit_bits != 32) {
+    size_t pw = 0;
+    for (int i = 0; i < 3; ++i) pw = std::max(pw, product_workspace_bound(lc, prime_index(kIntPrimes[i])));
+    for (int fused = 0; fused < 2; ++fused) {
+      IntLayout W;
+      W.pw = pw;
+      W.widen = !fused;
+      W.fused = fused != 0;
+      int_layout_sizes(na, nb, &W);
+      worst = std::max(worst, W.total);
+    }
+  }
+  if (digit_bits != 16) {
+    const long dc = int_digits32_lc(na, nb);
+    if (dc >= 2) {
+      IntLayout W;
+      for (int i = 0; i < 3; ++i) W.pw = std::max(W.pw, product_workspace_bound(dc, prime_index(kIntPrimes[i])));
+      W.fused = true;
+      W.d32 = true;
+      int_layout_sizes(na, nb, &W);
+      worst = std::max(worst, W.total);
+    }
   }
   *bytes = worst;
   return PM_OK;
 }
 
-pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint16_t* out, void* stream) {
+pm_status pm_int_mul_workspace_query(size_t na, size_t nb, size_t* bytes) {
+  return pm_int_mul_digits_workspace_query(na, nb, 0, bytes);
+}
+
+pm_status pm_int_mul_digits(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, int digit_bits,
+                            uint16_t* out, void* stream) {
   if (!a || !b || !out || na == 0 || nb == 0) return PM_EINVAL;
-  const long lc = (long)(na + nb - 1);
-  if (ceil_log2(lc) > 23) return PM_ETOOLARGE;
+  if (digit_bits != 0 && digit_bits != 16 && digit_bits != 32) return PM_EINVAL;
+  const long lc0 = (long)(na + nb - 1);
+  if (ceil_log2(lc0) > 23) return PM_ETOOLARGE;
   pm_status st;
   DevCtx* c = ctx_current(&st);
   if (!c) return st;
@@ -1101,8 +1165,9 @@ pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb,
   hipStream_t s = (hipStream_t)stream;
   const long nl = (long)(na + nb);
   IntLayout LY;
-  st = int_mul_layout(na, nb, &LY);
+  st = int_mul_layout(na, nb, digit_bits, &LY);
   if (st) return st;
+  const long lc = LY.lc;
   void* wsp = nullptr;
   st = stream_workspace(c, s, LY.total, &wsp);
   if (st) return st;
@@ -1128,10 +1193,10 @@ pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb,
     JobRef jr;
     jr.one = J[0];
     jr.many = djobs;
-    hipError_t e = launch_col_fwd_int3(P, J, djobs, s);
+    hipError_t e = launch_col_fwd_int3(P, J, djobs, LY.d32, s);
     if (e == hipSuccess) e = launch_row_conv(P, true, J[0].rows, jr, 3, s);
-    if (e == hipSuccess) e = launch_col_inv_crt3(P, djobs, X, s);
-    if (e == hipSuccess) e = launch_carry(X, lc, nl, cws, out, s);
+    if (e == hipSuccess) e = launch_col_inv_crt3(P, djobs, X, LY.d32, s);
+    if (e == hipSuccess) e = LY.d32 ? launch_carry32(X, lc, nl, cws, out, s) : launch_carry(X, lc, nl, cws, out, s);
     return dev_status(e);
   }
   if (LY.widen) {
@@ -1150,6 +1215,10 @@ pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb,
   hipError_t e = launch_crt_x(res[0], res[1], res[2], lc, X, s);
   if (e == hipSuccess) e = launch_carry(X, lc, nl, cws, out, s);
   return dev_status(e);
+}
+
+pm_status pm_int_mul(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint16_t* out, void* stream) {
+  return pm_int_mul_digits(a, na, b, nb, 0, out, stream);
 }
 
 }  // extern "C"

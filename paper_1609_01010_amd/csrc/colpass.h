@@ -7,6 +7,8 @@
 // row, j2 < C the column); the column transforms are length-R DIF networks
 // (natural in, bit-reversed out), and the rows t < mr are the ones kept.
 #pragma once
+#include <type_traits>
+
 #include "internal.h"
 
 namespace pm {
@@ -24,6 +26,18 @@ __device__ __forceinline__ long col_tile_paired() {
   return (g & 15u) ? (long)x : (long)(((x >> 4) << 4) | ((x & 7u) << 1) | ((x >> 3) & 1u));
 }
 
+// Input element type of the integer product with 32-bit digits: element j
+// of the operand is the digit l_{2j} + 2^16 l_{2j+1} of its 16-bit limbs l
+// (limbs at or beyond the operand's limb count are zero).  A digit may exceed
+// p; it is reduced on load by a Shoup product with the constant 1, which maps
+// any 32-bit value into [0, 2p).
+struct LimbPair {};
+
+template <typename TIn>
+constexpr bool is_limb_pair() {
+  return std::is_same<TIn, LimbPair>::value;
+}
+
 // radix (log2) of round k (outermost first) of a length-2^LR column transform
 template <int LR, int K>
 constexpr int col_round_lq() {
@@ -34,8 +48,8 @@ constexpr int col_round_lq() {
 
 // DIF round of radix 2^LQ over the blocks of 2^LB rows that start below mr;
 // FROM_GLOBAL: the input is the operand in global memory (rows beyond its
-// length are zero), else LDS; TO_GLOBAL: output rows below mr go to `out`,
-// else back to LDS
+// length z are zero; for LimbPair input z counts limbs), else LDS;
+// TO_GLOBAL: output rows below mr go to `out`, else back to LDS
 template <int LB, int LQ, bool FROM_GLOBAL, bool TO_GLOBAL, bool LAZY, typename TIn, bool TWIST>
 __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int lw, int mr, const PrimeTables& T,
                                               int tid, int nthr, const TIn* __restrict__ in, long z, long C, long col0,
@@ -44,6 +58,11 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
   constexpr int LS = LB - LQ;
   constexpr int K = 16 / Q;
   const int ntask = (((mr + (1 << LB) - 1) >> LB) << LS) << lw;
+  // the operand's length in elements, and the constant 1 as a Shoup pair
+  // (the digits' reduction)
+  const long ze = is_limb_pair<TIn>() ? (z + 1) >> 1 : z;
+  uint2 one = make_uint2(0u, 0u);
+  if constexpr (FROM_GLOBAL && is_limb_pair<TIn>()) one = cld(T.pf + 1);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int task = tid + k * nthr;
@@ -56,7 +75,13 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
 #pragma unroll
       for (int s = 0; s < Q; ++s) {
         const int row = base + (s << LS);
-        if constexpr (FROM_GLOBAL) {
+        if constexpr (FROM_GLOBAL && is_limb_pair<TIn>()) {
+          const uint16_t* __restrict__ l = (const uint16_t*)in;
+          const long i0 = 2 * (C * row + col0 + c);
+          const u32 lo = i0 < z ? (u32)gld(l + i0) : 0u;
+          const u32 hi = i0 + 1 < z ? (u32)gld(l + i0 + 1) : 0u;
+          x[s] = A.mul(lo | (hi << 16), one);
+        } else if constexpr (FROM_GLOBAL) {
           const long pos = C * row + col0 + c;
           x[s] = pos < z ? (u32)gld(in + pos) : 0u;
           bad |= x[s] >= A.p;
@@ -67,7 +92,7 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
       }
       // the first round spans whole columns (LB = log R): rows R/2 and up
       // are zero when the operand has at most L/2 values
-      if (FROM_GLOBAL && (C << (LB - 1)) >= z)
+      if (FROM_GLOBAL && (C << (LB - 1)) >= ze)
         dif_reg<Q, LAZY, (LS > 0), true>(A, x, T.pf);
       else
         dif_reg<Q, LAZY, (LS > 0)>(A, x, T.pf);

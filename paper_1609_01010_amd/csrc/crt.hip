@@ -1,8 +1,12 @@
-// Three-primes integer product (section 1): the limb sequences are
+// Three-primes integer product (section 1): the digit sequences are
 // convolved modulo p1 = 469762049, p2 = 998244353, p3 = 167772161, the three
 // residues of every coefficient give the exact coefficient x_k < p1 p2 p3
 // (Chinese remainder theorem, Garner's mixed-radix form), and sum_k x_k
-// 2^{16 k} is written in 16-bit limbs.
+// 2^{D k} is written in 16-bit limbs.  The digits are the 16-bit limbs
+// themselves (D = 16), or pairs of them (D = 32: digit j = l_{2j} + 2^16
+// l_{2j+1}), which halves the transform length; with at most 2^21 digits per
+// operand (na + nb - 1 <= 2^23 limbs) every x_k < 2^21 (2^32 - 1)^2 < 2^85
+// still lies below p1 p2 p3 (about 2^86.02), so it is exact.
 //
 // When the three primes share one four-step plan, the column passes run once
 // for all three: the forward pass reads each tile of limbs once and
@@ -12,7 +16,7 @@
 // supported sizes (na + nb - 1 <= 2^23, so min(na, nb) <= 2^22) every
 // x_k < 2^22 (2^16 - 1)^2 < 2^54 fits one 64-bit word.
 //
-// Carries: x_k < 2^54 is four 16-bit digits; digit d goes to limb k + d, so
+// Carries (D = 16): x_k < 2^54 is four 16-bit digits; digit d goes to limb k + d, so
 // the limb sum s_m = sum_{d<4} digit_d(x_{m-d}) < 2^18.  Splitting s_m into
 // its low 16 bits and its high part h_m <= 3, the value t_m = lo(s_m) +
 // h_{m-1} <= 2^16 + 2 leaves carries of 0 or 1 only: limb m is (t_m + c_m)
@@ -21,12 +25,16 @@
 // the carries are a scan, done in two passes: the map of every work-group's
 // run (the map of its last limb that does not propagate, so the pass reads
 // little more than one chunk of 64 limbs per run), then each work-group takes
-// its carry-in from the maps before it and writes its limbs.
+// its carry-in from the maps before it and writes its limbs.  With D = 32
+// the same scan runs over 32-bit words (below).
 #include "colpass.h"
 #include "internal.h"
 #include "trace.h"
 
 namespace pm {
+
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // Garner's reconstruction
@@ -58,6 +66,26 @@ __device__ __forceinline__ u64 crt_value(const CrtConsts& K, u32 r1, u32 r2, u32
   u = min(u, u - K.p3);
   const u32 v3 = shoup_canon(r3 + K.p3 - u, K.inv_p1p2_mod_p3, K.p3);
   return (u64)v1 + (u64)K.p1 * v2 + K.p1p2 * (u64)v3;
+}
+
+// the same value for x < 2^86 (32-bit digits): (low 64 bits, bits 64..)
+__device__ __forceinline__ uint4 crt_value_wide(const CrtConsts& K, u32 r1, u32 r2, u32 r3) {
+  const u32 v1 = r1;
+  const u32 v2 = shoup_canon(r2 + K.p2 - v1, K.inv_p1_mod_p2, K.p2);
+  u32 v1m3 = v1;
+  v1m3 = min(v1m3, v1m3 - K.p3);
+  v1m3 = min(v1m3, v1m3 - K.p3);
+  v1m3 = min(v1m3, v1m3 - K.p3);
+  u32 t = shoup_canon(v2, K.p1_mod_p3, K.p3);
+  u32 u = v1m3 + t;
+  u = min(u, u - K.p3);
+  const u32 v3 = shoup_canon(r3 + K.p3 - u, K.inv_p1p2_mod_p3, K.p3);
+  const u64 low = (u64)v1 + (u64)K.p1 * v2;  // < 2^59
+  const u64 plo = K.p1p2 * (u64)v3;          // p1 p2 v3 mod 2^64
+  const u64 phi = __umul64hi(K.p1p2, (u64)v3);
+  const u64 lo = low + plo;
+  const u32 hi = (u32)phi + (lo < plo ? 1u : 0u);
+  return make_uint4((u32)lo, (u32)(lo >> 32), hi, 0u);
 }
 
 static CrtConsts crt_consts() {
@@ -108,7 +136,7 @@ struct JobsOf3 {
 // prime's round reads the tile from memory, the others find it in the L2
 // cache (each limb is read from HBM once), and the stores of one prime drain
 // while the next one computes.
-template <int LR>
+template <int LR, typename TIn>
 __global__ void __launch_bounds__(1024) k_col_fwd_int3(JobsOf3 t, ConvJob* __restrict__ jobs_out, int logC, int lw) {
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     jobs_out[0] = t.j[0];
@@ -129,11 +157,11 @@ __global__ void __launch_bounds__(1024) k_col_fwd_int3(JobsOf3 t, ConvJob* __res
     asm volatile("" : "+v"(tid));
     const ConvJob J = t.j[pr];
     const Arith<true> A(J.mp);
-    const uint16_t* in = (const uint16_t*)(blockIdx.y ? J.b : J.a);
+    const TIn* in = (const TIn*)(blockIdx.y ? J.b : J.a);
     const long z = blockIdx.y ? J.lb : J.la;
     u32* out = blockIdx.y ? J.Tb : J.Ta;
-    col_dif_rounds<LR, 0, LR, true, uint16_t, false>(A, sm, lw, J.rows, fresh(J.T), tid, nthr, in, z, C, col0, out,
-                                                     nullptr, bad);
+    col_dif_rounds<LR, 0, LR, true, TIn, false>(A, sm, lw, J.rows, fresh(J.T), tid, nthr, in, z, C, col0, out,
+                                                nullptr, bad);
     __syncthreads();  // the next prime reuses the tile
   }
 }
@@ -181,9 +209,21 @@ __device__ __forceinline__ void inv_tile_prime(const ConvJob* jobs, int pr, u32*
   __syncthreads();  // the next prime reuses the tile
 }
 
-template <int LRA, int LRB>
+// WIDE (32-bit digits): x_k is written as four 32-bit words (the low 64
+// bits, the bits from 64 on, and 0), else as one 64-bit word.
+template <bool WIDE>
+__device__ __forceinline__ void crt_store(void* X, long pos, const CrtConsts& K, u32 r1, u32 r2, u32 r3) {
+  if constexpr (WIDE) {
+    const uint4 v = crt_value_wide(K, r1, r2, r3);
+    *((PM_GMEM u32x4*)X + pos) = u32x4{v.x, v.y, v.z, v.w};
+  } else {
+    gst((u64*)X + pos, crt_value(K, r1, r2, r3));
+  }
+}
+
+template <int LRA, int LRB, bool WIDE>
 __global__ void __launch_bounds__(512) k_col_inv_crt3(const ConvJob* jobs, int logC, int lw, CrtConsts K,
-                                                      u64* __restrict__ X) {
+                                                      void* __restrict__ X) {
   constexpr int RA = 1 << LRA, RB = 1 << LRB;
   constexpr int TPT = 16 / RA;
   static_assert(LRA <= 4, "at most one task of 16 values per thread");
@@ -208,7 +248,7 @@ __global__ void __launch_bounds__(512) k_col_inv_crt3(const ConvJob* jobs, int l
 #pragma unroll
     for (int e = 0; e < RA; ++e) {
       const long pos = C * (j1b + RB * e) + c0 + cc;
-      if (e < ma && pos < lc) gst(X + pos, crt_value(K, r1[q][e], r2[q][e], r3[q][e]));
+      if (e < ma && pos < lc) crt_store<WIDE>(X, pos, K, r1[q][e], r2[q][e], r3[q][e]);
     }
   }
 }
@@ -254,9 +294,9 @@ __device__ __forceinline__ void inv_tile_prime32(const ConvJob* jobs, int pr, u3
   __syncthreads();  // the next prime reuses the tile
 }
 
-template <int LRB>
+template <int LRB, bool WIDE>
 __global__ void __launch_bounds__(512) k_col_inv_crt3_32(const ConvJob* jobs, int logC, int lw, CrtConsts K,
-                                                         u64* __restrict__ X) {
+                                                         void* __restrict__ X) {
   constexpr int RB = 1 << LRB;
   extern __shared__ u32 sm[];  // [R][W]
   const long C = 1l << logC;
@@ -277,7 +317,7 @@ __global__ void __launch_bounds__(512) k_col_inv_crt3_32(const ConvJob* jobs, in
   for (int i = 0; i < 16; ++i) {
     const int e = 16 * half + i;
     const long pos = C * (j1b + RB * e) + c0 + cc;
-    if (e < ma && pos < lc) gst(X + pos, crt_value(K, r1[i], r2[i], r3[i]));
+    if (e < ma && pos < lc) crt_store<WIDE>(X, pos, K, r1[i], r2[i], r3[i]);
   }
 }
 
@@ -290,35 +330,42 @@ bool int3_fused_ok(const Plan& P) {
   return P.logRA == 4 || (P.logRA == 5 && P.ma >= 32 - kFillMax);
 }
 
-template <int LR>
+template <int LR, typename TIn>
 static hipError_t fwd_int3_lr(const Plan& P, const JobsOf3& t, ConvJob* jobs, hipStream_t s) {
   const int lw = col_lw(LR, P.logC, 2);
   const long C = 1l << P.logC;
   if (C < (1l << lw) || col_threads(LR, lw) > 1024) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << (lw + LR)) * sizeof(u32);
-  auto kern = k_col_fwd_int3<LR>;
+  auto kern = k_col_fwd_int3<LR, TIn>;
   ensure_lds_attr((const void*)kern, lds);
   return launch("col_fwd", kern, dim3((unsigned)(C >> lw), 2, 1), col_threads(LR, lw), lds, s, t, jobs, P.logC, lw);
 }
 
-// host: J, the three descriptors; jobs, their device copy the pass writes
-hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* J, ConvJob* jobs, hipStream_t s) {
-  if (!int3_fused_ok(P)) return hipErrorInvalidValue;
-  JobsOf3 t;
-  for (int i = 0; i < 3; ++i) t.j[i] = J[i];
+template <typename TIn>
+static hipError_t fwd_int3_t(const Plan& P, const JobsOf3& t, ConvJob* jobs, hipStream_t s) {
   switch (P.logRA + P.logRB) {
-    case 6: return fwd_int3_lr<6>(P, t, jobs, s);
-    case 7: return fwd_int3_lr<7>(P, t, jobs, s);
-    case 8: return fwd_int3_lr<8>(P, t, jobs, s);
-    case 9: return fwd_int3_lr<9>(P, t, jobs, s);
-    case 10: return fwd_int3_lr<10>(P, t, jobs, s);
+    case 6: return fwd_int3_lr<6, TIn>(P, t, jobs, s);
+    case 7: return fwd_int3_lr<7, TIn>(P, t, jobs, s);
+    case 8: return fwd_int3_lr<8, TIn>(P, t, jobs, s);
+    case 9: return fwd_int3_lr<9, TIn>(P, t, jobs, s);
+    case 10: return fwd_int3_lr<10, TIn>(P, t, jobs, s);
     default: break;
   }
   return hipErrorInvalidValue;
 }
 
-template <int LRA, int LRB>
-static hipError_t inv_crt3_inst(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s) {
+// host: J, the three descriptors (operand lengths in limbs); jobs, their
+// device copy the pass writes; digits32: the transforms' elements are pairs
+// of limbs
+hipError_t launch_col_fwd_int3(const Plan& P, const ConvJob* J, ConvJob* jobs, bool digits32, hipStream_t s) {
+  if (!int3_fused_ok(P)) return hipErrorInvalidValue;
+  JobsOf3 t;
+  for (int i = 0; i < 3; ++i) t.j[i] = J[i];
+  return digits32 ? fwd_int3_t<LimbPair>(P, t, jobs, s) : fwd_int3_t<uint16_t>(P, t, jobs, s);
+}
+
+template <int LRA, int LRB, bool WIDE>
+static hipError_t inv_crt3_inst(const Plan& P, const ConvJob* jobs, void* X, hipStream_t s) {
   int lw = col_lw(LRA + LRB, P.logC, 1);
   while (lw > 0 && col_threads(LRA + LRB, lw) > 512) --lw;
   const long C = 1l << P.logC;
@@ -326,14 +373,14 @@ static hipError_t inv_crt3_inst(const Plan& P, const ConvJob* jobs, u64* X, hipS
   if (C < (1l << lw) || col_threads(LRA + LRB, lw) > 512 || 16 * col_threads(LRA + LRB, lw) != (1 << (lw + LRA + LRB)))
     return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << (lw + LRA + LRB)) * sizeof(u32);
-  auto kern = k_col_inv_crt3<LRA, LRB>;
+  auto kern = k_col_inv_crt3<LRA, LRB, WIDE>;
   ensure_lds_attr((const void*)kern, lds);
   return launch("col_inv", kern, dim3((unsigned)(C >> lw), 1, 1), col_threads(LRA + LRB, lw), lds, s, jobs, P.logC,
                 lw, crt_consts(), X);
 }
 
-template <int LRB>
-static hipError_t inv_crt3_32_inst(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s) {
+template <int LRB, bool WIDE>
+static hipError_t inv_crt3_32_inst(const Plan& P, const ConvJob* jobs, void* X, hipStream_t s) {
   int lw = col_lw(5 + LRB, P.logC, 1);
   while (lw > 0 && col_threads(5 + LRB, lw) > 512) --lw;
   const long C = 1l << P.logC;
@@ -341,30 +388,36 @@ static hipError_t inv_crt3_32_inst(const Plan& P, const ConvJob* jobs, u64* X, h
   const int nthr = col_threads(5 + LRB, lw);
   if (C < (1l << lw) || nthr > 512 || nthr != 2 * ((1 << lw) << LRB)) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << (lw + 5 + LRB)) * sizeof(u32);
-  auto kern = k_col_inv_crt3_32<LRB>;
+  auto kern = k_col_inv_crt3_32<LRB, WIDE>;
   ensure_lds_attr((const void*)kern, lds);
   return launch("col_inv", kern, dim3((unsigned)(C >> lw), 1, 1), nthr, lds, s, jobs, P.logC, lw, crt_consts(), X);
 }
 
-hipError_t launch_col_inv_crt3(const Plan& P, const ConvJob* jobs, u64* X, hipStream_t s) {
-  if (!int3_fused_ok(P)) return hipErrorInvalidValue;
+template <bool WIDE>
+static hipError_t inv_crt3_w(const Plan& P, const ConvJob* jobs, void* X, hipStream_t s) {
   if (P.logRA == 5) {
     switch (P.logRB) {
-      case 2: return inv_crt3_32_inst<2>(P, jobs, X, s);
-      case 3: return inv_crt3_32_inst<3>(P, jobs, X, s);
-      case 4: return inv_crt3_32_inst<4>(P, jobs, X, s);
-      case 5: return inv_crt3_32_inst<5>(P, jobs, X, s);
+      case 2: return inv_crt3_32_inst<2, WIDE>(P, jobs, X, s);
+      case 3: return inv_crt3_32_inst<3, WIDE>(P, jobs, X, s);
+      case 4: return inv_crt3_32_inst<4, WIDE>(P, jobs, X, s);
+      case 5: return inv_crt3_32_inst<5, WIDE>(P, jobs, X, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (P.logRB) {
-    case 2: return inv_crt3_inst<4, 2>(P, jobs, X, s);
-    case 3: return inv_crt3_inst<4, 3>(P, jobs, X, s);
-    case 4: return inv_crt3_inst<4, 4>(P, jobs, X, s);
-    case 5: return inv_crt3_inst<4, 5>(P, jobs, X, s);
+    case 2: return inv_crt3_inst<4, 2, WIDE>(P, jobs, X, s);
+    case 3: return inv_crt3_inst<4, 3, WIDE>(P, jobs, X, s);
+    case 4: return inv_crt3_inst<4, 4, WIDE>(P, jobs, X, s);
+    case 5: return inv_crt3_inst<4, 5, WIDE>(P, jobs, X, s);
     default: break;
   }
   return hipErrorInvalidValue;
+}
+
+// X: u64 per coefficient, or (digits32) uint4 per coefficient
+hipError_t launch_col_inv_crt3(const Plan& P, const ConvJob* jobs, void* X, bool digits32, hipStream_t s) {
+  if (!int3_fused_ok(P)) return hipErrorInvalidValue;
+  return digits32 ? inv_crt3_w<true>(P, jobs, X, s) : inv_crt3_w<false>(P, jobs, X, s);
 }
 
 hipError_t launch_crt_x(const u32* r1, const u32* r2, const u32* r3, long lc, u64* X, hipStream_t s) {
@@ -390,8 +443,6 @@ __device__ __forceinline__ u32 cmap_apply(u32 f, u32 c) { return (f >> c) & 1u; 
 
 __device__ __forceinline__ u32 digit16(u64 x, int d) { return (u32)(x >> (16 * d)) & 0xFFFFu; }
 
-typedef u64 u64x2 __attribute__((ext_vector_type(2)));
-typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 
 // The thread's limbs m = m1 + i, i < kCarryPer: t_m = lo16(s_m) + hi(s_{m-1})
 // with s_m = sum_{d<4} digit_d(x_{m-d}) < 2^18 (x_k = 0 outside [0, lc)), so
@@ -540,6 +591,133 @@ hipError_t launch_carry(const u64* X, long lc, long nl, void* ws, uint16_t* out,
   hipError_t e = launch("carry_maps", k_carry_maps, (unsigned)nblk, 64, 0, s, X, lc, nl, bmap);
   if (e == hipSuccess)
     e = launch("carry_limbs", k_carry_limbs, (unsigned)nblk, kCarryThreads, 0, s, X, lc, nl, bmap, out, out16);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// carries over 32-bit words (32-bit digits): x_k < 2^85 is three 32-bit
+// words w0, w1, w2 (w2 < 2^21), and word w goes to result word k + w, so the
+// word sum S_m = w0(x_m) + w1(x_{m-1}) + w2(x_{m-2}) < 2^33 + 2^21.  With
+// hi(S) = S >> 32 <= 2, t_m = lo32(S_m) + hi(S_{m-1}) <= 2^32 + 1 again leaves
+// carries of 0 or 1: result word m is (t_m + c_m) mod 2^32 (limbs 2m and
+// 2m + 1) and c_{m+1} = (t_m + c_m) >> 32.  The carry maps and their scan are
+// those of the limbs, with 2^32 in place of 2^16.
+
+__device__ __forceinline__ u32 cmap_word(u64 t) { return (u32)(t >> 32) | ((u32)((t + 1u) >> 32) << 1); }
+
+__device__ __forceinline__ uint4 x4_at(const uint4* __restrict__ X, long lc, long k) {
+  if (k < 0 || k >= lc) return make_uint4(0u, 0u, 0u, 0u);
+  const PM_GMEM u32x4* q = (const PM_GMEM u32x4*)X + k;
+  const u32x4 v = *q;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// t_m for the thread's words m = m1 + i, i < kCarryPer
+__device__ __forceinline__ void carry_front32(const uint4* __restrict__ X, long lc, long m1, u64 (&t)[kCarryPer]) {
+  uint4 x[kCarryPer + 3];  // x_{m1 - 3 + i}
+#pragma unroll
+  for (int i = 0; i < kCarryPer + 3; ++i) x[i] = x4_at(X, lc, m1 - 3 + i);
+  u64 sprev = (u64)x[2].x + x[1].y + x[0].z;  // S_{m1 - 1}
+#pragma unroll
+  for (int i = 0; i < kCarryPer; ++i) {
+    const u64 sv = (u64)x[i + 3].x + x[i + 2].y + x[i + 1].z;
+    t[i] = (sv & 0xFFFFFFFFull) + (sprev >> 32);
+    sprev = sv;
+  }
+}
+
+__device__ __forceinline__ u64 carry_t_one32(const uint4* __restrict__ X, long lc, long m) {
+  const uint4 x0 = x4_at(X, lc, m - 3), x1 = x4_at(X, lc, m - 2), x2 = x4_at(X, lc, m - 1), x3 = x4_at(X, lc, m);
+  const u64 sv = (u64)x3.x + x2.y + x1.z;
+  const u64 sp = (u64)x2.x + x1.y + x0.z;
+  return (sv & 0xFFFFFFFFull) + (sp >> 32);
+}
+
+// Pass 1 over words: the map of each work-group's run of kCarryBlock words
+// (the map of its last word that does not propagate)
+__global__ void __launch_bounds__(64) k_carry_maps32(const uint4* __restrict__ X, long lc, long nw,
+                                                     u32* __restrict__ bmap) {
+  const int lane = threadIdx.x;
+  const long m0 = (long)blockIdx.x * kCarryBlock;
+  const long mend = min(m0 + (long)kCarryBlock, nw);
+  u32 B = kCmapIdentity;
+  for (long top = mend; top > m0; top -= 64) {
+    const long m = top - 64 + lane;
+    const u32 F = m >= m0 ? cmap_word(carry_t_one32(X, lc, m)) : kCmapIdentity;
+    const u64 nz = __ballot(F != kCmapIdentity);
+    if (nz) {
+      B = __shfl(F, 63 - __clzll((long long)nz));
+      break;
+    }
+  }
+  if (lane == 0) gst(bmap + blockIdx.x, B);
+}
+
+// Pass 2 over words: each work-group's carry-in, each thread's, and the
+// words, written as limbs 2m and 2m + 1 below nl.  out16: the output is
+// 16-byte aligned.
+__global__ void __launch_bounds__(kCarryThreads) k_carry_limbs32(const uint4* __restrict__ X, long lc, long nw,
+                                                                 long nl, const u32* __restrict__ bmap,
+                                                                 uint16_t* __restrict__ out, int out16) {
+  __shared__ int wlast[kCarryThreads / 64];
+  __shared__ u32 wmap[kCarryThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int blk = (int)blockIdx.x;
+  int last = -1;
+  for (int j = tid; j < blk; j += kCarryThreads)
+    if (gld(bmap + j) != kCmapIdentity) last = j;
+  for (int off = 32; off > 0; off >>= 1) last = max(last, __shfl_xor(last, off));
+  const long m1 = (long)blockIdx.x * kCarryBlock + (long)tid * kCarryPer;
+  u64 t[kCarryPer];
+  carry_front32(X, lc, m1, t);
+  u32 F = kCmapIdentity;
+#pragma unroll
+  for (int i = 0; i < kCarryPer; ++i) F = cmap_compose(cmap_word(t[i]), F);
+  const u32 below = wave_prefix_map(F, (1ull << lane) - 1);
+  const u32 W = wave_prefix_map(F, ~0ull);
+  if (lane == 0) {
+    wlast[w] = last;
+    wmap[w] = W;
+  }
+  __syncthreads();
+  last = wlast[0];
+#pragma unroll
+  for (int i = 1; i < kCarryThreads / 64; ++i) last = max(last, wlast[i]);
+  u32 c = last >= 0 ? cmap_apply(gld(bmap + last), 0) : 0u;
+  for (int i = 0; i < w; ++i) c = cmap_apply(wmap[i], c);
+  c = cmap_apply(below, c);
+  u32 word[kCarryPer];
+#pragma unroll
+  for (int i = 0; i < kCarryPer; ++i) {
+    const u64 v = t[i] + c;
+    word[i] = (u32)v;
+    c = (u32)(v >> 32);
+  }
+  const long l1 = 2 * m1;  // the thread's first limb
+  if (out16 && l1 + 2 * kCarryPer <= nl) {
+    PM_GMEM u32x4* o = (PM_GMEM u32x4*)(out + l1);
+#pragma unroll
+    for (int q = 0; q < kCarryPer / 4; ++q)
+      o[q] = u32x4{word[4 * q], word[4 * q + 1], word[4 * q + 2], word[4 * q + 3]};
+  } else {
+#pragma unroll
+    for (int i = 0; i < kCarryPer; ++i) {
+      if (l1 + 2 * i < nl) gst(out + l1 + 2 * i, (uint16_t)word[i]);
+      if (l1 + 2 * i + 1 < nl) gst(out + l1 + 2 * i + 1, (uint16_t)(word[i] >> 16));
+    }
+  }
+}
+
+// X: dc coefficients as uint4; nl limbs of output
+hipError_t launch_carry32(const void* X, long dc, long nl, void* ws, uint16_t* out, hipStream_t s) {
+  const long nw = (nl + 1) / 2;
+  const long nblk = (nw + kCarryBlock - 1) / kCarryBlock;
+  u32* bmap = (u32*)ws;
+  const uint4* X4 = (const uint4*)X;
+  const int out16 = ((uintptr_t)out & 15u) == 0;
+  hipError_t e = launch("carry_maps", k_carry_maps32, (unsigned)nblk, 64, 0, s, X4, dc, nw, bmap);
+  if (e == hipSuccess)
+    e = launch("carry_limbs", k_carry_limbs32, (unsigned)nblk, kCarryThreads, 0, s, X4, dc, nw, nl, bmap, out, out16);
   return e;
 }
 

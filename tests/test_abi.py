@@ -58,6 +58,8 @@ def test_host_validation_without_device(L):
     assert L.pm_poly_mul(fake, 1 << 23, fake, 1 << 23, 998244353, fake, null) == 3
     assert L.pm_int_mul(fake, 1 << 23, fake, 1 << 23, fake, null) == 3
     assert L.pm_int_mul(null, 3, fake, 3, fake, null) == 1
+    assert L.pm_int_mul_digits(fake, 3, fake, 3, 24, fake, null) == 1
+    assert L.pm_int_mul_digits(fake, 1 << 23, fake, 1 << 23, 32, fake, null) == 3
     assert L.pm_ntt(fake, fake, 1, 998244353, 0, null) == 1           # n < 2
     assert L.pm_ntt(fake, fake, 3, 998244353, 0, null) == 2           # 3 does not divide p - 1
     assert L.pm_ntt(fake, fake, 18, 2013265921, 0, null) == 2         # odd part 9: no kernels
@@ -95,6 +97,15 @@ def test_workspace_queries_on_host(L):
     assert L.pm_int_mul_workspace_query(1 << 21, 1 << 21, ctypes.byref(n)) == 0
     assert n.value >= 3 * 4 * ((1 << 22) - 1) + 2 * (1 << 22)  # three residue arrays and the limb sums
     assert L.pm_int_mul_workspace_query(1 << 23, 1 << 23, ctypes.byref(n)) == 3
+    # 32-bit digits halve the transforms: less workspace than the 16-bit limbs,
+    # and the default choice at 2^21 + 2^21 limbs
+    q = {}
+    for d in (0, 16, 32):
+        assert L.pm_int_mul_digits_workspace_query(1 << 21, 1 << 21, d, ctypes.byref(n)) == 0
+        q[d] = n.value
+    assert q[32] < q[16] and q[0] == q[32]
+    assert q[32] >= 3 * 2 * 4 * (1 << 21) + 16 * ((1 << 21) - 1)  # three primes' Ta, Tb and the 16-byte x_k
+    assert L.pm_int_mul_digits_workspace_query(1 << 21, 1 << 21, 8, ctypes.byref(n)) == 1
     # a batch needs the sum of its four-step items' workspaces (each rounded to 256 bytes)
     lens = [(100, 50), (5000, 4000), (70001, 9000), (300000, 20001), (40, 30)]
     probs = (pm.Problem * len(lens))()

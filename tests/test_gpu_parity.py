@@ -186,13 +186,15 @@ def test_maximum_sizes(gpu_lib):
         for _ in range(4):
             x = rng.randrange(2, p)
             assert op.eval_at(got, p, x) == op.eval_at(a, p, x) * op.eval_at(b, p, x) % p
-    say("case: maximum integer product")
     ia, ib = inputs.int_operands(1 << 22, tag=105)
-    ic = host(pm.int_mul(dev(ia, np.uint16), dev(ib, np.uint16)))
-    assert pm.stream_check() == 0
     q = (1 << 61) - 1
-    assert op.limbs_to_int(ic) % q == (op.limbs_to_int(ia) % q) * (op.limbs_to_int(ib) % q) % q
-    assert ic.size == 1 << 23
+    want = (op.limbs_to_int(ia) % q) * (op.limbs_to_int(ib) % q) % q
+    for digits in (32, 16):
+        say("case: maximum integer product, digits", digits)
+        ic = host(pm.int_mul(dev(ia, np.uint16), dev(ib, np.uint16), digits=digits))
+        assert pm.stream_check() == 0
+        assert op.limbs_to_int(ic) % q == want, digits
+        assert ic.size == 1 << 23
     say("case: transform of 2^24 points")
     p, g = 2013265921, inputs.PRIMES[2013265921]
     x = inputs.uniform_mod(inputs.rng_for(106), 1 << 24, p)
@@ -279,24 +281,28 @@ def test_tft_and_itft_hooks(gpu_lib, p, g):
 def test_int_mul(gpu_lib):
     pm = gpu_lib
     rng = np.random.default_rng(9)
-    for na, nb in ((1, 1), (2, 3), (64, 64), (1000, 999), (3000, 5000), (70000, 65537), (1 << 17, 1 << 17)):
-        say("case: int", na, nb)
+    for na, nb in ((1, 1), (2, 3), (64, 64), (1000, 999), (3000, 5000), (70000, 65537), (100001, 77777),
+                   (1 << 17, 1 << 17)):
         a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
         b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
-        got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16)))
-        assert np.array_equal(got, op.int_mul(a, b)), (na, nb)
+        want = op.int_mul(a, b)
+        for digits in (None, 16):
+            say("case: int", na, nb, "digits", digits)
+            got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16), digits=digits))
+            assert np.array_equal(got, want), (na, nb, digits)
     # all-0xFFFF limbs: the longest carry chains
-    for n in (100, 5000, 1 << 16):
-        say("case: int ffff", n)
-        ff = np.full(n, 0xFFFF, dtype=np.uint16)
-        got = host(pm.int_mul(dev(ff, np.uint16), dev(ff, np.uint16)))
-        assert np.array_equal(got, op.int_mul(ff, ff))
+    for n in (100, 5000, 1 << 16, 100001):
+        for digits in (None, 16):
+            say("case: int ffff", n, "digits", digits)
+            ff = np.full(n, 0xFFFF, dtype=np.uint16)
+            got = host(pm.int_mul(dev(ff, np.uint16), dev(ff, np.uint16), digits=digits))
+            assert np.array_equal(got, op.int_mul(ff, ff)), (n, digits)
     # a product of 0xFFFF..FF by 1 is one propagate chain across every run of
     # limbs (carry maps of the identity), and an output that is not 16-byte
     # aligned takes the limb-by-limb stores
     import torch
 
-    for n in (1, 4095, 4096, 4097, 20000):
+    for n in (1, 4095, 4096, 4097, 20000, 140001, 140002):
         say("case: int chain and unaligned output", n)
         ff = np.full(n, 0xFFFF, dtype=np.uint16)
         one = np.ones(1, dtype=np.uint16)
@@ -308,32 +314,76 @@ def test_int_mul(gpu_lib):
         assert np.array_equal(h[1:], op.int_mul(ff, one)) and h[0] == 0x5A5A, n
 
 
+def test_int_mul_digits32(gpu_lib):
+    """32-bit digits (pairs of limbs): forced where the plans allow it,
+    refused where they do not, exact against CPython with odd and even limb
+    counts, operands of very different lengths, carry runs that span many
+    work-groups (0xFFFF..FF times a one-limb integer: every run propagates)
+    and an output that is not 16-byte aligned."""
+    import torch
+
+    pm = gpu_lib
+    rng = np.random.default_rng(91)
+    for na, nb in ((70000, 65537), (100001, 77777), (65536, 65535), (300001, 2000), (1 << 18, 1 << 18)):
+        say("case: int digits 32", na, nb)
+        a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+        b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+        got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16), digits=32))
+        assert pm.stream_check() == 0
+        assert np.array_equal(got, op.int_mul(a, b)), (na, nb)
+    for n in (200001, 200002):
+        for m, fill in ((1, 1), (3, 0xFFFF)):
+            say("case: int digits 32 chain, unaligned output", n, m)
+            ff = np.full(n, 0xFFFF, dtype=np.uint16)
+            y = np.full(m, fill, dtype=np.uint16)
+            buf = torch.full((n + m + 1,), 0x5A5A, dtype=torch.int32).to(torch.uint16).cuda()
+            out = buf[1:]
+            pm.int_mul(dev(ff, np.uint16), dev(y, np.uint16), out=out, digits=32)
+            assert pm.stream_check() == 0
+            h = host(buf)
+            assert np.array_equal(h[1:], op.int_mul(ff, y)) and h[0] == 0x5A5A, (n, m)
+    # too short for a shared four-step plan at the digit length: refused
+    a = rng.integers(0, 1 << 16, 1000, dtype=np.uint16)
+    with pytest.raises(pm.PolymulError) as e:
+        pm.int_mul(dev(a, np.uint16), dev(a, np.uint16), digits=32)
+    assert e.value.status == 2  # PM_EUNSUPPORTED
+    with pytest.raises(pm.PolymulError) as e:
+        pm.int_mul(dev(a, np.uint16), dev(a, np.uint16), digits=24)
+    assert e.value.status == 1  # PM_EINVAL
+
+
 def test_int_mul_plans_differ(gpu_lib):
     """With one plan for the three primes, each pass runs once over the three
     products; with plans that differ (one pinned here) the products run one
-    after the other.  Both give the exact product."""
+    after the other (16-bit digits), and 32-bit digits are refused.  Both
+    give the exact product."""
     pm = gpu_lib
     rng = np.random.default_rng(19)
-    na, nb = 40000, 39000
-    lc = na + nb - 1
-    a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
-    b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
-    want = op.int_mul(a, b)
     primes = (469762049, 998244353, 167772161)
-    base = pm.plan_for(lc, primes[0])
-    assert base.kind == 2 and all(pm.plan_for(lc, p).as_tuple() == base.as_tuple() for p in primes)
-    t = list(base.as_tuple())
-    t[7] = t[7] + 1 if t[4] - t[7] > 3 else t[7] - 1  # twice or half the row threads
-    try:
-        for pinned in (None, pm.Plan(*t)):
-            say("case: int plans", pinned.as_tuple() if pinned else "shared")
-            if pinned:
-                pm.plan_cache_put(lc, primes[1], pinned)
-            got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16)))
-            assert pm.stream_check() == 0
-            assert np.array_equal(got, want)
-    finally:
-        pm.plan_cache_clear()
+    for digits, (na, nb) in ((16, (40000, 39000)), (32, (80000, 77999))):
+        lc = na + nb - 1 if digits == 16 else (na + 1) // 2 + (nb + 1) // 2 - 1
+        a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+        b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+        want = op.int_mul(a, b)
+        base = pm.plan_for(lc, primes[0])
+        assert base.kind == 2 and all(pm.plan_for(lc, p).as_tuple() == base.as_tuple() for p in primes)
+        t = list(base.as_tuple())
+        t[7] = t[7] + 1 if t[4] - t[7] > 3 else t[7] - 1  # twice or half the row threads
+        try:
+            for pinned in (None, pm.Plan(*t)):
+                say("case: int plans", digits, pinned.as_tuple() if pinned else "shared")
+                if pinned:
+                    pm.plan_cache_put(lc, primes[1], pinned)
+                if pinned and digits == 32:
+                    with pytest.raises(pm.PolymulError):
+                        pm.int_mul(dev(a, np.uint16), dev(b, np.uint16), digits=32)
+                    got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16)))  # falls back to 16-bit digits
+                else:
+                    got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16), digits=digits))
+                assert pm.stream_check() == 0
+                assert np.array_equal(got, want), (digits, pinned)
+        finally:
+            pm.plan_cache_clear()
 
 
 def test_int_mul_three_prime_column_passes(gpu_lib):
@@ -345,27 +395,30 @@ def test_int_mul_three_prime_column_passes(gpu_lib):
     rng = np.random.default_rng(29)
     primes = (469762049, 998244353, 167772161)
     try:
-        for log_rb, log_c, (na, nb) in ((2, 10, (40000, 25537)), (3, 10, (70001, 60000)), (4, 10, (131072, 100000)),
+        for log_rb, log_c, (n1, n2) in ((2, 10, (40000, 25537)), (3, 10, (70001, 60000)), (4, 10, (131072, 100000)),
                                         (5, 10, (200000, 262144))):
-            lc = na + nb - 1
-            log_l = (lc - 1).bit_length()
-            assert log_l == 4 + log_rb + log_c
-            gran = 1 << (log_l - 4)
-            plan = pm.Plan(2, log_l, 4, log_rb, log_c, (lc + gran - 1) // gran, 3, log_c - 4)
-            pm.plan_cache_clear()
-            for p in primes:
-                pm.plan_cache_put(lc, p, plan)
-            for ff in (False, True):
-                say("case: int fused", plan.as_tuple(), na, nb, "ffff" if ff else "random")
-                if ff:
-                    a = np.full(na, 0xFFFF, dtype=np.uint16)
-                    b = np.full(nb, 0xFFFF, dtype=np.uint16)
-                else:
-                    a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
-                    b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
-                got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16)))
-                assert pm.stream_check() == 0
-                assert np.array_equal(got, op.int_mul(a, b)), (plan.as_tuple(), ff)
+            # 16-bit digits: na, nb limbs; 32-bit digits: the same digit
+            # counts from 2 n1 - 1 (odd) and 2 n2 limbs
+            for digits, (na, nb) in ((16, (n1, n2)), (32, (2 * n1 - 1, 2 * n2))):
+                lc = n1 + n2 - 1
+                log_l = (lc - 1).bit_length()
+                assert log_l == 4 + log_rb + log_c
+                gran = 1 << (log_l - 4)
+                plan = pm.Plan(2, log_l, 4, log_rb, log_c, (lc + gran - 1) // gran, 3, log_c - 4)
+                pm.plan_cache_clear()
+                for p in primes:
+                    pm.plan_cache_put(lc, p, plan)
+                for ff in (False, True):
+                    say("case: int fused", digits, plan.as_tuple(), na, nb, "ffff" if ff else "random")
+                    if ff:
+                        a = np.full(na, 0xFFFF, dtype=np.uint16)
+                        b = np.full(nb, 0xFFFF, dtype=np.uint16)
+                    else:
+                        a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+                        b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+                    got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16), digits=digits))
+                    assert pm.stream_check() == 0
+                    assert np.array_equal(got, op.int_mul(a, b)), (digits, plan.as_tuple(), ff)
     finally:
         pm.plan_cache_clear()
 
@@ -382,38 +435,44 @@ def test_int_mul_first_radix_32(gpu_lib):
              (4, 10, 31, (260000, 240000), False), (5, 10, 32, (524288, 500000), True),
              (5, 11, 20, (700000, 600000), False))
     try:
-        for log_rb, log_c, ma, (na, nb), ff in cases:
-            lc = na + nb - 1
-            log_l = 5 + log_rb + log_c
-            gran = 1 << (log_l - 5)
-            assert (lc - 1).bit_length() == log_l and (lc + gran - 1) // gran == ma
-            plan = pm.Plan(2, log_l, 5, log_rb, log_c, ma, 3, log_c - 4)
-            pm.plan_cache_clear()
-            for p in primes:
-                pm.plan_cache_put(lc, p, plan)
-            for f in ((False, True) if ff else (False,)):
-                say("case: int fused radix 32", plan.as_tuple(), na, nb, "ffff" if f else "random")
-                if f:
-                    a = np.full(na, 0xFFFF, dtype=np.uint16)
-                    b = np.full(nb, 0xFFFF, dtype=np.uint16)
-                else:
-                    a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
-                    b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
-                got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16)))
-                assert pm.stream_check() == 0
-                assert np.array_equal(got, op.int_mul(a, b)), (plan.as_tuple(), f)
+        for log_rb, log_c, ma, (n1, n2), ff in cases:
+            for digits, (na, nb) in ((16, (n1, n2)), (32, (2 * n1, 2 * n2 - 1))):
+                if digits == 32 and log_c > 10:
+                    continue  # the twin at 2^21 digits: covered by the 16-bit digits
+                lc = n1 + n2 - 1
+                log_l = 5 + log_rb + log_c
+                gran = 1 << (log_l - 5)
+                assert (lc - 1).bit_length() == log_l and (lc + gran - 1) // gran == ma
+                plan = pm.Plan(2, log_l, 5, log_rb, log_c, ma, 3, log_c - 4)
+                pm.plan_cache_clear()
+                for p in primes:
+                    pm.plan_cache_put(lc, p, plan)
+                for f in ((False, True) if ff else (False,)):
+                    say("case: int fused radix 32", digits, plan.as_tuple(), na, nb, "ffff" if f else "random")
+                    if f:
+                        a = np.full(na, 0xFFFF, dtype=np.uint16)
+                        b = np.full(nb, 0xFFFF, dtype=np.uint16)
+                    else:
+                        a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+                        b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+                    got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16), digits=digits))
+                    assert pm.stream_check() == 0
+                    assert np.array_equal(got, op.int_mul(a, b)), (digits, plan.as_tuple(), f)
     finally:
         pm.plan_cache_clear()
 
 
 def test_int_mul_full_size(gpu_lib):
-    """Two random 2^21-limb integers, bit-exact against CPython's multiply."""
+    """Two random 2^21-limb integers, bit-exact against CPython's multiply,
+    with 32-bit digits (2^21-point transforms) and 16-bit digits (2^22)."""
     pm = gpu_lib
     a, b = inputs.int_operands()
-    say("case: int 2^21 x 2^21")
-    got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16)))
-    assert pm.stream_check() == 0
-    assert np.array_equal(got, op.int_mul(a, b))
+    want = op.int_mul(a, b)
+    for digits in (None, 16):
+        say("case: int 2^21 x 2^21, digits", digits)
+        got = host(pm.int_mul(dev(a, np.uint16), dev(b, np.uint16), digits=digits))
+        assert pm.stream_check() == 0
+        assert np.array_equal(got, want), digits
 
 
 def test_batch_matches_oracle(gpu_lib):
