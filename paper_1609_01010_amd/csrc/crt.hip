@@ -612,20 +612,6 @@ __device__ __forceinline__ uint4 x4_at(const uint4* __restrict__ X, long lc, lon
   return make_uint4(v.x, v.y, v.z, v.w);
 }
 
-// t_m for the thread's words m = m1 + i, i < kCarryPer
-__device__ __forceinline__ void carry_front32(const uint4* __restrict__ X, long lc, long m1, u64 (&t)[kCarryPer]) {
-  uint4 x[kCarryPer + 3];  // x_{m1 - 3 + i}
-#pragma unroll
-  for (int i = 0; i < kCarryPer + 3; ++i) x[i] = x4_at(X, lc, m1 - 3 + i);
-  u64 sprev = (u64)x[2].x + x[1].y + x[0].z;  // S_{m1 - 1}
-#pragma unroll
-  for (int i = 0; i < kCarryPer; ++i) {
-    const u64 sv = (u64)x[i + 3].x + x[i + 2].y + x[i + 1].z;
-    t[i] = (sv & 0xFFFFFFFFull) + (sprev >> 32);
-    sprev = sv;
-  }
-}
-
 __device__ __forceinline__ u64 carry_t_one32(const uint4* __restrict__ X, long lc, long m) {
   const uint4 x0 = x4_at(X, lc, m - 3), x1 = x4_at(X, lc, m - 2), x2 = x4_at(X, lc, m - 1), x3 = x4_at(X, lc, m);
   const u64 sv = (u64)x3.x + x2.y + x1.z;
@@ -653,23 +639,53 @@ __global__ void __launch_bounds__(64) k_carry_maps32(const uint4* __restrict__ X
   if (lane == 0) gst(bmap + blockIdx.x, B);
 }
 
+// LDS index of entry j of a work-group's staged coefficients: one pad word
+// per 16, so that threads reading runs of 16 consecutive entries (a stride
+// of 17 words) hit distinct banks
+__device__ __forceinline__ int carry_pad(int j) { return j + (j >> 4); }
+constexpr int kCarryStage = kCarryBlock + 3;                   // x_{m0-3} .. x_{m0+4095}
+constexpr int kCarryStageLds = kCarryStage + kCarryStage / 16 + 1;
+
 // Pass 2 over words: each work-group's carry-in, each thread's, and the
-// words, written as limbs 2m and 2m + 1 below nl.  out16: the output is
-// 16-byte aligned.
+// words, written as limbs 2m and 2m + 1 below nl.  The work-group's
+// coefficients are read once, coalesced, into LDS (their three words in
+// three arrays), and each thread forms the t_m of its run from there.
+// out16: the output is 16-byte aligned.
 __global__ void __launch_bounds__(kCarryThreads) k_carry_limbs32(const uint4* __restrict__ X, long lc, long nw,
                                                                  long nl, const u32* __restrict__ bmap,
                                                                  uint16_t* __restrict__ out, int out16) {
   __shared__ int wlast[kCarryThreads / 64];
   __shared__ u32 wmap[kCarryThreads / 64];
+  __shared__ u32 xw[3][kCarryStageLds];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int blk = (int)blockIdx.x;
+  const long m0 = (long)blk * kCarryBlock;
+  for (int j = tid; j < kCarryStage; j += kCarryThreads) {
+    const uint4 v = x4_at(X, lc, m0 - 3 + j);
+    const int q = carry_pad(j);
+    xw[0][q] = v.x;
+    xw[1][q] = v.y;
+    xw[2][q] = v.z;
+  }
   int last = -1;
   for (int j = tid; j < blk; j += kCarryThreads)
     if (gld(bmap + j) != kCmapIdentity) last = j;
   for (int off = 32; off > 0; off >>= 1) last = max(last, __shfl_xor(last, off));
-  const long m1 = (long)blockIdx.x * kCarryBlock + (long)tid * kCarryPer;
+  const long m1 = m0 + (long)tid * kCarryPer;
+  __syncthreads();
+  // entry j = m - m0 + 3 holds x_m; S_m = w0(x_m) + w1(x_{m-1}) + w2(x_{m-2})
   u64 t[kCarryPer];
-  carry_front32(X, lc, m1, t);
+  {
+    const int j0 = tid * kCarryPer + 3;
+    u64 sprev = (u64)xw[0][carry_pad(j0 - 1)] + xw[1][carry_pad(j0 - 2)] + xw[2][carry_pad(j0 - 3)];
+#pragma unroll
+    for (int i = 0; i < kCarryPer; ++i) {
+      const int j = j0 + i;
+      const u64 sv = (u64)xw[0][carry_pad(j)] + xw[1][carry_pad(j - 1)] + xw[2][carry_pad(j - 2)];
+      t[i] = (sv & 0xFFFFFFFFull) + (sprev >> 32);
+      sprev = sv;
+    }
+  }
   u32 F = kCmapIdentity;
 #pragma unroll
   for (int i = 0; i < kCarryPer; ++i) F = cmap_compose(cmap_word(t[i]), F);
