@@ -63,6 +63,8 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
   const long ze = is_limb_pair<TIn>() ? (z + 1) >> 1 : z;
   uint2 one = make_uint2(0u, 0u);
   if constexpr (FROM_GLOBAL && is_limb_pair<TIn>()) one = cld(T.pf + 1);
+  // limb pairs in one 32-bit load when the limbs are 4-byte aligned
+  const bool w32 = is_limb_pair<TIn>() && (((uintptr_t)in & 3u) == 0);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int task = tid + k * nthr;
@@ -78,9 +80,15 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
         if constexpr (FROM_GLOBAL && is_limb_pair<TIn>()) {
           const uint16_t* __restrict__ l = (const uint16_t*)in;
           const long i0 = 2 * (C * row + col0 + c);
-          const u32 lo = i0 < z ? (u32)gld(l + i0) : 0u;
-          const u32 hi = i0 + 1 < z ? (u32)gld(l + i0 + 1) : 0u;
-          x[s] = A.mul(lo | (hi << 16), one);
+          u32 d;
+          if (w32 && i0 + 1 < z) {
+            d = gld((const u32*)l + (i0 >> 1));
+          } else {
+            const u32 lo = i0 < z ? (u32)gld(l + i0) : 0u;
+            const u32 hi = i0 + 1 < z ? (u32)gld(l + i0 + 1) : 0u;
+            d = lo | (hi << 16);
+          }
+          x[s] = A.mul(d, one);
         } else if constexpr (FROM_GLOBAL) {
           const long pos = C * row + col0 + c;
           x[s] = pos < z ? (u32)gld(in + pos) : 0u;

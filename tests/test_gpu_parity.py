@@ -342,6 +342,17 @@ def test_int_mul_digits32(gpu_lib):
             assert pm.stream_check() == 0
             h = host(buf)
             assert np.array_equal(h[1:], op.int_mul(ff, y)) and h[0] == 0x5A5A, (n, m)
+    # operands that are not 4-byte aligned: the limb pairs are loaded one limb at a time
+    for na, nb in ((90001, 80000), (80000, 90001)):
+        say("case: int digits 32, operands at odd limb offsets", na, nb)
+        a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+        b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+        ta = torch.from_numpy(np.concatenate([[7], a]).astype(np.uint16)).cuda()[1:]
+        tb = torch.from_numpy(np.concatenate([[7], b]).astype(np.uint16)).cuda()[1:]
+        assert ta.data_ptr() % 4 == 2 and tb.data_ptr() % 4 == 2
+        got = host(pm.int_mul(ta, tb, digits=32))
+        assert pm.stream_check() == 0
+        assert np.array_equal(got, op.int_mul(a, b)), (na, nb)
     # too short for a shared four-step plan at the digit length: refused
     a = rng.integers(0, 1 << 16, 1000, dtype=np.uint16)
     with pytest.raises(pm.PolymulError) as e:
