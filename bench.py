@@ -517,6 +517,43 @@ def standalone_transform(pm, torch, dev, copy_bw, n_calls=40):
     return out
 
 
+def int_product(pm, torch, dev, reps=5):
+    """The three-primes product of two 2^21-limb integers (config 3), with
+    both digit sizes; per-kernel durations from a traced call."""
+    from paper_1609_01010_amd import inputs
+
+    out = {}
+    # the three-primes product of two 2^21-limb integers: pm_int_mul's own
+    # choice (32-bit digits, 2^21-point transforms), and the 16-bit limbs as
+    # digits (2^22-point transforms)
+    ia, ib = inputs.int_operands()
+    tia, tib = torch.from_numpy(ia).to(dev), torch.from_numpy(ib).to(dev)
+    ic = torch.empty(ia.size + ib.size, dtype=torch.uint16, device=dev)
+    q = (1 << 61) - 1
+    want = (limbs_value(ia) % q) * (limbs_value(ib) % q) % q
+    for key, digits in (("int_mul_2^21x2^21_limbs", None), ("int_mul_2^21x2^21_limbs_digits16", 16)):
+        pm.int_mul(tia, tib, out=ic, digits=digits)
+        ms = time_calls(torch, lambda: pm.int_mul(tia, tib, out=ic, digits=digits), reps)
+        pm.trace_reset()
+        pm.trace_enable(True)
+        pm.int_mul(tia, tib, out=ic, digits=digits)
+        torch.cuda.synchronize()
+        pm.trace_enable(False)
+        ik = {}
+        for name in pm.trace_names():
+            tot, n = pm.trace_query(name)
+            ik[name] = 1e3 * tot
+        pm.trace_reset()
+        got = ic.cpu().numpy()
+        ok = limbs_value(got) % q == want
+        out[key] = {"digits": "32-bit (pairs of limbs), 2^21-point transforms" if digits is None
+                    else "16-bit limbs, 2^22-point transforms",
+                    "ms": ms, "limbs_per_s": got.size / (ms * 1e-3), "kernels_us": ik,
+                    "check": "product mod 2^61-1 matches" if ok else "MISMATCH"}
+    del tia, tib, ic
+    return out
+
+
 def large_products(pm, torch, dev, args):
     """The two plain large products over Z/2013265921Z (2^21 x 2^21 through
     L = 2^22, and 600001 x 400000 with 10^6 outputs through L = 2^20), with
@@ -617,34 +654,7 @@ def extra_configs(pm, torch, dev, copy_bw, args, reps=5):
 
     out["plain_large_products"] = large_products(pm, torch, dev, args)
 
-    # the three-primes product of two 2^21-limb integers: pm_int_mul's own
-    # choice (32-bit digits, 2^21-point transforms), and the 16-bit limbs as
-    # digits (2^22-point transforms)
-    ia, ib = inputs.int_operands()
-    tia, tib = torch.from_numpy(ia).to(dev), torch.from_numpy(ib).to(dev)
-    ic = torch.empty(ia.size + ib.size, dtype=torch.uint16, device=dev)
-    q = (1 << 61) - 1
-    want = (limbs_value(ia) % q) * (limbs_value(ib) % q) % q
-    for key, digits in (("int_mul_2^21x2^21_limbs", None), ("int_mul_2^21x2^21_limbs_digits16", 16)):
-        pm.int_mul(tia, tib, out=ic, digits=digits)
-        ms = time_calls(torch, lambda: pm.int_mul(tia, tib, out=ic, digits=digits), reps)
-        pm.trace_reset()
-        pm.trace_enable(True)
-        pm.int_mul(tia, tib, out=ic, digits=digits)
-        torch.cuda.synchronize()
-        pm.trace_enable(False)
-        ik = {}
-        for name in pm.trace_names():
-            tot, n = pm.trace_query(name)
-            ik[name] = 1e3 * tot
-        pm.trace_reset()
-        got = ic.cpu().numpy()
-        ok = limbs_value(got) % q == want
-        out[key] = {"digits": "32-bit (pairs of limbs), 2^21-point transforms" if digits is None
-                    else "16-bit limbs, 2^22-point transforms",
-                    "ms": ms, "limbs_per_s": got.size / (ms * 1e-3), "kernels_us": ik,
-                    "check": "product mod 2^61-1 matches" if ok else "MISMATCH"}
-    del tia, tib, ic
+    out.update(int_product(pm, torch, dev, reps))
 
     out.update(standalone_transform(pm, torch, dev, copy_bw))
 
@@ -711,6 +721,9 @@ def main():
     ap.add_argument("--transform-only", action="store_true",
                     help="only the forward transforms of 2^22 points (the command their counters are taken with); "
                          "prints their timings, not the headline line")
+    ap.add_argument("--int-only", action="store_true",
+                    help="only the three-primes integer product of two 2^21-limb integers, both digit sizes (the "
+                         "command its profile is taken with); prints its timings, not the headline line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 256 MiB three times (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -746,6 +759,9 @@ def main():
         return
     if args.large_only:
         print(json.dumps(large_products(pm, torch, dev, args)), flush=True)
+        return
+    if args.int_only:
+        print(json.dumps(int_product(pm, torch, dev)), flush=True)
         return
 
     if args.headline_only:
