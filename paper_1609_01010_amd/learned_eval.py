@@ -27,6 +27,7 @@ or below 5%, and the gain of the learned policy over the default one
 use p = 2013265921 (transforms up to 2^27 exist for it).
 
     python -m paper_1609_01010_amd.learned_eval --out DIR [--reps 5] [--quick]
+    python -m paper_1609_01010_amd.learned_eval --out DIR --batch-families
 
 With --model PATH, steps 1 and 2 are skipped and the given cost model (for
 instance the shipped data/cost_model.txt) is evaluated.  With --budget S the
@@ -222,6 +223,97 @@ def batch_policies(pm, reps: int):
     return out
 
 
+def batch_families(pm, model: str, out_dir: str, n_classes: int = 3, k: int = 30):
+    """The learned batch plans against a search on the whole batch: the 4096
+    uneven products run with the model's plans (learned policy, batch
+    context); then for each of the n_classes four-step classes with the most
+    points (transform length and prime range), every plan family of the
+    class (each candidate shape of its longest product, each product taking
+    that shape's fewest kept blocks) is put in the plan cache for the class's
+    products, the other classes keeping the model's plans, and the whole
+    batch is timed (median of three groups of k back-to-back launches)."""
+    import collections
+
+    import torch
+
+    items = inputs.batch_uneven()
+    lcs = [it.a.size + it.b.size - 1 for it in items]
+    dev = torch.device("cuda")
+    probs = [(torch.from_numpy(it.a).to(dev), torch.from_numpy(it.b).to(dev), it.p) for it in items]
+    outs = [torch.empty(lc, dtype=torch.uint32, device=dev) for lc in lcs]
+    pm.model_load(model)
+    pm.set_policy(pm.POLICY_LEARNED)
+    pm.plan_cache_clear()
+    pb = pm.PreparedBatch(probs, outs=outs)
+    pb.run()
+    torch.cuda.synchronize()
+    plans = pm.batch_plans_used(len(items))
+
+    def timed():
+        pb.run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(k):
+                pb.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / k)
+        return float(np.median(ts))
+
+    base = timed()
+    log(f"model's batch plans: {base:.4f} ms")
+    cls = collections.defaultdict(list)
+    for i, (it, P0) in enumerate(zip(items, plans)):
+        if P0.kind == 2:
+            cls[(P0.log_l, it.p != P)].append(i)
+    top = sorted(cls, key=lambda key: -(len(cls[key]) << key[0]))[:n_classes]
+    res = {"model_ms": base, "classes": []}
+    for key in top:
+        idx = cls[key]
+        P0 = plans[idx[0]]
+        fam0 = (P0.log_ra, P0.log_rb, P0.log_c, P0.lq, P0.lnt)
+        i_max = max(idx, key=lambda i: lcs[i])
+        fams = []
+        for c in pm.plan_candidates(lcs[i_max], items[i_max].p, general_radix=False):
+            f = (c.log_ra, c.log_rb, c.log_c, c.lq, c.lnt)
+            if c.kind == 2 and f not in fams:
+                fams.append(f)
+        rows = []
+        for f in fams:
+            pm.plan_cache_clear()
+            ok = True
+            for i in idx:
+                best = None
+                for c in pm.plan_candidates(lcs[i], items[i].p, general_radix=False):
+                    if c.kind == 2 and (c.log_ra, c.log_rb, c.log_c, c.lq, c.lnt) == f and (best is None or
+                                                                                             c.ma < best.ma):
+                        best = c
+                if best is None:
+                    ok = False
+                    break
+                pm.plan_cache_put(lcs[i], items[i].p, best)
+            if ok:
+                rows.append({"family": list(f), "ms": timed(), "model": f == fam0})
+        pm.plan_cache_clear()
+        best = min(rows, key=lambda r: r["ms"])
+        entry = {"log_l": key[0], "prime_below_2^30": key[1], "products": len(idx), "model_family": list(fam0),
+                 "best_family": best["family"], "best_ms": best["ms"], "families": rows}
+        res["classes"].append(entry)
+        log(f"class L = 2^{key[0]} ({'p < 2^30' if key[1] else 'p = 2013265921'}, {len(idx)} products): model "
+            f"{fam0}, best {tuple(best['family'])} at {best['ms']:.4f} ms, {len(rows)} families")
+    pm.set_policy(pm.POLICY_DEFAULT)
+    if pm.stream_check() != 0:
+        raise SystemExit("device error in the batch")
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "batch_families.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", required=True)
@@ -230,7 +322,16 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true", help="30 + 20 random lengths instead of 300 + 200")
     ap.add_argument("--model", help="evaluate this cost model (no tuning of the training lengths, no training)")
     ap.add_argument("--budget", type=float, help="seconds for the held-out loop; resume by running again")
+    ap.add_argument("--batch-families", action="store_true",
+                    help="only the whole-batch check of the model's batch plans (--model, default: the shipped "
+                         "cost model): every plan family of the three largest classes timed on the whole batch")
     a = ap.parse_args(argv)
+    if a.batch_families:
+        import paper_1609_01010_amd as pm
+
+        model = a.model or os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "cost_model.txt")
+        batch_families(pm, model, a.out)
+        return 0
     if run(a.out, reps=a.reps, steps=a.steps, quick=a.quick, model=a.model, budget=a.budget) is None:
         return 3
     return 0
