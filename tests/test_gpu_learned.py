@@ -180,6 +180,48 @@ def test_learned_batch_policy_stays_exact(gpu_lib):
         pm.plan_cache_clear()
 
 
+def test_learned_policy_integer_product_in_caller_workspace(gpu_lib):
+    """Under the learned policy the integer product's plans come from the cost
+    model at call time, so its workspace query returns the most any candidate
+    plan and digit size could need: a caller workspace of exactly that size
+    runs the product (whatever digits the model's plans allow), exact against
+    CPython, and so does one sized for forced 16-bit digits."""
+    import os
+
+    import torch
+
+    pm = gpu_lib
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pm.model_load(os.path.join(root, "paper_1609_01010_amd", "data", "cost_model.txt"))
+    rng = np.random.default_rng(117)
+    s = torch.cuda.Stream()
+    pm.plan_cache_clear()
+    pm.set_policy(pm.POLICY_LEARNED)
+    try:
+        for na, nb in ((5000, 3001), (100001, 77777), (1 << 18, (1 << 18) - 3)):
+            a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+            b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+            want = op.int_mul(a, b)
+            for digits in (None, 16):
+                need = pm.int_mul_workspace_query(na, nb, digits=digits)
+                say("case: learned int product in a caller workspace", na, nb, digits, need)
+                buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+                torch.cuda.synchronize()
+                pm.set_workspace(buf, stream=s)
+                try:
+                    with torch.cuda.stream(s):
+                        ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+                        c = pm.int_mul(ta, tb, stream=s, digits=digits)
+                    s.synchronize()
+                finally:
+                    pm.set_workspace(None, stream=s)
+                assert pm.stream_check() == 0
+                assert np.array_equal(c.cpu().numpy(), want), (na, nb, digits)
+    finally:
+        pm.set_policy(pm.POLICY_DEFAULT)
+        pm.plan_cache_clear()
+
+
 def test_learned_policy_trains_predicts_and_stays_exact(gpu_lib, tmp_path):
     """A small version of the learned-plan experiment: tune a few lengths,
     train the network on the device, pick plans for unseen lengths; the
