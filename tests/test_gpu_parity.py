@@ -448,8 +448,6 @@ def test_int_mul_first_radix_32(gpu_lib):
     try:
         for log_rb, log_c, ma, (n1, n2), ff in cases:
             for digits, (na, nb) in ((16, (n1, n2)), (32, (2 * n1, 2 * n2 - 1))):
-                if digits == 32 and log_c > 10:
-                    continue  # the twin at 2^21 digits: covered by the 16-bit digits
                 lc = n1 + n2 - 1
                 log_l = 5 + log_rb + log_c
                 gran = 1 << (log_l - 5)
