@@ -29,9 +29,22 @@ namespace {
 
 typedef std::tuple<int, int, int, int, int, int, int, int> ClassKey;  // kind, L, RA, RB, C, lq, lnt, lazy
 
+// The one-work-group products of the lengths the several-length kernel
+// takes form one class per value range (L = 0 in the key): one launch for
+// all of them instead of one per length and first radix.
 ClassKey class_key(const Plan& P, bool lazy) {
+  if (lds_multi_ok(P)) return ClassKey(P.kind, 0, 0, 0, 0, 0, 0, lazy ? 1 : 0);
   return ClassKey(P.kind, P.logL, P.logRA, P.logRB, P.logC, P.lq, P.kind == PLAN_FOURSTEP ? plan_row_lnt(P) : 0,
                   lazy ? 1 : 0);
+}
+
+// the launches of one class (the several-length one-work-group class has
+// its own kernel)
+pm_status launch_run(const ClassKey& key, const Plan& P, bool lazy, const JobRef& jr, int njobs, int max_rows,
+                     hipStream_t s) {
+  if (std::get<0>(key) == PLAN_LDS && std::get<1>(key) == 0)
+    return launch_lds_conv_multi(lazy, jr, njobs, s) == hipSuccess ? PM_OK : PM_EDEVICE;
+  return launch_class(P, lazy, 0, jr, njobs, max_rows, s);
 }
 
 struct ClassRun {
@@ -49,6 +62,10 @@ struct ClassRun {
 // units cannot fill it: its time is the latency of its rounds, and it runs
 // beside the large classes rather than after them.
 constexpr long kSmallClassWgs = 256;
+
+// latency-bound classes, which start first on branch 0 beside the large
+// ones: fewer work-groups than compute units, or the one-work-group products
+bool small_class(const ClassRun& r) { return r.wgs < kSmallClassWgs || r.plan.kind == PLAN_LDS; }
 
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
@@ -134,11 +151,11 @@ pm_status capture_graph(BatchState* B, const std::vector<ClassRun>& runs, const 
   std::vector<size_t> order;
   for (int pass = 0; pass < 2; ++pass)
     for (size_t k = 0; k < runs.size(); ++k)
-      if ((runs[k].wgs < kSmallClassWgs) == (pass == 0)) order.push_back(k);
+      if (small_class(runs[k]) == (pass == 0)) order.push_back(k);
   for (size_t k : order) {
     if (st != PM_OK) break;
     const ClassRun& r = runs[k];
-    const size_t bi = r.wgs < kSmallClassWgs
+    const size_t bi = small_class(r)
                           ? 0
                           : (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
     load[bi] += r.work;
@@ -150,7 +167,7 @@ pm_status capture_graph(BatchState* B, const std::vector<ClassRun>& runs, const 
     JobRef jr;
     memset(&jr.one, 0, sizeof(jr.one));
     jr.many = djobs + r.first;
-    st = launch_class(r.plan, r.lazy, 0, jr, r.count, r.max_rows, bs);
+    st = launch_run(r.key, r.plan, r.lazy, jr, r.count, r.max_rows, bs);
   }
   for (size_t bi = 0; bi < B->branches.size(); ++bi) {
     if (!used[bi]) continue;
@@ -257,7 +274,7 @@ static pm_status launch_batch(GraphEntry* G, const std::vector<ClassRun>& runs, 
       JobRef jr;
       memset(&jr.one, 0, sizeof(jr.one));
       jr.many = G->djobs + r.first;
-      const pm_status st = launch_class(r.plan, r.lazy, 0, jr, r.count, r.max_rows, s);
+      const pm_status st = launch_run(r.key, r.plan, r.lazy, jr, r.count, r.max_rows, s);
       if (st) return st;
     }
     return PM_OK;
@@ -354,6 +371,9 @@ static pm_status batch_run(DevCtx* c, BatchState* B, const pm_problem* probs, si
   jobs.reserve(count);
   char* ws = (char*)wsp;
   for (auto& kv : groups) {
+    if (std::get<0>(kv.first) == PLAN_LDS && std::get<1>(kv.first) == 0)  // longest first: the tail is short
+      std::stable_sort(kv.second.begin(), kv.second.end(),
+                       [&](size_t x, size_t y) { return plans[x].logL > plans[y].logL; });
     ClassRun r;
     r.key = kv.first;
     r.plan = plans[kv.second[0]];

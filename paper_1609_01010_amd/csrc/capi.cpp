@@ -319,6 +319,8 @@ pm_status make_job(DevCtx* c, const Plan& P, int pidx, const void* a, long la, c
   J->Tb = Tb;
   J->ma = P.ma;
   J->rows = P.ma << P.logRB;
+  J->logL = P.logL;
+  J->logRA = P.logRA;
   J->mp = modp_of(PI);
   J->T = c->tabs[pidx];
   J->err = c->errflag;

@@ -18,6 +18,14 @@ PM_DECL2(launch_row_xform, const Plan&, const u32*, u32*, long, int, int, const 
 PM_DECL2(launch_lds_xform, const Plan&, const u32*, long, u32*, long, int, int, int, const PrimeTables&, uint2, int*,
          hipStream_t)
 #undef PM_DECL2
+hipError_t launch_lds_conv_multi_lazy0(const JobRef&, int, hipStream_t);
+hipError_t launch_lds_conv_multi_lazy1(const JobRef&, int, hipStream_t);
+bool lds_multi_ok_lazy1(const Plan&);
+
+hipError_t launch_lds_conv_multi(bool lazy, const JobRef& jr, int njobs, hipStream_t s) {
+  return lazy ? launch_lds_conv_multi_lazy1(jr, njobs, s) : launch_lds_conv_multi_lazy0(jr, njobs, s);
+}
+bool lds_multi_ok(const Plan& P) { return lds_multi_ok_lazy1(P); }
 
 hipError_t launch_lds_conv(const Plan& P, bool lazy, const JobRef& jr, int njobs, hipStream_t s) {
   return lazy ? launch_lds_conv_lazy1(P, jr, njobs, s) : launch_lds_conv_lazy0(P, jr, njobs, s);

@@ -212,6 +212,10 @@ hipError_t launch_mixed_perm(const u32* in, int q, long M, u32* out, int to_flat
 // Convolution launches over njobs jobs of one plan class (jobs in jr: the
 // single inline job, or a device array indexed by blockIdx.z).
 hipError_t launch_lds_conv(const Plan& P, bool lazy, const JobRef& jr, int njobs, hipStream_t s);
+// one launch over one-work-group products of several lengths (each job's
+// logL and logRA pick its body); lds_multi_ok: the plans it takes
+hipError_t launch_lds_conv_multi(bool lazy, const JobRef& jr, int njobs, hipStream_t s);
+bool lds_multi_ok(const Plan& P);
 // four-step passes; in_type 0 = u32 inputs, 1 = u16; nops = 1 transforms a only
 hipError_t launch_col_fwd(const Plan& P, bool lazy, int in_type, int nops, const JobRef& jr, int njobs,
                           hipStream_t s);

@@ -36,6 +36,8 @@ struct ConvJob {
   // operands / writes the result (s = C for four-step plans, 1 otherwise)
   const uint2* twf;
   const uint2* twi;
+  int logL;        // the plan's transform length and first radix (log2): the
+  int logRA;       // one-work-group kernel that runs products of several lengths
 };
 
 struct JobRef {

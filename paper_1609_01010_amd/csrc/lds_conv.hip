@@ -36,17 +36,15 @@ constexpr bool kLazy = PM_LAZY != 0;
 // output blocks; the remaining rounds transform those blocks in LDS.
 
 template <int LN, int LRA, int LQ, bool LAZY, bool TWIST>
-__global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
+__device__ __forceinline__ void lds_conv_body(const ConvJob& J, u32* sm) {
   constexpr int N = 1 << LN;
   constexpr int RA = 1 << LRA;
   constexpr int LS = LN - LRA;
   constexpr int S = 1 << LS;
-  const ConvJob J = load_job(jr);
   const u32* __restrict__ a = (const u32*)J.a;
   const u32* __restrict__ b = (const u32*)J.b;
   const int la = (int)J.la, lb = (int)J.lb, lc = (int)J.lc, ma = J.ma;
   const PrimeTables& T = J.T;
-  extern __shared__ u32 sm[];
   u32* sa = sm;
   u32* sb = sm + N;
   const Arith<LAZY> A(J.mp);
@@ -118,6 +116,53 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
       if (s < ma && pos < lc) gst(c + pos, A.canon(TWIST ? A.mul(x[s], cld(J.twi + pos)) : x[s]));
     }
   }
+}
+
+template <int LN, int LRA, int LQ, bool LAZY, bool TWIST>
+__global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
+  extern __shared__ u32 sm[];
+  const ConvJob J = load_job(jr);
+  lds_conv_body<LN, LRA, LQ, LAZY, TWIST>(J, sm);
+}
+
+// The same for a batch's products of several lengths up to 2^kMultiMaxLN in
+// one launch: work-group z takes job z and runs the body of its own length
+// and first radix (from the descriptor); the work-group has the threads and
+// LDS of the longest.
+constexpr int kMultiMaxLN = 11;
+constexpr int kMultiThreads = 128;
+
+template <bool LAZY>
+__global__ void __launch_bounds__(kMultiThreads) k_lds_conv_multi(JobRef jr) {
+  extern __shared__ u32 sm[];
+  const ConvJob J = load_job(jr);
+  switch (J.logL * 8 + J.logRA) {
+#define PM_BODY(ln, ra)                                  \
+  case ln * 8 + ra:                                      \
+    lds_conv_body<ln, ra, 4, LAZY, false>(J, sm);        \
+    break;
+    PM_BODY(6, 3) PM_BODY(6, 4) PM_BODY(6, 5)
+    PM_BODY(7, 3) PM_BODY(7, 4) PM_BODY(7, 5)
+    PM_BODY(8, 3) PM_BODY(8, 4) PM_BODY(8, 5)
+    PM_BODY(9, 3) PM_BODY(9, 4) PM_BODY(9, 5)
+    PM_BODY(10, 3) PM_BODY(10, 4) PM_BODY(10, 5)
+    PM_BODY(11, 3) PM_BODY(11, 4) PM_BODY(11, 5)
+#undef PM_BODY
+    default:
+      break;
+  }
+}
+
+// whether a one-work-group plan may run in the several-length launch
+bool PM_SUFFIX(lds_multi_ok)(const Plan& P) {
+  return P.kind == PLAN_LDS && !P.twist && P.logL >= 6 && P.logL <= kMultiMaxLN && P.logRA >= 3 && P.logRA <= 5;
+}
+
+hipError_t PM_SUFFIX(launch_lds_conv_multi)(const JobRef& jr, int njobs, hipStream_t s) {
+  const size_t lds = 2 * ((size_t)1 << kMultiMaxLN) * sizeof(u32);
+  auto kern = k_lds_conv_multi<kLazy>;
+  ensure_lds_attr((const void*)kern, lds);
+  return launch("lds_conv", kern, dim3(1, 1, njobs), kMultiThreads, lds, s, jr);
 }
 
 // threads of the one-work-group convolution of length 2^ln: 16 values per
