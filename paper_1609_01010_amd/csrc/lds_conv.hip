@@ -125,10 +125,12 @@ __global__ void __launch_bounds__(1024) k_lds_conv(JobRef jr) {
   lds_conv_body<LN, LRA, LQ, LAZY, TWIST>(J, sm);
 }
 
-// The same for a batch's products of several lengths up to 2^kMultiMaxLN in
-// one launch: work-group z takes job z and runs the body of its own length
-// and first radix (from the descriptor); the work-group has the threads and
-// LDS of the longest.
+// The same for a batch's products of several lengths up to 2^kMultiMaxLN,
+// first radix 8 (the default and the tuner's usual pick there), in one
+// launch: work-group z takes job z and runs the body of its own length (from
+// the descriptor); the work-group has the threads and LDS of the longest.
+// (The bodies of the larger first radices carry the truncated inverse for
+// every count of kept blocks, whose registers would spill here.)
 constexpr int kMultiMaxLN = 11;
 constexpr int kMultiThreads = 128;
 
@@ -136,17 +138,12 @@ template <bool LAZY>
 __global__ void __launch_bounds__(kMultiThreads) k_lds_conv_multi(JobRef jr) {
   extern __shared__ u32 sm[];
   const ConvJob J = load_job(jr);
-  switch (J.logL * 8 + J.logRA) {
-#define PM_BODY(ln, ra)                                  \
-  case ln * 8 + ra:                                      \
-    lds_conv_body<ln, ra, 4, LAZY, false>(J, sm);        \
+  switch (J.logL) {
+#define PM_BODY(ln)                                     \
+  case ln:                                              \
+    lds_conv_body<ln, 3, 4, LAZY, false>(J, sm);        \
     break;
-    PM_BODY(6, 3) PM_BODY(6, 4) PM_BODY(6, 5)
-    PM_BODY(7, 3) PM_BODY(7, 4) PM_BODY(7, 5)
-    PM_BODY(8, 3) PM_BODY(8, 4) PM_BODY(8, 5)
-    PM_BODY(9, 3) PM_BODY(9, 4) PM_BODY(9, 5)
-    PM_BODY(10, 3) PM_BODY(10, 4) PM_BODY(10, 5)
-    PM_BODY(11, 3) PM_BODY(11, 4) PM_BODY(11, 5)
+    PM_BODY(6) PM_BODY(7) PM_BODY(8) PM_BODY(9) PM_BODY(10) PM_BODY(11)
 #undef PM_BODY
     default:
       break;
@@ -155,7 +152,7 @@ __global__ void __launch_bounds__(kMultiThreads) k_lds_conv_multi(JobRef jr) {
 
 // whether a one-work-group plan may run in the several-length launch
 bool PM_SUFFIX(lds_multi_ok)(const Plan& P) {
-  return P.kind == PLAN_LDS && !P.twist && P.logL >= 6 && P.logL <= kMultiMaxLN && P.logRA >= 3 && P.logRA <= 5;
+  return P.kind == PLAN_LDS && !P.twist && P.logL >= 6 && P.logL <= kMultiMaxLN && P.logRA == 3;
 }
 
 hipError_t PM_SUFFIX(launch_lds_conv_multi)(const JobRef& jr, int njobs, hipStream_t s) {
