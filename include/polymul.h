@@ -157,7 +157,9 @@ typedef struct {
  * Batch of independent products (each as pm_poly_mul), of uneven lengths and
  * mixed primes.  `probs` is a HOST array of `count` <= 65535 problems.  The
  * products are grouped into classes of equal plan (those of at most 64
- * outputs, computed by their defining sums, form one class); each class runs
+ * outputs, computed by their defining sums, form one class, and so do, per
+ * value range of the prime, the one-work-group products of 2^6 .. 2^11
+ * points with first radix 8); each class runs
  * one launch per pass over all its products, and the classes are captured
  * into one hipGraph, cached by the batch's class signature.  A call whose problems
  * have the same lengths and primes, in order, as the previous call on the
