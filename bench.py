@@ -483,19 +483,22 @@ def standalone_transform(pm, torch, dev, copy_bw, n_calls=40):
     out = {}
     for pp in (2013265921, 998244353):
         g = inputs.PRIMES[pp]
+        # 16 inputs and 16 outputs of 16 MiB each (512 MiB, twice the MALL),
+        # rotated, so every transform reads and writes HBM
+        nb = 16
         xs = [torch.from_numpy(inputs.uniform_mod(inputs.rng_for((140, pp % 1000, k)), N, pp)).to(dev)
-              for k in range(8)]
-        ys = [torch.empty(N, dtype=torch.uint32, device=dev) for _ in range(8)]
+              for k in range(nb)]
+        ys = [torch.empty(N, dtype=torch.uint32, device=dev) for _ in range(nb)]
 
         def fwd(i):
-            pm.tft(xs[i % 8], N, N, pp, out=ys[i % 8])
+            pm.tft(xs[i % nb], N, N, pp, out=ys[i % nb])
 
-        for i in range(8):
+        for i in range(nb):
             fwd(i)
         ms = time_loop(torch, fwd, n_calls)
         pm.trace_reset()
         pm.trace_enable(True)
-        for i in range(8):
+        for i in range(nb):
             fwd(i)
         torch.cuda.synchronize()
         pm.trace_enable(False)
