@@ -38,12 +38,13 @@ ClassKey class_key(const Plan& P, bool lazy) {
                   lazy ? 1 : 0);
 }
 
+bool multi_lds_class(const ClassKey& k) { return std::get<0>(k) == PLAN_LDS && std::get<1>(k) == 0; }
+
 // the launches of one class (the several-length one-work-group class has
 // its own kernel)
 pm_status launch_run(const ClassKey& key, const Plan& P, bool lazy, const JobRef& jr, int njobs, int max_rows,
                      hipStream_t s) {
-  if (std::get<0>(key) == PLAN_LDS && std::get<1>(key) == 0)
-    return launch_lds_conv_multi(lazy, jr, njobs, s) == hipSuccess ? PM_OK : PM_EDEVICE;
+  if (multi_lds_class(key)) return launch_lds_conv_multi(lazy, jr, njobs, s) == hipSuccess ? PM_OK : PM_EDEVICE;
   return launch_class(P, lazy, 0, jr, njobs, max_rows, s);
 }
 
@@ -64,8 +65,9 @@ struct ClassRun {
 constexpr long kSmallClassWgs = 256;
 
 // latency-bound classes, which start first on branch 0 beside the large
-// ones: fewer work-groups than compute units, or the one-work-group products
-bool small_class(const ClassRun& r) { return r.wgs < kSmallClassWgs || r.plan.kind == PLAN_LDS; }
+// ones: fewer work-groups than compute units, or the several-length class of
+// one-work-group products (at most 2^11 points each)
+bool small_class(const ClassRun& r) { return r.wgs < kSmallClassWgs || multi_lds_class(r.key); }
 
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
@@ -371,7 +373,7 @@ static pm_status batch_run(DevCtx* c, BatchState* B, const pm_problem* probs, si
   jobs.reserve(count);
   char* ws = (char*)wsp;
   for (auto& kv : groups) {
-    if (std::get<0>(kv.first) == PLAN_LDS && std::get<1>(kv.first) == 0)  // longest first: the tail is short
+    if (multi_lds_class(kv.first))  // longest first: the tail is short
       std::stable_sort(kv.second.begin(), kv.second.end(),
                        [&](size_t x, size_t y) { return plans[x].logL > plans[y].logL; });
     ClassRun r;
