@@ -503,6 +503,42 @@ def test_batch_matches_oracle(gpu_lib):
             assert np.array_equal(host(c), op.poly_mul(it.a, it.b, it.p))
 
 
+def test_batch_one_work_group_lengths_share_a_launch(gpu_lib):
+    """The batch's one-work-group products of 2^6 .. 2^11 points (default
+    plans, first radix 8) run as one launch per value range of the prime,
+    whatever their lengths: under tracing (the classes one after the other)
+    a batch with lengths from 65 to 2047 outputs over all four primes makes
+    exactly two such launches, and every product is exact."""
+    pm = gpu_lib
+    items = inputs.batch_uneven(count=200, lo=33, hi=1024, tag=(118,))
+    lcs = [it.a.size + it.b.size - 1 for it in items]
+    assert min(lcs) > 64 and max(lcs) <= 2047
+    assert len({it.p for it in items}) == 4
+    pm.plan_cache_clear()
+    for lc, it in zip(lcs, items):
+        P = pm.plan_for(lc, it.p)
+        assert P.kind == 1 and P.log_ra == 3 and P.log_l <= 11, (lc, P)
+    probs = [(dev(it.a), dev(it.b), it.p) for it in items]
+    say("case: batch of one-work-group lengths 65..2047")
+    pm.trace_reset()
+    pm.trace_enable(True)
+    try:
+        outs = pm.poly_mul_batch(probs)
+        assert pm.stream_check() == 0
+    finally:
+        pm.trace_enable(False)
+    tot, n = pm.trace_query("lds_conv")
+    pm.trace_reset()
+    assert n == 2, n
+    for it, c in zip(items, outs):
+        assert np.array_equal(host(c), op.poly_mul(it.a, it.b, it.p))
+    # and in the captured graph (tracing off), the same products again
+    outs = pm.poly_mul_batch(probs)
+    assert pm.stream_check() == 0
+    for it, c in zip(items, outs):
+        assert np.array_equal(host(c), op.poly_mul(it.a, it.b, it.p))
+
+
 def test_batch_uneven_4096(gpu_lib):
     """The full batch: 4096 products, lengths log-uniform in [64, 65536], four
     primes; every product against the oracle's transform route, and sampled
