@@ -484,6 +484,33 @@ def test_crt_bound_for_int_products():
         assert (q - 1) % (1 << 22) == 0
 
 
+def test_crt_bound_for_32_bit_digits():
+    """Pairs of limbs as 32-bit digits: for every supported size (na + nb - 1
+    <= 2^23 limbs, so at most 2^21 digits in the shorter operand) the exact
+    digit-product sums stay below p1 p2 p3, and the transform length (at
+    most 2^22 points) divides p - 1 for each prime; the digits' convolution,
+    summed at 2^32 per position, is the integer product (checked exactly on
+    small operands, odd limb counts included, by CPython integers)."""
+    P = inputs.INT_PRIMES
+    assert (1 << 21) * (0xFFFFFFFF ** 2) < P[0] * P[1] * P[2]
+    for q in P:
+        assert (q - 1) % (1 << 22) == 0
+    rng = np.random.default_rng(81)
+    for na, nb in ((1, 1), (3, 2), (17, 40), (255, 256), (1001, 998)):
+        a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+        b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+        da = [int(a[2 * j]) + (int(a[2 * j + 1]) << 16 if 2 * j + 1 < na else 0) for j in range((na + 1) // 2)]
+        db = [int(b[2 * j]) + (int(b[2 * j + 1]) << 16 if 2 * j + 1 < nb else 0) for j in range((nb + 1) // 2)]
+        x = [0] * (len(da) + len(db) - 1)
+        for i, u in enumerate(da):
+            for j, v in enumerate(db):
+                x[i + j] += u * v
+        assert max(x) < min(len(da), len(db)) * (1 << 64)
+        value = sum(xk << (32 * k) for k, xk in enumerate(x))
+        assert value == op.limbs_to_int(a) * op.limbs_to_int(b)
+        assert np.array_equal(op.int_mul(a, b), op.carry_limbs(op.int_convolve(a, b), na + nb))
+
+
 # --- cost-model network pins ------------------------------------------------------
 
 def _mlp_params(F=7, H=16, seed=0):
