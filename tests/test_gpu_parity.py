@@ -220,6 +220,26 @@ def test_large_tft_product(gpu_lib):
     assert np.array_equal(got[ks], op.poly_mul_sample(a, b, p, ks))
 
 
+def test_large_products_with_the_bench_plans(gpu_lib):
+    """The two plain large products in the launch configuration bench.py
+    times (its plans, pinned per call): 2^21 x 2^21 and 600001 x 400000 mod
+    2013265921, whole arrays against the oracle's transform route."""
+    import importlib.util
+    import os
+
+    pm = gpu_lib
+    spec = importlib.util.spec_from_file_location(
+        "bench_plans", os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    plans = [pm.Plan(*[int(v) for v in t.split(",")]) for t in bench.TUNED_PLANS.split(";")]
+    for (a, b, p), plan in zip((inputs.large_pow2_product(), inputs.large_tft_product()), plans):
+        say("case: bench plan", plan.as_tuple(), a.size, b.size)
+        got = _product(pm, a, b, p, plan=plan)
+        assert got.size == a.size + b.size - 1
+        assert np.array_equal(got, op.poly_mul_ntt(a, b, p, 31)), plan.as_tuple()
+
+
 @pytest.mark.parametrize("p,g", PRIMES)
 def test_ntt_hook(gpu_lib, p, g):
     pm = gpu_lib
