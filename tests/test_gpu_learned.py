@@ -304,6 +304,38 @@ def test_learned_batch_policy_keeps_the_faster_plans(gpu_lib):
         pm.model_load(os.path.join(root, "paper_1609_01010_amd", "data", "cost_model.txt"))
 
 
+def test_learned_plans_on_the_4096_product_batch(gpu_lib):
+    """The launch configuration bench.py times: the 4096 uneven products under
+    the learned policy with the shipped cost model (batch context, plans
+    checked against the default ones on the first call), then the repeated
+    shape on a second buffer set; every product of both calls against the
+    oracle's transform route."""
+    import os
+
+    import torch
+
+    pm = gpu_lib
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pm.model_load(os.path.join(root, "paper_1609_01010_amd", "data", "cost_model.txt"))
+    items = inputs.batch_uneven()
+    want = [op.poly_mul_ntt(it.a, it.b, it.p, inputs.PRIMES[it.p]) for it in items]
+    pm.plan_cache_clear()
+    pm.set_policy(pm.POLICY_LEARNED)
+    try:
+        for call in range(2):
+            probs = [(torch.from_numpy(it.a).cuda(), torch.from_numpy(it.b).cuda(), it.p) for it in items]
+            say("case: learned 4096-product batch, call", call)
+            outs = pm.poly_mul_batch(probs)
+            assert pm.stream_check() == 0
+            for k, (w, c) in enumerate(zip(want, outs)):
+                assert np.array_equal(c.cpu().numpy(), w), (call, k)
+        used = pm.batch_plans_used(len(items))
+        assert sum(P.kind == 2 for P in used) > len(items) // 2
+    finally:
+        pm.set_policy(pm.POLICY_DEFAULT)
+        pm.plan_cache_clear()
+
+
 def _geomean(xs):
     return float(np.exp(np.mean(np.log(np.asarray(xs, dtype=np.float64)))))
 
