@@ -120,6 +120,96 @@ __device__ __forceinline__ void col_dif_round(const Arith<LAZY>& A, u32* sm, int
   }
 }
 
+// The first round's inputs of a tile (the operand's values, zero beyond
+// its length z; a limb pair as its raw 32-bit digit), read once by kernels
+// that transform the same tile modulo several primes: task k of the thread
+// (as col_dif_round numbers them) holds raw[k][s].
+template <int LB, int LQ, typename TIn>
+__device__ __forceinline__ void col_first_load(u32 (&raw)[16 >> LQ][1 << LQ], int lw, int mr, int tid, int nthr,
+                                               const TIn* __restrict__ in, long z, long C, long col0) {
+  constexpr int Q = 1 << LQ;
+  constexpr int LS = LB - LQ;
+  constexpr int K = 16 / Q;
+  const int ntask = (((mr + (1 << LB) - 1) >> LB) << LS) << lw;
+  const bool w32 = is_limb_pair<TIn>() && (((uintptr_t)in & 3u) == 0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int task = tid + k * nthr;
+    const int c = task & ((1 << lw) - 1);
+    const int g = task >> lw;
+    const int j = g & ((1 << LS) - 1);
+    const int base = ((g >> LS) << LB) + j;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+      const int row = base + (s << LS);
+      const long pos = C * row + col0 + c;
+      u32 d = 0;
+      if (task < ntask) {
+        if constexpr (is_limb_pair<TIn>()) {
+          const uint16_t* __restrict__ l = (const uint16_t*)in;
+          const long i0 = 2 * pos;
+          if (w32 && i0 + 1 < z) {
+            d = gld((const u32*)l + pos);
+          } else {
+            const u32 lo = i0 < z ? (u32)gld(l + i0) : 0u;
+            const u32 hi = i0 + 1 < z ? (u32)gld(l + i0 + 1) : 0u;
+            d = lo | (hi << 16);
+          }
+        } else {
+          d = pos < z ? (u32)gld(in + pos) : 0u;
+        }
+      }
+      raw[k][s] = d;
+    }
+  }
+}
+
+// The first DIF round (blocks of 2^LB rows, as col_dif_round's from global
+// memory) on values col_first_load read, modulo the prime of A: limb pairs
+// reduced by the Shoup product with 1, other inputs taken as they are (they
+// must be below p: 16-bit limbs are, for every prime); ze: the operand's
+// length in elements.
+template <int LB, int LQ, bool TO_GLOBAL, bool LAZY, typename TIn>
+__device__ __forceinline__ void col_dif_first_pre(const Arith<LAZY>& A, const u32 (&raw)[16 >> LQ][1 << LQ], u32* sm,
+                                                  int lw, int mr, const PrimeTables& T, int tid, int nthr, long ze,
+                                                  long C, long col0, u32* __restrict__ out) {
+  constexpr int Q = 1 << LQ;
+  constexpr int LS = LB - LQ;
+  constexpr int K = 16 / Q;
+  const int ntask = (((mr + (1 << LB) - 1) >> LB) << LS) << lw;
+  uint2 one = make_uint2(0u, 0u);
+  if constexpr (is_limb_pair<TIn>()) one = cld(T.pf + 1);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int task = tid + k * nthr;
+    if (task < ntask) {
+      const int c = task & ((1 << lw) - 1);
+      const int g = task >> lw;
+      const int j = g & ((1 << LS) - 1);
+      const int base = ((g >> LS) << LB) + j;
+      u32 x[Q];
+#pragma unroll
+      for (int s = 0; s < Q; ++s) x[s] = is_limb_pair<TIn>() ? A.mul(raw[k][s], one) : raw[k][s];
+      if ((C << (LB - 1)) >= ze)  // rows R/2 and up are zero
+        dif_reg<Q, LAZY, (LS > 0), true>(A, x, T.pf);
+      else
+        dif_reg<Q, LAZY, (LS > 0)>(A, x, T.pf);
+      const uint2* tw = T.rf[LQ - 1] + (1 << LB) + j * Q;
+#pragma unroll
+      for (int t = 0; t < Q; ++t) {
+        const int row = base + (t << LS);
+        u32 v = x[t];
+        if (LS > 0 && t > 0) v = A.mul(v, cld(tw + t));
+        if constexpr (TO_GLOBAL) {
+          if (row < mr) gst(out + C * row + col0 + c, v);
+        } else {
+          sm[(row << lw) + c] = v;
+        }
+      }
+    }
+  }
+}
+
 // rounds K.. of the forward column transform on blocks of 2^LB rows; a
 // barrier separates consecutive rounds
 template <int LR, int K, int LB, bool LAZY, typename TIn, bool TWIST>

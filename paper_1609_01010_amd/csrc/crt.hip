@@ -132,10 +132,10 @@ struct JobsOf3 {
 };
 
 // Forward columns of one operand (blockIdx.y) modulo the three primes
-// (t.j[0..2]), one after the other on the same tile of limbs: the first
-// prime's round reads the tile from memory, the others find it in the L2
-// cache (each limb is read from HBM once), and the stores of one prime drain
-// while the next one computes.
+// (t.j[0..2]), one after the other on the same tile of limbs: the tile's
+// first-round values are read from memory once, into registers, and each
+// prime reduces and transforms them; the stores of one prime drain while the
+// next one computes.
 template <int LR, typename TIn>
 __global__ void __launch_bounds__(1024) k_col_fwd_int3(JobsOf3 t, ConvJob* __restrict__ jobs_out, int logC, int lw) {
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
@@ -144,9 +144,17 @@ __global__ void __launch_bounds__(1024) k_col_fwd_int3(JobsOf3 t, ConvJob* __res
     jobs_out[2] = t.j[2];
   }
   extern __shared__ u32 sm[];  // [R][W]
+  constexpr int LQ0 = col_round_lq<LR, 0>();
   const int nthr = blockDim.x;
   const long C = 1l << logC;
   const long col0 = (long)blockIdx.x << lw;
+  // the operand, its length and the kept rows are the same for the three
+  // primes (one plan)
+  const TIn* in = (const TIn*)(blockIdx.y ? t.j[0].b : t.j[0].a);
+  const long z = blockIdx.y ? t.j[0].lb : t.j[0].la;
+  const long ze = is_limb_pair<TIn>() ? (z + 1) >> 1 : z;
+  u32 raw[16 >> LQ0][1 << LQ0];
+  col_first_load<LR, LQ0, TIn>(raw, lw, t.j[0].rows, threadIdx.x, nthr, in, z, C, col0);
   bool bad = false;
 #pragma unroll 1
   for (int pr = 0; pr < 3; ++pr) {
@@ -157,11 +165,14 @@ __global__ void __launch_bounds__(1024) k_col_fwd_int3(JobsOf3 t, ConvJob* __res
     asm volatile("" : "+v"(tid));
     const ConvJob J = t.j[pr];
     const Arith<true> A(J.mp);
-    const TIn* in = (const TIn*)(blockIdx.y ? J.b : J.a);
-    const long z = blockIdx.y ? J.lb : J.la;
+    const PrimeTables T = fresh(J.T);
     u32* out = blockIdx.y ? J.Tb : J.Ta;
-    col_dif_rounds<LR, 0, LR, true, TIn, false>(A, sm, lw, J.rows, fresh(J.T), tid, nthr, in, z, C, col0, out,
-                                                nullptr, bad);
+    col_dif_first_pre<LR, LQ0, LQ0 == LR, true, TIn>(A, raw, sm, lw, J.rows, T, tid, nthr, ze, C, col0, out);
+    if constexpr (LQ0 < LR) {
+      __syncthreads();
+      col_dif_rounds<LR, 1, LR - LQ0, true, TIn, false>(A, sm, lw, J.rows, T, tid, nthr, in, z, C, col0, out,
+                                                        nullptr, bad);
+    }
     __syncthreads();  // the next prime reuses the tile
   }
 }
