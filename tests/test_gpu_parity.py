@@ -868,6 +868,48 @@ def test_caller_owned_workspace(gpu_lib):
     assert np.array_equal(host(c), op.poly_mul_ntt(a, b, p, inputs.PRIMES[p]))
 
 
+def test_integer_product_workspace_is_exact(gpu_lib):
+    """Under the default policy the integer product's workspace query is the
+    exact need of the layout the call takes (32-bit digits here, and 16-bit
+    ones when forced): a caller workspace of that size runs the product
+    exactly; 256 bytes less is refused with PM_ENOMEM and nothing is
+    written."""
+    import torch
+
+    pm = gpu_lib
+    rng = np.random.default_rng(173)
+    na, nb = 100001, 77777
+    a = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+    b = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+    want = op.int_mul(a, b)
+    ta, tb = dev(a, np.uint16), dev(b, np.uint16)
+    s = torch.cuda.Stream()
+    pm.plan_cache_clear()
+    try:
+        for digits in (None, 16):
+            need = pm.int_mul_workspace_query(na, nb, digits=digits)
+            say("case: integer product in an exact workspace", digits, need)
+            buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+            torch.cuda.synchronize()
+            pm.set_workspace(buf, stream=s)
+            with torch.cuda.stream(s):
+                c = pm.int_mul(ta, tb, stream=s, digits=digits)
+            s.synchronize()
+            assert pm.stream_check() == 0
+            assert np.array_equal(host(c), want), digits
+            pm.set_workspace(buf[:need - 256], stream=s)
+            out = torch.full((na + nb,), 0x5A5A, dtype=torch.int32).to(torch.uint16).cuda()
+            torch.cuda.synchronize()
+            with pytest.raises(pm.PolymulError) as e:
+                pm.int_mul(ta, tb, out=out, stream=s, digits=digits)
+            assert e.value.status == pm.PM_ENOMEM
+            s.synchronize()
+            assert bool((out == 0x5A5A).all())
+            pm.set_workspace(None, stream=s)
+    finally:
+        pm.set_workspace(None, stream=s)
+
+
 def test_not_reduced_input_is_reported(gpu_lib):
     pm = gpu_lib
     p = 998244353
