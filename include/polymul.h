@@ -49,7 +49,9 @@ typedef enum {
 const char* pm_status_str(pm_status s);
 
 /* Initialise the library on the current device (optional: every call does it
- * on first use).  Builds the twiddle tables of all four primes. */
+ * on first use).  Builds the twiddle tables of all four primes.  The first
+ * pm_init of a process also applies pm_config_from_env(); if that fails, this
+ * and every later pm_init return its status. */
 pm_status pm_init(void);
 
 /*
@@ -307,6 +309,18 @@ typedef struct {
 
 /* Select the policy used by pm_poly_mul / pm_poly_mul_batch to pick plans. */
 pm_status pm_set_policy(pm_policy policy);
+/* The policy in force (PM_POLICY_DEFAULT until one is set). */
+pm_policy pm_get_policy(void);
+/* Plan choice from the process environment (host only; needs no device):
+ *   PM_PLAN_POLICY  "default", "exhaustive" or "learned": pm_set_policy;
+ *   PM_TUNE_DB      path of a timing database: pm_tune_db_load (appends);
+ *   PM_MLP_WEIGHTS  path of cost-model weights: pm_model_load.
+ * Unset or empty variables change nothing.  Another policy name gives
+ * PM_EINVAL before anything is applied; otherwise the database and the model
+ * load first (their status is returned at the first failure, leaving the
+ * rest unapplied) and the policy is set last.  May be called again to re-read
+ * the environment. */
+pm_status pm_config_from_env(void);
 
 /* Timing contexts of the tuner, the database and the cost model.  A product
  * on its own is bound by its own parallelism (its plan should spread it over

@@ -102,6 +102,8 @@ SIGNATURES = {
     "pm_itft_granularity": (_sz, [_sz]),
     "pm_stream_check": (_int, [_vp]),
     "pm_set_policy": (_int, [_int]),
+    "pm_get_policy": (_int, []),
+    "pm_config_from_env": (_int, []),
     "pm_plan_for": (_int, [_sz, _u32, ctypes.POINTER(Plan)]),
     "pm_plan_for_ctx": (_int, [_sz, _u32, _int, ctypes.POINTER(Plan)]),
     "pm_poly_mul_plan": (_int, [_vp, _sz, _vp, _sz, _u32, _vp, ctypes.POINTER(Plan), _vp]),
@@ -422,6 +424,15 @@ def stream_check(stream=None) -> int:
 
 def set_policy(policy: int):
     _check(lib().pm_set_policy(policy), "pm_set_policy")
+
+
+def get_policy() -> int:
+    return int(lib().pm_get_policy())
+
+
+def config_from_env():
+    """Apply PM_PLAN_POLICY, PM_TUNE_DB and PM_MLP_WEIGHTS (host only)."""
+    _check(lib().pm_config_from_env(), "pm_config_from_env")
 
 
 def plan_for(lc: int, p: int, context: int = 0) -> Plan:

@@ -2,7 +2,9 @@
 // and the launch sequences of the product, the hooks and the integer product.
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <set>
 #include <tuple>
 
@@ -556,6 +558,11 @@ const char* pm_status_str(pm_status s) {
 }
 
 pm_status pm_init(void) {
+  // the environment is read once per process; a bad setting fails every pm_init
+  static std::once_flag env_once;
+  static pm_status env_st = PM_OK;
+  std::call_once(env_once, [] { env_st = pm_config_from_env(); });
+  if (env_st) return env_st;
   pm_status st;
   DevCtx* c = ctx_current(&st);
   if (!c) return st;
@@ -746,6 +753,32 @@ pm_status pm_set_policy(pm_policy policy) {
   g_policy.store(policy);
   plan_epoch_bump();
   return PM_OK;
+}
+
+pm_policy pm_get_policy(void) { return current_policy(); }
+
+// the plan choice from the process environment: the policy's name is checked
+// before anything is applied, then the database and the model are loaded, and
+// the policy is set last (a failed load leaves it as it was)
+pm_status pm_config_from_env(void) {
+  const char* pol = std::getenv("PM_PLAN_POLICY");
+  const char* db = std::getenv("PM_TUNE_DB");
+  const char* model = std::getenv("PM_MLP_WEIGHTS");
+  int policy = -1;
+  if (pol && *pol) {
+    if (!strcmp(pol, "default"))
+      policy = PM_POLICY_DEFAULT;
+    else if (!strcmp(pol, "exhaustive"))
+      policy = PM_POLICY_EXHAUSTIVE;
+    else if (!strcmp(pol, "learned"))
+      policy = PM_POLICY_LEARNED;
+    else
+      return PM_EINVAL;
+  }
+  pm_status st;
+  if (db && *db && (st = pm_tune_db_load(db))) return st;
+  if (model && *model && (st = pm_model_load(model))) return st;
+  return policy >= 0 ? pm_set_policy((pm_policy)policy) : PM_OK;
 }
 
 pm_status pm_plan_for(size_t lc, uint32_t p, pm_plan* plan) { return pm_plan_for_ctx(lc, p, PM_CTX_SINGLE, plan); }

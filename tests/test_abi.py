@@ -237,3 +237,80 @@ def test_plan_space_on_host():
     assert (P.ma << (P.log_l - P.log_ra)) < (1 << 20)
     P = pm.plan_for(2047, 998244353)
     assert P.kind == 1 and P.log_l == 11
+
+
+_ENV_CHILD = r"""
+import os, sys
+import numpy as np
+import paper_1609_01010_amd as pm
+
+db, weights = sys.argv[1], sys.argv[2]
+assert pm.get_policy() == pm.POLICY_DEFAULT
+P1 = pm.plan_candidates(70001, 998244353)[0]
+P2 = pm.plan_candidates(3000, 2013265921, general_radix=False)[-1]
+pm.tune_db_add(70001, 998244353, P1, 12.5, pm.CTX_SINGLE)
+pm.tune_db_add(3000, 2013265921, P2, 3.25, pm.CTX_BATCH)
+pm.tune_db_save(db)
+pm.tune_db_clear()
+
+def status(f):
+    try:
+        f()
+        return 0
+    except pm.PolymulError as e:
+        return e.status
+
+# empty variables change nothing
+os.environ.update(PM_PLAN_POLICY="", PM_TUNE_DB="", PM_MLP_WEIGHTS="")
+pm.config_from_env()
+assert pm.get_policy() == pm.POLICY_DEFAULT and pm.lib().pm_tune_db_size() == 0
+assert status(pm.model_get) != 0  # no model yet
+
+# an unknown policy name is refused before the files are read
+os.environ.update(PM_PLAN_POLICY="fastest", PM_TUNE_DB=db, PM_MLP_WEIGHTS=weights)
+assert status(pm.config_from_env) == pm.PM_EINVAL
+assert pm.get_policy() == pm.POLICY_DEFAULT and pm.lib().pm_tune_db_size() == 0
+assert status(pm.model_get) != 0
+
+# a missing database: the error is returned and the policy is not set
+os.environ.update(PM_PLAN_POLICY="exhaustive", PM_TUNE_DB=db + ".missing")
+assert status(pm.config_from_env) == pm.PM_EINVAL
+assert pm.get_policy() == pm.POLICY_DEFAULT
+
+# all three applied
+os.environ.update(PM_PLAN_POLICY="learned", PM_TUNE_DB=db)
+pm.config_from_env()
+assert pm.get_policy() == pm.POLICY_LEARNED
+rows = [(r[0], r[1], r[2].as_tuple(), r[3]) for r in pm.tune_db_rows(pm.CTX_SINGLE)]
+assert rows == [(70001, 998244353, P1.as_tuple(), 12.5)], rows
+rows = [(r[0], r[1], r[2].as_tuple(), r[3]) for r in pm.tune_db_rows(pm.CTX_BATCH)]
+assert rows == [(3000, 2013265921, P2.as_tuple(), 3.25)], rows
+w, mean, sd = pm.model_get()
+vals = open(weights).read().split("\n")
+assert (mean, sd) == tuple(float(np.float32(v)) for v in vals[1].split()), (mean, sd)
+want = np.array([float(v) for v in vals[2:] if v.strip()], dtype=np.float32)
+assert np.array_equal(w, want)
+
+# the other names set the policy too
+for name, want_policy in (("exhaustive", pm.POLICY_EXHAUSTIVE), ("default", pm.POLICY_DEFAULT)):
+    os.environ.update(PM_PLAN_POLICY=name, PM_TUNE_DB="", PM_MLP_WEIGHTS="")
+    pm.config_from_env()
+    assert pm.get_policy() == want_policy
+print("env ok")
+"""
+
+
+def test_plan_choice_from_the_environment(tmp_path):
+    """PM_PLAN_POLICY, PM_TUNE_DB and PM_MLP_WEIGHTS are applied on the host
+    (in a child process, so the loaded model stays out of this one): empty
+    variables change nothing, an unknown policy name and a missing file are
+    refused without setting the policy, and the database rows and the weights
+    arrive exactly as written."""
+    import subprocess
+    import sys
+
+    weights = os.path.join(ROOT, "paper_1609_01010_amd", "data", "cost_model.txt")
+    env = {k: v for k, v in os.environ.items() if not k.startswith("PM_")}
+    r = subprocess.run([sys.executable, "-c", _ENV_CHILD, str(tmp_path / "db.txt"), weights], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "env ok" in r.stdout, r.stdout + r.stderr
